@@ -1,0 +1,81 @@
+"""Tracer time stepping for dX/dt = u(X) (oracle; test infrastructure only).
+
+Follows Sec. 2.2, Eq. "tracers" (tracer ODE with X(x,0) = x) and the
+multi-step Adams-Bashforth integration with an rhs history kept per particle
+(Sec. 2.2; Sec. 3.3.1, the *state* and *rhs* arrays).
+
+Readings (the paper gives neither the order nor the start-up):
+
+* The field is frozen (no fluid solver runs beside the particles).
+* Euler:  X <- W(X + dt*u(X)).
+* Heun:   k1 = u(X); Xs = W(X + dt*k1); k2 = u(Xs); X <- W(X + (dt/2)*(k1 + k2)).
+* AB2:    X <- W(X + dt*(3/2*u_n - 1/2*u_{n-1})) with an Euler first step; the
+  history holds [u_n, u_{n-1}] and its length (0, 1 or 2) so a run can resume.
+* W is the periodic wrap of ``geometry.wrap``: the state is stored wrapped.
+* Every operation is a separately rounded binary64 operation in the order
+  written (``dt/2`` is formed once as 0.5*dt).
+* When a gradient is requested it is evaluated at each step's start position
+  (together with the first velocity evaluation); the value returned is the one
+  of the last step.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .geometry import wrap
+
+EULER, HEUN, AB2 = 1, 2, 3
+
+
+def euler_update(X, dt, u):
+    return wrap(np.add(X, np.multiply(dt, u)))
+
+
+def heun_predict(X, dt, k1):
+    return wrap(np.add(X, np.multiply(dt, k1)))
+
+
+def heun_correct(X, dt, k1, k2):
+    return wrap(np.add(X, np.multiply(0.5 * dt, np.add(k1, k2))))
+
+
+def ab2_update(X, dt, u_n, u_prev):
+    inc = np.subtract(np.multiply(1.5, u_n), np.multiply(0.5, u_prev))
+    return wrap(np.add(X, np.multiply(dt, inc)))
+
+
+def advance(X, velocity, scheme: int, dt: float, nsteps: int, hist=None, hist_len: int = 0,
+            gradient=None):
+    """Advance positions X[Np][3] by nsteps.
+
+    ``velocity(X) -> u[Np][3]``; ``gradient(X) -> (u, grad)`` if given.
+    Returns (X, hist, hist_len, grad_last).
+    """
+    X = np.array(X, dtype=np.float64)
+    grad_last = None
+    if hist is None:
+        hist = np.zeros((2,) + X.shape)
+    hist = np.array(hist, dtype=np.float64)
+    for _ in range(nsteps):
+        if gradient is not None:
+            u0, grad_last = gradient(X)
+        else:
+            u0 = velocity(X)
+        if scheme == EULER:
+            X = euler_update(X, dt, u0)
+        elif scheme == HEUN:
+            Xs = heun_predict(X, dt, u0)
+            k2 = velocity(Xs)
+            X = heun_correct(X, dt, u0, k2)
+        elif scheme == AB2:
+            if hist_len == 0:
+                Xn = euler_update(X, dt, u0)
+            else:
+                Xn = ab2_update(X, dt, u0, hist[0])
+            hist[1] = hist[0]
+            hist[0] = u0
+            hist_len = min(hist_len + 1, 2)
+            X = Xn
+        else:
+            raise ValueError("unknown scheme")
+    return X, hist, hist_len, grad_last

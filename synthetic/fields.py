@@ -1,0 +1,148 @@
+"""Seeded synthetic velocity fields on the periodic grid [0, 2*pi)^3.
+
+Layout of every grid returned here: ``u[x3][x2][x1][a]`` (x1 fastest, the three
+components fastest within a node), grid spacing delta = 2*pi/N, node j at j*delta.
+
+* ``fourier_mode_field``: u_a(x) = sum_k A_{a,k} cos(k.x + phi_{a,k}) over integer
+  wave vectors 1 <= |k| <= kmax in a half space, A ~ N(0,1), phi ~ U[0, 2*pi),
+  numpy ``default_rng(seed)``.  Grid values are the direct FP64 sum; the same
+  sum evaluated at arbitrary points (``fourier_mode_eval``) is the exact field.
+* ``single_mode_field``: one cosine mode per component, with its exact value and
+  gradient, for convergence-order checks.
+* ``spectral_field``: solenoidal Gaussian random-phase field
+      u^(k) = sqrt(E(|k|) / (4 pi |k|^2)) (1 - k k^T/|k|^2) xi(k),
+  xi complex standard normal, E(k) = k^(-5/3) for 1 <= k <= kc and
+  k^(-5/3) exp(-(k - kc)/(0.1 kc)) above, modes with any |k_j| >= N/2 removed,
+  transformed with an inverse real FFT and scaled so that the mean over grid
+  and components of u_a^2 is 1.  Built with torch on the requested device
+  (the FFT is input synthesis only).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+L = 2.0 * math.pi
+
+
+def _half_space_modes(kmax: int) -> np.ndarray:
+    ks = []
+    r = range(-kmax, kmax + 1)
+    for k3 in r:
+        for k2 in r:
+            for k1 in r:
+                n2 = k1 * k1 + k2 * k2 + k3 * k3
+                if n2 < 1 or n2 > kmax * kmax:
+                    continue
+                if k3 > 0 or (k3 == 0 and (k2 > 0 or (k2 == 0 and k1 > 0))):
+                    ks.append((k1, k2, k3))
+    return np.array(ks, dtype=np.int64)
+
+
+def fourier_mode_field(N: int, kmax: int = 8, seed: int = 0):
+    """Returns (u[N,N,N,3] float64, modes) with modes = dict(k, A, phi)."""
+    k = _half_space_modes(kmax)
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((k.shape[0], 3))
+    phi = rng.uniform(0.0, L, (k.shape[0], 3))
+    modes = {"k": k, "A": A, "phi": phi}
+    x = np.arange(N) * (L / N)
+    u = np.empty((N, N, N, 3))
+    E1 = np.exp(1j * np.outer(k[:, 0], x))      # [M, N]
+    E2 = np.exp(1j * np.outer(k[:, 1], x))
+    E3 = np.exp(1j * np.outer(k[:, 2], x))
+    for a in range(3):
+        C = A[:, a] * np.exp(1j * phi[:, a])
+        for i3 in range(N):
+            T = (C * E3[:, i3])[:, None] * E2       # [M, N(x2)]
+            u[i3, :, :, a] = np.real(T.T @ E1)       # [x2, x1]
+    return u, modes
+
+
+def fourier_mode_eval(modes, X: np.ndarray, gradient: bool = False):
+    """Exact field (and gradient [P,a,b]) of a Fourier-mode field at X[P,3]."""
+    X = np.asarray(X, dtype=np.float64).reshape(-1, 3)
+    k = modes["k"].astype(np.float64)
+    ph = X @ k.T                                   # [P, M]
+    u = np.empty((X.shape[0], 3))
+    g = np.empty((X.shape[0], 3, 3)) if gradient else None
+    for a in range(3):
+        arg = ph + modes["phi"][:, a]
+        u[:, a] = np.cos(arg) @ modes["A"][:, a]
+        if gradient:
+            s = -np.sin(arg) * modes["A"][:, a]
+            g[:, a, :] = s @ k
+    return (u, g) if gradient else u
+
+
+def single_mode_field(N: int, kvec, amp=(1.0, 0.7, -0.4), phase=(0.3, 1.1, 2.0)):
+    """Grid of u_a = amp_a cos(k.x + phase_a) and its exact evaluator."""
+    kvec = np.asarray(kvec, dtype=np.float64)
+    x = np.arange(N) * (L / N)
+    X3, X2, X1 = np.meshgrid(x, x, x, indexing="ij")
+    arg = kvec[0] * X1 + kvec[1] * X2 + kvec[2] * X3
+    u = np.stack([amp[a] * np.cos(arg + phase[a]) for a in range(3)], axis=-1)
+
+    def exact(X, gradient=False):
+        X = np.asarray(X, dtype=np.float64).reshape(-1, 3)
+        ar = X @ kvec
+        val = np.stack([amp[a] * np.cos(ar + phase[a]) for a in range(3)], axis=-1)
+        if not gradient:
+            return val
+        g = np.stack([-amp[a] * np.sin(ar + phase[a])[:, None] * kvec[None, :]
+                      for a in range(3)], axis=1)
+        return val, g
+
+    return u, exact
+
+
+def spectral_field(N: int, kc: float, seed: int, device="cpu", dtype=None):
+    """Solenoidal random-phase field as a torch tensor [N,N,N,3] (see module doc)."""
+    import torch
+    if dtype is None:
+        dtype = torch.float32
+    cdtype = torch.complex128 if dtype == torch.float64 else torch.complex64
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    kf = torch.fft.fftfreq(N, d=1.0 / N, device=device, dtype=dtype)
+    kr = torch.fft.rfftfreq(N, d=1.0 / N, device=device, dtype=dtype)
+    K3 = kf.view(N, 1, 1)
+    K2 = kf.view(1, N, 1)
+    K1 = kr.view(1, 1, -1)
+    kk = torch.sqrt(K1 * K1 + K2 * K2 + K3 * K3)
+    kk_safe = torch.where(kk > 0, kk, torch.ones_like(kk))
+    E = kk_safe ** (-5.0 / 3.0)
+    E = torch.where(kk > kc, E * torch.exp(-(kk - kc) / (0.1 * kc)), E)
+    keep = (kk >= 1) & (K1.abs() < N / 2) & (K2.abs() < N / 2) & (K3.abs() < N / 2)
+    amp = torch.where(keep, torch.sqrt(E / (4.0 * math.pi * kk_safe * kk_safe)),
+                      torch.zeros_like(E))
+    del E
+    shape = (N, N, N // 2 + 1)
+
+    def cnormal():
+        re = torch.randn(shape, generator=gen, device=device, dtype=dtype)
+        im = torch.randn(shape, generator=gen, device=device, dtype=dtype)
+        return torch.complex(re, im) * (1.0 / math.sqrt(2.0))
+
+    xi = [cnormal() for _ in range(3)]
+    kdot = (K1 * xi[0] + K2 * xi[1] + K3 * xi[2]) / kk_safe
+    Ks = (K1, K2, K3)
+    out = torch.empty((N, N, N, 3), device=device, dtype=dtype)
+    for a in range(3):
+        uh = (xi[a] - (Ks[a] / kk_safe) * kdot) * amp
+        xi[a] = None
+        out[..., a] = torch.fft.irfftn(uh.to(cdtype), s=(N, N, N), dim=(0, 1, 2))
+        del uh
+    del kdot, xi
+    ms = torch.mean(out.to(torch.float64) ** 2) if N <= 256 else _chunked_ms(out)
+    out *= (1.0 / math.sqrt(float(ms)))
+    return out
+
+
+def _chunked_ms(u):
+    import torch
+    acc = 0.0
+    for i in range(0, u.shape[0], 64):
+        acc += float(torch.sum(u[i:i + 64].to(torch.float64) ** 2))
+    return acc / u.numel()

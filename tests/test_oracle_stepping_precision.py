@@ -1,0 +1,101 @@
+"""Pins of the oracle's time stepping and reduced-precision storage (CPU only)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import geometry, precision, stepping
+
+L = geometry.L
+
+
+def _circ(a, b):
+    d = np.abs(a - b) % L
+    return np.minimum(d, L - d)
+
+
+def shear(X):
+    u = np.zeros_like(X)
+    u[:, 0] = np.sin(X[:, 1])
+    return u
+
+
+def abc(X):
+    return np.stack([np.sin(X[:, 1]) + 0.5 * np.cos(X[:, 2]),
+                     np.sin(X[:, 2]) + 0.5 * np.cos(X[:, 0]),
+                     np.sin(X[:, 0]) + 0.5 * np.cos(X[:, 1])], axis=1)
+
+
+def rk4(X, f, dt, n):
+    for _ in range(n):
+        k1 = f(X)
+        k2 = f(X + 0.5 * dt * k1)
+        k3 = f(X + 0.5 * dt * k2)
+        k4 = f(X + dt * k3)
+        X = X + dt / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return X
+
+
+@pytest.mark.parametrize("scheme", [stepping.EULER, stepping.HEUN, stepping.AB2])
+def test_shear_flow_exact(scheme):
+    X0 = np.random.default_rng(0).uniform(0, L, (500, 3))
+    dt, n = 1e-2, 37
+    X, _, _, _ = stepping.advance(X0, shear, scheme, dt, n)
+    ex = X0.copy()
+    ex[:, 0] = X0[:, 0] + n * dt * np.sin(X0[:, 1])
+    assert np.max(_circ(X, ex)) < 1e-12
+    assert np.all((X >= 0) & (X < L))
+
+
+@pytest.mark.parametrize("scheme", [stepping.EULER, stepping.HEUN, stepping.AB2])
+def test_constant_velocity(scheme):
+    X0 = np.random.default_rng(1).uniform(0, L, (100, 3))
+    c = np.array([0.7, -1.3, 2.1])
+    X, _, _, _ = stepping.advance(X0, lambda X: np.broadcast_to(c, X.shape).copy(), scheme, 1e-3, 50)
+    assert np.max(_circ(X, X0 + 50 * 1e-3 * c)) < 1e-13
+
+
+@pytest.mark.parametrize("scheme,order", [(stepping.EULER, 1), (stepping.HEUN, 2), (stepping.AB2, 2)])
+def test_convergence_order_in_dt(scheme, order):
+    X0 = np.random.default_rng(2).uniform(0, L, (200, 3))
+    T = 0.5
+    ref = rk4(X0.copy(), abc, T / 2000, 2000)
+    errs = []
+    for n in [50, 100, 200]:
+        X, _, _, _ = stepping.advance(X0, abc, scheme, T / n, n)
+        errs.append(np.max(_circ(X, ref)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - order) < 0.25), rates
+
+
+def test_ab2_resume_bitwise():
+    X0 = np.random.default_rng(3).uniform(0, L, (300, 3))
+    Xa, ha, la, _ = stepping.advance(X0, abc, stepping.AB2, 2e-3, 40)
+    Xb, hb, lb, _ = stepping.advance(X0, abc, stepping.AB2, 2e-3, 17)
+    Xb, hb, lb, _ = stepping.advance(Xb, abc, stepping.AB2, 2e-3, 23, hist=hb, hist_len=lb)
+    assert np.array_equal(Xa, Xb) and np.array_equal(ha, hb) and la == lb == 2
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.standard_normal(100000).astype(np.float32),
+                        np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, -1 - 2 ** -8, 0.0, -0.0,
+                                  1e-40, 3.0e38, 65504.0, 2 ** -126], dtype=np.float32)])
+    ours = precision.f32_to_bf16_bits(x)
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(ours, ref)
+
+
+def test_f16_rounding_matches_torch():
+    x = np.random.default_rng(5).standard_normal(100000).astype(np.float32) * 3
+    ref = torch.from_numpy(x).to(torch.float16).to(torch.float64).numpy()
+    assert np.array_equal(x.astype(np.float16).astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("storage,rel", [(precision.BF16, 2.0 ** -8), (precision.F16, 2.0 ** -11)])
+def test_store_scale_and_error(storage, rel):
+    rng = np.random.default_rng(6)
+    u = (rng.standard_normal((8, 8, 8, 3)) * np.array([0.5, 2.0, 7.0])).astype(np.float32)
+    vals, s = precision.store(u, storage)
+    assert np.allclose(np.sqrt(np.mean(vals.reshape(-1, 3) ** 2, axis=0)), 1.0, rtol=1e-2)
+    back = vals * s
+    assert np.max(np.abs(back - u) / np.abs(u).clip(1e-3)) <= rel * 1.01
