@@ -1,0 +1,234 @@
+"""Benchmark of the particle-tracking hot path on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): a 1024^3
+periodic grid holding a solenoidal random-phase FP32 velocity field (E(k) ~
+k^-5/3 up to k = 340, exponential cutoff above, unit rms, seed 2), 1e8 uniform
+particles (seed 12), the C2 spline kernel with I = 8, velocity and velocity
+gradient (9 components via derivative kernels), Heun steps with dt = 1e-3.
+
+One step = one Heun step of every particle through the whole path: position
+update, re-binning (keys + stable radix sort + offsets + state permutation),
+interpolation of velocity and gradient at X_n, velocity at the re-binned
+predictor, corrector.  That is two particle-interpolations per particle per
+step; ``value`` counts both.
+
+Prints ONE JSON line.  Extra fields: ``roofline`` (dominant kernel, timed with
+HIP events on the library's stream), ``cpu_baseline`` (the oracle on the host
+cores, on a bounded sample) and ``forms`` (BF16/FP16 storage and FP32
+interpolation-only timings with their errors against the FP64 oracle).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_GRID = 1024
+N_PART = 100_000_000
+KC = 340.0
+DT = 1e-3
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "interp_grad_f32_i8_1024_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2107_01104_amd", "csrc", "interp.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(N, Np, node_bytes, out_bytes_per_particle):
+    """Field read once + positions read + outputs written."""
+    return N ** 3 * node_bytes + Np * 24 + Np * out_bytes_per_particle
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(kind):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha") != kernel_sha():
+        return None
+    return rec.get(kind)
+
+
+def cpu_baseline(u_host, X_host, budget_s=12.0):
+    """Time the C oracle (value+gradient and value, as in one Heun step) on a sample."""
+    import numpy as np
+    from oracle import cbuild
+    from oracle import kernels as K
+    n = 2000
+    t0 = time.perf_counter()
+    cbuild.triple_sum(u_host, X_host[:n], K.SPLINE, 8, 2, gradient=True)
+    cbuild.triple_sum(u_host, X_host[:n], K.SPLINE, 8, 2, gradient=False)
+    dt0 = time.perf_counter() - t0
+    n = int(min(len(X_host), max(n, n * budget_s / max(dt0, 1e-3))))
+    t0 = time.perf_counter()
+    _, _, th = cbuild.triple_sum(u_host, X_host[:n], K.SPLINE, 8, 2, gradient=True)
+    cbuild.triple_sum(u_host, X_host[:n], K.SPLINE, 8, 2, gradient=False)
+    el = time.perf_counter() - t0
+    return {"value": 2 * n / el, "unit": "particle-interpolations/s", "cores": int(th), "kind": "oracle",
+            "sample": (f"first {n} of the 1e8 workload particles, each evaluated twice as in one Heun "
+                       f"step (velocity+gradient, then velocity), I=8 C2 spline on the 1024^3 FP32 field "
+                       f"values in FP64 arithmetic; plain C oracle with OpenMP over particles; "
+                       f"{el:.1f} s wall")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--particles", type=float, default=N_PART)
+    ap.add_argument("--grid", type=int, default=N_GRID)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus above 1 is not supported "
+                                   "(the multi-GPU slab sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2107_01104_amd import ptk
+    from synthetic import fields, particles
+
+    dev = torch.device("cuda", 0)
+    N, Np = args.grid, int(args.particles)
+    kc = KC * N / 1024
+    t0 = time.time()
+    u = fields.spectral_field(N, kc=kc, seed=2, device=dev, dtype=torch.float32)
+    torch.cuda.synchronize()
+    log(f"field {N}^3 synthesised in {time.time() - t0:.1f} s")
+    need_host = not (args.no_cpu_baseline and args.no_forms)
+    u_host = u.cpu().numpy() if need_host else None
+    ctx = ptk.Context(0)
+    ctx.set_field(u, ptk.SPLINE, 8, 2, storage=ptk.F32)
+    torch.cuda.synchronize()
+    del u
+    torch.cuda.empty_cache()
+    X0 = particles.uniform_particles(Np, seed=12, device=dev)
+    X = X0.clone()
+    grad = torch.empty((Np, 3, 3), dtype=torch.float32, device=dev)
+
+    # a plain device copy of known size (1 GiB each way): the reference for
+    # scaling hardware byte counters in profiling runs of this script
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    del a, b
+
+    ctx.advance(X, ptk.HEUN, DT, args.warmup, grad_out=grad)
+    torch.cuda.synchronize()
+    log("warmup done")
+    ctx.timing(True)
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ctx.advance(X, ptk.HEUN, DT, args.steps, grad_out=grad)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    timers = ctx.timing_read()
+    ctx.timing(False)
+    K = args.steps
+    value = 2.0 * Np * K / (total_ms * 1e-3)
+    log(f"{K} Heun steps in {total_ms:.1f} ms; timers: {timers}")
+
+    # dominant kernel: the interpolation with gradient (or without, if larger)
+    kind = max(("interp_grad", "interp"), key=lambda k: timers[k][0])
+    ms, launches = timers[kind]
+    avg_ms = ms / max(launches, 1)
+    out_b = 12 + 36 if kind == "interp_grad" else 12
+    alg = algorithmic_bytes(N, Np, 12, out_b)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(kind),
+                "kernel": f"k_interp<F32, I=8, grad={kind == 'interp_grad'}>",
+                "avg_launch_ms": round(avg_ms, 3), "algorithmic_bytes_per_launch": alg,
+                "launches": launches}
+    breakdown = {k: round(v[0] / K, 3) for k, v in timers.items()}
+
+    forms = None
+    if not args.no_forms:
+        forms = run_forms(ctx, ptk, u_host, X0, N, Np)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(u_host, X0[:200000].cpu().numpy())
+
+    line = {
+        "metric": "particle-interpolations/sec at I=8, 1024^3 grid; % HBM roofline; RMS err vs FP64",
+        "value": value, "unit": "particle-interpolations/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": total_ms / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"cfg2: {N}^3 FP32 spectral field (k<={kc:g}), {Np:.3g} particles, "
+                               f"C2 spline I=8, velocity+gradient, Heun dt={DT}",
+                   "grid": N, "particles": Np, "kernel": "spline I=8 m=2", "scheme": "heun",
+                   "gradient": True, "storage": "f32"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "ms_per_step_breakdown": breakdown,
+        "forms": forms,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def run_forms(ctx, ptk, u_host, X0, N, Np):
+    """Interpolation-only timings (velocity) for FP32/BF16/FP16 storage and their errors."""
+    import numpy as np
+    import torch
+    from oracle import interp
+    from oracle import kernels as K
+    dev = X0.device
+    sample = X0[:20000].cpu().numpy()
+    ref = interp.interp_vec(u_host.astype(np.float64) if N <= 256 else u_host, sample, K.SPLINE, 8, 2)
+    rms_ref = float(np.sqrt(np.mean(ref ** 2)))
+    out = torch.empty((Np, 3), dtype=torch.float32, device=dev)
+    res = {}
+    u_dev = torch.from_numpy(u_host).to(dev)
+    for name, code in (("f32", ptk.F32), ("bf16", ptk.BF16), ("f16", ptk.F16)):
+        ctx.set_field(u_dev, ptk.SPLINE, 8, 2, storage=code)
+        ctx.interpolate(X0, out=out)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            ctx.interpolate(X0, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        t = ctx.timing_read()
+        ctx.timing(False)
+        kms = t["interp"][0] / max(t["interp"][1], 1)
+        got = ctx.interpolate(torch.from_numpy(sample).to(dev)).cpu().numpy().astype(np.float64)
+        err = got - ref
+        node_b = 12 if code == ptk.F32 else 6
+        alg = algorithmic_bytes(N, Np, node_b, 12)
+        res[name] = {"end_to_end_ms": round(ms, 3), "interp_kernel_ms": round(kms, 3),
+                     "interp_per_s_end_to_end": Np / (ms * 1e-3),
+                     "interp_per_s_kernel": Np / (kms * 1e-3),
+                     "kernel_hbm_frac": round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "rms_err_rel": float(np.sqrt(np.mean(err ** 2)) / rms_ref),
+                     "max_err_rel": float(np.max(np.abs(err)) / rms_ref)}
+        log(f"form {name}: {res[name]}")
+    del u_dev
+    ctx.set_field(torch.zeros((8, 8, 8, 3), dtype=torch.float32, device=dev), ptk.SPLINE, 8, 2)
+    return res
+
+
+if __name__ == "__main__":
+    main()

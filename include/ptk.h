@@ -1,0 +1,197 @@
+/*
+ * ptk.h -- particle-tracking interpolation on one MI355X (gfx950).
+ *
+ * C ABI of libptk.so.  It computes the particle-tracking hot path of
+ * Lalescu, Bramas, Rampp & Wilczek, "An Efficient Particle Tracking Algorithm
+ * for Large-Scale Parallel Pseudo-Spectral Simulations of Turbulence":
+ * interpolation of a periodic 3-component field given on an N^3 grid at
+ * particle positions with I-point tensor-product kernels (Sec. 2.2, the four
+ * enumerated steps and Eq. "triple_sum"), its gradient through derivative
+ * kernels, and the tracer ODE dX/dt = u(X) (Eq. "tracers") advanced with
+ * Euler, Heun or two-step Adams-Bashforth using a per-particle rhs history
+ * (Sec. 2.2; Sec. 3.3.1 "Particle data structure").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Domain [0, 2*pi)^3, grid spacing delta = 2*pi/N, node (j1,j2,j3) at
+ * j*delta.  Field layout u[x3][x2][x1][a]: x1 fastest, the 3 components
+ * fastest within a node (Sec. 2.2 "array of vectorial field values", with the
+ * paper's x3-slab convention, Sec. 3.2).  Positions X[p][3] = (x1, x2, x3) in
+ * binary64 with |x| < 2^50 (they are wrapped modulo 2*pi; beyond 2^50 the
+ * binary64 wrap is no longer exact enough and such positions, like NaN and
+ * infinities, are reported as PTK_EDOMAIN).  Gradients
+ * grad[p][a][b] = d u_a / d x_b.
+ *
+ * Pointers named as device pointers must be device memory of the context's
+ * GPU, owned by the caller, and must not overlap each other.  Work is enqueued
+ * on `stream` (a hipStream_t; NULL = the null stream).  Every call returns after
+ * enqueueing, except that it waits for its own work when it has to report a
+ * device-side condition (positions outside the domain) -- set PTK_NO_CHECK=1 in the
+ * environment to skip that check and the wait.  The library keeps device
+ * scratch that grows with the largest call and is freed by ptk_destroy; one
+ * context must not be used by two host threads at once, and calls on one
+ * context must be issued on one stream or ordered by the caller.
+ *
+ * Errors: every function returns PTK_OK (0) or a negative code and never
+ * throws.  Argument errors are detected before any work is enqueued and leave
+ * the context unchanged.  ptk_last_error() describes the last error.
+ */
+#ifndef PTK_H
+#define PTK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ptk_ctx ptk_ctx;
+
+/* Element types of fields, outputs and field storage. */
+enum { PTK_F64 = 0, PTK_F32 = 1, PTK_BF16 = 2, PTK_F16 = 3 };
+
+/* Kernel families (Sec. 2.2): Lagrange polynomials, or local splines of
+ * smoothness m (m = 0 gives the Lagrange kernel). */
+enum { PTK_LAGRANGE = 0, PTK_SPLINE = 1 };
+
+/* Time-stepping schemes for ptk_advance_particles. */
+enum { PTK_EULER = 1, PTK_HEUN = 2, PTK_AB2 = 3 };
+
+/* Return codes. */
+enum {
+  PTK_OK = 0,
+  PTK_EINVAL = -1,        /* bad argument (NULL pointer, size, enum value) */
+  PTK_ENOFIELD = -2,      /* no field set on the context */
+  PTK_ENOMEM = -3,        /* device allocation failed (or the test byte cap) */
+  PTK_EHIP = -4,          /* a HIP runtime call failed */
+  PTK_EDOMAIN = -5,       /* a position was NaN, infinite or |x| >= 2^50 */
+  PTK_EUNSUPPORTED = -6   /* valid but unsupported request (e.g. odd I) */
+};
+
+/* Interpolation kernel: family, points per direction I (even; 4, 6 or 8 here)
+ * and smoothness m (0 <= m <= I/2 - 1; ignored for PTK_LAGRANGE).  Nodes of a
+ * particle in cell c are c + i, i = 1 - I/2 .. I/2 per axis (Eq. "triple_sum").
+ * Spline (I = 2n+2, m): on each cell the degree-(2n+1) polynomial that takes the
+ * node values at the cell ends, takes at each end the derivatives 1..m of the
+ * centred degree-2n Lagrange interpolant about that end, and interpolates the
+ * 2(n-m) nodes nearest the cell. */
+typedef struct {
+  int family;
+  int I;
+  int m;
+} ptk_kernel;
+
+/* Coefficients of the kernel polynomials as the library derives them (exact
+ * rationals rounded once to binary64): val[j*I + p] is the coefficient of t^p
+ * of beta for node offset j - (I/2 - 1), der[j*I + p] that of d beta/dt (its
+ * last column is 0).  Host buffers of I*I doubles each; der may be NULL.
+ * Host-only, needs no device or context. */
+int ptk_kernel_table(const ptk_kernel *k, double *val, double *der);
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int ptk_create(ptk_ctx **out, int device);
+
+/* Release the context, its field copy and its scratch.  NULL is accepted. */
+void ptk_destroy(ptk_ctx *ctx);
+
+/* Text of the last error on this context (empty if none).  Valid until the
+ * next call on the context. */
+const char *ptk_last_error(const ptk_ctx *ctx);
+
+/* Set the field and the interpolation kernel.
+ * u: device pointer, N*N*N*3 elements of `in_dtype` (PTK_F64 or PTK_F32),
+ *    layout u[x3][x2][x1][a].  The library copies it into its own periodic,
+ *    halo-padded layout in `storage_dtype` (F64, F32, BF16 or F16); the caller
+ *    may free u once the call's work on `stream` has completed.
+ * Storage: F64 keeps binary64; F32 rounds to nearest-even.  BF16 and F16 scale
+ *    each component by its root-mean-square over the grid, s_a, stored as
+ *    RNE(fl32(u_a * fl32(1/s_a))), and multiply results by fl32(s_a).
+ * N: 8 <= N <= 4096.  Sums are FP64 for F64 storage and FP32 otherwise.
+ * Waits for the stream when storage is BF16/F16 (it reads back s_a). */
+int ptk_set_field(ptk_ctx *ctx, const void *u, int64_t N, int in_dtype, int storage_dtype,
+                  const ptk_kernel *k, void *stream);
+
+/* Per-component scale s_a of the stored field (1 for F64/F32) into host
+ * float[3]. */
+int ptk_get_field_scale(const ptk_ctx *ctx, float *scale3);
+
+/* Steps 1-3 of the interpolation algorithm (Sec. 2.2) for every coordinate:
+ * Xtilde = X mod 2*pi; cell c = floor(Xtilde/delta); offset t = Xtilde/delta - c
+ * in [0,1).  Fixed binary64 sequence per coordinate x (no fused operations):
+ *   q = floor(x / L); y = x - L*q; if (y < 0) y += L; if (y >= L) y = 0;
+ *   s = y * invd; c = floor(s); t = s - c; if (c == N) { c = 0; t = 0; }
+ * with L = fl64(2*pi), invd = fl64(N / L).
+ * X: device [Np][3] binary64.  cell: device int32 [Np][3].  t: device binary64
+ * [Np][3] or NULL.  Requires a field (for N). */
+int ptk_locate(ptk_ctx *ctx, const double *X, int64_t Np, int32_t *cell, double *t, void *stream);
+
+/* Interpolate the field at Np positions (Eq. "triple_sum", indices modulo N).
+ * X: device [Np][3] binary64.  out: device [Np][3] of out_dtype (PTK_F64 or
+ * PTK_F32), in the order of X.  Internally particles are binned by cell
+ * (bricks of B^3 cells, B = ptk_binning_info's bin_edge) with a stable sort,
+ * as the paper groups particles by slice (Sec. 3.3.1). */
+int ptk_interpolate(ptk_ctx *ctx, const double *X, int64_t Np, void *out, int out_dtype,
+                    void *stream);
+
+/* Interpolate the field and its gradient: the same sum with the kernel
+ * replaced by its derivative on the differentiated axis, times 1/delta.
+ * u_out: device [Np][3] or NULL; grad: device [Np][3][3], grad[p][a][b] =
+ * d u_a/d x_b; both of out_dtype and in the order of X. */
+int ptk_interpolate_gradient(ptk_ctx *ctx, const double *X, int64_t Np, void *u_out, void *grad,
+                             int out_dtype, void *stream);
+
+/* Advance tracers dX/dt = u(X) (Eq. "tracers") by nsteps steps of dt in the
+ * frozen field.
+ * X: device [Np][3] binary64, in/out; positions are returned wrapped to
+ *    [0, 2*pi).
+ * scheme PTK_EULER: X <- W(X + dt u(X)).
+ * scheme PTK_HEUN:  k1 = u(X); Xs = W(X + dt k1); k2 = u(Xs);
+ *                   X <- W(X + (0.5 dt)(k1 + k2)).
+ * scheme PTK_AB2:   X <- W(X + dt (1.5 u_n - 0.5 u_{n-1})), an Euler step while
+ *    the history is empty.  rhs_hist: device [2][Np][3] holding u_n, u_{n-1}
+ *    (binary64 for F64 storage, else FP32), in the order of X; *hist_len (host,
+ *    0..2) says how many entries are valid and is updated, so a run can resume.
+ *    rhs_hist/hist_len may be NULL for Euler and Heun.
+ * W is the wrap of ptk_locate; every update is separately rounded binary64.
+ * grad_out: device [Np][3][3] (binary64 for F64 storage, else FP32) or NULL;
+ *    if given, every step also evaluates the gradient at its start position,
+ *    and on return grad_out holds the one of the last step.
+ * Particles are re-binned (stable sort by bin) after every position update
+ * and kept in bin order internally; results are returned in the order of X. */
+int ptk_advance_particles(ptk_ctx *ctx, double *X, int64_t Np, void *rhs_hist, int *hist_len,
+                          int scheme, double dt, int nsteps, void *grad_out, void *stream);
+
+/* Binning of the last ptk_interpolate / ptk_interpolate_gradient call:
+ * number of particles, number of bins and bin edge B in cells.  Bin of cell c:
+ *   key = ((c3/B) * nb + c2/B) * nb + c1/B, nb = ceil(N/B). */
+int ptk_binning_info(const ptk_ctx *ctx, int64_t *np, int64_t *n_bins, int *bin_edge);
+
+/* Copy that binning to device buffers: perm[k] (uint32 [np]) = index in X of
+ * the k-th particle in bin order (a stable sort of the keys), offsets (uint32
+ * [n_bins+1]) with offsets[b] = number of particles with key < b and
+ * offsets[n_bins] = np (the paper's offset array, Sec. 3.3.1). */
+int ptk_get_binning(ptk_ctx *ctx, uint32_t *perm, uint32_t *offsets, void *stream);
+
+/* Kernel timing, a tracing aid.  While enabled, the library brackets its main
+ * launch sequences with HIP events on the call's stream and accumulates their
+ * durations per kind:
+ *   PTK_T_INTERP       interpolation kernel, values only
+ *   PTK_T_INTERP_GRAD  interpolation kernel with gradient
+ *   PTK_T_SORT         stable radix sort + bin offsets
+ *   PTK_T_KEYS         bin keys of caller positions
+ *   PTK_T_UPDATE       position update (+ keys of the new positions)
+ *   PTK_T_PERMUTE      gathers/scatters of particle state between orders
+ * ptk_timing_enable(ctx, 1) starts (and clears) the accumulators, 0 stops.
+ * ptk_timing_read waits for the recorded events, adds their durations to the
+ * accumulators and copies them out: ms[PTK_T_COUNT] (milliseconds) and
+ * launches[PTK_T_COUNT] (number of timed sequences); either may be NULL. */
+enum { PTK_T_INTERP = 0, PTK_T_INTERP_GRAD = 1, PTK_T_SORT = 2, PTK_T_KEYS = 3, PTK_T_UPDATE = 4,
+       PTK_T_PERMUTE = 5, PTK_T_COUNT = 6 };
+int ptk_timing_enable(ptk_ctx *ctx, int enable);
+int ptk_timing_read(ptk_ctx *ctx, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTK_H */

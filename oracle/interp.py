@@ -48,9 +48,17 @@ def _gather(field: np.ndarray, c: np.ndarray, I: int) -> np.ndarray:
 
 
 def interp_vec(field: np.ndarray, X: np.ndarray, family: int, I: int, m: int = 0,
-               gradient: bool = False, chunk: int = 4096):
-    """Vectorised triple sum; returns u[P,3] (and grad[P,3,3] if requested)."""
-    field = np.asarray(field, dtype=np.float64)
+               gradient: bool = False, chunk: int = 4096, absolute: bool = False):
+    """Vectorised triple sum; returns u[P,3] (and grad[P,3,3] if requested).
+
+    With ``absolute=True`` every weight and field value is replaced by its
+    absolute value: the result is the sum of |terms|, which bounds the rounding
+    error of any evaluation order of the same sum (used to derive tolerances
+    for reduced-precision arithmetic).
+    """
+    field = np.asarray(field)           # FP32 or FP64 values; gathered stencils become FP64
+    if absolute:
+        field = np.abs(field)
     N = field.shape[0]
     X = np.asarray(X, dtype=np.float64).reshape(-1, 3)
     P = X.shape[0]
@@ -61,10 +69,14 @@ def interp_vec(field: np.ndarray, X: np.ndarray, family: int, I: int, m: int = 0
         e = min(P, s + chunk)
         c, t = geometry.cell_and_offset(X[s:e], N)
         w = weights_f64(family, I, m, t)            # [p, axis, I]
-        G = _gather(field, c, I)                     # [p, k3, k2, k1, a]
+        if absolute:
+            w = np.abs(w)
+        G = _gather(field, c, I).astype(np.float64)  # [p, k3, k2, k1, a]
         u[s:e] = np.einsum("pk,pj,pi,pkjia->pa", w[:, 2], w[:, 1], w[:, 0], G)
         if gradient:
             d = weights_f64(family, I, m, t, deriv=True) * invd
+            if absolute:
+                d = np.abs(d)
             g[s:e, :, 0] = np.einsum("pk,pj,pi,pkjia->pa", w[:, 2], w[:, 1], d[:, 0], G)
             g[s:e, :, 1] = np.einsum("pk,pj,pi,pkjia->pa", w[:, 2], d[:, 1], w[:, 0], G)
             g[s:e, :, 2] = np.einsum("pk,pj,pi,pkjia->pa", d[:, 2], w[:, 1], w[:, 0], G)

@@ -1,0 +1,661 @@
+// C ABI of libptk (declarations and contracts in include/ptk.h).
+//
+// Host runtime: argument validation, device scratch that grows monotonically
+// (no allocation in steady state), and the sequence of kernel launches for each
+// entry point, all on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "launch.h"
+#include "ptk.h"
+#include "ptk_internal.h"
+
+using namespace ptk;
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int d) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != d) err = hipSetDevice(d);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int fail(ptk_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(ptk_ctx* c, hipError_t e, const char* what) {
+  return fail(c, PTK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define PTK_HIP(ctx, expr, what)                 \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+#define PTK_TRY(expr)           \
+  do {                          \
+    int r_ = (expr);            \
+    if (r_ != PTK_OK) return r_; \
+  } while (0)
+
+// Make `b` hold at least `bytes`.  Growing waits for the device first, so no
+// enqueued kernel still uses the old allocation when it is freed.
+int ensure(ptk_ctx* c, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.cap >= bytes) return PTK_OK;
+  size_t want = bytes + bytes / 8;
+  want = (want + 255) & ~(size_t)255;
+  if (c->byte_cap && c->bytes_in_use - b.cap + want > c->byte_cap)
+    return fail(c, PTK_ENOMEM, "device scratch would exceed PTK_TEST_MAX_BYTES");
+  if (b.ptr) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b.ptr);
+    c->bytes_in_use -= b.cap;
+    b.ptr = nullptr;
+    b.cap = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, PTK_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  b.ptr = p;
+  b.cap = want;
+  c->bytes_in_use += want;
+  return PTK_OK;
+}
+
+void release(DevBuf& b) {
+  if (b.ptr) (void)hipFree(b.ptr);
+  b.ptr = nullptr;
+  b.cap = 0;
+}
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+hipEvent_t take_event(ptk_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets a launch sequence with events when timing is enabled.
+struct Timed {
+  ptk_ctx* c;
+  hipStream_t s;
+  int kind;
+  hipEvent_t start = nullptr;
+  Timed(ptk_ctx* c_, hipStream_t s_, int k) : c(c_), s(s_), kind(k) {
+    if (!c->timing) return;
+    start = take_event(c);
+    if (start && hipEventRecord(start, s) != hipSuccess) {
+      c->event_pool.push_back(start);
+      start = nullptr;
+    }
+  }
+  ~Timed() {
+    if (!start) return;
+    hipEvent_t stop = take_event(c);
+    if (stop && hipEventRecord(stop, s) == hipSuccess) {
+      c->pending.push_back(TimedPair{start, stop, kind});
+    } else {
+      c->event_pool.push_back(start);
+      if (stop) c->event_pool.push_back(stop);
+    }
+  }
+};
+
+// Waits for the recorded pairs and folds them into the accumulators.
+void drain_timers(ptk_ctx* c) {
+  for (TimedPair& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.stop) == hipSuccess && hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+      c->timer_ms[p.kind] += ms;
+      c->timer_count[p.kind] += 1;
+    }
+    c->event_pool.push_back(p.start);
+    c->event_pool.push_back(p.stop);
+  }
+  c->pending.clear();
+}
+
+inline int64_t nb_of(int64_t N) { return (N + kBinEdge - 1) / kBinEdge; }
+
+inline int bits_for(int64_t n_bins) {
+  int b = 0;
+  while (((int64_t)1 << b) < n_bins) ++b;
+  return b;
+}
+
+inline double invd_of(int64_t N) { return (double)N / kL; }
+
+int vel_bytes(const ptk_ctx* c) { return c->storage == PTK_F64 ? 8 : 4; }
+
+int check_flag(ptk_ctx* c, hipStream_t s) {
+  if (!c->check) return PTK_OK;
+  int h = 0;
+  PTK_HIP(c, hipMemcpyAsync(&h, c->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s), "flag read");
+  PTK_HIP(c, hipStreamSynchronize(s), "stream synchronize");
+  if (h) return fail(c, PTK_EDOMAIN, "a particle position is NaN, infinite or has |x| >= 2^50");
+  return PTK_OK;
+}
+
+// scratch for binning Np particles over n_bins bins
+int ensure_binning(ptk_ctx* c, int64_t Np, int64_t n_bins) {
+  const size_t n4 = (size_t)Np * 4;
+  PTK_TRY(ensure(c, c->keys_a, n4));
+  PTK_TRY(ensure(c, c->keys_b, n4));
+  PTK_TRY(ensure(c, c->vals_a, n4));
+  PTK_TRY(ensure(c, c->vals_b, n4));
+  const size_t hw = sort_hist_words(Np);
+  PTK_TRY(ensure(c, c->hist, hw * 4));
+  PTK_TRY(ensure(c, c->scan_tmp, scan_tmp_words((int64_t)hw) * 4));
+  PTK_TRY(ensure(c, c->offsets, (size_t)(n_bins + 1) * 4));
+  return PTK_OK;
+}
+
+// keys -> stable sort -> offsets.  keys of the particles must be in keys_a.
+int bin_sorted(ptk_ctx* c, int64_t Np, int64_t n_bins, uint32_t** perm, hipStream_t s) {
+  uint32_t* sk = nullptr;
+  PTK_HIP(c,
+          radix_sort_keys((uint32_t*)c->keys_a.ptr, (uint32_t*)c->keys_b.ptr, (uint32_t*)c->vals_a.ptr,
+                          (uint32_t*)c->vals_b.ptr, Np, bits_for(n_bins), (uint32_t*)c->hist.ptr,
+                          (uint32_t*)c->scan_tmp.ptr, &sk, perm, s),
+          "radix sort");
+  PTK_HIP(c, launch_offsets(sk, Np, n_bins, (uint32_t*)c->offsets.ptr, s), "bin offsets");
+  return PTK_OK;
+}
+
+InterpArgs base_args(const ptk_ctx* c, int64_t n_bins) {
+  InterpArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.field = c->field.ptr;
+  a.row_pitch = c->geom.row_pitch;
+  a.plane_pitch = c->geom.plane_pitch;
+  a.P = c->geom.P;
+  a.N = (int)c->geom.N;
+  a.nb = (int)nb_of(c->geom.N);
+  a.invd = invd_of(c->geom.N);
+  a.offsets = (const uint32_t*)c->offsets.ptr;
+  a.coef = c->coef.ptr;
+  a.scale[0] = c->scale[0];
+  a.scale[1] = c->scale[1];
+  a.scale[2] = c->scale[2];
+  a.n_bins = n_bins;
+  return a;
+}
+
+int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* grad, int out_dtype,
+                  void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
+  if (Np < 0 || Np > (int64_t)0xFFFFFFFF) return fail(c, PTK_EINVAL, "Np out of range [0, 2^32)");
+  if (out_dtype != PTK_F64 && out_dtype != PTK_F32) return fail(c, PTK_EINVAL, "out_dtype must be F64 or F32");
+  if (Np > 0 && (!X || (!u_out && !grad))) return fail(c, PTK_EINVAL, "NULL pointer");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  const int64_t N = c->geom.N, nb = nb_of(N), n_bins = nb * nb * nb;
+  c->bin_valid = false;
+  if (Np == 0) {
+    c->bin_np = 0;
+    c->bin_nbins = n_bins;
+    PTK_TRY(ensure(c, c->offsets, (size_t)(n_bins + 1) * 4));
+    PTK_HIP(c, launch_offsets((const uint32_t*)c->keys_a.ptr, 0, n_bins, (uint32_t*)c->offsets.ptr, s),
+            "bin offsets");
+    c->bin_perm = nullptr;
+    c->bin_valid = true;
+    return PTK_OK;
+  }
+  PTK_TRY(ensure_binning(c, Np, n_bins));
+  PTK_TRY(ensure(c, c->xs, (size_t)Np * 24));
+  PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
+  {
+    Timed t(c, s, PTK_T_KEYS);
+    PTK_HIP(c,
+            launch_keys(X, Np, (int)N, invd_of(N), kBinEdge, (int)nb, (uint32_t*)c->keys_a.ptr,
+                        (int*)c->flag.ptr, s),
+            "keys");
+  }
+  uint32_t* perm = nullptr;
+  {
+    Timed t(c, s, PTK_T_SORT);
+    PTK_TRY(bin_sorted(c, Np, n_bins, &perm, s));
+  }
+  {
+    Timed t(c, s, PTK_T_PERMUTE);
+    PTK_HIP(c, gather3_f64(X, perm, Np, (double*)c->xs.ptr, s), "gather positions");
+  }
+  InterpArgs a = base_args(c, n_bins);
+  a.X = (const double*)c->xs.ptr;
+  a.orig = perm;
+  a.out = u_out;
+  a.grad = grad;
+  a.out_f64 = out_dtype == PTK_F64;
+  {
+    Timed t(c, s, grad ? PTK_T_INTERP_GRAD : PTK_T_INTERP);
+    PTK_HIP(c, launch_interp(c->storage, c->I, a, s), "interpolate");
+  }
+  c->bin_perm = perm;
+  c->bin_np = Np;
+  c->bin_nbins = n_bins;
+  c->bin_valid = true;
+  return check_flag(c, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ptk_kernel_table(const ptk_kernel* k, double* val, double* der) {
+  if (!k || !val) return PTK_EINVAL;
+  if (k->family != PTK_LAGRANGE && k->family != PTK_SPLINE) return PTK_EINVAL;
+  if (k->I % 2 != 0) return PTK_EUNSUPPORTED;
+  if (k->I != 4 && k->I != 6 && k->I != 8) return PTK_EUNSUPPORTED;
+  const int m = k->family == PTK_LAGRANGE ? 0 : k->m;
+  if (m < 0 || m > k->I / 2 - 1) return PTK_EINVAL;
+  KernelTables tab;
+  int r = build_kernel_tables(k->family, k->I, m, &tab);
+  if (r != 0) return r == -6 ? PTK_EUNSUPPORTED : PTK_EINVAL;
+  for (int j = 0; j < k->I; ++j)
+    for (int p = 0; p < k->I; ++p) {
+      val[j * k->I + p] = tab.val64[j][p];
+      if (der) der[j * k->I + p] = tab.der64[j][p];
+    }
+  return PTK_OK;
+}
+
+int ptk_create(ptk_ctx** out, int device) {
+  if (!out) return PTK_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PTK_EINVAL;
+  ptk_ctx* c = new (std::nothrow) ptk_ctx();
+  if (!c) return PTK_ENOMEM;
+  c->device = device;
+  if (const char* cap = std::getenv("PTK_TEST_MAX_BYTES")) c->byte_cap = (size_t)std::strtoull(cap, nullptr, 10);
+  if (const char* nc = std::getenv("PTK_NO_CHECK")) c->check = !(nc[0] == '1');
+  DeviceGuard g(device);
+  if (g.err != hipSuccess) {
+    delete c;
+    return PTK_EHIP;
+  }
+  int r = ensure(c, c->flag, 256);
+  if (r != PTK_OK) {
+    delete c;
+    return r;
+  }
+  *out = c;
+  return PTK_OK;
+}
+
+void ptk_destroy(ptk_ctx* c) {
+  if (!c) return;
+  {
+    DeviceGuard g(c->device);
+    (void)hipDeviceSynchronize();
+    DevBuf* bufs[] = {&c->field, &c->coef, &c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->offsets,
+                      &c->hist, &c->scan_tmp, &c->flag, &c->xs, &c->xn, &c->orig, &c->orig_b, &c->k1,
+                      &c->k2, &c->h0, &c->h1, &c->h0b, &c->h1b, &c->gint, &c->stage};
+    for (DevBuf* b : bufs) release(*b);
+    for (TimedPair& p : c->pending) {
+      (void)hipEventDestroy(p.start);
+      (void)hipEventDestroy(p.stop);
+    }
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  }
+  delete c;
+}
+
+const char* ptk_last_error(const ptk_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+int ptk_set_field(ptk_ctx* c, const void* u, int64_t N, int in_dtype, int storage_dtype, const ptk_kernel* k,
+                  void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!u || !k) return fail(c, PTK_EINVAL, "NULL pointer");
+  if (N < 8 || N > 4096) return fail(c, PTK_EINVAL, "N must be in [8, 4096]");
+  if (in_dtype != PTK_F64 && in_dtype != PTK_F32) return fail(c, PTK_EINVAL, "in_dtype must be F64 or F32");
+  if (storage_dtype < PTK_F64 || storage_dtype > PTK_F16) return fail(c, PTK_EINVAL, "bad storage dtype");
+  if (k->family != PTK_LAGRANGE && k->family != PTK_SPLINE) return fail(c, PTK_EINVAL, "bad kernel family");
+  if (k->I % 2 != 0) return fail(c, PTK_EUNSUPPORTED, "odd kernel sizes are not defined");
+  if (k->I != 4 && k->I != 6 && k->I != 8) return fail(c, PTK_EUNSUPPORTED, "kernel size I must be 4, 6 or 8");
+  const int m = k->family == PTK_LAGRANGE ? 0 : k->m;
+  if (m < 0 || m > k->I / 2 - 1) return fail(c, PTK_EINVAL, "smoothness m must be in [0, I/2-1]");
+  KernelTables tab;
+  int tr = build_kernel_tables(k->family, k->I, m, &tab);
+  if (tr != 0) return fail(c, tr == -6 ? PTK_EUNSUPPORTED : PTK_EINVAL, "kernel table construction failed");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+
+  FieldGeom geo;
+  geo.N = N;
+  geo.P = N + k->I - 1;
+  geo.node_bytes = storage_dtype == PTK_F64 ? 24 : storage_dtype == PTK_F32 ? 12 : 6;
+  geo.halo_lo = k->I / 2 - 1;
+  geo.row_pitch = ((geo.P * geo.node_bytes + 48) + 63) / 64 * 64;
+  geo.plane_pitch = geo.row_pitch * geo.P;
+  const size_t field_bytes = (size_t)(geo.plane_pitch * geo.P) + 64;
+
+  // per-component scale for 16-bit storage
+  float inv[3] = {1.f, 1.f, 1.f}, scl[3] = {1.f, 1.f, 1.f};
+  const int64_t nodes = N * N * N;
+  if (storage_dtype == PTK_BF16 || storage_dtype == PTK_F16) {
+    const int nblk = 1024;
+    PTK_TRY(ensure(c, c->stage, (size_t)nblk * 3 * sizeof(double)));
+    PTK_HIP(c, launch_sumsq(u, in_dtype == PTK_F64, nodes, (double*)c->stage.ptr, nblk, s), "sum of squares");
+    double* part = new (std::nothrow) double[nblk * 3];
+    if (!part) return fail(c, PTK_ENOMEM, "host allocation failed");
+    hipError_t e = hipMemcpyAsync(part, c->stage.ptr, sizeof(double) * nblk * 3, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      delete[] part;
+      return hip_fail(c, e, "scale read-back");
+    }
+    for (int q = 0; q < 3; ++q) {
+      double sum = 0.0;
+      for (int b = 0; b < nblk; ++b) sum += part[3 * b + q];
+      const double rms = std::sqrt(sum / (double)nodes);
+      if (!(rms > 0.0) || !std::isfinite(rms)) {
+        delete[] part;
+        return fail(c, PTK_EINVAL, "a field component is zero or not finite: cannot scale to unit rms");
+      }
+      inv[q] = (float)(1.0 / rms);
+      scl[q] = (float)rms;
+    }
+    delete[] part;
+  }
+  PTK_TRY(ensure(c, c->field, field_bytes));
+  PTK_TRY(ensure(c, c->coef, sizeof(KernelTables)));
+  c->tables = tab;
+  PTK_HIP(c, hipMemcpyAsync(c->coef.ptr, &c->tables, sizeof(KernelTables), hipMemcpyHostToDevice, s),
+          "coefficient upload");
+  PTK_HIP(c,
+          launch_pack(u, in_dtype == PTK_F64, N, storage_dtype, k->I, c->field.ptr, geo.row_pitch,
+                      geo.plane_pitch, inv, s),
+          "field pack");
+  c->geom = geo;
+  c->family = k->family;
+  c->I = k->I;
+  c->m = m;
+  c->storage = storage_dtype;
+  for (int q = 0; q < 3; ++q) c->scale[q] = scl[q];
+  c->has_field = true;
+  c->bin_valid = false;
+  return PTK_OK;
+}
+
+int ptk_get_field_scale(const ptk_ctx* c, float* scale3) {
+  if (!c || !scale3) return PTK_EINVAL;
+  if (!c->has_field) return PTK_ENOFIELD;
+  for (int q = 0; q < 3; ++q) scale3[q] = c->scale[q];
+  return PTK_OK;
+}
+
+int ptk_locate(ptk_ctx* c, const double* X, int64_t Np, int32_t* cell, double* t, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
+  if (Np < 0 || Np > ((int64_t)1 << 40)) return fail(c, PTK_EINVAL, "Np out of range");
+  if (Np > 0 && (!X || !cell)) return fail(c, PTK_EINVAL, "NULL pointer");
+  if (Np == 0) return PTK_OK;
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
+  PTK_HIP(c, launch_locate(X, 3 * Np, (int)c->geom.N, invd_of(c->geom.N), cell, t, (int*)c->flag.ptr, s),
+          "locate");
+  return check_flag(c, s);
+}
+
+int ptk_interpolate(ptk_ctx* c, const double* X, int64_t Np, void* out, int out_dtype, void* stream) {
+  if (c && Np > 0 && !out) return fail(c, PTK_EINVAL, "NULL output");
+  return interp_common(c, X, Np, out, nullptr, out_dtype, stream);
+}
+
+int ptk_interpolate_gradient(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* grad, int out_dtype,
+                             void* stream) {
+  if (c && Np > 0 && !grad) return fail(c, PTK_EINVAL, "NULL gradient output");
+  return interp_common(c, X, Np, u_out, grad, out_dtype, stream);
+}
+
+int ptk_binning_info(const ptk_ctx* c, int64_t* np, int64_t* n_bins, int* bin_edge) {
+  if (!c || !np || !n_bins || !bin_edge) return PTK_EINVAL;
+  if (!c->bin_valid) return PTK_ENOFIELD;
+  *np = c->bin_np;
+  *n_bins = c->bin_nbins;
+  *bin_edge = kBinEdge;
+  return PTK_OK;
+}
+
+int ptk_get_binning(ptk_ctx* c, uint32_t* perm, uint32_t* offsets, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!c->bin_valid) return fail(c, PTK_ENOFIELD, "no binning recorded");
+  if ((c->bin_np > 0 && !perm) || !offsets) return fail(c, PTK_EINVAL, "NULL pointer");
+  DeviceGuard g(c->device);
+  hipStream_t s = S(stream);
+  if (c->bin_np > 0)
+    PTK_HIP(c, hipMemcpyAsync(perm, c->bin_perm, (size_t)c->bin_np * 4, hipMemcpyDeviceToDevice, s), "copy perm");
+  PTK_HIP(c,
+          hipMemcpyAsync(offsets, c->offsets.ptr, (size_t)(c->bin_nbins + 1) * 4, hipMemcpyDeviceToDevice, s),
+          "copy offsets");
+  return PTK_OK;
+}
+
+int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int* hist_len, int scheme,
+                          double dt, int nsteps, void* grad_out, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
+  if (scheme != PTK_EULER && scheme != PTK_HEUN && scheme != PTK_AB2) return fail(c, PTK_EINVAL, "bad scheme");
+  if (Np < 0 || Np > (int64_t)0xFFFFFFFF) return fail(c, PTK_EINVAL, "Np out of range [0, 2^32)");
+  if (nsteps < 0) return fail(c, PTK_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(c, PTK_EINVAL, "dt must be finite");
+  if (scheme == PTK_AB2) {
+    if (!rhs_hist || !hist_len) return fail(c, PTK_EINVAL, "AB2 needs rhs_hist and hist_len");
+    if (*hist_len < 0 || *hist_len > 2) return fail(c, PTK_EINVAL, "hist_len must be 0, 1 or 2");
+  }
+  if (Np > 0 && !X) return fail(c, PTK_EINVAL, "NULL positions");
+  if (Np == 0 || nsteps == 0) return PTK_OK;
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  const int64_t N = c->geom.N, nb = nb_of(N), n_bins = nb * nb * nb;
+  const double invd = invd_of(N);
+  const int vb = vel_bytes(c);
+  const bool vf64 = vb == 8;
+  const size_t v3 = (size_t)Np * 3 * vb;
+
+  PTK_TRY(ensure_binning(c, Np, n_bins));
+  PTK_TRY(ensure(c, c->xs, (size_t)Np * 24));
+  PTK_TRY(ensure(c, c->xn, (size_t)Np * 24));
+  PTK_TRY(ensure(c, c->stage, (size_t)Np * 24));
+  PTK_TRY(ensure(c, c->orig, (size_t)Np * 4));
+  PTK_TRY(ensure(c, c->orig_b, (size_t)Np * 4));
+  PTK_TRY(ensure(c, c->k1, v3));
+  if (scheme == PTK_HEUN) PTK_TRY(ensure(c, c->k2, v3));
+  if (scheme == PTK_AB2) {
+    PTK_TRY(ensure(c, c->h0, v3));
+    PTK_TRY(ensure(c, c->h1, v3));
+    PTK_TRY(ensure(c, c->h0b, v3));
+    PTK_TRY(ensure(c, c->h1b, v3));
+  }
+  if (grad_out) PTK_TRY(ensure(c, c->gint, (size_t)Np * 9 * vb));
+  c->bin_valid = false;
+
+  double* xs = (double*)c->xs.ptr;
+  double* xn = (double*)c->xn.ptr;
+  double* xp = (double*)c->stage.ptr;
+  uint32_t* orig = (uint32_t*)c->orig.ptr;
+  uint32_t* orig_b = (uint32_t*)c->orig_b.ptr;
+  uint32_t* keys = (uint32_t*)c->keys_a.ptr;
+  int* flag = (int*)c->flag.ptr;
+  void* k1 = c->k1.ptr;
+  void* k2 = c->k2.ptr;
+  void *h0 = c->h0.ptr, *h1 = c->h1.ptr, *h0b = c->h0b.ptr, *h1b = c->h1b.ptr;
+  int hl = scheme == PTK_AB2 ? *hist_len : 0;
+  auto gather_v = [&](const void* in, const uint32_t* pm, void* out) -> hipError_t {
+    return vf64 ? gather3_f64((const double*)in, pm, Np, (double*)out, s)
+                : gather3_f32((const float*)in, pm, Np, (float*)out, s);
+  };
+  auto scatter_v = [&](const void* in, const uint32_t* idx, int width, void* out) -> hipError_t {
+    return vf64 ? scatter_f64((const double*)in, idx, Np, width, (double*)out, s)
+                : scatter_f32((const float*)in, idx, Np, width, (float*)out, s);
+  };
+  auto update = [&](int kind, const void* ka, const void* kb) -> int {
+    Timed t(c, s, PTK_T_UPDATE);
+    PTK_HIP(c, launch_update(kind, vf64, xs, ka, kb, dt, Np, xn, keys, (int)N, invd, kBinEdge, (int)nb, flag, s),
+            "position update");
+    return PTK_OK;
+  };
+  auto sort = [&](uint32_t** pm) -> int {
+    Timed t(c, s, PTK_T_SORT);
+    return bin_sorted(c, Np, n_bins, pm, s);
+  };
+
+  PTK_HIP(c, hipMemsetAsync(flag, 0, sizeof(int), s), "flag clear");
+  // initial binning of the caller's positions; the state is then kept in bin order
+  {
+    Timed t(c, s, PTK_T_KEYS);
+    PTK_HIP(c, launch_keys(X, Np, (int)N, invd, kBinEdge, (int)nb, keys, flag, s), "keys");
+  }
+  uint32_t* perm = nullptr;
+  PTK_TRY(sort(&perm));
+  {
+    Timed t(c, s, PTK_T_PERMUTE);
+    PTK_HIP(c, gather3_f64(X, perm, Np, xs, s), "gather positions");
+    PTK_HIP(c, hipMemcpyAsync(orig, perm, (size_t)Np * 4, hipMemcpyDeviceToDevice, s), "copy order");
+    if (scheme == PTK_AB2) {
+      if (hl >= 1) PTK_HIP(c, gather_v(rhs_hist, perm, h0), "gather history");
+      if (hl >= 2) PTK_HIP(c, gather_v((const char*)rhs_hist + v3, perm, h1), "gather history");
+    }
+  }
+  for (int step = 0; step < nsteps; ++step) {
+    const bool last = step == nsteps - 1;
+    // u(X_n), and its gradient, at the bin-ordered positions
+    {
+      InterpArgs a = base_args(c, n_bins);
+      a.X = xs;
+      a.out = k1;
+      a.grad = grad_out ? c->gint.ptr : nullptr;
+      a.out_f64 = vf64;
+      Timed t(c, s, grad_out ? PTK_T_INTERP_GRAD : PTK_T_INTERP);
+      PTK_HIP(c, launch_interp(c->storage, c->I, a, s), "interpolate");
+    }
+    if (grad_out && last) {
+      Timed t(c, s, PTK_T_PERMUTE);
+      PTK_HIP(c, scatter_v(c->gint.ptr, orig, 9, grad_out), "scatter gradient");
+    }
+    if (scheme == PTK_EULER) {
+      PTK_TRY(update(kEulerOrPredict, k1, nullptr));
+    } else if (scheme == PTK_HEUN) {
+      // predictor, re-binned; u at the predictor is written back in xs order
+      PTK_TRY(update(kEulerOrPredict, k1, nullptr));
+      uint32_t* pp = nullptr;
+      PTK_TRY(sort(&pp));
+      {
+        Timed t(c, s, PTK_T_PERMUTE);
+        PTK_HIP(c, gather3_f64(xn, pp, Np, xp, s), "gather predictor");
+      }
+      {
+        InterpArgs b = base_args(c, n_bins);
+        b.X = xp;
+        b.orig = pp;
+        b.out = k2;
+        b.out_f64 = vf64;
+        Timed t(c, s, PTK_T_INTERP);
+        PTK_HIP(c, launch_interp(c->storage, c->I, b, s), "interpolate predictor");
+      }
+      PTK_TRY(update(kHeunCorrect, k1, k2));
+    } else {
+      PTK_TRY(update(hl == 0 ? kEulerOrPredict : kAB2, k1, h0));
+      // history rotation: u_{n-1} <- u_n, u_n <- k1
+      void* t = h1;
+      h1 = h0;
+      h0 = k1;
+      k1 = t;
+      hl = hl < 2 ? hl + 1 : 2;
+    }
+    if (last) {
+      Timed t(c, s, PTK_T_PERMUTE);
+      PTK_HIP(c, scatter_f64(xn, orig, Np, 3, X, s), "scatter positions");
+      if (scheme == PTK_AB2) {
+        PTK_HIP(c, scatter_v(h0, orig, 3, rhs_hist), "scatter history");
+        if (hl >= 2) PTK_HIP(c, scatter_v(h1, orig, 3, (char*)rhs_hist + v3), "scatter history");
+      }
+      break;
+    }
+    // re-bin the new positions and carry the per-particle state along
+    PTK_TRY(sort(&perm));
+    {
+      Timed t(c, s, PTK_T_PERMUTE);
+      PTK_HIP(c, gather3_f64(xn, perm, Np, xs, s), "gather positions");
+      PTK_HIP(c, gather_u32(orig, perm, Np, orig_b, s), "gather order");
+      if (scheme == PTK_AB2) {
+        PTK_HIP(c, gather_v(h0, perm, h0b), "gather history");
+        if (hl >= 2) PTK_HIP(c, gather_v(h1, perm, h1b), "gather history");
+      }
+    }
+    uint32_t* to = orig;
+    orig = orig_b;
+    orig_b = to;
+    if (scheme == PTK_AB2) {
+      void* t0 = h0;
+      h0 = h0b;
+      h0b = t0;
+      void* t1 = h1;
+      h1 = h1b;
+      h1b = t1;
+    }
+  }
+  if (scheme == PTK_AB2) *hist_len = hl;
+  return check_flag(c, s);
+}
+
+int ptk_timing_enable(ptk_ctx* c, int enable) {
+  if (!c) return PTK_EINVAL;
+  DeviceGuard g(c->device);
+  drain_timers(c);
+  for (int k = 0; k < kTimerKinds; ++k) {
+    c->timer_ms[k] = 0.0;
+    c->timer_count[k] = 0;
+  }
+  c->timing = enable != 0;
+  return PTK_OK;
+}
+
+int ptk_timing_read(ptk_ctx* c, double* ms, int64_t* launches) {
+  if (!c) return PTK_EINVAL;
+  DeviceGuard g(c->device);
+  drain_timers(c);
+  for (int k = 0; k < kTimerKinds; ++k) {
+    if (ms) ms[k] = c->timer_ms[k];
+    if (launches) launches[k] = c->timer_count[k];
+  }
+  return PTK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,349 @@
+// Particle binning: cell keys, a stable LSD radix sort of (key, index) pairs,
+// the bin offset array, and permutation gathers/scatters.
+//
+// This is the GPU form of the paper's local particle ordering (Sec. 3.3.1,
+// "Ordering the particles locally"): particles of one group are stored
+// contiguously, groups in increasing order, with an offset array of size
+// groups+1 whose last entry is the particle count.  The paper partitions by
+// x3 slice with an incomplete Quicksort; here the groups are bricks of B^3
+// cells and the partition is a stable radix sort, so that ties keep their
+// input order and the result is reproducible bit for bit.
+#include "device_common.h"
+#include "launch.h"
+
+namespace ptk {
+
+// ---------------------------------------------------------------------------
+// keys and locate
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_keys(const double* __restrict__ X, int64_t n, int N,
+                                              double invd, int B, int nb, uint32_t* __restrict__ keys,
+                                              int* __restrict__ flag) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double x1 = X[3 * i], x2 = X[3 * i + 1], x3 = X[3 * i + 2];
+  if (!in_domain3(x1, x2, x3)) {
+    flag[0] = 1;
+    keys[i] = 0;
+    return;
+  }
+  int c1, c2, c3;
+  double t;
+  locate(x1, N, invd, &c1, &t);
+  locate(x2, N, invd, &c2, &t);
+  locate(x3, N, invd, &c3, &t);
+  keys[i] = bin_key(c1, c2, c3, B, nb);
+}
+
+__global__ __launch_bounds__(256) void k_locate(const double* __restrict__ X, int64_t n3, int N,
+                                                double invd, int32_t* __restrict__ cell,
+                                                double* __restrict__ off, int* __restrict__ flag) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n3) return;
+  double x = X[i];
+  if (!in_domain(x)) {
+    flag[0] = 1;
+    cell[i] = 0;
+    if (off) off[i] = 0.0;
+    return;
+  }
+  int c;
+  double t;
+  locate(x, N, invd, &c, &t);
+  cell[i] = c;
+  if (off) off[i] = t;
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, one pass per digit
+//   tile = 256 threads x 8 items; each wave owns 512 consecutive items and
+//   ranks them in 8 rounds of 64 with a ballot-built "same digit" lane mask.
+// ---------------------------------------------------------------------------
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kTile = kSortThreads * kSortItems;  // 2048
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                    int shift, uint32_t mask,
+                                                    uint32_t* __restrict__ hist, int64_t n_tiles) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  for (int k = 0; k < kSortItems; ++k) {
+    int64_t i = base + k * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, int64_t n, int shift,
+    uint32_t mask, int bits, const uint32_t* __restrict__ prefix, int64_t n_tiles,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t wcount[4][256];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < 4 * 256; d += 256) (&wcount[0][0])[d] = 0;
+  __syncthreads();
+  const int64_t wbase = (int64_t)blockIdx.x * kTile + wave * (64 * kSortItems);
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+  for (int r = 0; r < kSortItems; ++r) {
+    int64_t i = wbase + r * 64 + lane;
+    bool valid = i < n;
+    uint32_t k = valid ? keys_in[i] : 0u;
+    uint32_t v = valid ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
+    uint32_t d = (k >> shift) & mask;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+      uint64_t m = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    uint32_t before = (uint32_t)__popcll(peers & lt_mask);
+    uint32_t base = valid ? wcount[wave][d] : 0u;
+    // every lane of this wave has read the running count before the leader of
+    // each digit group adds the group's size
+    __builtin_amdgcn_wave_barrier();
+    if (valid && before == 0) wcount[wave][d] = base + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    key[r] = k;
+    val[r] = v;
+    rank[r] = valid ? base + before : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  // exclusive prefix of the per-wave counts over waves, per digit
+  {
+    uint32_t run = 0;
+    for (int w = 0; w < 4; ++w) {
+      uint32_t c = wcount[w][threadIdx.x];
+      wcount[w][threadIdx.x] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int r = 0; r < kSortItems; ++r) {
+    if (rank[r] == 0xFFFFFFFFu) continue;
+    uint32_t d = (key[r] >> shift) & mask;
+    uint64_t pos = (uint64_t)prefix[(int64_t)d * n_tiles + blockIdx.x] + wcount[wave][d] + rank[r];
+    keys_out[pos] = key[r];
+    vals_out[pos] = val[r];
+  }
+}
+
+// exclusive scan of n uint32 (in place): block sums, scan of sums, apply
+constexpr int kScanBlock = 1024;  // elements per block (256 threads x 4)
+
+__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  uint32_t wpre = 0, tot = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) wpre += sh[w];
+    tot += sh[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return wpre + x - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ a, int64_t n,
+                                                     uint32_t* __restrict__ sums) {
+  __shared__ uint32_t sh[4];
+  int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+  uint32_t s = 0;
+  for (int k = 0; k < 4; ++k)
+    if (base + k < n) s += a[base + k];
+  uint32_t tot;
+  block_excl_scan_256(s, sh, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ sums, int64_t nb) {
+  __shared__ uint32_t sh[4];
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += 256) {
+    int64_t i = base + threadIdx.x;
+    uint32_t v = i < nb ? sums[i] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan_256(v, sh, &tot);
+    if (i < nb) sums[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(uint32_t* __restrict__ a, int64_t n,
+                                                    const uint32_t* __restrict__ sums) {
+  __shared__ uint32_t sh[4];
+  int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+  uint32_t v[4], s = 0;
+  for (int k = 0; k < 4; ++k) {
+    v[k] = (base + k < n) ? a[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t ex = block_excl_scan_256(s, sh, &tot) + sums[blockIdx.x];
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) a[base + k] = ex;
+    ex += v[k];
+  }
+}
+
+// offsets[b] = first sorted index with key >= b, for b in [0, n_bins]
+__global__ __launch_bounds__(256) void k_offsets(const uint32_t* __restrict__ skeys, int64_t n,
+                                                 int64_t n_bins, uint32_t* __restrict__ offsets) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i > n) return;
+  int64_t lo = (i == 0) ? -1 : (int64_t)skeys[i - 1];
+  int64_t hi = (i == n) ? n_bins : (int64_t)skeys[i];
+  if (hi > n_bins) hi = n_bins;  // keys are < n_bins by construction; never write past the array
+  for (int64_t b = lo + 1; b <= hi; ++b) offsets[b] = (uint32_t)i;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather3(const T* __restrict__ in, const uint32_t* __restrict__ perm,
+                                                 int64_t n, T* __restrict__ out) {
+  int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  int64_t s = perm[k];
+  out[3 * k] = in[3 * s];
+  out[3 * k + 1] = in[3 * s + 1];
+  out[3 * k + 2] = in[3 * s + 2];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatterW(const T* __restrict__ in, const uint32_t* __restrict__ idx,
+                                                  int64_t n, int width, T* __restrict__ out) {
+  int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  int64_t d = idx[k];
+  for (int e = 0; e < width; ++e) out[d * width + e] = in[k * width + e];
+}
+
+__global__ __launch_bounds__(256) void k_gather_u32(const uint32_t* __restrict__ in,
+                                                    const uint32_t* __restrict__ perm, int64_t n,
+                                                    uint32_t* __restrict__ out) {
+  int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  out[k] = in[perm[k]];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_keys(const double* X, int64_t n, int N, double invd, int B, int nb, uint32_t* keys,
+                       int* flag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_keys<<<blocks_for(n, 256), 256, 0, s>>>(X, n, N, invd, B, nb, keys, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_locate(const double* X, int64_t n3, int N, double invd, int32_t* cell, double* off,
+                         int* flag, hipStream_t s) {
+  if (n3 == 0) return hipSuccess;
+  k_locate<<<blocks_for(n3, 256), 256, 0, s>>>(X, n3, N, invd, cell, off, flag);
+  return hipGetLastError();
+}
+
+size_t sort_hist_words(int64_t n) {
+  int64_t n_tiles = (n + kTile - 1) / kTile;
+  return (size_t)256 * (size_t)(n_tiles > 0 ? n_tiles : 1);
+}
+
+size_t scan_tmp_words(int64_t m) { return (size_t)((m + kScanBlock - 1) / kScanBlock + 1); }
+
+hipError_t exclusive_scan_u32(uint32_t* a, int64_t m, uint32_t* tmp, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  int64_t nb = (m + kScanBlock - 1) / kScanBlock;
+  k_scan_reduce<<<(unsigned)nb, 256, 0, s>>>(a, m, tmp);
+  k_scan_top<<<1, 256, 0, s>>>(tmp, nb);
+  k_scan_apply<<<(unsigned)nb, 256, 0, s>>>(a, m, tmp);
+  return hipGetLastError();
+}
+
+// Stable sort of keys (values = input positions).  On return *keys_sorted and
+// *perm point into {ka, kb} / {va, vb}.
+hipError_t radix_sort_keys(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* vb, int64_t n,
+                           int key_bits, uint32_t* hist, uint32_t* tmp, uint32_t** keys_sorted,
+                           uint32_t** perm, hipStream_t s) {
+  if (n == 0) {
+    *keys_sorted = ka;
+    *perm = va;
+    return hipSuccess;
+  }
+  const int64_t n_tiles = (n + kTile - 1) / kTile;
+  const int passes = key_bits <= 0 ? 1 : (key_bits + 7) / 8;
+  const int bits = key_bits <= 0 ? 1 : (key_bits + passes - 1) / passes;
+  const uint32_t mask = (1u << bits) - 1u;
+  // pass p reads (kin, vin) and writes (kout, vout); the first pass takes the
+  // input positions as values
+  uint32_t *kin = ka, *kout = kb, *vin = nullptr, *vout = va, *vspare = vb;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * bits;
+    k_radix_hist<<<(unsigned)n_tiles, 256, 0, s>>>(kin, n, shift, mask, hist, n_tiles);
+    hipError_t e = exclusive_scan_u32(hist, 256 * n_tiles, tmp, s);
+    if (e != hipSuccess) return e;
+    k_radix_scatter<<<(unsigned)n_tiles, 256, 0, s>>>(kin, vin, n, shift, mask, bits, hist, n_tiles, kout,
+                                                      vout);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint32_t* t = kin;
+    kin = kout;
+    kout = t;
+    uint32_t* old_vin = vin;
+    vin = vout;
+    vout = old_vin ? old_vin : vspare;
+  }
+  *keys_sorted = kin;
+  *perm = vin;
+  return hipSuccess;
+}
+
+hipError_t launch_offsets(const uint32_t* skeys, int64_t n, int64_t n_bins, uint32_t* offsets,
+                          hipStream_t s) {
+  k_offsets<<<blocks_for(n + 1, 256), 256, 0, s>>>(skeys, n, n_bins, offsets);
+  return hipGetLastError();
+}
+
+hipError_t gather3_f64(const double* in, const uint32_t* perm, int64_t n, double* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_gather3<double><<<blocks_for(n, 256), 256, 0, s>>>(in, perm, n, out);
+  return hipGetLastError();
+}
+
+hipError_t gather3_f32(const float* in, const uint32_t* perm, int64_t n, float* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_gather3<float><<<blocks_for(n, 256), 256, 0, s>>>(in, perm, n, out);
+  return hipGetLastError();
+}
+
+hipError_t gather_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_t* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_gather_u32<<<blocks_for(n, 256), 256, 0, s>>>(in, perm, n, out);
+  return hipGetLastError();
+}
+
+hipError_t scatter_f64(const double* in, const uint32_t* idx, int64_t n, int width, double* out,
+                       hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_scatterW<double><<<blocks_for(n, 256), 256, 0, s>>>(in, idx, n, width, out);
+  return hipGetLastError();
+}
+
+hipError_t scatter_f32(const float* in, const uint32_t* idx, int64_t n, int width, float* out,
+                       hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_scatterW<float><<<blocks_for(n, 256), 256, 0, s>>>(in, idx, n, width, out);
+  return hipGetLastError();
+}
+
+}  // namespace ptk

@@ -1,0 +1,62 @@
+// Host-side launchers of the libptk kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ptk {
+
+// binning.hip
+hipError_t launch_keys(const double* X, int64_t n, int N, double invd, int B, int nb, uint32_t* keys,
+                       int* flag, hipStream_t s);
+hipError_t launch_locate(const double* X, int64_t n3, int N, double invd, int32_t* cell, double* off,
+                         int* flag, hipStream_t s);
+size_t sort_hist_words(int64_t n);
+size_t scan_tmp_words(int64_t m);
+hipError_t exclusive_scan_u32(uint32_t* a, int64_t m, uint32_t* tmp, hipStream_t s);
+hipError_t radix_sort_keys(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* vb, int64_t n,
+                           int key_bits, uint32_t* hist, uint32_t* tmp, uint32_t** keys_sorted,
+                           uint32_t** perm, hipStream_t s);
+hipError_t launch_offsets(const uint32_t* skeys, int64_t n, int64_t n_bins, uint32_t* offsets,
+                          hipStream_t s);
+hipError_t gather3_f64(const double* in, const uint32_t* perm, int64_t n, double* out, hipStream_t s);
+hipError_t gather3_f32(const float* in, const uint32_t* perm, int64_t n, float* out, hipStream_t s);
+hipError_t gather_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_t* out, hipStream_t s);
+hipError_t scatter_f64(const double* in, const uint32_t* idx, int64_t n, int width, double* out,
+                       hipStream_t s);
+hipError_t scatter_f32(const float* in, const uint32_t* idx, int64_t n, int width, float* out,
+                       hipStream_t s);
+
+// field.hip
+hipError_t launch_sumsq(const void* u, int in_f64, int64_t nodes, double* partial, int nblocks,
+                        hipStream_t s);
+hipError_t launch_pack(const void* u, int in_f64, int64_t N, int storage, int I, void* field,
+                       int64_t row_pitch, int64_t plane_pitch, const float* inv_scale, hipStream_t s);
+
+// interp.hip
+struct InterpArgs {
+  const void* field;
+  int64_t row_pitch, plane_pitch, P;
+  int N, nb;
+  double invd;
+  const double* X;          // positions in bin order
+  const uint32_t* offsets;  // [n_bins + 1]
+  const uint32_t* orig;     // destination index of each bin-ordered particle, or NULL
+  void* out;                // [n][3] or NULL
+  void* grad;               // [n][3][3] or NULL
+  int out_f64;
+  const void* coef;         // device KernelTables
+  float scale[3];
+  int64_t n_bins;
+};
+hipError_t launch_interp(int storage, int I, const InterpArgs& a, hipStream_t s);
+
+// step.hip
+enum UpdateKind { kEulerOrPredict = 0, kHeunCorrect = 1, kAB2 = 2 };
+hipError_t launch_update(int kind, int vel_f64, const double* X, const void* ka, const void* kb, double dt,
+                         int64_t n, double* Xout, uint32_t* keys, int N, double invd, int B, int nb,
+                         int* flag, hipStream_t s);
+
+}  // namespace ptk

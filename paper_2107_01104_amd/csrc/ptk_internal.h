@@ -1,0 +1,84 @@
+// Internal declarations shared by the libptk translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ptk {
+
+constexpr int kMaxI = 8;           // largest kernel size built into the library
+constexpr int kBinEdge = 8;        // bin edge B in cells (bricks of B^3 cells)
+constexpr double kL = 6.283185307179586;  // fl64(2*pi)
+
+// Coefficients of beta_j (val) and d beta_j / dt (der) for node index
+// c = 0..I-1 (offset c - (I/2 - 1)), ascending powers of t.
+struct KernelTables {
+  int I = 0;
+  double val64[kMaxI][kMaxI];
+  double der64[kMaxI][kMaxI];
+  float val32[kMaxI][kMaxI];
+  float der32[kMaxI][kMaxI];
+};
+
+int build_kernel_tables(int family, int I, int m, KernelTables* out);
+
+// Geometry of the stored field: a periodic copy padded by I/2-1 nodes below
+// and I/2 above on every axis, rows padded to `row_pitch` bytes.
+struct FieldGeom {
+  int64_t N = 0;       // grid points per axis
+  int64_t P = 0;       // padded extent N + I - 1
+  int64_t row_pitch = 0;    // bytes per padded x1 row
+  int64_t plane_pitch = 0;  // bytes per padded (x2, x1) plane
+  int node_bytes = 0;       // 3 components in the storage type
+  int halo_lo = 0;          // I/2 - 1
+};
+
+// Kernel timing (ptk_timing_enable / ptk_timing_read): event pairs recorded on
+// the call's stream around each instrumented launch sequence.
+constexpr int kTimerKinds = 6;
+struct TimedPair {
+  hipEvent_t start, stop;
+  int kind;
+};
+
+// One growable device allocation.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace ptk
+
+struct ptk_ctx {
+  int device = 0;
+  std::string err;
+  // field
+  bool has_field = false;
+  int family = 0, I = 0, m = 0;
+  int storage = 0;          // PTK_F64 .. PTK_F16
+  float scale[3] = {1.f, 1.f, 1.f};
+  ptk::FieldGeom geom;
+  ptk::DevBuf field;
+  ptk::DevBuf coef;         // device copy of the coefficient tables (KernelTables)
+  ptk::KernelTables tables;
+  // binning of the last interpolate call
+  int64_t bin_np = 0, bin_nbins = 0;
+  uint32_t* bin_perm = nullptr;
+  bool bin_valid = false;
+  // scratch
+  ptk::DevBuf keys_a, keys_b, vals_a, vals_b, offsets, hist, scan_tmp, flag;
+  ptk::DevBuf xs, xn, orig, orig_b, k1, k2, h0, h1, h0b, h1b, gint, stage;
+  size_t bytes_in_use = 0;
+  size_t byte_cap = 0;      // 0 = unlimited (test hook PTK_TEST_MAX_BYTES)
+  bool check = true;        // PTK_NO_CHECK clears it
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<ptk::TimedPair> pending;
+  double timer_ms[ptk::kTimerKinds] = {0};
+  int64_t timer_count[ptk::kTimerKinds] = {0};
+};

@@ -1,0 +1,232 @@
+"""Python binding of libptk (include/ptk.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts torch device
+tensors to pointers, passes torch's current HIP stream, and turns return codes
+into exceptions.  Importing it without a built ``libptk.so`` raises: there is no
+fallback path.
+
+Low-level functions carry the C names (``ptk_create``, ``ptk_set_field``, ...);
+``Context`` wraps them for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libptk.so")
+
+F64, F32, BF16, F16 = 0, 1, 2, 3
+LAGRANGE, SPLINE = 0, 1
+EULER, HEUN, AB2 = 1, 2, 3
+OK, EINVAL, ENOFIELD, ENOMEM, EHIP, EDOMAIN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+TIMERS = ["interp", "interp_grad", "sort", "keys", "update", "permute"]
+
+EXPORTS = ["ptk_kernel_table", "ptk_create", "ptk_destroy", "ptk_last_error", "ptk_set_field", "ptk_get_field_scale",
+           "ptk_locate", "ptk_interpolate", "ptk_interpolate_gradient", "ptk_advance_particles",
+           "ptk_binning_info", "ptk_get_binning", "ptk_timing_enable", "ptk_timing_read"]
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2107_01104_amd/build.py (or "
+                      "__graft_entry__.build()) first")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+
+class ptk_kernel(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_int), ("I", ctypes.c_int), ("m", ctypes.c_int)]
+
+
+_vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+lib.ptk_kernel_table.argtypes = [ctypes.POINTER(ptk_kernel), _vp, _vp]
+lib.ptk_create.argtypes = [ctypes.POINTER(_vp), _int]
+lib.ptk_destroy.argtypes = [_vp]
+lib.ptk_destroy.restype = None
+lib.ptk_last_error.argtypes = [_vp]
+lib.ptk_last_error.restype = ctypes.c_char_p
+lib.ptk_set_field.argtypes = [_vp, _vp, _i64, _int, _int, ctypes.POINTER(ptk_kernel), _vp]
+lib.ptk_get_field_scale.argtypes = [_vp, ctypes.POINTER(ctypes.c_float)]
+lib.ptk_locate.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
+lib.ptk_interpolate.argtypes = [_vp, _vp, _i64, _vp, _int, _vp]
+lib.ptk_interpolate_gradient.argtypes = [_vp, _vp, _i64, _vp, _vp, _int, _vp]
+lib.ptk_advance_particles.argtypes = [_vp, _vp, _i64, _vp, ctypes.POINTER(_int), _int, _dbl, _int, _vp, _vp]
+lib.ptk_binning_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int)]
+lib.ptk_get_binning.argtypes = [_vp, _vp, _vp, _vp]
+lib.ptk_timing_enable.argtypes = [_vp, _int]
+lib.ptk_timing_read.argtypes = [_vp, _vp, _vp]
+for _name in EXPORTS:
+    if _name not in ("ptk_destroy", "ptk_last_error"):
+        getattr(lib, _name).restype = _int
+
+# the C entry points under their own names
+ptk_kernel_table = lib.ptk_kernel_table
+ptk_create = lib.ptk_create
+ptk_destroy = lib.ptk_destroy
+ptk_last_error = lib.ptk_last_error
+ptk_set_field = lib.ptk_set_field
+ptk_get_field_scale = lib.ptk_get_field_scale
+ptk_locate = lib.ptk_locate
+ptk_interpolate = lib.ptk_interpolate
+ptk_interpolate_gradient = lib.ptk_interpolate_gradient
+ptk_advance_particles = lib.ptk_advance_particles
+ptk_binning_info = lib.ptk_binning_info
+ptk_get_binning = lib.ptk_get_binning
+ptk_timing_enable = lib.ptk_timing_enable
+ptk_timing_read = lib.ptk_timing_read
+
+
+def kernel_table(family: int, I: int, m: int = 0):
+    """(val, der) coefficient tables [I][I] of the library's kernel (host only)."""
+    import numpy as np
+    val = np.zeros((I, I))
+    der = np.zeros((I, I))
+    k = ptk_kernel(int(family), int(I), int(m))
+    rc = lib.ptk_kernel_table(ctypes.byref(k), val.ctypes.data_as(_vp), der.ctypes.data_as(_vp))
+    if rc != OK:
+        raise PtkError(rc, "ptk_kernel_table failed")
+    return val, der
+
+
+class PtkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ptk error {code}: {msg}")
+        self.code = code
+
+
+_TORCH_OF = {F64: torch.float64, F32: torch.float32}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_tensor(t, dtype, shape_tail, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
+        raise ValueError(f"{name} must end in shape {shape_tail}")
+    return t
+
+
+class Context:
+    """One libptk context on one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        rc = lib.ptk_create(ctypes.byref(h), int(device))
+        if rc != OK:
+            raise PtkError(rc, "ptk_create failed")
+        self._h = h
+        self.storage = None
+        self.N = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.ptk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != OK:
+            raise PtkError(rc, lib.ptk_last_error(self._h).decode())
+
+    def set_field(self, u: torch.Tensor, family: int, I: int, m: int = 0, storage: int = F32):
+        if u.dtype not in (torch.float64, torch.float32):
+            raise TypeError("field must be float64 or float32")
+        _dev_tensor(u, u.dtype, (3,), "u")
+        N = u.shape[0]
+        if tuple(u.shape) != (N, N, N, 3):
+            raise ValueError("field must have shape (N, N, N, 3)")
+        k = ptk_kernel(int(family), int(I), int(m))
+        in_dt = F64 if u.dtype == torch.float64 else F32
+        self._check(lib.ptk_set_field(self._h, _ptr(u), N, in_dt, int(storage), ctypes.byref(k),
+                                      _stream(self.device)))
+        self.storage, self.N = int(storage), N
+
+    def field_scale(self):
+        s = (ctypes.c_float * 3)()
+        self._check(lib.ptk_get_field_scale(self._h, s))
+        return [s[0], s[1], s[2]]
+
+    def vel_dtype(self):
+        return torch.float64 if self.storage == F64 else torch.float32
+
+    def locate(self, X: torch.Tensor, with_offset: bool = True):
+        _dev_tensor(X, torch.float64, (3,), "X")
+        n = X.numel() // 3
+        cell = torch.empty((n, 3), dtype=torch.int32, device=X.device)
+        t = torch.empty((n, 3), dtype=torch.float64, device=X.device) if with_offset else None
+        self._check(lib.ptk_locate(self._h, _ptr(X), n, _ptr(cell), _ptr(t), _stream(self.device)))
+        return (cell, t) if with_offset else cell
+
+    def interpolate(self, X: torch.Tensor, out_dtype=torch.float32, out=None):
+        _dev_tensor(X, torch.float64, (3,), "X")
+        n = X.numel() // 3
+        if out is None:
+            out = torch.empty((n, 3), dtype=out_dtype, device=X.device)
+        code = F64 if out.dtype == torch.float64 else F32
+        self._check(lib.ptk_interpolate(self._h, _ptr(X), n, _ptr(out), code, _stream(self.device)))
+        return out
+
+    def interpolate_gradient(self, X: torch.Tensor, out_dtype=torch.float32, with_value: bool = True):
+        _dev_tensor(X, torch.float64, (3,), "X")
+        n = X.numel() // 3
+        u = torch.empty((n, 3), dtype=out_dtype, device=X.device) if with_value else None
+        g = torch.empty((n, 3, 3), dtype=out_dtype, device=X.device)
+        code = F64 if out_dtype == torch.float64 else F32
+        self._check(lib.ptk_interpolate_gradient(self._h, _ptr(X), n, _ptr(u), _ptr(g), code,
+                                                 _stream(self.device)))
+        return u, g
+
+    def advance(self, X: torch.Tensor, scheme: int, dt: float, nsteps: int, hist=None, hist_len: int = 0,
+                grad_out=None):
+        """Advance X in place; returns the new history length (AB2) or 0."""
+        _dev_tensor(X, torch.float64, (3,), "X")
+        n = X.numel() // 3
+        hl = ctypes.c_int(int(hist_len))
+        if hist is not None:
+            _dev_tensor(hist, self.vel_dtype(), (3,), "rhs_hist")
+            if tuple(hist.shape) != (2, n, 3):
+                raise ValueError("rhs_hist must have shape (2, Np, 3)")
+        if grad_out is not None:
+            _dev_tensor(grad_out, self.vel_dtype(), (3, 3), "grad_out")
+        self._check(lib.ptk_advance_particles(self._h, _ptr(X), n, _ptr(hist),
+                                              ctypes.byref(hl) if hist is not None else None,
+                                              int(scheme), float(dt), int(nsteps), _ptr(grad_out),
+                                              _stream(self.device)))
+        return hl.value
+
+    def binning(self):
+        np_, nb, be = _i64(), _i64(), _int()
+        self._check(lib.ptk_binning_info(self._h, ctypes.byref(np_), ctypes.byref(nb), ctypes.byref(be)))
+        perm = torch.empty(max(np_.value, 1), dtype=torch.int32, device=self.device)
+        off = torch.empty(nb.value + 1, dtype=torch.int32, device=self.device)
+        self._check(lib.ptk_get_binning(self._h, _ptr(perm), _ptr(off), _stream(self.device)))
+        return perm[: np_.value], off, be.value
+
+    def timing(self, enable: bool):
+        self._check(lib.ptk_timing_enable(self._h, int(bool(enable))))
+
+    def timing_read(self):
+        """{kind: (total_ms, launches)} accumulated since timing was enabled."""
+        import numpy as np
+        ms = np.zeros(len(TIMERS))
+        cnt = np.zeros(len(TIMERS), dtype=np.int64)
+        self._check(lib.ptk_timing_read(self._h, ms.ctypes.data_as(_vp), cnt.ctypes.data_as(_vp)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(TIMERS)}

@@ -1,0 +1,74 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* libptk.so loads and exports every function include/ptk.h declares;
+* the library's own kernel-coefficient derivation (exact rationals, rounded
+  once) equals the oracle's coefficients bit for bit;
+* host-side argument validation.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import kernels as K
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ptk.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ptk_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def ptk():
+    from paper_2107_01104_amd import ptk as mod
+    return mod
+
+
+def test_every_declared_symbol_exported(ptk):
+    names = _declared()
+    assert len(names) >= 12
+    raw = ctypes.CDLL(ptk.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+    assert sorted(ptk.EXPORTS) == names
+
+
+@pytest.mark.parametrize("fam,I,m", [(K.LAGRANGE, 4, 0), (K.LAGRANGE, 6, 0), (K.LAGRANGE, 8, 0),
+                                     (K.SPLINE, 4, 1), (K.SPLINE, 6, 1), (K.SPLINE, 6, 2),
+                                     (K.SPLINE, 8, 1), (K.SPLINE, 8, 2), (K.SPLINE, 8, 3),
+                                     (K.SPLINE, 8, 0)])
+def test_kernel_tables_match_oracle_bitwise(ptk, fam, I, m):
+    val, der = ptk.kernel_table(fam, I, m)
+    ref = K.coeff_table_f64(fam, I, m)
+    dref = np.zeros((I, I))
+    dref[:, : I - 1] = K.coeff_table_f64(fam, I, m, deriv=True)[:, : I - 1]
+    assert np.array_equal(val, ref)
+    assert np.array_equal(der, dref)
+
+
+def test_kernel_table_rejects(ptk):
+    with pytest.raises(ptk.PtkError) as e:
+        ptk.kernel_table(K.SPLINE, 5, 1)
+    assert e.value.code == ptk.EUNSUPPORTED
+    with pytest.raises(ptk.PtkError) as e:
+        ptk.kernel_table(K.SPLINE, 6, 3)
+    assert e.value.code == ptk.EINVAL
+    with pytest.raises(ptk.PtkError) as e:
+        ptk.kernel_table(7, 6, 1)
+    assert e.value.code == ptk.EINVAL
+
+
+def test_null_and_bad_arguments_without_device(ptk):
+    assert ptk.lib.ptk_create(None, 0) == ptk.EINVAL
+    h = ctypes.c_void_p()
+    assert ptk.lib.ptk_create(ctypes.byref(h), -1) == ptk.EINVAL
+    assert ptk.lib.ptk_set_field(None, None, 32, 0, 0, None, None) == ptk.EINVAL
+    assert ptk.lib.ptk_interpolate(None, None, 0, None, 0, None) == ptk.EINVAL
+    assert ptk.lib.ptk_advance_particles(None, None, 0, None, None, 2, 1e-3, 1, None, None) == ptk.EINVAL
+    ptk.lib.ptk_destroy(None)
