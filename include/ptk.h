@@ -127,9 +127,9 @@ int ptk_locate(ptk_ctx *ctx, const double *X, int64_t Np, int32_t *cell, double 
 
 /* Interpolate the field at Np positions (Eq. "triple_sum", indices modulo N).
  * X: device [Np][3] binary64.  out: device [Np][3] of out_dtype (PTK_F64 or
- * PTK_F32), in the order of X.  Internally particles are binned by cell
- * (bricks of B^3 cells, B = ptk_binning_info's bin_edge) with a stable sort,
- * as the paper groups particles by slice (Sec. 3.3.1). */
+ * PTK_F32), in the order of X.  Internally particles are binned by cell with a
+ * stable sort (tile columns cut into x3 windows, see ptk_binning_info), as the
+ * paper groups particles by x3 slice (Sec. 3.3.1). */
 int ptk_interpolate(ptk_ctx *ctx, const double *X, int64_t Np, void *out, int out_dtype,
                     void *stream);
 
@@ -162,9 +162,13 @@ int ptk_advance_particles(ptk_ctx *ctx, double *X, int64_t Np, void *rhs_hist, i
                           int scheme, double dt, int nsteps, void *grad_out, void *stream);
 
 /* Binning of the last ptk_interpolate / ptk_interpolate_gradient call:
- * number of particles, number of bins and bin edge B in cells.  Bin of cell c:
- *   key = ((c3/B) * nb + c2/B) * nb + c1/B, nb = ceil(N/B). */
-int ptk_binning_info(const ptk_ctx *ctx, int64_t *np, int64_t *n_bins, int *bin_edge);
+ * number of particles, number of bins, tile edge T and window depth W (cells).
+ * Bins are tile columns of T x T cells in (x1, x2), each cut along x3 into
+ * windows of W cell layers; bin of cell c:
+ *   key = ((c2/T) * ntx + c1/T) * nw + c3/W,  ntx = ceil(N/T), nw = ceil(N/W),
+ * so within a column particles are ordered along x3 like the paper's slices.
+ * T is 16 for FP32/BF16/FP16 storage and 8 for FP64 storage; W is 4. */
+int ptk_binning_info(const ptk_ctx *ctx, int64_t *np, int64_t *n_bins, int *tile, int *window);
 
 /* Copy that binning to device buffers: perm[k] (uint32 [np]) = index in X of
  * the k-th particle in bin order (a stable sort of the keys), offsets (uint32

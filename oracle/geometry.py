@@ -17,10 +17,12 @@ Readings (the paper fixes no floating-point sequence):
       if c == N: c = 0, t = 0
   "closest grid cell" is read as the cell whose lower node is floor(Xtilde/delta),
   and t = xbar/delta is formed as s - c (equal to it in exact arithmetic).
-* The bin of a particle is the brick of B x B x B cells holding its cell, with
-  the bin index ordered x3 slowest, x1 fastest (the paper's slice order
-  generalised to bricks):  key = ((c3//B)*nb + c2//B)*nb + c1//B,
-  nb = ceil(N/B).
+* The bin of a particle: the (x1, x2) plane is cut into tile columns of
+  T x T cells (ntx = ceil(N/T) per axis), each column into windows of W cell
+  layers along x3 (nw = ceil(N/W)); bins are ordered column by column (x2 tile
+  slowest) and along x3 within a column, i.e. the paper's x3-slice order
+  applied inside each column:
+      key = ((c2//T)*ntx + c1//T)*nw + c3//W.
 * The particle order is the stable sort of keys (ties keep their current order),
   and offsets[b] = number of particles with key < b, offsets[n_bins] = Np.
 """
@@ -80,16 +82,17 @@ def cell_and_offset_scalar(x: float, N: int):
     return int(c), float(t)
 
 
-def n_bins_per_axis(N: int, B: int) -> int:
-    return -(-N // B)
+def n_bins(N: int, T: int, W: int) -> int:
+    ntx = -(-N // T)
+    return ntx * ntx * (-(-N // W))
 
 
-def bin_keys(X: np.ndarray, N: int, B: int) -> np.ndarray:
+def bin_keys(X: np.ndarray, N: int, T: int, W: int) -> np.ndarray:
     """Bin key per particle for positions X[Np][3] (x1, x2, x3)."""
     c, _ = cell_and_offset(np.asarray(X, dtype=np.float64), N)
-    nb = n_bins_per_axis(N, B)
-    b = c // B
-    return ((b[:, 2] * nb + b[:, 1]) * nb + b[:, 0]).astype(np.int64)
+    ntx = -(-N // T)
+    nw = -(-N // W)
+    return (((c[:, 1] // T) * ntx + c[:, 0] // T) * nw + c[:, 2] // W).astype(np.int64)
 
 
 def stable_order(keys: np.ndarray) -> np.ndarray:

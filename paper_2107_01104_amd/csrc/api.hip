@@ -139,7 +139,16 @@ void drain_timers(ptk_ctx* c) {
   c->pending.clear();
 }
 
-inline int64_t nb_of(int64_t N) { return (N + kBinEdge - 1) / kBinEdge; }
+BinGeom bin_geom(const ptk_ctx* c) {
+  BinGeom g;
+  g.T = c->storage == PTK_F64 ? kTileF64 : kTileF32;
+  g.ntx = (int)((c->geom.N + g.T - 1) / g.T);
+  g.W = kWindow;
+  g.nw = (int)((c->geom.N + g.W - 1) / g.W);
+  return g;
+}
+
+inline int64_t n_bins_of(const BinGeom& g) { return (int64_t)g.ntx * g.ntx * g.nw; }
 
 inline int bits_for(int64_t n_bins) {
   int b = 0;
@@ -186,22 +195,30 @@ int bin_sorted(ptk_ctx* c, int64_t Np, int64_t n_bins, uint32_t** perm, hipStrea
   return PTK_OK;
 }
 
-InterpArgs base_args(const ptk_ctx* c, int64_t n_bins) {
+InterpArgs base_args(const ptk_ctx* c) {
   InterpArgs a;
   std::memset(&a, 0, sizeof(a));
+  const BinGeom g = bin_geom(c);
   a.field = c->field.ptr;
   a.row_pitch = c->geom.row_pitch;
   a.plane_pitch = c->geom.plane_pitch;
   a.P = c->geom.P;
   a.N = (int)c->geom.N;
-  a.nb = (int)nb_of(c->geom.N);
   a.invd = invd_of(c->geom.N);
+  a.ntx = g.ntx;
+  a.n_tiles = (int64_t)g.ntx * g.ntx;
+  a.nw = g.nw;
+  // enough workgroups to fill the GPU: split columns along x3 when there are few
+  int64_t nseg = (1024 + a.n_tiles - 1) / a.n_tiles;
+  if (nseg > a.nw) nseg = a.nw;
+  if (nseg < 1) nseg = 1;
+  a.wps = (a.nw + nseg - 1) / nseg;
+  a.nseg = (a.nw + a.wps - 1) / a.wps;
   a.offsets = (const uint32_t*)c->offsets.ptr;
   a.coef = c->coef.ptr;
   a.scale[0] = c->scale[0];
   a.scale[1] = c->scale[1];
   a.scale[2] = c->scale[2];
-  a.n_bins = n_bins;
   return a;
 }
 
@@ -216,7 +233,9 @@ int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* gr
   DeviceGuard g(c->device);
   if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
   hipStream_t s = S(stream);
-  const int64_t N = c->geom.N, nb = nb_of(N), n_bins = nb * nb * nb;
+  const int64_t N = c->geom.N;
+  const BinGeom bg = bin_geom(c);
+  const int64_t n_bins = n_bins_of(bg);
   c->bin_valid = false;
   if (Np == 0) {
     c->bin_np = 0;
@@ -234,7 +253,7 @@ int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* gr
   {
     Timed t(c, s, PTK_T_KEYS);
     PTK_HIP(c,
-            launch_keys(X, Np, (int)N, invd_of(N), kBinEdge, (int)nb, (uint32_t*)c->keys_a.ptr,
+            launch_keys(X, Np, (int)N, invd_of(N), bg, (uint32_t*)c->keys_a.ptr,
                         (int*)c->flag.ptr, s),
             "keys");
   }
@@ -247,7 +266,7 @@ int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* gr
     Timed t(c, s, PTK_T_PERMUTE);
     PTK_HIP(c, gather3_f64(X, perm, Np, (double*)c->xs.ptr, s), "gather positions");
   }
-  InterpArgs a = base_args(c, n_bins);
+  InterpArgs a = base_args(c);
   a.X = (const double*)c->xs.ptr;
   a.orig = perm;
   a.out = u_out;
@@ -441,12 +460,14 @@ int ptk_interpolate_gradient(ptk_ctx* c, const double* X, int64_t Np, void* u_ou
   return interp_common(c, X, Np, u_out, grad, out_dtype, stream);
 }
 
-int ptk_binning_info(const ptk_ctx* c, int64_t* np, int64_t* n_bins, int* bin_edge) {
-  if (!c || !np || !n_bins || !bin_edge) return PTK_EINVAL;
+int ptk_binning_info(const ptk_ctx* c, int64_t* np, int64_t* n_bins, int* tile, int* window) {
+  if (!c || !np || !n_bins || !tile || !window) return PTK_EINVAL;
   if (!c->bin_valid) return PTK_ENOFIELD;
+  const BinGeom g = bin_geom(c);
   *np = c->bin_np;
   *n_bins = c->bin_nbins;
-  *bin_edge = kBinEdge;
+  *tile = g.T;
+  *window = g.W;
   return PTK_OK;
 }
 
@@ -483,7 +504,9 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
   DeviceGuard g(c->device);
   if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
   hipStream_t s = S(stream);
-  const int64_t N = c->geom.N, nb = nb_of(N), n_bins = nb * nb * nb;
+  const int64_t N = c->geom.N;
+  const BinGeom bg = bin_geom(c);
+  const int64_t n_bins = n_bins_of(bg);
   const double invd = invd_of(N);
   const int vb = vel_bytes(c);
   const bool vf64 = vb == 8;
@@ -527,7 +550,7 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
   };
   auto update = [&](int kind, const void* ka, const void* kb) -> int {
     Timed t(c, s, PTK_T_UPDATE);
-    PTK_HIP(c, launch_update(kind, vf64, xs, ka, kb, dt, Np, xn, keys, (int)N, invd, kBinEdge, (int)nb, flag, s),
+    PTK_HIP(c, launch_update(kind, vf64, xs, ka, kb, dt, Np, xn, keys, (int)N, invd, bg, flag, s),
             "position update");
     return PTK_OK;
   };
@@ -540,7 +563,7 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
   // initial binning of the caller's positions; the state is then kept in bin order
   {
     Timed t(c, s, PTK_T_KEYS);
-    PTK_HIP(c, launch_keys(X, Np, (int)N, invd, kBinEdge, (int)nb, keys, flag, s), "keys");
+    PTK_HIP(c, launch_keys(X, Np, (int)N, invd, bg, keys, flag, s), "keys");
   }
   uint32_t* perm = nullptr;
   PTK_TRY(sort(&perm));
@@ -557,7 +580,7 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     const bool last = step == nsteps - 1;
     // u(X_n), and its gradient, at the bin-ordered positions
     {
-      InterpArgs a = base_args(c, n_bins);
+      InterpArgs a = base_args(c);
       a.X = xs;
       a.out = k1;
       a.grad = grad_out ? c->gint.ptr : nullptr;
@@ -581,7 +604,7 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
         PTK_HIP(c, gather3_f64(xn, pp, Np, xp, s), "gather predictor");
       }
       {
-        InterpArgs b = base_args(c, n_bins);
+        InterpArgs b = base_args(c);
         b.X = xp;
         b.orig = pp;
         b.out = k2;

@@ -5,8 +5,9 @@
 // "Ordering the particles locally"): particles of one group are stored
 // contiguously, groups in increasing order, with an offset array of size
 // groups+1 whose last entry is the particle count.  The paper partitions by
-// x3 slice with an incomplete Quicksort; here the groups are bricks of B^3
-// cells and the partition is a stable radix sort, so that ties keep their
+// x3 slice with an incomplete Quicksort; here a group is a window of W cell
+// layers of a T x T tile column (x3 fastest within a column, as the paper's
+// slices), and the partition is a stable radix sort, so that ties keep their
 // input order and the result is reproducible bit for bit.
 #include "device_common.h"
 #include "launch.h"
@@ -17,7 +18,7 @@ namespace ptk {
 // keys and locate
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_keys(const double* __restrict__ X, int64_t n, int N,
-                                              double invd, int B, int nb, uint32_t* __restrict__ keys,
+                                              double invd, BinGeom g, uint32_t* __restrict__ keys,
                                               int* __restrict__ flag) {
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
@@ -32,7 +33,7 @@ __global__ __launch_bounds__(256) void k_keys(const double* __restrict__ X, int6
   locate(x1, N, invd, &c1, &t);
   locate(x2, N, invd, &c2, &t);
   locate(x3, N, invd, &c3, &t);
-  keys[i] = bin_key(c1, c2, c3, B, nb);
+  keys[i] = bin_key(c1, c2, c3, g);
 }
 
 __global__ __launch_bounds__(256) void k_locate(const double* __restrict__ X, int64_t n3, int N,
@@ -240,10 +241,10 @@ __global__ __launch_bounds__(256) void k_gather_u32(const uint32_t* __restrict__
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-hipError_t launch_keys(const double* X, int64_t n, int N, double invd, int B, int nb, uint32_t* keys,
+hipError_t launch_keys(const double* X, int64_t n, int N, double invd, const BinGeom& g, uint32_t* keys,
                        int* flag, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_keys<<<blocks_for(n, 256), 256, 0, s>>>(X, n, N, invd, B, nb, keys, flag);
+  k_keys<<<blocks_for(n, 256), 256, 0, s>>>(X, n, N, invd, g, keys, flag);
   return hipGetLastError();
 }
 

@@ -8,6 +8,8 @@
 
 #include <cstdint>
 
+#include "launch.h"
+
 namespace ptk {
 
 // Positions accepted by the library: finite with |x| < 2^50.  Beyond that the
@@ -52,9 +54,10 @@ __device__ __forceinline__ bool in_domain3(double a, double b, double c) {
   return in_domain(a) && in_domain(b) && in_domain(c);
 }
 
-// Bin key of a cell: bricks of B^3 cells, x3 slowest (the paper's slice order).
-__device__ __forceinline__ uint32_t bin_key(int c1, int c2, int c3, int B, int nb) {
-  return (uint32_t)(((c3 / B) * nb + c2 / B) * nb + c1 / B);
+// Bin key of a cell: tile column (x2 tile slowest), then the x3 window --
+// within a column, particles are ordered along x3 like the paper's slices.
+__device__ __forceinline__ uint32_t bin_key(int c1, int c2, int c3, const BinGeom& g) {
+  return (uint32_t)(((c2 / g.T) * g.ntx + c1 / g.T) * g.nw + c3 / g.W);
 }
 
 // bf16 <-> f32 (bit patterns in uint16).

@@ -2,26 +2,29 @@
 // sum of Sec. 2.2, Eq. "triple_sum", and the gradient through derivative
 // kernels.
 //
-// One workgroup per bin (a brick of B^3 cells).  The workgroup first copies
-// the brick's halo -- the (B+I-1)^3 nodes any particle of the brick can touch
-// -- from the padded field into LDS, converting 3-component nodes to a 4-wide,
-// 16-byte-aligned (FP32) / 32-byte (FP64) / 8-byte (BF16, FP16) LDS layout.
-// Then each group of GS lanes (GS = 8 for I = 6, 8; 4 for I = 4) takes one
-// particle: lane j owns the x1 node offset j and contracts x2 then x3 for the
-// three components,
-//     s_a(i3) = sum_i2 beta_i2(t2) u_a(c1+j, c2+i2, c3+i3)
-//     r_a     = beta_j(t1) * sum_i3 beta_i3(t3) s_a(i3),
-// and the group reduces r_a over its lanes (the x1 sum).  This is the paper's
-// split of the triple sum into partial sums over some directions finished
-// along the remaining one (Sec. 3.3, "split into I double sums"), done inside
-// one wavefront instead of across processes.  The eight lanes of a group read
-// eight consecutive LDS nodes per (i2, i3), i.e. 128 contiguous bytes.
+// Work decomposition: a workgroup owns one tile column -- T x T cells in
+// (x1, x2), a run of x3 -- and sweeps it along x3, the paper's slice
+// direction, in windows of W = 4 cell layers.  Particles are binned by (tile,
+// window) with x3 fastest, so a window's particles are contiguous.  The
+// (T+I-1)^2 halo nodes of every x3 plane live in a 16-slot LDS ring; each plane
+// is read from HBM once per tile column (halo over-fetch ((T+I-1)/T)^2 = 2.07
+// for T = 16, I = 8) and the next window's planes are loaded into registers
+// while the current window is computed.
 //
-// Weights are evaluated per lane by Horner from the lane's own row of the
-// coefficient table and shared in the group with cross-lane reads.
-// Sums are FP64 for FP64 storage and FP32 otherwise.  Workgroup-to-bin mapping
-// is XCD-aware: consecutive workgroups go round-robin to the 8 XCDs, so each
-// XCD is given a contiguous run of bins and neighbouring bricks share its L2.
+// Per particle: a group of 16 lanes.  Lane j = lane & 7 owns the x1 node
+// offset j; the two half-rows split the x3 planes (half h takes i3 in
+// [h I/2, (h+1) I/2)).  Each lane contracts x2 for each of its planes and x3
+// over its half, scales by its x1 weight, and the group sums over its 16
+// lanes with DPP: the paper's split of the triple sum into partial sums
+// finished along the remaining direction (Sec. 3.3), inside one wavefront.
+// The LDS plane pitch is 32 mod 64 bytes, so the two half-rows (4 planes apart)
+// of a quarter-wave read disjoint banks; each half reads 8 consecutive
+// 16-byte nodes, so every ds_read_b128 of a quarter-wave touches all 64 banks
+// once.
+//
+// Weights: every lane evaluates its own node of beta (and beta') by Horner from
+// its row of the coefficient table; the group shares them with DPP
+// row_newbcast.  Sums are FP64 for FP64 storage and FP32 otherwise.
 #include "device_common.h"
 #include "launch.h"
 #include "ptk_internal.h"
@@ -31,137 +34,308 @@ namespace ptk {
 enum { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_F16 = 3 };
 
 template <int ST>
-struct StoreT;
-template <>
-struct StoreT<ST_F64> {
-  using acc = double;
-  static constexpr int lds_bytes = 32, glob_bytes = 24, G = 2;
+struct StoreT {
+  using acc = float;
+  static constexpr int T = kTileF32;   // tile edge in cells
+  static constexpr int NB = 8;         // LDS bytes per node
+  static constexpr int GB = 6;         // global (stored) bytes per node
+  static constexpr int THREADS = 512;
 };
 template <>
 struct StoreT<ST_F32> {
   using acc = float;
-  static constexpr int lds_bytes = 16, glob_bytes = 12, G = 4;
+  static constexpr int T = kTileF32;
+  static constexpr int NB = 16;
+  static constexpr int GB = 12;
+  static constexpr int THREADS = 512;
 };
 template <>
-struct StoreT<ST_BF16> {
-  using acc = float;
-  static constexpr int lds_bytes = 8, glob_bytes = 6, G = 8;
-};
-template <>
-struct StoreT<ST_F16> {
-  using acc = float;
-  static constexpr int lds_bytes = 8, glob_bytes = 6, G = 8;
+struct StoreT<ST_F64> {
+  using acc = double;
+  static constexpr int T = kTileF64;
+  static constexpr int NB = 32;
+  static constexpr int GB = 24;
+  static constexpr int THREADS = 256;
 };
 
-// write node q of a 48-byte global chunk (12 words) into LDS node slot n
+template <int ST, int I>
+struct Geom {
+  static constexpr int T = StoreT<ST>::T;
+  static constexpr int TX = T + I - 1;                   // halo tile edge in nodes
+  static constexpr int NB = StoreT<ST>::NB;
+  static constexpr int RAW = TX * TX * NB;
+  static constexpr int PP = RAW + ((32 - RAW % 64) + 64) % 64;  // plane pitch, = 32 mod 64
+  static constexpr int R = 16;                            // ring slots
+  static constexpr int LDS = R * PP;
+  static constexpr int G = 48 / StoreT<ST>::GB;           // nodes per 48-byte chunk
+  static constexpr int RG = (TX + G - 1) / G;             // chunks per halo row
+  static constexpr int UNITS_PER_PLANE = TX * RG;
+  static constexpr int THREADS = StoreT<ST>::THREADS;
+  static constexpr int PRE = (kWindow * UNITS_PER_PLANE + THREADS - 1) / THREADS;  // chunks per thread
+  static_assert(kWindow + I - 1 <= R - kWindow, "ring too small for the prefetch window");
+};
+
+// ---- DPP helpers (rows of 16 lanes = one particle group)
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dppi(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// value of lane L of this row
+template <int L, typename V>
+__device__ __forceinline__ V bcast(V v) {
+  return dpp<0x150 + L>(v);
+}
+template <int L>
+__device__ __forceinline__ int bcasti(int v) {
+  return dppi<0x150 + L>(v);
+}
+// sum over the 16 lanes of the row (every lane gets the total)
+template <typename V>
+__device__ __forceinline__ V rowsum(V v) {
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  return v;
+}
+
+// ---- node access
+// copy node q of a 48-byte chunk (12 words) into LDS at byte offset `off`
 template <int ST>
-__device__ __forceinline__ void lds_put(unsigned char* smem, int n, const uint32_t* w, int q) {
+__device__ __forceinline__ void lds_put(unsigned char* smem, int off, const uint32_t* w, int q) {
   if constexpr (ST == ST_F32) {
-    ((uint4*)smem)[n] = make_uint4(w[3 * q], w[3 * q + 1], w[3 * q + 2], 0u);
+    *(uint4*)(smem + off) = make_uint4(w[3 * q], w[3 * q + 1], w[3 * q + 2], 0u);
   } else if constexpr (ST == ST_F64) {
-    ((uint4*)smem)[2 * n] = make_uint4(w[6 * q], w[6 * q + 1], w[6 * q + 2], w[6 * q + 3]);
-    ((uint4*)smem)[2 * n + 1] = make_uint4(w[6 * q + 4], w[6 * q + 5], 0u, 0u);
+    *(uint4*)(smem + off) = make_uint4(w[6 * q], w[6 * q + 1], w[6 * q + 2], w[6 * q + 3]);
+    *(uint4*)(smem + off + 16) = make_uint4(w[6 * q + 4], w[6 * q + 5], 0u, 0u);
   } else {
     const int k = 3 * q;
-    uint32_t h0 = (w[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
-    uint32_t h1 = (w[(k + 1) >> 1] >> (((k + 1) & 1) * 16)) & 0xFFFFu;
-    uint32_t h2 = (w[(k + 2) >> 1] >> (((k + 2) & 1) * 16)) & 0xFFFFu;
-    ((uint2*)smem)[n] = make_uint2(h0 | (h1 << 16), h2);
+    const uint32_t h0 = (w[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
+    const uint32_t h1 = (w[(k + 1) >> 1] >> (((k + 1) & 1) * 16)) & 0xFFFFu;
+    const uint32_t h2 = (w[(k + 2) >> 1] >> (((k + 2) & 1) * 16)) & 0xFFFFu;
+    *(uint2*)(smem + off) = make_uint2(h0 | (h1 << 16), h2);
   }
 }
 
-template <int ST>
-__device__ __forceinline__ void lds_get(const unsigned char* smem, int n, typename StoreT<ST>::acc* v) {
+// read a node; the unused fourth word is kept alive until `keep` so the
+// compiler issues one full 16-byte read (ds_read_b128) instead of a slower b96
+template <int ST, typename V>
+__device__ __forceinline__ void lds_get(const unsigned char* smem, int off, V* v, uint32_t& keep) {
   if constexpr (ST == ST_F32) {
-    float4 f = ((const float4*)smem)[n];
+    const float4 f = *(const float4*)(smem + off);
     v[0] = f.x;
     v[1] = f.y;
     v[2] = f.z;
+    keep = __float_as_uint(f.w);
   } else if constexpr (ST == ST_F64) {
-    double2 a = ((const double2*)smem)[2 * n];
-    double2 b = ((const double2*)smem)[2 * n + 1];
+    const double2 a = *(const double2*)(smem + off);
+    const double2 b = *(const double2*)(smem + off + 16);
     v[0] = a.x;
     v[1] = a.y;
     v[2] = b.x;
+    keep = (uint32_t)__double_as_longlong(b.y);
   } else if constexpr (ST == ST_BF16) {
-    uint2 u = ((const uint2*)smem)[n];
+    const uint2 u = *(const uint2*)(smem + off);
     v[0] = __uint_as_float(u.x << 16);
     v[1] = __uint_as_float(u.x & 0xFFFF0000u);
     v[2] = __uint_as_float(u.y << 16);
+    keep = 0;
   } else {
-    uint2 u = ((const uint2*)smem)[n];
+    const uint2 u = *(const uint2*)(smem + off);
     v[0] = __half2float(__ushort_as_half((unsigned short)(u.x & 0xFFFFu)));
     v[1] = __half2float(__ushort_as_half((unsigned short)(u.x >> 16)));
     v[2] = __half2float(__ushort_as_half((unsigned short)(u.y & 0xFFFFu)));
+    keep = 0;
   }
 }
 
-template <int I, typename T>
-__device__ __forceinline__ T horner(const T* c, T t) {
-  T acc = c[I - 1];
+template <int NC, typename V>
+__device__ __forceinline__ V horner(const V* c, V t) {
+  V acc = c[NC - 1];
 #pragma unroll
-  for (int p = I - 2; p >= 0; --p) acc = fma(acc, t, c[p]);
+  for (int p = NC - 2; p >= 0; --p) acc = fma(acc, t, c[p]);
   return acc;
 }
 
-template <int ST, int I, bool GRAD>
-__global__ __launch_bounds__(256) void k_interp(InterpArgs a, int64_t per_xcd) {
-  using T = typename StoreT<ST>::acc;
-  constexpr int B = kBinEdge;
-  constexpr int BX = B + I - 1;
-  constexpr int NODES = BX * BX * BX;
-  constexpr int G = StoreT<ST>::G;
-  constexpr int RG = (BX + G - 1) / G;   // 48-byte chunks per box row
-  constexpr int GS = (I <= 4) ? 4 : 8;   // lanes per particle
-  constexpr int GPB = 256 / GS;          // particles per workgroup round
-  __shared__ __attribute__((aligned(16))) unsigned char smem[NODES * StoreT<ST>::lds_bytes];
+// load unit u (one 48-byte chunk of a halo row of plane zp) from HBM.  The
+// load is unconditional (a chunk outside the padded field reads the field's
+// first chunk instead and is reported invalid), so the compiler keeps it in
+// flight rather than waiting for it at a branch merge.
+template <int ST, int I>
+__device__ __forceinline__ bool load_unit(const InterpArgs& a, int64_t x0, int64_t y0, int64_t zp, int u,
+                                          uint4* c) {
+  using Gm = Geom<ST, I>;
+  const int g = u % Gm::RG;
+  const int r = u / Gm::RG;
+  const int64_t Y = y0 + r, X = x0 + (int64_t)g * Gm::G;
+  const bool ok = zp < a.P && Y < a.P && X < a.P;
+  const int64_t off = ok ? zp * a.plane_pitch + Y * a.row_pitch + X * StoreT<ST>::GB : 0;
+  const uint4* src = (const uint4*)((const unsigned char*)a.field + off);
+  c[0] = src[0];
+  c[1] = src[1];
+  c[2] = src[2];
+  return ok;
+}
 
-  const int64_t bid = blockIdx.x;
-  const int64_t bin = (bid & 7) * per_xcd + (bid >> 3);
-  if (bin >= a.n_bins) return;
-  const uint32_t start = a.offsets[bin], end = a.offsets[bin + 1];
-  if (start >= end) return;
-  const int nb = a.nb;
-  const int bx = (int)(bin % nb), by = (int)((bin / nb) % nb), bz = (int)(bin / ((int64_t)nb * nb));
-
-  // ---- stage the halo brick: box node (z, y, x) = padded node (bz*B+z, by*B+y, bx*B+x)
-  {
-    const unsigned char* f = (const unsigned char*)a.field;
-    const int64_t P = a.P;
-    const int64_t x0 = (int64_t)bx * B;
-    for (int it = threadIdx.x; it < BX * BX * RG; it += 256) {
-      const int g = it % RG;
-      const int y = (it / RG) % BX;
-      const int z = it / (RG * BX);
-      const int64_t Z = (int64_t)bz * B + z, Y = (int64_t)by * B + y;
-      const int xs = g * G;
-      if (Z >= P || Y >= P || x0 + xs >= P) continue;
-      const uint4* src = (const uint4*)(f + Z * a.plane_pitch + Y * a.row_pitch +
-                                        (x0 + xs) * StoreT<ST>::glob_bytes);
-      uint32_t w[12];
-      uint4 c0 = src[0], c1 = src[1], c2 = src[2];
-      w[0] = c0.x; w[1] = c0.y; w[2] = c0.z; w[3] = c0.w;
-      w[4] = c1.x; w[5] = c1.y; w[6] = c1.z; w[7] = c1.w;
-      w[8] = c2.x; w[9] = c2.y; w[10] = c2.z; w[11] = c2.w;
-      const int rowbase = (z * BX + y) * BX;
+template <int ST, int I>
+__device__ __forceinline__ void store_unit(unsigned char* smem, int64_t zp, int u, const uint4* c) {
+  using Gm = Geom<ST, I>;
+  const int g = u % Gm::RG;
+  const int r = u / Gm::RG;
+  const uint32_t w[12] = {c[0].x, c[0].y, c[0].z, c[0].w, c[1].x, c[1].y,
+                          c[1].z, c[1].w, c[2].x, c[2].y, c[2].z, c[2].w};
+  const int slot = (int)(zp & (Gm::R - 1));
 #pragma unroll
-      for (int q = 0; q < G; ++q)
-        if (xs + q < BX) lds_put<ST>(smem, rowbase + xs + q, w, q);
+  for (int q = 0; q < Gm::G; ++q) {
+    const int x = g * Gm::G + q;
+    if (x < Gm::TX) lds_put<ST>(smem, slot * Gm::PP + (r * Gm::TX + x) * Gm::NB, w, q);
+  }
+}
+
+// One particle: 16 lanes (this lane owns x1 offset j and plane half h).
+// Accumulates the 3 values (and 9 gradient entries) summed over the group.
+template <int ST, int I, bool GRAD, typename V>
+__device__ __forceinline__ void particle_sums(const unsigned char* smem, const V* cv, const V* cd, int j, int jj,
+                                              int h, V t1, V t2, V t3, int l1, int l2, int z3, V* r) {
+  using Gm = Geom<ST, I>;
+  constexpr int TX = Gm::TX, NB = Gm::NB, PP = Gm::PP, R = Gm::R;
+  constexpr int HALF = I / 2;
+  // weights: half 0 evaluates beta_j(t2), half 1 beta_j(t3); all lanes beta_j(t1)
+  const V tsel = h ? t3 : t2;
+  const V wsel = horner<I>(cv, tsel);
+  V w1 = horner<I>(cv, t1);
+  if (j >= I) w1 = (V)0;
+  V w2[I], w3[HALF];
+#define PTK_B2(k) if constexpr ((k) < I) w2[k] = bcast<k>(wsel);
+  PTK_B2(0) PTK_B2(1) PTK_B2(2) PTK_B2(3) PTK_B2(4) PTK_B2(5) PTK_B2(6) PTK_B2(7)
+#undef PTK_B2
+#define PTK_B3(k) if constexpr ((k) < HALF) { const V lo = bcast<8 + (k)>(wsel), hi = bcast<8 + HALF + (k)>(wsel); w3[k] = h ? hi : lo; }
+  PTK_B3(0) PTK_B3(1) PTK_B3(2) PTK_B3(3)
+#undef PTK_B3
+  V d1 = (V)0, dw2[I], dw3[HALF];
+  if constexpr (GRAD) {
+    const V dsel = horner<I - 1>(cd, tsel);
+    d1 = horner<I - 1>(cd, t1);
+    if (j >= I) d1 = (V)0;
+#define PTK_D2(k) if constexpr ((k) < I) dw2[k] = bcast<k>(dsel);
+    PTK_D2(0) PTK_D2(1) PTK_D2(2) PTK_D2(3) PTK_D2(4) PTK_D2(5) PTK_D2(6) PTK_D2(7)
+#undef PTK_D2
+#define PTK_D3(k) if constexpr ((k) < HALF) { const V lo = bcast<8 + (k)>(dsel), hi = bcast<8 + HALF + (k)>(dsel); dw3[k] = h ? hi : lo; }
+    PTK_D3(0) PTK_D3(1) PTK_D3(2) PTK_D3(3)
+#undef PTK_D3
+  }
+  // contraction: x2 per plane, x3 over this half's planes
+  const int noff = ((l2 * TX) + l1 + jj) * NB;
+  V acc[3] = {0, 0, 0}, ad2[3] = {0, 0, 0}, ad3[3] = {0, 0, 0};
+  uint32_t keep[HALF][I];
+#pragma unroll
+  for (int kk = 0; kk < HALF; ++kk) {
+    const int slot = (z3 + h * HALF + kk) & (R - 1);
+    const int base = slot * PP + noff;
+    V s[3] = {0, 0, 0}, sd[3] = {0, 0, 0};
+#pragma unroll
+    for (int i2 = 0; i2 < I; ++i2) {
+      V v[3];
+      lds_get<ST>(smem, base + i2 * TX * NB, v, keep[kk][i2]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        s[q] = fma(w2[i2], v[q], s[q]);
+        if constexpr (GRAD) sd[q] = fma(dw2[i2], v[q], sd[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      acc[q] = fma(w3[kk], s[q], acc[q]);
+      if constexpr (GRAD) {
+        ad3[q] = fma(dw3[kk], s[q], ad3[q]);
+        ad2[q] = fma(w3[kk], sd[q], ad2[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < HALF; ++kk)
+#pragma unroll
+    for (int i2 = 0; i2 < I; ++i2) asm volatile("" ::"v"(keep[kk][i2]));
+  // x1 weight, then the sum over the group's 16 lanes
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    r[q] = w1 * acc[q];
+    if constexpr (GRAD) {
+      r[3 + 3 * q + 0] = d1 * acc[q];
+      r[3 + 3 * q + 1] = w1 * ad2[q];
+      r[3 + 3 * q + 2] = w1 * ad3[q];
+    }
+  }
+  constexpr int NV = GRAD ? 12 : 3;
+#pragma unroll
+  for (int e = 0; e < NV; ++e) r[e] = rowsum(r[e]);
+}
+
+template <int ST, int I, bool GRAD>
+__global__ __launch_bounds__(StoreT<ST>::THREADS) void k_interp(InterpArgs a) {
+  using V = typename StoreT<ST>::acc;
+  using Gm = Geom<ST, I>;
+  constexpr int T = Gm::T;
+  constexpr int W = kWindow;
+  constexpr int NT = Gm::THREADS;
+  constexpr int GROUPS = NT / 16;        // particles per round
+  constexpr int NV = GRAD ? 12 : 3;
+  constexpr int CH = 4 * GROUPS;         // particles located per chunk (4 rounds)
+  // particle record: t1, t2, t3 (V) at 0; cells l1, l2, z3 (u16) at 32;
+  // destination index (u32) at 40
+  constexpr int RECB = 48;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[Gm::LDS];
+  __shared__ __attribute__((aligned(16))) unsigned char recs[CH * RECB];
+
+  // ---- block -> (tile column, x3 segment); consecutive blocks go round-robin
+  // to the 8 XCDs, so XCD x is given a contiguous range of columns
+  const int64_t nblk = a.n_tiles * a.nseg;
+  const int64_t per_xcd = (nblk + 7) / 8;
+  const int64_t b = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (b >= nblk) return;
+  const int64_t tile = b / a.nseg;
+  const int seg = (int)(b % a.nseg);
+  const int64_t w_begin = (int64_t)seg * a.wps;
+  const int64_t w_end = min(a.nw, w_begin + a.wps);
+  if (w_begin >= w_end) return;
+  const int tx = (int)(tile % a.ntx), ty = (int)(tile / a.ntx);
+  const int64_t x0 = (int64_t)tx * T, y0 = (int64_t)ty * T;
+  const int tid = threadIdx.x;
+
+  // ---- initial fill: planes [W*w_begin, W*w_begin + W + I - 1)
+  {
+    const int64_t z_lo = W * w_begin;
+    constexpr int UNITS = (W + I - 1) * Gm::UNITS_PER_PLANE;
+    for (int u = tid; u < UNITS; u += NT) {
+      uint4 c[3];
+      const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
+      if (load_unit<ST, I>(a, x0, y0, z_lo + pl, uu, c)) store_unit<ST, I>(smem, z_lo + pl, uu, c);
     }
   }
   __syncthreads();
 
   // ---- per-lane constants
-  const int lane = threadIdx.x & 63;
-  const int j = threadIdx.x % GS;            // x1 node offset owned by this lane
-  const int jj = j < I ? j : I - 1;          // clamped for the idle lanes of I = 6
-  const int gbase = lane - j;                // first lane of this group in the wave
-  const int grp = threadIdx.x / GS;
+  const int l16 = tid & 15;
+  const int j = l16 & 7;              // x1 node offset
+  const int h = l16 >> 3;             // plane half
+  const int jj = j < I ? j : I - 1;
+  const int grp = tid >> 4;
   const KernelTables* tab = (const KernelTables*)a.coef;
-  T cv[I], cd[I];
+  V cv[I], cd[I];
 #pragma unroll
   for (int p = 0; p < I; ++p) {
-    if constexpr (sizeof(T) == 8) {
+    if constexpr (sizeof(V) == 8) {
       cv[p] = tab->val64[jj][p];
       cd[p] = tab->der64[jj][p];
     } else {
@@ -171,122 +345,131 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a, int64_t per_xcd) {
   }
   const int N = a.N;
   const double invd = a.invd;
-  const int ox = bx * B, oy = by * B, oz = bz * B;
 
-  for (uint32_t p0 = start; p0 < end; p0 += GPB) {
-    const uint32_t p = p0 + grp;
-    const bool active = p < end;
-    const uint32_t pl = active ? p : end - 1;
-    // lanes 0, 1, 2 of the group locate axes x1, x2, x3
-    const int ax = j < 3 ? j : 2;
-    int c;
-    double td;
-    locate(a.X[3 * (int64_t)pl + ax], N, invd, &c, &td);
-    const int c1 = __shfl(c, gbase + 0, 64), c2 = __shfl(c, gbase + 1, 64), c3 = __shfl(c, gbase + 2, 64);
-    const double t1d = __shfl(td, gbase + 0, 64), t2d = __shfl(td, gbase + 1, 64),
-                 t3d = __shfl(td, gbase + 2, 64);
-    const T t1 = (T)t1d, t2 = (T)t2d, t3 = (T)t3d;
-    // local cell inside the brick (clamped: the LDS index stays in the box)
-    const int l1 = min(max(c1 - ox, 0), B - 1), l2 = min(max(c2 - oy, 0), B - 1),
-              l3 = min(max(c3 - oz, 0), B - 1);
-    // weights: lane evaluates node jj on every axis, then the group shares x2/x3
-    T w1 = horner<I>(cv, t1);
-    const T w2j = horner<I>(cv, t2), w3j = horner<I>(cv, t3);
-    if (j >= I) w1 = (T)0;
-    T w2[I], w3[I];
-#pragma unroll
-    for (int k = 0; k < I; ++k) {
-      w2[k] = __shfl(w2j, gbase + k, 64);
-      w3[k] = __shfl(w3j, gbase + k, 64);
-    }
-    T d1 = 0, dw2[I], dw3[I];
-    if constexpr (GRAD) {
-      d1 = horner<I - 1>(cd, t1);
-      const T d2j = horner<I - 1>(cd, t2), d3j = horner<I - 1>(cd, t3);
-      if (j >= I) d1 = (T)0;
-#pragma unroll
-      for (int k = 0; k < I; ++k) {
-        dw2[k] = __shfl(d2j, gbase + k, 64);
-        dw3[k] = __shfl(d3j, gbase + k, 64);
-      }
-    }
-    // contraction over x2 then x3 for this lane's x1 node
-    const int nbase = (l3 * BX + l2) * BX + l1 + jj;
-    T acc[3] = {0, 0, 0}, ad2[3] = {0, 0, 0}, ad3[3] = {0, 0, 0};
-#pragma unroll
-    for (int i3 = 0; i3 < I; ++i3) {
-      T s[3] = {0, 0, 0}, sd[3] = {0, 0, 0};
-#pragma unroll
-      for (int i2 = 0; i2 < I; ++i2) {
-        T v[3];
-        lds_get<ST>(smem, nbase + (i3 * BX + i2) * BX, v);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          s[q] = fma(w2[i2], v[q], s[q]);
-          if constexpr (GRAD) sd[q] = fma(dw2[i2], v[q], sd[q]);
+  uint4 pre[Gm::PRE][3];
+  bool pre_ok[Gm::PRE];
+
+  for (int64_t w = w_begin; w < w_end; ++w) {
+    const bool more = w + 1 < w_end;
+    const int64_t z_new = W * (w + 1) + I - 1;  // planes the next window adds: [z_new, z_new + W)
+    const int64_t bin = tile * a.nw + w;
+    const uint32_t start = a.offsets[bin], end = a.offsets[bin + 1];
+    bool issued = false;
+    for (uint32_t c0 = start;; c0 += CH) {
+      const int n = (int)min((int64_t)CH, (int64_t)end - (int64_t)c0);
+      if (c0 > start) __syncthreads();  // the previous chunk's records are no longer read
+      // steps 1-3 of Sec. 2.2 once per coordinate: one thread per (particle, axis)
+      if (tid < 3 * n) {
+        const int pi = tid / 3, ax = tid % 3;
+        int c;
+        double td;
+        locate(a.X[3 * ((int64_t)c0 + pi) + ax], N, invd, &c, &td);
+        int lc;
+        if (ax == 0)
+          lc = min(max(c - (int)x0, 0), T - 1);
+        else if (ax == 1)
+          lc = min(max(c - (int)y0, 0), T - 1);
+        else
+          lc = (int)min(max((int64_t)c, W * w), W * w + W - 1);
+        unsigned char* rp = recs + pi * RECB;
+        if constexpr (sizeof(V) == 8)
+          ((double*)rp)[ax] = td;
+        else
+          ((float*)rp)[ax] = (float)td;
+        ((uint16_t*)(rp + 32))[ax] = (uint16_t)lc;
+        if (ax == 0) {
+          const uint32_t p = c0 + (uint32_t)pi;
+          *(uint32_t*)(rp + 40) = a.orig ? a.orig[p] : p;
         }
       }
+      // the next window's planes are requested only now, after this chunk's
+      // position loads, so waiting for those never waits for the prefetch
+      if (!issued && more) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        acc[q] = fma(w3[i3], s[q], acc[q]);
-        if constexpr (GRAD) {
-          ad3[q] = fma(dw3[i3], s[q], ad3[q]);
-          ad2[q] = fma(w3[i3], sd[q], ad2[q]);
+        for (int k = 0; k < Gm::PRE; ++k) {
+          const int uraw = tid + k * NT;
+          const int u = min(uraw, W * Gm::UNITS_PER_PLANE - 1);
+          const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
+          pre_ok[k] = load_unit<ST, I>(a, x0, y0, z_new + pl, uu, pre[k]) && uraw < W * Gm::UNITS_PER_PLANE;
         }
+        issued = true;
       }
-    }
-    // x1 weight, then the sum over the group's lanes
-    constexpr int NV = GRAD ? 12 : 3;
-    T r[NV];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      r[q] = w1 * acc[q];
-      if constexpr (GRAD) {
-        r[3 + 3 * q + 0] = d1 * acc[q];
-        r[3 + 3 * q + 1] = w1 * ad2[q];
-        r[3 + 3 * q + 2] = w1 * ad3[q];
-      }
-    }
-#pragma unroll
-    for (int o = 1; o < GS; o <<= 1)
-#pragma unroll
-      for (int e = 0; e < NV; ++e) r[e] += __shfl_xor(r[e], o, 64);
-    if (active) {
-      const int64_t q = a.orig ? (int64_t)a.orig[p] : (int64_t)p;
-#pragma unroll
-      for (int e = 0; e < NV; ++e) {
-        if (e % GS != j) continue;
-        if (e < 3) {
-          if (!a.out) continue;
-          T val = r[e];
-          if constexpr (ST == ST_BF16 || ST == ST_F16) val *= a.scale[e];
-          if (a.out_f64)
-            ((double*)a.out)[3 * q + e] = (double)val;
-          else
-            ((float*)a.out)[3 * q + e] = (float)val;
+      __syncthreads();
+
+      // ---- this chunk's particles, GROUPS at a time
+      for (int r0 = 0; r0 < n; r0 += GROUPS) {
+        const int pi = r0 + grp;
+        const bool active = pi < n;
+        const unsigned char* rp = recs + (active ? pi : n - 1) * RECB;
+        V t1, t2, t3;
+        if constexpr (sizeof(V) == 8) {
+          const double2 ta = *(const double2*)rp;
+          const double2 tb = *(const double2*)(rp + 16);
+          t1 = ta.x;
+          t2 = ta.y;
+          t3 = tb.x;
         } else {
-          const int comp = (e - 3) / 3;
-          T val = r[e] * (T)invd;
-          if constexpr (ST == ST_BF16 || ST == ST_F16) val *= a.scale[comp];
-          if (a.out_f64)
-            ((double*)a.grad)[9 * q + (e - 3)] = (double)val;
-          else
-            ((float*)a.grad)[9 * q + (e - 3)] = (float)val;
+          const float4 tf = *(const float4*)rp;
+          t1 = tf.x;
+          t2 = tf.y;
+          t3 = tf.z;
+        }
+        const uint4 lc = *(const uint4*)(rp + 32);
+        const int l1 = (int)(lc.x & 0xFFFFu), l2 = (int)(lc.x >> 16), z3 = (int)(lc.y & 0xFFFFu);
+        V r[NV];
+        particle_sums<ST, I, GRAD>(smem, cv, cd, j, jj, h, t1, t2, t3, l1, l2, z3, r);
+        if (active) {
+          const int64_t q = (int64_t)lc.z;
+#pragma unroll
+          for (int e = 0; e < NV; ++e) {
+            if (e != l16) continue;
+            if (e < 3) {
+              if (!a.out) continue;
+              V val = r[e];
+              if constexpr (ST == ST_BF16 || ST == ST_F16) val *= (V)a.scale[e];
+              if (a.out_f64)
+                ((double*)a.out)[3 * q + e] = (double)val;
+              else
+                ((float*)a.out)[3 * q + e] = (float)val;
+            } else {
+              V val = r[e] * (V)invd;
+              if constexpr (ST == ST_BF16 || ST == ST_F16) val *= (V)a.scale[(e - 3) / 3];
+              if (a.out_f64)
+                ((double*)a.grad)[9 * q + (e - 3)] = (double)val;
+              else
+                ((float*)a.grad)[9 * q + (e - 3)] = (float)val;
+            }
+          }
+        }
+      }
+      if ((int64_t)c0 + CH >= (int64_t)end) break;
+    }
+
+    // planes of the next window go into ring slots this window does not read
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < Gm::PRE; ++k) {
+        const int u = tid + k * NT;
+        if (pre_ok[k]) {
+          const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
+          store_unit<ST, I>(smem, z_new + pl, uu, pre[k]);
         }
       }
     }
+    __syncthreads();
   }
 }
 
 template <int ST, int I>
 static hipError_t launch_one(const InterpArgs& a, hipStream_t s) {
-  const int64_t per_xcd = (a.n_bins + 7) / 8;
-  const int64_t grid = per_xcd * 8;
+  const int64_t nblk = a.n_tiles * a.nseg;
+  const int64_t grid = (nblk + 7) / 8 * 8;
   if (grid == 0) return hipSuccess;
+  constexpr int NT = StoreT<ST>::THREADS;
   if (a.grad)
-    k_interp<ST, I, true><<<(unsigned)grid, 256, 0, s>>>(a, per_xcd);
+    k_interp<ST, I, true><<<(unsigned)grid, NT, 0, s>>>(a);
   else
-    k_interp<ST, I, false><<<(unsigned)grid, 256, 0, s>>>(a, per_xcd);
+    k_interp<ST, I, false><<<(unsigned)grid, NT, 0, s>>>(a);
   return hipGetLastError();
 }
 

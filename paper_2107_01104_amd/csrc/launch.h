@@ -8,8 +8,14 @@
 
 namespace ptk {
 
+// Bin geometry: tile columns of T x T cells in (x1, x2), ntx = ceil(N/T) per
+// axis, each cut along x3 into nw = ceil(N/W) windows of W cell layers.
+struct BinGeom {
+  int T, ntx, W, nw;
+};
+
 // binning.hip
-hipError_t launch_keys(const double* X, int64_t n, int N, double invd, int B, int nb, uint32_t* keys,
+hipError_t launch_keys(const double* X, int64_t n, int N, double invd, const BinGeom& g, uint32_t* keys,
                        int* flag, hipStream_t s);
 hipError_t launch_locate(const double* X, int64_t n3, int N, double invd, int32_t* cell, double* off,
                          int* flag, hipStream_t s);
@@ -39,8 +45,10 @@ hipError_t launch_pack(const void* u, int in_f64, int64_t N, int storage, int I,
 struct InterpArgs {
   const void* field;
   int64_t row_pitch, plane_pitch, P;
-  int N, nb;
+  int N;
   double invd;
+  int64_t ntx, n_tiles, nw;  // tile columns per axis, columns, x3 windows per column
+  int64_t nseg, wps;         // x3 segments per column (one workgroup each), windows per segment
   const double* X;          // positions in bin order
   const uint32_t* offsets;  // [n_bins + 1]
   const uint32_t* orig;     // destination index of each bin-ordered particle, or NULL
@@ -49,14 +57,13 @@ struct InterpArgs {
   int out_f64;
   const void* coef;         // device KernelTables
   float scale[3];
-  int64_t n_bins;
 };
 hipError_t launch_interp(int storage, int I, const InterpArgs& a, hipStream_t s);
 
 // step.hip
 enum UpdateKind { kEulerOrPredict = 0, kHeunCorrect = 1, kAB2 = 2 };
 hipError_t launch_update(int kind, int vel_f64, const double* X, const void* ka, const void* kb, double dt,
-                         int64_t n, double* Xout, uint32_t* keys, int N, double invd, int B, int nb,
+                         int64_t n, double* Xout, uint32_t* keys, int N, double invd, const BinGeom& g,
                          int* flag, hipStream_t s);
 
 }  // namespace ptk

@@ -15,7 +15,7 @@ template <typename V>
 __global__ __launch_bounds__(256) void k_update(int kind, const double* __restrict__ X, const V* __restrict__ ka,
                                                 const V* __restrict__ kb, double dt, int64_t n,
                                                 double* __restrict__ Xout, uint32_t* __restrict__ keys, int N,
-                                                double invd, int B, int nb, int* __restrict__ flag) {
+                                                double invd, BinGeom g, int* __restrict__ flag) {
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   int c[3];
@@ -43,20 +43,20 @@ __global__ __launch_bounds__(256) void k_update(int kind, const double* __restri
     Xout[3 * i + d] = y;
   }
   if (!ok) flag[0] = 1;
-  keys[i] = bin_key(c[0], c[1], c[2], B, nb);
+  keys[i] = bin_key(c[0], c[1], c[2], g);
 }
 
 hipError_t launch_update(int kind, int vel_f64, const double* X, const void* ka, const void* kb, double dt,
-                         int64_t n, double* Xout, uint32_t* keys, int N, double invd, int B, int nb,
+                         int64_t n, double* Xout, uint32_t* keys, int N, double invd, const BinGeom& g,
                          int* flag, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n + 255) / 256);
   if (vel_f64)
     k_update<double><<<blocks, 256, 0, s>>>(kind, X, (const double*)ka, (const double*)kb, dt, n, Xout, keys,
-                                            N, invd, B, nb, flag);
+                                            N, invd, g, flag);
   else
     k_update<float><<<blocks, 256, 0, s>>>(kind, X, (const float*)ka, (const float*)kb, dt, n, Xout, keys, N,
-                                           invd, B, nb, flag);
+                                           invd, g, flag);
   return hipGetLastError();
 }
 

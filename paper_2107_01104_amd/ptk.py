@@ -52,7 +52,8 @@ lib.ptk_locate.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
 lib.ptk_interpolate.argtypes = [_vp, _vp, _i64, _vp, _int, _vp]
 lib.ptk_interpolate_gradient.argtypes = [_vp, _vp, _i64, _vp, _vp, _int, _vp]
 lib.ptk_advance_particles.argtypes = [_vp, _vp, _i64, _vp, ctypes.POINTER(_int), _int, _dbl, _int, _vp, _vp]
-lib.ptk_binning_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int)]
+lib.ptk_binning_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int),
+                                 ctypes.POINTER(_int)]
 lib.ptk_get_binning.argtypes = [_vp, _vp, _vp, _vp]
 lib.ptk_timing_enable.argtypes = [_vp, _int]
 lib.ptk_timing_read.argtypes = [_vp, _vp, _vp]
@@ -213,12 +214,14 @@ class Context:
         return hl.value
 
     def binning(self):
-        np_, nb, be = _i64(), _i64(), _int()
-        self._check(lib.ptk_binning_info(self._h, ctypes.byref(np_), ctypes.byref(nb), ctypes.byref(be)))
+        """(perm, offsets, tile, window) of the last interpolate call."""
+        np_, nb, tile, win = _i64(), _i64(), _int(), _int()
+        self._check(lib.ptk_binning_info(self._h, ctypes.byref(np_), ctypes.byref(nb), ctypes.byref(tile),
+                                         ctypes.byref(win)))
         perm = torch.empty(max(np_.value, 1), dtype=torch.int32, device=self.device)
         off = torch.empty(nb.value + 1, dtype=torch.int32, device=self.device)
         self._check(lib.ptk_get_binning(self._h, _ptr(perm), _ptr(off), _stream(self.device)))
-        return perm[: np_.value], off, be.value
+        return perm[: np_.value], off, tile.value, win.value
 
     def timing(self, enable: bool):
         self._check(lib.ptk_timing_enable(self._h, int(bool(enable))))

@@ -109,12 +109,29 @@ def test_binning_bit_exact(ptk, N, Np):
     Xd = torch.from_numpy(X).to(DEV)
     out = ctx.interpolate(Xd)
     torch.cuda.synchronize()
-    perm, off, B = ctx.binning()
-    keys = geometry.bin_keys(X, N, B)
-    nb = geometry.n_bins_per_axis(N, B)
-    assert off.numel() == nb ** 3 + 1
+    perm, off, T, W = ctx.binning()
+    assert (T, W) == (16, 4)
+    keys = geometry.bin_keys(X, N, T, W)
+    nbins = geometry.n_bins(N, T, W)
+    assert off.numel() == nbins + 1
     assert np.array_equal(perm.cpu().numpy().astype(np.int64), geometry.stable_order(keys))
-    assert np.array_equal(off.cpu().numpy().astype(np.int64), geometry.offsets_from_keys(keys, nb ** 3))
+    assert np.array_equal(off.cpu().numpy().astype(np.int64), geometry.offsets_from_keys(keys, nbins))
+    ctx.close()
+
+
+def test_binning_bit_exact_f64_tiles(ptk):
+    say("[binning f64 tiles]")
+    N, Np = 40, 50001
+    ctx = ptk.Context(0)
+    ctx.set_field(torch.zeros((N, N, N, 3), dtype=torch.float64, device=DEV), K.LAGRANGE, 4, storage=ptk.F64)
+    X = np.random.default_rng(3).uniform(-L, 2 * L, (Np, 3))
+    ctx.interpolate(torch.from_numpy(X).to(DEV), out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    perm, off, T, W = ctx.binning()
+    assert (T, W) == (8, 4)
+    keys = geometry.bin_keys(X, N, T, W)
+    assert np.array_equal(perm.cpu().numpy().astype(np.int64), geometry.stable_order(keys))
+    assert np.array_equal(off.cpu().numpy().astype(np.int64), geometry.offsets_from_keys(keys, geometry.n_bins(N, T, W)))
     ctx.close()
 
 
@@ -137,7 +154,7 @@ def test_interp_f64_matches_oracle(ptk, f0, fam, I, m):
 
 
 @pytest.mark.parametrize("fam,I,m", [(K.LAGRANGE, 4, 0), (K.SPLINE, 6, 1), (K.SPLINE, 8, 2)])
-@pytest.mark.parametrize("N", [8, 12, 40])
+@pytest.mark.parametrize("N", [8, 12, 40, 70])
 def test_interp_f64_small_and_ragged_grids(ptk, fam, I, m, N):
     say(f"[interp f64 ragged] N={N} I={I}")
     rng = np.random.default_rng(N + I)

@@ -95,17 +95,21 @@ def test_wrap_range():
 
 def test_keys_order_offsets_against_naive():
     rng = np.random.default_rng(11)
-    for N, B, Np in [(8, 8, 50), (9, 8, 200), (32, 8, 3000), (24, 4, 1000)]:
+    for N, T, W, Np in [(8, 8, 4, 50), (9, 16, 4, 200), (32, 16, 4, 3000), (24, 8, 4, 1000), (40, 16, 4, 700)]:
         X = rng.uniform(-L, 2 * L, (Np, 3))
-        keys = G.bin_keys(X, N, B)
-        nb = G.n_bins_per_axis(N, B)
-        # naive key from per-axis scalar cells
+        keys = G.bin_keys(X, N, T, W)
+        ntx, nw = -(-N // T), -(-N // W)
+        nbins = G.n_bins(N, T, W)
+        assert nbins == ntx * ntx * nw
+        # naive key from per-axis scalar cells: column (x2 tile, x1 tile), then x3 window
         for p in range(0, Np, 37):
             cs = [G.cell_and_offset_scalar(float(X[p, d]), N)[0] for d in range(3)]
-            assert keys[p] == ((cs[2] // B) * nb + cs[1] // B) * nb + cs[0] // B
+            column = (cs[1] // T) * ntx + cs[0] // T
+            assert keys[p] == column * nw + cs[2] // W
+            assert 0 <= keys[p] < nbins
         perm = G.stable_order(keys)
         assert list(perm) == G.naive_stable_order(keys)
-        off = G.offsets_from_keys(keys, nb ** 3)
-        assert off[0] == 0 and off[-1] == Np and len(off) == nb ** 3 + 1
-        for b in range(nb ** 3):
+        off = G.offsets_from_keys(keys, nbins)
+        assert off[0] == 0 and off[-1] == Np and len(off) == nbins + 1
+        for b in range(nbins):
             assert off[b + 1] - off[b] == sum(1 for k in keys if k == b)
