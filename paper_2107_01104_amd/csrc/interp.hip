@@ -6,21 +6,20 @@
 // (x1, x2), a run of x3 -- and sweeps it along x3, the paper's slice
 // direction, in windows of W = 4 cell layers.  Particles are binned by (tile,
 // window) with x3 fastest, so a window's particles are contiguous.  The
-// (T+I-1)^2 halo nodes of every x3 plane live in a 16-slot LDS ring; each plane
-// is read from HBM once per tile column (halo over-fetch ((T+I-1)/T)^2 = 2.07
-// for T = 16, I = 8) and the next window's planes are loaded into registers
-// while the current window is computed.
+// (T+I-1)^2 halo nodes of the W+I-1 x3 planes a window touches live in an LDS
+// ring; each plane is read from HBM once per tile column (halo over-fetch
+// ((T+I-1)/T)^2, 2.5 for T = 12, I = 8), and the planes the next window adds
+// are loaded into registers while the current window is computed.  The ring is
+// small enough for two workgroups per CU (16 waves) to hide latency.
 //
 // Per particle: a group of 16 lanes.  Lane j = lane & 7 owns the x1 node
-// offset j; the two half-rows split the x3 planes (half h takes i3 in
-// [h I/2, (h+1) I/2)).  Each lane contracts x2 for each of its planes and x3
-// over its half, scales by its x1 weight, and the group sums over its 16
-// lanes with DPP: the paper's split of the triple sum into partial sums
-// finished along the remaining direction (Sec. 3.3), inside one wavefront.
-// The LDS plane pitch is 32 mod 64 bytes, so the two half-rows (4 planes apart)
-// of a quarter-wave read disjoint banks; each half reads 8 consecutive
-// 16-byte nodes, so every ds_read_b128 of a quarter-wave touches all 64 banks
-// once.
+// offset j; the two half-rows split the x2 rows (half h takes i2 in
+// [h I/2, (h+1) I/2)).  Each lane contracts x2 over its rows for every plane,
+// then x3, scales by its x1 weight, and the group sums over its 16 lanes with
+// DPP: the paper's split of the triple sum into partial sums finished along
+// the remaining direction (Sec. 3.3), inside one wavefront.  LDS rows are
+// padded to a pitch of 32 mod 64 bytes, so the two half-rows of a quarter-wave
+// (I/2 rows apart) read complementary halves of the 64 banks.
 //
 // Weights: every lane evaluates its own node of beta (and beta') by Horner from
 // its row of the coefficient table; the group shares them with DPP
@@ -63,16 +62,15 @@ struct Geom {
   static constexpr int T = StoreT<ST>::T;
   static constexpr int TX = T + I - 1;                   // halo tile edge in nodes
   static constexpr int NB = StoreT<ST>::NB;
-  static constexpr int RAW = TX * TX * NB;
-  static constexpr int PP = RAW + ((32 - RAW % 64) + 64) % 64;  // plane pitch, = 32 mod 64
-  static constexpr int R = 16;                            // ring slots
-  static constexpr int LDS = R * PP;
+  static constexpr int RP = TX * NB + ((32 - (TX * NB) % 64) + 64) % 64;  // row pitch, = 32 mod 64
+  static constexpr int PL = TX * RP;                      // plane bytes
+  static constexpr int R = kWindow + I - 1;               // ring slots: the planes one window touches
+  static constexpr int LDS = R * PL;
   static constexpr int G = 48 / StoreT<ST>::GB;           // nodes per 48-byte chunk
   static constexpr int RG = (TX + G - 1) / G;             // chunks per halo row
   static constexpr int UNITS_PER_PLANE = TX * RG;
   static constexpr int THREADS = StoreT<ST>::THREADS;
   static constexpr int PRE = (kWindow * UNITS_PER_PLANE + THREADS - 1) / THREADS;  // chunks per thread
-  static_assert(kWindow + I - 1 <= R - kWindow, "ring too small for the prefetch window");
 };
 
 // ---- DPP helpers (rows of 16 lanes = one particle group)
@@ -128,8 +126,9 @@ __device__ __forceinline__ void lds_put(unsigned char* smem, int off, const uint
   }
 }
 
-// read a node; the unused fourth word is kept alive until `keep` so the
-// compiler issues one full 16-byte read (ds_read_b128) instead of a slower b96
+// read a node; the caller consumes the unused fourth word (`keep`) in an empty
+// asm statement so the compiler issues one full 16-byte read (ds_read_b128)
+// instead of a slower b96
 template <int ST, typename V>
 __device__ __forceinline__ void lds_get(const unsigned char* smem, int off, V* v, uint32_t& keep) {
   if constexpr (ST == ST_F32) {
@@ -195,78 +194,76 @@ __device__ __forceinline__ void store_unit(unsigned char* smem, int64_t zp, int 
   const int r = u / Gm::RG;
   const uint32_t w[12] = {c[0].x, c[0].y, c[0].z, c[0].w, c[1].x, c[1].y,
                           c[1].z, c[1].w, c[2].x, c[2].y, c[2].z, c[2].w};
-  const int slot = (int)(zp & (Gm::R - 1));
+  const int slot = (int)(zp % Gm::R);
 #pragma unroll
   for (int q = 0; q < Gm::G; ++q) {
     const int x = g * Gm::G + q;
-    if (x < Gm::TX) lds_put<ST>(smem, slot * Gm::PP + (r * Gm::TX + x) * Gm::NB, w, q);
+    if (x < Gm::TX) lds_put<ST>(smem, slot * Gm::PL + r * Gm::RP + x * Gm::NB, w, q);
   }
 }
 
-// One particle: 16 lanes (this lane owns x1 offset j and plane half h).
-// Accumulates the 3 values (and 9 gradient entries) summed over the group.
+// One particle: 16 lanes (this lane owns x1 offset j and row half h).
+// Leaves in r the 3 values (and 9 gradient entries) summed over the group.
 template <int ST, int I, bool GRAD, typename V>
 __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V* cv, const V* cd, int j, int jj,
                                               int h, V t1, V t2, V t3, int l1, int l2, int z3, V* r) {
   using Gm = Geom<ST, I>;
-  constexpr int TX = Gm::TX, NB = Gm::NB, PP = Gm::PP, R = Gm::R;
+  constexpr int NB = Gm::NB, RP = Gm::RP, PL = Gm::PL, R = Gm::R;
   constexpr int HALF = I / 2;
-  // weights: half 0 evaluates beta_j(t2), half 1 beta_j(t3); all lanes beta_j(t1)
+  // weights: lanes 0-7 evaluate beta_j(t2), lanes 8-15 beta_j(t3); all lanes beta_j(t1)
   const V tsel = h ? t3 : t2;
   const V wsel = horner<I>(cv, tsel);
   V w1 = horner<I>(cv, t1);
   if (j >= I) w1 = (V)0;
-  V w2[I], w3[HALF];
-#define PTK_B2(k) if constexpr ((k) < I) w2[k] = bcast<k>(wsel);
-  PTK_B2(0) PTK_B2(1) PTK_B2(2) PTK_B2(3) PTK_B2(4) PTK_B2(5) PTK_B2(6) PTK_B2(7)
+  V w2[HALF], w3[I];
+#define PTK_B2(k) if constexpr ((k) < HALF) { const V lo = bcast<(k)>(wsel), hi = bcast<HALF + (k)>(wsel); w2[k] = h ? hi : lo; }
+  PTK_B2(0) PTK_B2(1) PTK_B2(2) PTK_B2(3)
 #undef PTK_B2
-#define PTK_B3(k) if constexpr ((k) < HALF) { const V lo = bcast<8 + (k)>(wsel), hi = bcast<8 + HALF + (k)>(wsel); w3[k] = h ? hi : lo; }
-  PTK_B3(0) PTK_B3(1) PTK_B3(2) PTK_B3(3)
+#define PTK_B3(k) if constexpr ((k) < I) w3[k] = bcast<8 + (k)>(wsel);
+  PTK_B3(0) PTK_B3(1) PTK_B3(2) PTK_B3(3) PTK_B3(4) PTK_B3(5) PTK_B3(6) PTK_B3(7)
 #undef PTK_B3
-  V d1 = (V)0, dw2[I], dw3[HALF];
+  V d1 = (V)0, dw2[HALF], dw3[I];
   if constexpr (GRAD) {
     const V dsel = horner<I - 1>(cd, tsel);
     d1 = horner<I - 1>(cd, t1);
     if (j >= I) d1 = (V)0;
-#define PTK_D2(k) if constexpr ((k) < I) dw2[k] = bcast<k>(dsel);
-    PTK_D2(0) PTK_D2(1) PTK_D2(2) PTK_D2(3) PTK_D2(4) PTK_D2(5) PTK_D2(6) PTK_D2(7)
+#define PTK_D2(k) if constexpr ((k) < HALF) { const V lo = bcast<(k)>(dsel), hi = bcast<HALF + (k)>(dsel); dw2[k] = h ? hi : lo; }
+    PTK_D2(0) PTK_D2(1) PTK_D2(2) PTK_D2(3)
 #undef PTK_D2
-#define PTK_D3(k) if constexpr ((k) < HALF) { const V lo = bcast<8 + (k)>(dsel), hi = bcast<8 + HALF + (k)>(dsel); dw3[k] = h ? hi : lo; }
-    PTK_D3(0) PTK_D3(1) PTK_D3(2) PTK_D3(3)
+#define PTK_D3(k) if constexpr ((k) < I) dw3[k] = bcast<8 + (k)>(dsel);
+    PTK_D3(0) PTK_D3(1) PTK_D3(2) PTK_D3(3) PTK_D3(4) PTK_D3(5) PTK_D3(6) PTK_D3(7)
 #undef PTK_D3
   }
-  // contraction: x2 per plane, x3 over this half's planes
-  const int noff = ((l2 * TX) + l1 + jj) * NB;
+  // contraction: x2 over this half's rows per plane, then x3 over all planes
+  const int noff = (l2 + h * HALF) * RP + (l1 + jj) * NB;
+  const int s0 = z3 % R;
   V acc[3] = {0, 0, 0}, ad2[3] = {0, 0, 0}, ad3[3] = {0, 0, 0};
-  uint32_t keep[HALF][I];
 #pragma unroll
-  for (int kk = 0; kk < HALF; ++kk) {
-    const int slot = (z3 + h * HALF + kk) & (R - 1);
-    const int base = slot * PP + noff;
+  for (int k = 0; k < I; ++k) {
+    const int slot = s0 + k < R ? s0 + k : s0 + k - R;
+    const int base = slot * PL + noff;
     V s[3] = {0, 0, 0}, sd[3] = {0, 0, 0};
 #pragma unroll
-    for (int i2 = 0; i2 < I; ++i2) {
+    for (int rr = 0; rr < HALF; ++rr) {
       V v[3];
-      lds_get<ST>(smem, base + i2 * TX * NB, v, keep[kk][i2]);
+      uint32_t keep;
+      lds_get<ST>(smem, base + rr * RP, v, keep);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        s[q] = fma(w2[i2], v[q], s[q]);
-        if constexpr (GRAD) sd[q] = fma(dw2[i2], v[q], sd[q]);
+        s[q] = fma(w2[rr], v[q], s[q]);
+        if constexpr (GRAD) sd[q] = fma(dw2[rr], v[q], sd[q]);
       }
+      asm volatile("" ::"v"(keep));  // the unused word ends here: the read stays 16 bytes wide
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      acc[q] = fma(w3[kk], s[q], acc[q]);
+      acc[q] = fma(w3[k], s[q], acc[q]);
       if constexpr (GRAD) {
-        ad3[q] = fma(dw3[kk], s[q], ad3[q]);
-        ad2[q] = fma(w3[kk], sd[q], ad2[q]);
+        ad3[q] = fma(dw3[k], s[q], ad3[q]);
+        ad2[q] = fma(w3[k], sd[q], ad2[q]);
       }
     }
   }
-#pragma unroll
-  for (int kk = 0; kk < HALF; ++kk)
-#pragma unroll
-    for (int i2 = 0; i2 < I; ++i2) asm volatile("" ::"v"(keep[kk][i2]));
   // x1 weight, then the sum over the group's 16 lanes
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -283,7 +280,7 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
 }
 
 template <int ST, int I, bool GRAD>
-__global__ __launch_bounds__(StoreT<ST>::THREADS) void k_interp(InterpArgs a) {
+__global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a) {
   using V = typename StoreT<ST>::acc;
   using Gm = Geom<ST, I>;
   constexpr int T = Gm::T;
@@ -291,7 +288,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS) void k_interp(InterpArgs a) {
   constexpr int NT = Gm::THREADS;
   constexpr int GROUPS = NT / 16;        // particles per round
   constexpr int NV = GRAD ? 12 : 3;
-  constexpr int CH = 4 * GROUPS;         // particles located per chunk (4 rounds)
+  constexpr int CH = 2 * GROUPS;         // particles located per chunk (2 rounds)
   // particle record: t1, t2, t3 (V) at 0; cells l1, l2, z3 (u16) at 32;
   // destination index (u32) at 40
   constexpr int RECB = 48;
@@ -418,34 +415,38 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS) void k_interp(InterpArgs a) {
         const int l1 = (int)(lc.x & 0xFFFFu), l2 = (int)(lc.x >> 16), z3 = (int)(lc.y & 0xFFFFu);
         V r[NV];
         particle_sums<ST, I, GRAD>(smem, cv, cd, j, jj, h, t1, t2, t3, l1, l2, z3, r);
-        if (active) {
-          const int64_t q = (int64_t)lc.z;
+        // lane e < NV writes result e: select it without branches
+        V val = r[0];
 #pragma unroll
-          for (int e = 0; e < NV; ++e) {
-            if (e != l16) continue;
-            if (e < 3) {
-              if (!a.out) continue;
-              V val = r[e];
-              if constexpr (ST == ST_BF16 || ST == ST_F16) val *= (V)a.scale[e];
+        for (int e = 1; e < NV; ++e) val = (l16 == e) ? r[e] : val;
+        if (active && l16 < NV) {
+          const int64_t q = (int64_t)lc.z;
+          if (l16 < 3) {
+            if (ST == ST_BF16 || ST == ST_F16)
+              val *= (V)(l16 == 0 ? a.scale[0] : l16 == 1 ? a.scale[1] : a.scale[2]);
+            if (a.out) {
               if (a.out_f64)
-                ((double*)a.out)[3 * q + e] = (double)val;
+                ((double*)a.out)[3 * q + l16] = (double)val;
               else
-                ((float*)a.out)[3 * q + e] = (float)val;
-            } else {
-              V val = r[e] * (V)invd;
-              if constexpr (ST == ST_BF16 || ST == ST_F16) val *= (V)a.scale[(e - 3) / 3];
-              if (a.out_f64)
-                ((double*)a.grad)[9 * q + (e - 3)] = (double)val;
-              else
-                ((float*)a.grad)[9 * q + (e - 3)] = (float)val;
+                ((float*)a.out)[3 * q + l16] = (float)val;
             }
+          } else {
+            val *= (V)invd;
+            if (ST == ST_BF16 || ST == ST_F16)
+              val *= (V)(l16 < 6 ? a.scale[0] : l16 < 9 ? a.scale[1] : a.scale[2]);
+            if (a.out_f64)
+              ((double*)a.grad)[9 * q + (l16 - 3)] = (double)val;
+            else
+              ((float*)a.grad)[9 * q + (l16 - 3)] = (float)val;
           }
         }
       }
       if ((int64_t)c0 + CH >= (int64_t)end) break;
     }
 
-    // planes of the next window go into ring slots this window does not read
+    // the ring holds exactly the planes one window touches: the next window's
+    // new planes replace this window's first W planes once every wave is done
+    __syncthreads();
     if (more) {
 #pragma unroll
       for (int k = 0; k < Gm::PRE; ++k) {
@@ -456,7 +457,6 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS) void k_interp(InterpArgs a) {
         }
       }
     }
-    __syncthreads();
   }
 }
 

@@ -110,7 +110,7 @@ def test_binning_bit_exact(ptk, N, Np):
     out = ctx.interpolate(Xd)
     torch.cuda.synchronize()
     perm, off, T, W = ctx.binning()
-    assert (T, W) == (16, 4)
+    assert (T, W) == (12, 4)
     keys = geometry.bin_keys(X, N, T, W)
     nbins = geometry.n_bins(N, T, W)
     assert off.numel() == nbins + 1
