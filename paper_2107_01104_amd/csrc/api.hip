@@ -268,6 +268,7 @@ int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* gr
   }
   InterpArgs a = base_args(c);
   a.X = (const double*)c->xs.ptr;
+  a.np = Np;
   a.orig = perm;
   a.out = u_out;
   a.grad = grad;
@@ -582,6 +583,7 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     {
       InterpArgs a = base_args(c);
       a.X = xs;
+      a.np = Np;
       a.out = k1;
       a.grad = grad_out ? c->gint.ptr : nullptr;
       a.out_f64 = vf64;
@@ -606,6 +608,7 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
       {
         InterpArgs b = base_args(c);
         b.X = xp;
+        b.np = Np;
         b.orig = pp;
         b.out = k2;
         b.out_f64 = vf64;

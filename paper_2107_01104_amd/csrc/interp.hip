@@ -13,13 +13,14 @@
 // small enough for two workgroups per CU (16 waves) to hide latency.
 //
 // Per particle: a group of 16 lanes.  Lane j = lane & 7 owns the x1 node
-// offset j; the two half-rows split the x2 rows (half h takes i2 in
-// [h I/2, (h+1) I/2)).  Each lane contracts x2 over its rows for every plane,
-// then x3, scales by its x1 weight, and the group sums over its 16 lanes with
+// offset j; the two half-rows split the particle's I planes by ring-slot
+// parity (the ring has an even number of slots, so consecutive planes
+// alternate).  Each lane contracts x2 for each of its planes and x3 over
+// them, scales by its x1 weight, and the group sums over its 16 lanes with
 // DPP: the paper's split of the triple sum into partial sums finished along
-// the remaining direction (Sec. 3.3), inside one wavefront.  LDS rows are
-// padded to a pitch of 32 mod 64 bytes, so the two half-rows of a quarter-wave
-// (I/2 rows apart) read complementary halves of the 64 banks.
+// the remaining direction (Sec. 3.3), inside one wavefront.  The plane pitch
+// is 128 mod 256 bytes, so the two half-rows of a quarter-wave -- an odd
+// number of planes apart -- read complementary halves of the 64 banks.
 //
 // Weights: every lane evaluates its own node of beta (and beta') by Horner from
 // its row of the coefficient table; the group shares them with DPP
@@ -62,9 +63,9 @@ struct Geom {
   static constexpr int T = StoreT<ST>::T;
   static constexpr int TX = T + I - 1;                   // halo tile edge in nodes
   static constexpr int NB = StoreT<ST>::NB;
-  static constexpr int RP = TX * NB + ((32 - (TX * NB) % 64) + 64) % 64;  // row pitch, = 32 mod 64
-  static constexpr int PL = TX * RP;                      // plane bytes
-  static constexpr int R = kWindow + I - 1;               // ring slots: the planes one window touches
+  static constexpr int RP = TX * NB;                      // row pitch
+  static constexpr int PL = TX * RP + ((128 - (TX * RP) % 256) + 256) % 256;  // plane pitch, = 128 mod 256
+  static constexpr int R = (kWindow + I - 1 + 1) / 2 * 2;  // ring slots (even): the planes one window touches
   static constexpr int LDS = R * PL;
   static constexpr int G = 48 / StoreT<ST>::GB;           // nodes per 48-byte chunk
   static constexpr int RG = (TX + G - 1) / G;             // chunks per halo row
@@ -73,30 +74,24 @@ struct Geom {
   static constexpr int PRE = (kWindow * UNITS_PER_PLANE + THREADS - 1) / THREADS;  // chunks per thread
 };
 
-// ---- DPP helpers (rows of 16 lanes = one particle group)
+// ---- DPP helpers (rows of 16 lanes = one particle group).  Every control
+// used here reads a lane of the same row, so no lane keeps an old value and
+// the moves need no initialised destination.
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ int dppi(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
   const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 // value of lane L of this row
 template <int L, typename V>
 __device__ __forceinline__ V bcast(V v) {
   return dpp<0x150 + L>(v);
-}
-template <int L>
-__device__ __forceinline__ int bcasti(int v) {
-  return dppi<0x150 + L>(v);
 }
 // sum over the 16 lanes of the row (every lane gets the total)
 template <typename V>
@@ -202,7 +197,8 @@ __device__ __forceinline__ void store_unit(unsigned char* smem, int64_t zp, int 
   }
 }
 
-// One particle: 16 lanes (this lane owns x1 offset j and row half h).
+// One particle: 16 lanes (this lane owns x1 offset j and the planes whose ring
+// slot has parity h).
 // Leaves in r the 3 values (and 9 gradient entries) summed over the group.
 template <int ST, int I, bool GRAD, typename V>
 __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V* cv, const V* cd, int j, int jj,
@@ -210,57 +206,59 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
   using Gm = Geom<ST, I>;
   constexpr int NB = Gm::NB, RP = Gm::RP, PL = Gm::PL, R = Gm::R;
   constexpr int HALF = I / 2;
+  // planes of this lane: k = 2m + par, m = 0..I/2-1 (slot (z3 + k) mod R has parity h)
+  const int par = (z3 + h) & 1;
   // weights: lanes 0-7 evaluate beta_j(t2), lanes 8-15 beta_j(t3); all lanes beta_j(t1)
   const V tsel = h ? t3 : t2;
   const V wsel = horner<I>(cv, tsel);
   V w1 = horner<I>(cv, t1);
   if (j >= I) w1 = (V)0;
-  V w2[HALF], w3[I];
-#define PTK_B2(k) if constexpr ((k) < HALF) { const V lo = bcast<(k)>(wsel), hi = bcast<HALF + (k)>(wsel); w2[k] = h ? hi : lo; }
-  PTK_B2(0) PTK_B2(1) PTK_B2(2) PTK_B2(3)
+  V w2[I], w3[HALF];
+#define PTK_B2(k) if constexpr ((k) < I) w2[k] = bcast<k>(wsel);
+  PTK_B2(0) PTK_B2(1) PTK_B2(2) PTK_B2(3) PTK_B2(4) PTK_B2(5) PTK_B2(6) PTK_B2(7)
 #undef PTK_B2
-#define PTK_B3(k) if constexpr ((k) < I) w3[k] = bcast<8 + (k)>(wsel);
-  PTK_B3(0) PTK_B3(1) PTK_B3(2) PTK_B3(3) PTK_B3(4) PTK_B3(5) PTK_B3(6) PTK_B3(7)
+#define PTK_B3(m) if constexpr ((m) < HALF) { const V e = bcast<8 + 2 * (m)>(wsel), o = bcast<9 + 2 * (m)>(wsel); w3[m] = par ? o : e; }
+  PTK_B3(0) PTK_B3(1) PTK_B3(2) PTK_B3(3)
 #undef PTK_B3
-  V d1 = (V)0, dw2[HALF], dw3[I];
+  V d1 = (V)0, dw2[I], dw3[HALF];
   if constexpr (GRAD) {
     const V dsel = horner<I - 1>(cd, tsel);
     d1 = horner<I - 1>(cd, t1);
     if (j >= I) d1 = (V)0;
-#define PTK_D2(k) if constexpr ((k) < HALF) { const V lo = bcast<(k)>(dsel), hi = bcast<HALF + (k)>(dsel); dw2[k] = h ? hi : lo; }
-    PTK_D2(0) PTK_D2(1) PTK_D2(2) PTK_D2(3)
+#define PTK_D2(k) if constexpr ((k) < I) dw2[k] = bcast<k>(dsel);
+    PTK_D2(0) PTK_D2(1) PTK_D2(2) PTK_D2(3) PTK_D2(4) PTK_D2(5) PTK_D2(6) PTK_D2(7)
 #undef PTK_D2
-#define PTK_D3(k) if constexpr ((k) < I) dw3[k] = bcast<8 + (k)>(dsel);
-    PTK_D3(0) PTK_D3(1) PTK_D3(2) PTK_D3(3) PTK_D3(4) PTK_D3(5) PTK_D3(6) PTK_D3(7)
+#define PTK_D3(m) if constexpr ((m) < HALF) { const V e = bcast<8 + 2 * (m)>(dsel), o = bcast<9 + 2 * (m)>(dsel); dw3[m] = par ? o : e; }
+    PTK_D3(0) PTK_D3(1) PTK_D3(2) PTK_D3(3)
 #undef PTK_D3
   }
-  // contraction: x2 over this half's rows per plane, then x3 over all planes
-  const int noff = (l2 + h * HALF) * RP + (l1 + jj) * NB;
-  const int s0 = z3 % R;
+  // contraction: x2 over all rows per plane, x3 over this lane's planes
+  const int noff = l2 * RP + (l1 + jj) * NB;
+  const int s0 = (z3 + par) % R;
   V acc[3] = {0, 0, 0}, ad2[3] = {0, 0, 0}, ad3[3] = {0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < I; ++k) {
-    const int slot = s0 + k < R ? s0 + k : s0 + k - R;
+  for (int m = 0; m < HALF; ++m) {
+    const int slot = s0 + 2 * m < R ? s0 + 2 * m : s0 + 2 * m - R;
     const int base = slot * PL + noff;
     V s[3] = {0, 0, 0}, sd[3] = {0, 0, 0};
 #pragma unroll
-    for (int rr = 0; rr < HALF; ++rr) {
+    for (int i2 = 0; i2 < I; ++i2) {
       V v[3];
       uint32_t keep;
-      lds_get<ST>(smem, base + rr * RP, v, keep);
+      lds_get<ST>(smem, base + i2 * RP, v, keep);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        s[q] = fma(w2[rr], v[q], s[q]);
-        if constexpr (GRAD) sd[q] = fma(dw2[rr], v[q], sd[q]);
+        s[q] = fma(w2[i2], v[q], s[q]);
+        if constexpr (GRAD) sd[q] = fma(dw2[i2], v[q], sd[q]);
       }
       asm volatile("" ::"v"(keep));  // the unused word ends here: the read stays 16 bytes wide
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      acc[q] = fma(w3[k], s[q], acc[q]);
+      acc[q] = fma(w3[m], s[q], acc[q]);
       if constexpr (GRAD) {
-        ad3[q] = fma(dw3[k], s[q], ad3[q]);
-        ad2[q] = fma(w3[k], sd[q], ad2[q]);
+        ad3[q] = fma(dw3[m], s[q], ad3[q]);
+        ad2[q] = fma(w3[m], sd[q], ad2[q]);
       }
     }
   }
@@ -288,7 +286,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
   constexpr int NT = Gm::THREADS;
   constexpr int GROUPS = NT / 16;        // particles per round
   constexpr int NV = GRAD ? 12 : 3;
-  constexpr int CH = 2 * GROUPS;         // particles located per chunk (2 rounds)
+  constexpr int CH = NT / 3 / GROUPS * GROUPS;  // particles located per chunk: one thread per coordinate
   // particle record: t1, t2, t3 (V) at 0; cells l1, l2, z3 (u16) at 32;
   // destination index (u32) at 40
   constexpr int RECB = 48;
@@ -343,120 +341,175 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
   const int N = a.N;
   const double invd = a.invd;
 
-  uint4 pre[Gm::PRE][3];
-  bool pre_ok[Gm::PRE];
+  // ---- software pipeline over windows: while window w is computed, the
+  // positions of window w+1 and the planes window w+2 adds are in flight
+  // (issued in that order, so each wait only covers older loads).
+  constexpr int DEPTH = GRAD ? 1 : 2;  // windows of plane prefetch
+  uint4 preA[Gm::PRE][3], preB[DEPTH == 2 ? Gm::PRE : 1][3];
+  bool okA[Gm::PRE], okB[DEPTH == 2 ? Gm::PRE : 1];
 
-  for (int64_t w = w_begin; w < w_end; ++w) {
-    const bool more = w + 1 < w_end;
-    const int64_t z_new = W * (w + 1) + I - 1;  // planes the next window adds: [z_new, z_new + W)
+  auto issue_planes = [&](int64_t wn, uint4 (&pre)[Gm::PRE][3], bool (&ok)[Gm::PRE]) {
+    const int64_t zn = W * wn + I - 1;  // planes window wn adds: [zn, zn + W)
+#pragma unroll
+    for (int k = 0; k < Gm::PRE; ++k) {
+      const int uraw = tid + k * NT;
+      const int u = min(uraw, W * Gm::UNITS_PER_PLANE - 1);
+      const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
+      ok[k] = load_unit<ST, I>(a, x0, y0, zn + pl, uu, pre[k]) && uraw < W * Gm::UNITS_PER_PLANE && wn < w_end;
+    }
+  };
+  auto store_planes = [&](int64_t wn, const uint4 (&pre)[Gm::PRE][3], const bool (&ok)[Gm::PRE]) {
+    const int64_t zn = W * wn + I - 1;
+#pragma unroll
+    for (int k = 0; k < Gm::PRE; ++k) {
+      const int u = tid + k * NT;
+      if (ok[k]) {
+        const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
+        store_unit<ST, I>(smem, zn + pl, uu, pre[k]);
+      }
+    }
+  };
+  // position coordinate + destination index of particle c0 + tid/3 (clamped, unconditional)
+  auto issue_pos = [&](uint32_t c0, int n, double& xv, uint32_t& qv) {
+    const int pi = min(tid / 3, max(n - 1, 0));
+    const int64_t p = min((int64_t)c0 + pi, (int64_t)a.np - 1);
+    xv = a.X[3 * p + tid % 3];
+    qv = a.orig ? a.orig[p] : (uint32_t)p;
+  };
+  // steps 1-3 of Sec. 2.2 once per coordinate: one thread per (particle, axis)
+  auto write_rec = [&](int64_t wr, int n, double xv, uint32_t qv) {
+    if (tid < 3 * n) {
+      const int pi = tid / 3, ax = tid % 3;
+      int c;
+      double td;
+      locate(xv, N, invd, &c, &td);
+      int lc;
+      if (ax == 0)
+        lc = min(max(c - (int)x0, 0), T - 1);
+      else if (ax == 1)
+        lc = min(max(c - (int)y0, 0), T - 1);
+      else
+        lc = (int)min(max((int64_t)c, W * wr), W * wr + W - 1);
+      unsigned char* rp = recs + pi * RECB;
+      if constexpr (sizeof(V) == 8)
+        ((double*)rp)[ax] = td;
+      else
+        ((float*)rp)[ax] = (float)td;
+      ((uint16_t*)(rp + 32))[ax] = (uint16_t)lc;
+      if (ax == 0) *(uint32_t*)(rp + 40) = qv;
+    }
+  };
+  auto compute_chunk = [&](int n) {
+    const int wave_grp0 = __builtin_amdgcn_readfirstlane(grp & ~3);  // first group of this wave
+    for (int r0 = 0; r0 < n; r0 += GROUPS) {
+      if (r0 + wave_grp0 >= n) break;  // nothing left for this wave: its SIMD serves other waves
+      const int pi = r0 + grp;
+      const bool active = pi < n;
+      const unsigned char* rp = recs + (active ? pi : n - 1) * RECB;
+      V t1, t2, t3;
+      if constexpr (sizeof(V) == 8) {
+        const double2 ta = *(const double2*)rp;
+        const double2 tb = *(const double2*)(rp + 16);
+        t1 = ta.x;
+        t2 = ta.y;
+        t3 = tb.x;
+      } else {
+        const float4 tf = *(const float4*)rp;
+        t1 = tf.x;
+        t2 = tf.y;
+        t3 = tf.z;
+        asm volatile("" ::"v"(tf.w));  // keep the record reads 16 bytes wide
+      }
+      const uint4 lc = *(const uint4*)(rp + 32);
+      asm volatile("" ::"v"(lc.w));
+      const int l1 = (int)(lc.x & 0xFFFFu), l2 = (int)(lc.x >> 16), z3 = (int)(lc.y & 0xFFFFu);
+      V r[NV];
+      particle_sums<ST, I, GRAD>(smem, cv, cd, j, jj, h, t1, t2, t3, l1, l2, z3, r);
+      // lane e < NV writes result e: select it without branches
+      V val = r[0];
+#pragma unroll
+      for (int e = 1; e < NV; ++e) val = (l16 == e) ? r[e] : val;
+      if (active && l16 < NV) {
+        const int64_t q = (int64_t)lc.z;
+        if (l16 < 3) {
+          if (ST == ST_BF16 || ST == ST_F16)
+            val *= (V)(l16 == 0 ? a.scale[0] : l16 == 1 ? a.scale[1] : a.scale[2]);
+          if (a.out) {
+            if (a.out_f64)
+              ((double*)a.out)[3 * q + l16] = (double)val;
+            else
+              ((float*)a.out)[3 * q + l16] = (float)val;
+          }
+        } else {
+          val *= (V)invd;
+          if (ST == ST_BF16 || ST == ST_F16)
+            val *= (V)(l16 < 6 ? a.scale[0] : l16 < 9 ? a.scale[1] : a.scale[2]);
+          if (a.out_f64)
+            ((double*)a.grad)[9 * q + (l16 - 3)] = (double)val;
+          else
+            ((float*)a.grad)[9 * q + (l16 - 3)] = (float)val;
+        }
+      }
+    }
+  };
+  // one window: records of w are in LDS, the ring holds w's planes.  With a
+  // two-window plane pipeline (value kernels), `cur` holds the planes of w+1
+  // (loaded during the previous window) and `nxt` receives w+2's; with a
+  // one-window pipeline (gradient kernels, which need the registers) `cur`
+  // receives w+1's planes in this window.
+  auto window = [&](int64_t w, uint4 (&cur)[Gm::PRE][3], bool (&cok)[Gm::PRE], uint4 (&nxt)[Gm::PRE][3],
+                    bool (&nok)[Gm::PRE]) {
     const int64_t bin = tile * a.nw + w;
     const uint32_t start = a.offsets[bin], end = a.offsets[bin + 1];
-    bool issued = false;
-    for (uint32_t c0 = start;; c0 += CH) {
-      const int n = (int)min((int64_t)CH, (int64_t)end - (int64_t)c0);
-      if (c0 > start) __syncthreads();  // the previous chunk's records are no longer read
-      // steps 1-3 of Sec. 2.2 once per coordinate: one thread per (particle, axis)
-      if (tid < 3 * n) {
-        const int pi = tid / 3, ax = tid % 3;
-        int c;
-        double td;
-        locate(a.X[3 * ((int64_t)c0 + pi) + ax], N, invd, &c, &td);
-        int lc;
-        if (ax == 0)
-          lc = min(max(c - (int)x0, 0), T - 1);
-        else if (ax == 1)
-          lc = min(max(c - (int)y0, 0), T - 1);
-        else
-          lc = (int)min(max((int64_t)c, W * w), W * w + W - 1);
-        unsigned char* rp = recs + pi * RECB;
-        if constexpr (sizeof(V) == 8)
-          ((double*)rp)[ax] = td;
-        else
-          ((float*)rp)[ax] = (float)td;
-        ((uint16_t*)(rp + 32))[ax] = (uint16_t)lc;
-        if (ax == 0) {
-          const uint32_t p = c0 + (uint32_t)pi;
-          *(uint32_t*)(rp + 40) = a.orig ? a.orig[p] : p;
-        }
-      }
-      // the next window's planes are requested only now, after this chunk's
-      // position loads, so waiting for those never waits for the prefetch
-      if (!issued && more) {
-#pragma unroll
-        for (int k = 0; k < Gm::PRE; ++k) {
-          const int uraw = tid + k * NT;
-          const int u = min(uraw, W * Gm::UNITS_PER_PLANE - 1);
-          const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
-          pre_ok[k] = load_unit<ST, I>(a, x0, y0, z_new + pl, uu, pre[k]) && uraw < W * Gm::UNITS_PER_PLANE;
-        }
-        issued = true;
-      }
+    const bool more = w + 1 < w_end;
+    const uint32_t end1 = more ? a.offsets[bin + 2] : end;
+    const int n1 = (int)min((int64_t)CH, (int64_t)end1 - (int64_t)end);
+    double xv = 0.0;
+    uint32_t qv = 0;
+    if (more && a.np > 0) issue_pos(end, n1, xv, qv);
+    if constexpr (DEPTH == 2)
+      issue_planes(w + 2, nxt, nok);
+    else
+      issue_planes(w + 1, cur, cok);
+    __syncthreads();  // records of w and the ring are complete
+    int n = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
+    compute_chunk(n);
+    // rare: more than CH particles in the window; later chunks are loaded in place
+    for (uint32_t c0 = start + CH; c0 < end; c0 += CH) {
+      const int m = (int)min((int64_t)CH, (int64_t)end - (int64_t)c0);
+      double xm;
+      uint32_t qm;
+      issue_pos(c0, m, xm, qm);
       __syncthreads();
-
-      // ---- this chunk's particles, GROUPS at a time
-      for (int r0 = 0; r0 < n; r0 += GROUPS) {
-        const int pi = r0 + grp;
-        const bool active = pi < n;
-        const unsigned char* rp = recs + (active ? pi : n - 1) * RECB;
-        V t1, t2, t3;
-        if constexpr (sizeof(V) == 8) {
-          const double2 ta = *(const double2*)rp;
-          const double2 tb = *(const double2*)(rp + 16);
-          t1 = ta.x;
-          t2 = ta.y;
-          t3 = tb.x;
-        } else {
-          const float4 tf = *(const float4*)rp;
-          t1 = tf.x;
-          t2 = tf.y;
-          t3 = tf.z;
-        }
-        const uint4 lc = *(const uint4*)(rp + 32);
-        const int l1 = (int)(lc.x & 0xFFFFu), l2 = (int)(lc.x >> 16), z3 = (int)(lc.y & 0xFFFFu);
-        V r[NV];
-        particle_sums<ST, I, GRAD>(smem, cv, cd, j, jj, h, t1, t2, t3, l1, l2, z3, r);
-        // lane e < NV writes result e: select it without branches
-        V val = r[0];
-#pragma unroll
-        for (int e = 1; e < NV; ++e) val = (l16 == e) ? r[e] : val;
-        if (active && l16 < NV) {
-          const int64_t q = (int64_t)lc.z;
-          if (l16 < 3) {
-            if (ST == ST_BF16 || ST == ST_F16)
-              val *= (V)(l16 == 0 ? a.scale[0] : l16 == 1 ? a.scale[1] : a.scale[2]);
-            if (a.out) {
-              if (a.out_f64)
-                ((double*)a.out)[3 * q + l16] = (double)val;
-              else
-                ((float*)a.out)[3 * q + l16] = (float)val;
-            }
-          } else {
-            val *= (V)invd;
-            if (ST == ST_BF16 || ST == ST_F16)
-              val *= (V)(l16 < 6 ? a.scale[0] : l16 < 9 ? a.scale[1] : a.scale[2]);
-            if (a.out_f64)
-              ((double*)a.grad)[9 * q + (l16 - 3)] = (double)val;
-            else
-              ((float*)a.grad)[9 * q + (l16 - 3)] = (float)val;
-          }
-        }
-      }
-      if ((int64_t)c0 + CH >= (int64_t)end) break;
+      write_rec(w, m, xm, qm);
+      __syncthreads();
+      compute_chunk(m);
     }
+    __syncthreads();  // every read of this window's ring slots and records is done
+    // the ring holds at least the planes one window touches: w+1's new planes
+    // replace planes no later window reads; then w+1's records
+    store_planes(w + 1, cur, cok);
+    if (more) write_rec(w + 1, n1, xv, qv);
+  };
 
-    // the ring holds exactly the planes one window touches: the next window's
-    // new planes replace this window's first W planes once every wave is done
-    __syncthreads();
-    if (more) {
-#pragma unroll
-      for (int k = 0; k < Gm::PRE; ++k) {
-        const int u = tid + k * NT;
-        if (pre_ok[k]) {
-          const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
-          store_unit<ST, I>(smem, z_new + pl, uu, pre[k]);
-        }
-      }
+  // ---- prologue: records of the first window, planes of the second in flight
+  {
+    const int64_t bin = tile * a.nw + w_begin;
+    const uint32_t start = a.offsets[bin], end = a.offsets[bin + 1];
+    const int n0 = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
+    double xv = 0.0;
+    uint32_t qv = 0;
+    if (a.np > 0) issue_pos(start, n0, xv, qv);
+    write_rec(w_begin, n0, xv, qv);
+  }
+  if constexpr (DEPTH == 2) {
+    issue_planes(w_begin + 1, preA, okA);
+    for (int64_t w = w_begin; w < w_end; w += 2) {
+      window(w, preA, okA, preB, okB);
+      if (w + 1 < w_end) window(w + 1, preB, okB, preA, okA);
     }
+  } else {
+    for (int64_t w = w_begin; w < w_end; ++w) window(w, preA, okA, preA, okA);
   }
 }
 
