@@ -35,6 +35,14 @@ N_PART = 100_000_000
 KC = 340.0
 DT = 1e-3
 HBM_PEAK_GBS = 8000.0
+# FP32 FMA issue rate without packed-FP32 instructions (which this library does
+# not emit): 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz.  The packed rate is 157.3.
+FP32_VALU_PEAK_TFLOPS = 78.6
+# algorithmic FLOP per particle of the separable I=8 sum: value 1920 FMA,
+# value + gradient 4080 FMA (x3 stage, x2 stage, x1 stage, Horner weights)
+FLOP_VALUE_I8 = 2 * 1920
+FLOP_GRAD_I8 = 2 * 4080
+COPY_BYTES = 1 << 30  # the calibration copy: 1 GiB read and 1 GiB written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "interp_grad_f32_i8_1024_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2107_01104_amd", "csrc", "interp.hip")
 
@@ -44,7 +52,7 @@ def log(*a):
 
 
 def algorithmic_bytes(N, Np, node_bytes, out_bytes_per_particle):
-    """Field read once + positions read + outputs written."""
+    """Field read once + positions read + outputs written: no halo over-fetch, no sort passes."""
     return N ** 3 * node_bytes + Np * 24 + Np * out_bytes_per_particle
 
 
@@ -64,26 +72,86 @@ def traffic_for(kind):
     return rec.get(kind)
 
 
-def cpu_baseline(u_host, X_host, budget_s=12.0):
-    """Time the C oracle (value+gradient and value, as in one Heun step) on a sample."""
-    import numpy as np
+def cpu_baseline(u_host, X_dev, budget_s=15.0):
+    """Time the C oracle (value+gradient and value, as in one Heun step) on a sample.
+
+    A 20000-particle calibration run sizes the timed sample to about
+    ``budget_s`` seconds of host work."""
     from oracle import cbuild
     from oracle import kernels as K
-    n = 2000
+    n = 20000
+    X_host = X_dev[:n].cpu().numpy()
     t0 = time.perf_counter()
-    cbuild.triple_sum(u_host, X_host[:n], K.SPLINE, 8, 2, gradient=True)
-    cbuild.triple_sum(u_host, X_host[:n], K.SPLINE, 8, 2, gradient=False)
+    cbuild.triple_sum(u_host, X_host, K.SPLINE, 8, 2, gradient=True)
+    cbuild.triple_sum(u_host, X_host, K.SPLINE, 8, 2, gradient=False)
     dt0 = time.perf_counter() - t0
-    n = int(min(len(X_host), max(n, n * budget_s / max(dt0, 1e-3))))
+    n = int(min(len(X_dev), max(n, n * budget_s / max(dt0, 1e-3))))
+    X_host = X_dev[:n].cpu().numpy()
     t0 = time.perf_counter()
-    _, _, th = cbuild.triple_sum(u_host, X_host[:n], K.SPLINE, 8, 2, gradient=True)
-    cbuild.triple_sum(u_host, X_host[:n], K.SPLINE, 8, 2, gradient=False)
+    _, _, th = cbuild.triple_sum(u_host, X_host, K.SPLINE, 8, 2, gradient=True)
+    cbuild.triple_sum(u_host, X_host, K.SPLINE, 8, 2, gradient=False)
     el = time.perf_counter() - t0
     return {"value": 2 * n / el, "unit": "particle-interpolations/s", "cores": int(th), "kind": "oracle",
             "sample": (f"first {n} of the 1e8 workload particles, each evaluated twice as in one Heun "
                        f"step (velocity+gradient, then velocity), I=8 C2 spline on the 1024^3 FP32 field "
                        f"values in FP64 arithmetic; plain C oracle with OpenMP over particles; "
                        f"{el:.1f} s wall")}
+
+
+def summarize_pmc(fetch_dir, write_dir):
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE) into HBM bytes per launch of the interpolation kernels.
+
+    Each counter (KiB per dispatch) is divided by what it reads for the 1 GiB
+    calibration copy, so the result is in bytes of the copy's own accounting.
+    Writes the traffic record next to the profiles and prints a summary."""
+    import csv
+    import glob
+    import statistics
+
+    def per_kernel(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        vals = {}
+        for fn in files:
+            with open(fn) as f:
+                for r in csv.DictReader(f):
+                    if r["Counter_Name"] == counter:
+                        vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    def pick(vals, needle):
+        hits = [v for k, v in vals.items() if needle in k]
+        if len(hits) != 1:
+            raise SystemExit(f"expected one kernel matching {needle!r}, found {len(hits)}")
+        return hits[0]
+
+    out = {"kernel_sha": kernel_sha()}
+    lines = []
+    for counter, d, key in (("FETCH_SIZE", fetch_dir, "fetch"), ("WRITE_SIZE", write_dir, "write")):
+        vals = per_kernel(d, counter)
+        copy_kib = pick(vals, "bitwise_not")
+        factor = statistics.mean(copy_kib) * 1024.0 / COPY_BYTES
+        out[f"copy_{key}_factor"] = factor
+        lines.append(f"| calibration copy (1 GiB) | {counter} | {statistics.mean(copy_kib):.0f} KiB | "
+                     f"factor {factor:.4f} |")
+        for kind, needle in (("interp_grad", "k_interp<1, 8, true>"), ("interp", "k_interp<1, 8, false>")):
+            kib = pick(vals, needle)
+            b = statistics.mean(kib) * 1024.0 / factor
+            out[f"{kind}_{key}"] = b
+            lines.append(f"| {needle} ({len(kib)} launches) | {counter} | {statistics.mean(kib):.0f} KiB | "
+                         f"{b / 1e9:.3f} GB scaled |")
+    for kind in ("interp_grad", "interp"):
+        out[kind] = out[f"{kind}_fetch"] + out[f"{kind}_write"]
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print("| kernel | counter | mean per dispatch | HBM bytes |")
+    print("|---|---|---|---|")
+    print("\n".join(lines))
+    for kind in ("interp_grad", "interp"):
+        print(f"\n{kind}: {out[kind] / 1e9:.3f} GB per launch (fetch {out[kind + '_fetch'] / 1e9:.3f}, "
+              f"write {out[kind + '_write'] / 1e9:.3f})")
 
 
 def main():
@@ -95,10 +163,15 @@ def main():
     ap.add_argument("--grid", type=int, default=N_GRID)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic record from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus above 1 is not supported "
-                                   "(the multi-GPU slab sharding is described in DESIGN.md, not built)"}))
+                                   "(x3-slab sharding over several GPUs is a design, not built)"}))
         sys.exit(2)
 
     import numpy as np
@@ -124,11 +197,13 @@ def main():
     X = X0.clone()
     grad = torch.empty((Np, 3, 3), dtype=torch.float32, device=dev)
 
-    # a plain device copy of known size (1 GiB each way): the reference for
-    # scaling hardware byte counters in profiling runs of this script
-    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    # a plain elementwise copy of known size (1 GiB read, 1 GiB written; a
+    # bitwise NOT of int32 words, so that its kernel is the only one of its
+    # name): the reference for scaling hardware byte counters in profiling runs
+    a = torch.zeros(COPY_BYTES // 4, dtype=torch.int32, device=dev)
     b = torch.empty_like(a)
-    b.copy_(a)
+    torch.bitwise_not(a, out=b)
+    torch.cuda.synchronize()
     del a, b
 
     ctx.advance(X, ptk.HEUN, DT, args.warmup, grad_out=grad)
@@ -149,31 +224,37 @@ def main():
     value = 2.0 * Np * K / (total_ms * 1e-3)
     log(f"{K} Heun steps in {total_ms:.1f} ms; timers: {timers}")
 
-    # dominant kernel: the interpolation with gradient (or without, if larger)
+    # dominant kernel: the interpolation with gradient (or without, if larger).
+    # Both are bound by FP32 vector issue (FMA plus the lane exchanges of the
+    # reductions), not by HBM: the roofline is the FP32 FMA rate.
     kind = max(("interp_grad", "interp"), key=lambda k: timers[k][0])
     ms, launches = timers[kind]
     avg_ms = ms / max(launches, 1)
     out_b = 12 + 36 if kind == "interp_grad" else 12
     alg = algorithmic_bytes(N, Np, 12, out_b)
-    achieved = alg / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(kind),
+    flop = Np * (FLOP_GRAD_I8 if kind == "interp_grad" else FLOP_VALUE_I8)
+    achieved = flop / (avg_ms * 1e-3) / 1e12
+    hbm = alg / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
+                "traffic": traffic_for(kind),
                 "kernel": f"k_interp<F32, I=8, grad={kind == 'interp_grad'}>",
-                "avg_launch_ms": round(avg_ms, 3), "algorithmic_bytes_per_launch": alg,
-                "launches": launches}
+                "avg_launch_ms": round(avg_ms, 3), "algorithmic_flop_per_launch": flop,
+                "algorithmic_bytes_per_launch": alg, "hbm_achieved_gbs": round(hbm, 1),
+                "hbm_frac": round(hbm / HBM_PEAK_GBS, 4), "launches": launches}
     breakdown = {k: round(v[0] / K, 3) for k, v in timers.items()}
 
     forms = None
     if not args.no_forms:
         forms = run_forms(ctx, ptk, u_host, X0, N, Np)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(u_host, X0[:200000].cpu().numpy())
+    cpu = None if args.no_cpu_baseline else cpu_baseline(u_host, X0)
 
     line = {
         "metric": "particle-interpolations/sec at I=8, 1024^3 grid; % HBM roofline; RMS err vs FP64",
         "value": value, "unit": "particle-interpolations/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": total_ms / K, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"cfg2: {N}^3 FP32 spectral field (k<={kc:g}), {Np:.3g} particles, "
+        "config": {"workload": f"{N}^3 FP32 spectral field (k<={kc:g}), {Np:.3g} particles, "
                                f"C2 spline I=8, velocity+gradient, Heun dt={DT}",
                    "grid": N, "particles": Np, "kernel": "spline I=8 m=2", "scheme": "heun",
                    "gradient": True, "storage": "f32"},
