@@ -185,14 +185,86 @@ int ptk_get_binning(ptk_ctx *ctx, uint32_t *perm, uint32_t *offsets, void *strea
  *   PTK_T_KEYS         bin keys of caller positions
  *   PTK_T_UPDATE       position update (+ keys of the new positions)
  *   PTK_T_PERMUTE      gathers/scatters of particle state between orders
+ *   PTK_T_LEARNED      learned-form inference kernel (features, L4 sum, network)
  * ptk_timing_enable(ctx, 1) starts (and clears) the accumulators, 0 stops.
  * ptk_timing_read waits for the recorded events, adds their durations to the
  * accumulators and copies them out: ms[PTK_T_COUNT] (milliseconds) and
  * launches[PTK_T_COUNT] (number of timed sequences); either may be NULL. */
 enum { PTK_T_INTERP = 0, PTK_T_INTERP_GRAD = 1, PTK_T_SORT = 2, PTK_T_KEYS = 3, PTK_T_UPDATE = 4,
-       PTK_T_PERMUTE = 5, PTK_T_COUNT = 6 };
+       PTK_T_PERMUTE = 5, PTK_T_LEARNED = 6, PTK_T_COUNT = 7 };
 int ptk_timing_enable(ptk_ctx *ctx, int enable);
 int ptk_timing_read(ptk_ctx *ctx, double *ms, int64_t *launches);
+
+/* ---- Learned correction form ------------------------------------------
+ * Beside the paper's weighted sum: a network of 195 -> 128 -> 128 -> 3
+ * units predicts, from the 4 x 4 x 4 stencil of the I = 4 Lagrange kernel and
+ * the in-cell offsets, the difference between the context's kernel (the
+ * "wide" kernel, e.g. the I = 8 C2 spline) and the I = 4 Lagrange interpolant:
+ * u ~ u_L4 + y.  Needs FP32 field storage and a wide kernel with I >= 4.
+ *
+ * Features of a particle in cell c with offsets t (steps 1-3 of Sec. 2.2):
+ * BF16 numbers (round to nearest even), f = ((k3*4 + k2)*4 + k1)*3 + a for
+ * the stored field component a at node c + (k - 1) (k in 0..3 per axis,
+ * indices modulo N), then t1, t2, t3 (rounded to FP32, then to BF16) at f =
+ * 192..194.  Rows are PTK_LEARNED_FEAT_PITCH = 200 BF16 wide (400 bytes);
+ * entries 195..199 are zero.
+ * Network: z1 = W1 x + b1, h1 = silu(z1), z2 = W2 h1 + b2, h2 = silu(z2),
+ * y = W3 h2 + b3, silu(z) = z / (1 + exp(-z)).  Parameters are one FP32
+ * vector of PTK_LEARNED_NPARAMS numbers: W1[128][195], b1[128], W2[128][128],
+ * b2[128], W3[3][128], b3[3].  The two hidden-layer products (and the
+ * backward products through them) take BF16 operands -- x, W1, h1, W2; dz2,
+ * h1, W2, dz1, x -- with FP32 sums on the matrix cores; the rest is FP32. */
+#define PTK_LEARNED_NFEAT 195
+#define PTK_LEARNED_FEAT_PITCH 200
+#define PTK_LEARNED_NPARAMS 41987
+
+/* Training pairs at Np positions: feat (device, uint16 BF16 bits
+ * [Np][PTK_LEARNED_FEAT_PITCH]) and target (device FP32 [Np][3]) =
+ * u_wide(X) - u_L4(X), both sums in FP32.  Either output may be NULL. */
+int ptk_learned_make_pairs(ptk_ctx *ctx, const double *X, int64_t Np, uint16_t *feat, float *target,
+                           void *stream);
+
+/* Load the FP32 master parameters (host, PTK_LEARNED_NPARAMS floats) and
+ * reset the optimiser state (moments and step count).  Synchronous. */
+int ptk_learned_set_params(ptk_ctx *ctx, const float *params);
+
+/* Copy the FP32 master parameters to host memory.  Synchronous. */
+int ptk_learned_get_params(ptk_ctx *ctx, float *params);
+
+/* Mean-square loss over n pairs and its gradient with respect to the
+ * parameters, without an update: loss (device FP32 [1]) = mean over rows and
+ * the 3 components of (y - target)^2; grad (device FP32 [PTK_LEARNED_NPARAMS],
+ * parameter layout).  n: multiple of 64, 64 <= n <= 16384. */
+int ptk_learned_loss_grad(ptk_ctx *ctx, const uint16_t *feat, const float *target, int64_t n,
+                          float *loss, float *grad, void *stream);
+
+/* Optimiser settings: Adam (Kingma and Ba) with bias correction, step size
+ * lr * (1 + cos(pi s / S)) / 2 at step s of S = epochs * (n / batch). */
+typedef struct {
+  int epochs;
+  int batch;    /* multiple of 64, 64 .. 16384 */
+  float lr;
+  float beta1;
+  float beta2;
+  float eps;
+} ptk_train_config;
+
+/* Train on n pairs: epochs passes over consecutive batches (a trailing
+ * partial batch is dropped), one Adam step per batch; the optimiser state
+ * continues from the last set_params/train call.  loss_curve: device FP32
+ * [epochs * (n / batch)] receiving each step's batch loss, or NULL. */
+int ptk_learned_train(ptk_ctx *ctx, const uint16_t *feat, const float *target, int64_t n,
+                      const ptk_train_config *cfg, float *loss_curve, void *stream);
+
+/* Learned interpolation: out (device FP32 [Np][3], in the order of X) =
+ * u_L4(X) + y(features).  Audit: the wide kernel is evaluated at particles
+ * 0, k, 2k, ... (k = round(1/audit_frac), audit_frac in (0, 1]); *audit_rms
+ * (host) receives sqrt(sum |out - u_wide|^2 / sum |u_wide|^2) over them, and
+ * if it exceeds tol_rel_rms the whole output is recomputed with the wide
+ * kernel and *fell_back (host) is set to 1 (else 0).  Waits for the stream
+ * (it reads the audit back). */
+int ptk_interpolate_learned(ptk_ctx *ctx, const double *X, int64_t Np, float *out, double audit_frac,
+                            double tol_rel_rms, double *audit_rms, int *fell_back, void *stream);
 
 #ifdef __cplusplus
 }

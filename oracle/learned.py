@@ -181,11 +181,12 @@ def train(params0, feats_bits, target, epochs: int, batch: int, lr0: float, emul
     return params, np.array(losses)
 
 
-def infer(params, field32, X, family: int, I: int, m: int, audit_frac: float, tol_rel_rms: float):
+def infer(params, field32, X, family: int, I: int, m: int, audit_frac: float, tol_rel_rms: float,
+          emulate_bf16: bool = False):
     """Learned interpolation with the audit and fallback; returns (u, audit_rms, fell_back)."""
     field32 = np.asarray(field32, dtype=np.float32)
     narrow = OI.interp_vec(field32, X, K.LAGRANGE, 4, 0)
-    y, _ = forward(params, bf16_bits_to_f64(features(field32, X)))
+    y, _ = forward(params, bf16_bits_to_f64(features(field32, X)), emulate_bf16)
     u = narrow + y
     k = max(1, int(round(1.0 / audit_frac)))
     idx = np.arange(0, X.shape[0], k)

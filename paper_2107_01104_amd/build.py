@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libptk.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "binning.hip", "field.hip", "interp.hip", "step.hip", "coeffs.cpp"]
+SOURCES = ["api.hip", "binning.hip", "field.hip", "interp.hip", "learned.hip", "step.hip", "coeffs.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unused-function",
           f"-I{INCLUDE}", f"-I{CSRC}"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -284,6 +284,41 @@ int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* gr
   return check_flag(c, s);
 }
 
+
+// ---- learned form helpers
+int learned_field(ptk_ctx* c, LearnedField* lf) {
+  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
+  if (c->storage != PTK_F32) return fail(c, PTK_EUNSUPPORTED, "the learned form needs FP32 field storage");
+  KernelTables t4;
+  if (build_kernel_tables(PTK_LAGRANGE, 4, 0, &t4) != 0) return fail(c, PTK_EINVAL, "L4 table");
+  lf->field = c->field.ptr;
+  lf->row_pitch = c->geom.row_pitch;
+  lf->plane_pitch = c->geom.plane_pitch;
+  lf->halo_lo = c->geom.halo_lo;
+  lf->N = (int)c->geom.N;
+  lf->invd = invd_of(c->geom.N);
+  for (int j = 0; j < 4; ++j)
+    for (int p = 0; p < 4; ++p) lf->l4[j][p] = t4.val32[j][p];
+  return PTK_OK;
+}
+
+constexpr int kLearnedMaxBatch = 16384;
+
+int check_rows(ptk_ctx* c, const uint16_t* feat, const float* target, int64_t n) {
+  if (!c->learned_ready) return fail(c, PTK_EINVAL, "no network parameters set");
+  if (!feat || !target) return fail(c, PTK_EINVAL, "NULL pointer");
+  if (((uintptr_t)feat & 15) != 0) return fail(c, PTK_EINVAL, "feature rows must be 16-byte aligned");
+  (void)n;
+  return PTK_OK;
+}
+
+int ensure_partials(ptk_ctx* c, int64_t batch) {
+  const int64_t parts = batch / 64;
+  PTK_TRY(ensure(c, c->lgpart, (size_t)parts * kLearnedNParams * 4));
+  PTK_TRY(ensure(c, c->llpart, (size_t)parts * 4));
+  return PTK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -337,7 +372,9 @@ void ptk_destroy(ptk_ctx* c) {
     (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->field, &c->coef, &c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->offsets,
                       &c->hist, &c->scan_tmp, &c->flag, &c->xs, &c->xn, &c->orig, &c->orig_b, &c->k1,
-                      &c->k2, &c->h0, &c->h1, &c->h0b, &c->h1b, &c->gint, &c->stage};
+                      &c->k2, &c->h0, &c->h1, &c->h0b, &c->h1b, &c->gint, &c->stage, &c->lparams,
+                      &c->lm, &c->lv, &c->lw1b, &c->lw2b, &c->lw2bt, &c->lgpart, &c->llpart, &c->lwide,
+                      &c->laudit_x, &c->laudit_u, &c->laudit_sums};
     for (DevBuf* b : bufs) release(*b);
     for (TimedPair& p : c->pending) {
       (void)hipEventDestroy(p.start);
@@ -680,6 +717,235 @@ int ptk_timing_read(ptk_ctx* c, double* ms, int64_t* launches) {
   for (int k = 0; k < kTimerKinds; ++k) {
     if (ms) ms[k] = c->timer_ms[k];
     if (launches) launches[k] = c->timer_count[k];
+  }
+  return PTK_OK;
+}
+
+int ptk_learned_make_pairs(ptk_ctx* c, const double* X, int64_t Np, uint16_t* feat, float* target,
+                           void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  LearnedField lf;
+  PTK_TRY(learned_field(c, &lf));
+  if (Np < 0 || Np > (int64_t)0xFFFFFFFF) return fail(c, PTK_EINVAL, "Np out of range [0, 2^32)");
+  if (Np > 0 && !X) return fail(c, PTK_EINVAL, "NULL positions");
+  if (feat && ((uintptr_t)feat & 7) != 0) return fail(c, PTK_EINVAL, "feature rows must be 8-byte aligned");
+  if (Np == 0 || (!feat && !target)) return PTK_OK;
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  if (target) {
+    PTK_TRY(ensure(c, c->lwide, (size_t)Np * 12));
+    PTK_TRY(interp_common(c, X, Np, c->lwide.ptr, nullptr, PTK_F32, stream));
+  }
+  PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
+  PTK_HIP(c,
+          launch_learned_pairs(lf, X, Np, (const float*)c->lwide.ptr, feat, target, (int*)c->flag.ptr, s),
+          "training pairs");
+  return check_flag(c, s);
+}
+
+int ptk_learned_set_params(ptk_ctx* c, const float* params) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!params) return fail(c, PTK_EINVAL, "NULL parameters");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  const size_t pb = (size_t)kLearnedNParams * 4;
+  PTK_TRY(ensure(c, c->lparams, pb));
+  PTK_TRY(ensure(c, c->lm, pb));
+  PTK_TRY(ensure(c, c->lv, pb));
+  PTK_TRY(ensure(c, c->lw1b, 128 * 208 * 2));
+  PTK_TRY(ensure(c, c->lw2b, 128 * 128 * 2));
+  PTK_TRY(ensure(c, c->lw2bt, 128 * 128 * 2));
+  PTK_HIP(c, hipDeviceSynchronize(), "synchronize");
+  PTK_HIP(c, hipMemcpy(c->lparams.ptr, params, pb, hipMemcpyHostToDevice), "parameter upload");
+  PTK_HIP(c, hipMemset(c->lm.ptr, 0, pb), "moment clear");
+  PTK_HIP(c, hipMemset(c->lv.ptr, 0, pb), "moment clear");
+  PTK_HIP(c, hipMemset(c->lw1b.ptr, 0, 128 * 208 * 2), "weight clear");
+  LearnedUpdate u;
+  std::memset(&u, 0, sizeof(u));
+  u.mode = 2;
+  PTK_HIP(c,
+          launch_learned_update((float*)c->lparams.ptr, (float*)c->lm.ptr, (float*)c->lv.ptr, nullptr, nullptr, u,
+                                (uint16_t*)c->lw1b.ptr, (uint16_t*)c->lw2b.ptr, (uint16_t*)c->lw2bt.ptr, nullptr),
+          "weight copies");
+  PTK_HIP(c, hipDeviceSynchronize(), "synchronize");
+  c->learned_ready = true;
+  c->learned_step = 0;
+  return PTK_OK;
+}
+
+int ptk_learned_get_params(ptk_ctx* c, float* params) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!params) return fail(c, PTK_EINVAL, "NULL parameters");
+  if (!c->learned_ready) return fail(c, PTK_EINVAL, "no network parameters set");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  PTK_HIP(c, hipDeviceSynchronize(), "synchronize");
+  PTK_HIP(c, hipMemcpy(params, c->lparams.ptr, (size_t)kLearnedNParams * 4, hipMemcpyDeviceToHost),
+          "parameter download");
+  return PTK_OK;
+}
+
+int ptk_learned_loss_grad(ptk_ctx* c, const uint16_t* feat, const float* target, int64_t n, float* loss,
+                          float* grad, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  PTK_TRY(check_rows(c, feat, target, n));
+  if (!loss || !grad) return fail(c, PTK_EINVAL, "NULL output");
+  if (n < 64 || n > kLearnedMaxBatch || n % 64) return fail(c, PTK_EINVAL, "n must be a multiple of 64 in [64, 16384]");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  PTK_TRY(ensure_partials(c, n));
+  PTK_HIP(c,
+          launch_learned_forward_backward(feat, target, n, (const float*)c->lparams.ptr, (const uint16_t*)c->lw1b.ptr,
+                                          (const uint16_t*)c->lw2b.ptr, (const uint16_t*)c->lw2bt.ptr,
+                                          (float*)c->lgpart.ptr, (float*)c->llpart.ptr, s),
+          "forward and backward");
+  LearnedUpdate u;
+  std::memset(&u, 0, sizeof(u));
+  u.mode = 0;
+  u.nparts = (int)(n / 64);
+  u.loss_scale = (float)(1.0 / (3.0 * (double)n));
+  u.loss_out = loss;
+  u.grad_out = grad;
+  PTK_HIP(c,
+          launch_learned_update((float*)c->lparams.ptr, (float*)c->lm.ptr, (float*)c->lv.ptr,
+                                (const float*)c->lgpart.ptr, (const float*)c->llpart.ptr, u, (uint16_t*)c->lw1b.ptr,
+                                (uint16_t*)c->lw2b.ptr, (uint16_t*)c->lw2bt.ptr, s),
+          "gradient sum");
+  return PTK_OK;
+}
+
+int ptk_learned_train(ptk_ctx* c, const uint16_t* feat, const float* target, int64_t n,
+                      const ptk_train_config* cfg, float* loss_curve, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  PTK_TRY(check_rows(c, feat, target, n));
+  if (!cfg) return fail(c, PTK_EINVAL, "NULL configuration");
+  if (cfg->epochs < 0) return fail(c, PTK_EINVAL, "epochs must be >= 0");
+  if (cfg->batch < 64 || cfg->batch > kLearnedMaxBatch || cfg->batch % 64)
+    return fail(c, PTK_EINVAL, "batch must be a multiple of 64 in [64, 16384]");
+  if (!(cfg->lr > 0.f) || !std::isfinite(cfg->lr)) return fail(c, PTK_EINVAL, "lr must be positive");
+  if (!(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) || !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f))
+    return fail(c, PTK_EINVAL, "betas must be in [0, 1)");
+  if (!(cfg->eps > 0.f)) return fail(c, PTK_EINVAL, "eps must be positive");
+  if (n < 0) return fail(c, PTK_EINVAL, "n must be >= 0");
+  const int64_t nb = n / cfg->batch;
+  const int64_t total = (int64_t)cfg->epochs * nb;
+  if (total == 0) return PTK_OK;
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  PTK_TRY(ensure_partials(c, cfg->batch));
+  const double kPi = 3.14159265358979323846;
+  for (int64_t st = 0; st < total; ++st) {
+    const int64_t b = st % nb;
+    const int64_t r0 = b * cfg->batch;
+    PTK_HIP(c,
+            launch_learned_forward_backward(feat + r0 * kLearnedPitch, target + r0 * 3, cfg->batch,
+                                            (const float*)c->lparams.ptr, (const uint16_t*)c->lw1b.ptr,
+                                            (const uint16_t*)c->lw2b.ptr, (const uint16_t*)c->lw2bt.ptr,
+                                            (float*)c->lgpart.ptr, (float*)c->llpart.ptr, s),
+            "forward and backward");
+    const int64_t gs = c->learned_step + 1;
+    LearnedUpdate u;
+    std::memset(&u, 0, sizeof(u));
+    u.mode = 1;
+    u.nparts = cfg->batch / 64;
+    u.lr = (float)((double)cfg->lr * 0.5 * (1.0 + std::cos(kPi * (double)st / (double)total)));
+    u.beta1 = cfg->beta1;
+    u.beta2 = cfg->beta2;
+    u.eps = cfg->eps;
+    u.c1 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta1, (double)gs)));
+    u.c2 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta2, (double)gs)));
+    u.loss_scale = (float)(1.0 / (3.0 * (double)cfg->batch));
+    u.loss_out = loss_curve ? loss_curve + st : nullptr;
+    PTK_HIP(c,
+            launch_learned_update((float*)c->lparams.ptr, (float*)c->lm.ptr, (float*)c->lv.ptr,
+                                  (const float*)c->lgpart.ptr, (const float*)c->llpart.ptr, u,
+                                  (uint16_t*)c->lw1b.ptr, (uint16_t*)c->lw2b.ptr, (uint16_t*)c->lw2bt.ptr, s),
+            "Adam step");
+    c->learned_step = gs;
+  }
+  return PTK_OK;
+}
+
+int ptk_interpolate_learned(ptk_ctx* c, const double* X, int64_t Np, float* out, double audit_frac,
+                            double tol_rel_rms, double* audit_rms, int* fell_back, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  LearnedField lf;
+  PTK_TRY(learned_field(c, &lf));
+  if (!c->learned_ready) return fail(c, PTK_EINVAL, "no network parameters set");
+  if (Np < 0 || Np > (int64_t)0xFFFFFFFF) return fail(c, PTK_EINVAL, "Np out of range [0, 2^32)");
+  if (!audit_rms || !fell_back) return fail(c, PTK_EINVAL, "NULL audit outputs");
+  if (!(audit_frac > 0.0 && audit_frac <= 1.0)) return fail(c, PTK_EINVAL, "audit_frac must be in (0, 1]");
+  if (!(tol_rel_rms >= 0.0)) return fail(c, PTK_EINVAL, "tol_rel_rms must be >= 0");
+  if (Np > 0 && (!X || !out)) return fail(c, PTK_EINVAL, "NULL pointer");
+  *audit_rms = 0.0;
+  *fell_back = 0;
+  if (Np == 0) return PTK_OK;
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  const int64_t N = c->geom.N;
+  const BinGeom bg = bin_geom(c);
+  const int64_t n_bins = n_bins_of(bg);
+  c->bin_valid = false;
+  PTK_TRY(ensure_binning(c, Np, n_bins));
+  PTK_TRY(ensure(c, c->xs, (size_t)Np * 24));
+  PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
+  {
+    Timed t(c, s, PTK_T_KEYS);
+    PTK_HIP(c, launch_keys(X, Np, (int)N, invd_of(N), bg, (uint32_t*)c->keys_a.ptr, (int*)c->flag.ptr, s),
+            "keys");
+  }
+  uint32_t* perm = nullptr;
+  {
+    Timed t(c, s, PTK_T_SORT);
+    PTK_TRY(bin_sorted(c, Np, n_bins, &perm, s));
+  }
+  {
+    Timed t(c, s, PTK_T_PERMUTE);
+    PTK_HIP(c, gather3_f64(X, perm, Np, (double*)c->xs.ptr, s), "gather positions");
+  }
+  {
+    Timed t(c, s, PTK_T_LEARNED);
+    PTK_HIP(c,
+            launch_learned_infer(lf, (const double*)c->xs.ptr, Np, perm, (const float*)c->lparams.ptr,
+                                 (const uint16_t*)c->lw1b.ptr, (const uint16_t*)c->lw2b.ptr, out, (int*)c->flag.ptr,
+                                 s),
+            "learned interpolation");
+  }
+  {
+    // positions outside the domain are reported before the audit re-bins
+    int h = 0;
+    PTK_HIP(c, hipMemcpyAsync(&h, c->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s), "flag read");
+    PTK_HIP(c, hipStreamSynchronize(s), "stream synchronize");
+    if (h) return fail(c, PTK_EDOMAIN, "a particle position is NaN, infinite or has |x| >= 2^50");
+  }
+  // audit with the wide kernel at particles 0, k, 2k, ...
+  int64_t k = (int64_t)std::llround(1.0 / audit_frac);
+  if (k < 1) k = 1;
+  const int64_t na = (Np + k - 1) / k;
+  PTK_TRY(ensure(c, c->laudit_x, (size_t)na * 24));
+  PTK_TRY(ensure(c, c->laudit_u, (size_t)na * 12));
+  PTK_TRY(ensure(c, c->laudit_sums, 16));
+  PTK_HIP(c, launch_stride_gather(X, k, na, (double*)c->laudit_x.ptr, s), "audit positions");
+  PTK_TRY(interp_common(c, (const double*)c->laudit_x.ptr, na, c->laudit_u.ptr, nullptr, PTK_F32, stream));
+  PTK_HIP(c, launch_audit(out, k, na, (const float*)c->laudit_u.ptr, (double*)c->laudit_sums.ptr, s), "audit");
+  double sums[2] = {0.0, 0.0};
+  PTK_HIP(c, hipMemcpyAsync(sums, c->laudit_sums.ptr, 16, hipMemcpyDeviceToHost, s), "audit read");
+  PTK_HIP(c, hipStreamSynchronize(s), "stream synchronize");
+  const double rms = sums[1] > 0.0 ? std::sqrt(sums[0] / sums[1]) : (sums[0] > 0.0 ? INFINITY : 0.0);
+  *audit_rms = rms;
+  if (!(rms <= tol_rel_rms)) {
+    PTK_TRY(interp_common(c, X, Np, out, nullptr, PTK_F32, stream));
+    *fell_back = 1;
   }
   return PTK_OK;
 }

@@ -67,4 +67,37 @@ hipError_t launch_update(int kind, int vel_f64, const double* X, const void* ka,
                          int64_t n, double* Xout, uint32_t* keys, int N, double invd, const BinGeom& g,
                          int* flag, hipStream_t s);
 
+// learned.hip
+struct LearnedField {
+  const void* field;  // FP32 storage, padded layout of set_field
+  int64_t row_pitch, plane_pitch;
+  int halo_lo;
+  int N;
+  double invd;
+  float l4[4][4];     // Lagrange I = 4 coefficients, [node][power of t]
+};
+struct LearnedUpdate {
+  int mode;           // 0 gradient + loss only, 1 Adam step, 2 BF16 copies only
+  int nparts;         // workgroup partials to sum
+  float lr, beta1, beta2, eps;
+  float c1, c2;       // bias corrections 1/(1 - beta1^s), 1/(1 - beta2^s)
+  float loss_scale;   // 1 / (3 batch)
+  float* loss_out;    // device, one float, or NULL
+  float* grad_out;    // device [kLearnedNParams] (mode 0)
+};
+hipError_t launch_learned_pairs(const LearnedField& f, const double* X, int64_t n, const float* uwide,
+                                uint16_t* feat, float* target, int* flag, hipStream_t s);
+hipError_t launch_learned_forward_backward(const uint16_t* feat, const float* target, int64_t batch,
+                                           const float* params, const uint16_t* w1b, const uint16_t* w2b,
+                                           const uint16_t* w2bt, float* gpart, float* lpart, hipStream_t s);
+hipError_t launch_learned_update(float* params, float* m, float* v, const float* gpart, const float* lpart,
+                                 const LearnedUpdate& u, uint16_t* w1b, uint16_t* w2b, uint16_t* w2bt,
+                                 hipStream_t s);
+hipError_t launch_learned_infer(const LearnedField& f, const double* X, int64_t n, const uint32_t* orig,
+                                const float* params, const uint16_t* w1b, const uint16_t* w2b, float* out,
+                                int* flag, hipStream_t s);
+hipError_t launch_stride_gather(const double* X, int64_t stride, int64_t na, double* Xa, hipStream_t s);
+hipError_t launch_audit(const float* out, int64_t stride, int64_t na, const float* uw, double* sums,
+                        hipStream_t s);
+
 }  // namespace ptk

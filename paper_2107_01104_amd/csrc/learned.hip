@@ -1,0 +1,619 @@
+// Learned correction form: stencil features and the I = 4 Lagrange sum at
+// particles, and a 195-128-128-3 SiLU network whose two hidden-layer products
+// run on the matrix cores (BF16 operands, FP32 sums) -- training (forward,
+// backward, Adam) and inference on binned particles.
+//
+// Matrix-core tiles: v_mfma_f32_32x32x16_bf16.  Lane l holds, of a 32 x 16 A
+// tile, row l%32 and the 8 consecutive k starting at 8*(l/32); of a 16 x 32 B
+// tile, column l%32 and the same k; of the 32 x 32 FP32 result, column l%32
+// and rows 8*(v/4) + 4*(l/32) + v%4 in register v.  A workgroup of 4 waves
+// takes 64 rows (particles or training pairs); wave w owns hidden units
+// [32w, 32w+32) in the forward products.
+#include "device_common.h"
+#include "launch.h"
+#include "ptk_internal.h"
+
+namespace ptk {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int NF = kLearnedNFeat;   // 195 features
+constexpr int FP = kLearnedPitch;   // 200: global feature row pitch
+constexpr int K1 = 208;             // layer-1 k extent, padded to 13 x 16
+constexpr int NH = 128, NO = 3;
+constexpr int oW1 = 0, oB1 = NH * NF, oW2 = oB1 + NH, oB2 = oW2 + NH * NH, oW3 = oB2 + NH, oB3 = oW3 + NO * NH;
+static_assert(oB3 + NO == kLearnedNParams, "parameter layout");
+constexpr int ROWS = 64, NT = 256;
+// LDS pitches in BF16 elements: rows of 16 x odd bytes, so that 32 lanes
+// reading 16 bytes each from 32 consecutive rows cover all banks
+constexpr int PX = 216;   // features (K1 + 8)
+constexpr int PH = 136;   // hidden activations
+constexpr int PT = 72;    // transposed tiles: 64 rows + 8
+constexpr int PH2 = 132;  // FP32 h2 rows
+
+__device__ __forceinline__ bf16x8 frag(const uint16_t* base, int pitch, int row, int k) {
+  return __builtin_bit_cast(bf16x8, *(const uint4*)(base + row * pitch + k));
+}
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
+__device__ __forceinline__ float dsilu(float z) {
+  const float s = sigm(z);
+  return s * (1.0f + z * (1.0f - s));
+}
+// row of result register v of this lane within a 32-row tile
+__device__ __forceinline__ int acc_row(int v, int hi) { return 8 * (v >> 2) + 4 * hi + (v & 3); }
+
+__device__ __forceinline__ float quad_sum(float v) {
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, true));
+  return v;
+}
+
+// One quarter of a particle's 4 x 4 x 4 stencil (the x3 plane k3): its 48
+// BF16 features, written to feat[48*k3 ...], and its part of the Lagrange
+// I = 4 sum.  Offsets t (FP64, exact) and cells come from locate().
+__device__ __forceinline__ void stencil_plane(const LearnedField& f, const int* c, const double* td, int k3,
+                                              uint16_t* feat, float* u) {
+  float w[3][4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float t = (float)td[d];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float acc = f.l4[j][3];
+#pragma unroll
+      for (int p = 2; p >= 0; --p) acc = fmaf(acc, t, f.l4[j][p]);
+      w[d][j] = acc;
+    }
+  }
+  u[0] = u[1] = u[2] = 0.f;
+  const int64_t z = c[2] - 1 + k3 + f.halo_lo;
+  const unsigned char* plane = (const unsigned char*)f.field + z * f.plane_pitch;
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    const int64_t y = c[1] - 1 + k2 + f.halo_lo;
+    const float* row = (const float*)(plane + y * f.row_pitch) + 3 * (c[0] - 1 + f.halo_lo);
+    const float w23 = w[2][k3] * w[1][k2];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      const float ww = w23 * w[0][k1];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float v = row[3 * k1 + a];
+        u[a] = fmaf(ww, v, u[a]);
+        feat[(k2 * 4 + k1) * 3 + a] = f32_to_bf16_rne(v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- pairs
+// thread = (particle, x3 plane of its stencil); caller order
+__global__ __launch_bounds__(NT) void k_pairs(LearnedField f, const double* X, int64_t n, const float* uwide,
+                                              uint16_t* feat, float* target, int* flag) {
+  const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t p = min(g >> 2, n - 1);
+  const int k3 = (int)(g & 3);
+  const bool active = (g >> 2) < n;
+  const double x[3] = {X[3 * p], X[3 * p + 1], X[3 * p + 2]};
+  const bool ok = in_domain3(x[0], x[1], x[2]);
+  if (active && !ok && k3 == 0) atomicOr(flag, 1);
+  int c[3];
+  double td[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) locate(ok ? x[d] : 0.0, f.N, f.invd, &c[d], &td[d]);
+  uint16_t fe[48];
+  float u[3];
+  stencil_plane(f, c, td, k3, fe, u);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] = quad_sum(u[a]);
+  if (!active) return;
+  if (feat) {
+    uint2* dst = (uint2*)(feat + p * FP + 48 * k3);
+#pragma unroll
+    for (int q = 0; q < 12; ++q)
+      dst[q] = make_uint2((uint32_t)fe[4 * q] | ((uint32_t)fe[4 * q + 1] << 16),
+                          (uint32_t)fe[4 * q + 2] | ((uint32_t)fe[4 * q + 3] << 16));
+    if (k3 == 0) {
+      uint32_t* tail = (uint32_t*)(feat + p * FP + 192);
+      const uint16_t t0 = f32_to_bf16_rne((float)td[0]), t1 = f32_to_bf16_rne((float)td[1]),
+                     t2 = f32_to_bf16_rne((float)td[2]);
+      tail[0] = (uint32_t)t0 | ((uint32_t)t1 << 16);
+      tail[1] = (uint32_t)t2;
+      tail[2] = 0u;
+      tail[3] = 0u;
+    }
+  }
+  if (target && k3 == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) target[3 * p + a] = uwide[3 * p + a] - u[a];
+  }
+}
+
+// ---------------------------------------------------------------- forward
+// Both hidden layers for the 64 rows whose features are in sX.  Leaves the
+// pre-activations' derivatives (training) in ds1/ds2, h1 in sH1 (and its
+// transpose in sH1t if given), h2 (FP32) in sH2.  sX and sH2 may alias: sX is
+// dead once layer 1 is done (a barrier separates them).
+template <bool TRAIN>
+__device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1, uint16_t* sH1t, float* sH2,
+                                               const bf16x8 (&bw1)[13], const bf16x8 (&bw2)[8], float bias1,
+                                               float bias2, f32x16 (&ds1)[2], f32x16 (&ds2)[2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r32 = lane & 31, hi = lane >> 5;
+  const int J = 32 * wave + r32;
+  f32x16 acc[2];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[rt][v] = 0.f;
+#pragma unroll
+  for (int s = 0; s < 13; ++s)
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) acc[rt] = mfma(frag(sX, PX, 32 * rt + r32, 16 * s + 8 * hi), bw1[s], acc[rt]);
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int v0 = 0; v0 < 16; v0 += 4) {
+      uint16_t hb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float z = acc[rt][v0 + q] + bias1;
+        hb[q] = f32_to_bf16_rne(silu(z));
+        if constexpr (TRAIN) ds1[rt][v0 + q] = dsilu(z);
+        sH1[(32 * rt + acc_row(v0 + q, hi)) * PH + J] = hb[q];
+      }
+      if (sH1t)
+        *(uint2*)(sH1t + J * PT + 32 * rt + acc_row(v0, hi)) =
+            make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
+    }
+  __syncthreads();  // h1 complete; sX is dead from here on
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[rt][v] = 0.f;
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) acc[rt] = mfma(frag(sH1, PH, 32 * rt + r32, 16 * s + 8 * hi), bw2[s], acc[rt]);
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float z = acc[rt][v] + bias2;
+      sH2[(32 * rt + acc_row(v, hi)) * PH2 + J] = silu(z);
+      if constexpr (TRAIN) ds2[rt][v] = dsilu(z);
+    }
+  __syncthreads();  // h2 complete
+}
+
+// y[r][a] = b3[a] + sum_c h2[r][c] W3[a][c] for thread t < 192 (r = t/3, a = t%3)
+__device__ __forceinline__ float output_layer(const float* sH2, const float* sW3, const float* b3, int t) {
+  const int r = t / 3, a = t - 3 * (t / 3);
+  const float4* h = (const float4*)(sH2 + r * PH2);
+  const float4* w = (const float4*)(sW3 + a * NH);
+  float y0 = 0.f, y1 = 0.f;
+#pragma unroll 8
+  for (int c = 0; c < NH / 4; c += 2) {
+    const float4 h0 = h[c], w0 = w[c], h1 = h[c + 1], w1 = w[c + 1];
+    y0 = fmaf(h0.x, w0.x, y0);
+    y0 = fmaf(h0.y, w0.y, y0);
+    y0 = fmaf(h0.z, w0.z, y0);
+    y0 = fmaf(h0.w, w0.w, y0);
+    y1 = fmaf(h1.x, w1.x, y1);
+    y1 = fmaf(h1.y, w1.y, y1);
+    y1 = fmaf(h1.z, w1.z, y1);
+    y1 = fmaf(h1.w, w1.w, y1);
+  }
+  return b3[a] + (y0 + y1);
+}
+
+__device__ __forceinline__ void load_weight_frags(const uint16_t* w1b, const uint16_t* w2b, bf16x8 (&bw1)[13],
+                                                  bf16x8 (&bw2)[8]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int J = 32 * wave + (lane & 31), hi = lane >> 5;
+#pragma unroll
+  for (int s = 0; s < 13; ++s) bw1[s] = frag(w1b, K1, J, 16 * s + 8 * hi);
+#pragma unroll
+  for (int s = 0; s < 8; ++s) bw2[s] = frag(w2b, NH, J, 16 * s + 8 * hi);
+}
+
+// ---------------------------------------------------------------- training
+// One workgroup: 64 consecutive pairs starting at row0 = 64 * blockIdx.x.
+// Writes its part of the gradient (parameter layout) to gpart[blockIdx.x] and
+// its sum of squared errors to lpart[blockIdx.x].
+__global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat, const float* target, int64_t batch,
+                                                            const float* params, const uint16_t* w1b,
+                                                            const uint16_t* w2b, const uint16_t* w2bt, float* gpart,
+                                                            float* lpart) {
+  // LDS regions (bytes): R0 transposed features [224][PT]; R1 transposed h1
+  // [128][PT]; R2 features [64][PX] -> h2 FP32 [64][PH2] -> dz2 [64][PH] +
+  // transposed dz2 [128][PT]; R3 h1 [64][PH] -> transposed dz1 [128][PT]
+  constexpr int R0 = 224 * PT * 2, R1 = NH * PT * 2;
+  constexpr int R2 = ROWS * PH * 2 + NH * PT * 2;  // the largest of its three uses
+  static_assert(R2 >= ROWS * PX * 2 && R2 >= ROWS * PH2 * 4, "R2 size");
+  constexpr int R3 = NH * PT * 2;
+  static_assert(R3 >= ROWS * PH * 2, "R3 size");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[R0 + R1 + R2 + R3];
+  __shared__ float sW3[NO * NH];
+  __shared__ float sdy[ROWS * NO];
+  __shared__ float sred[NT / 64];
+  uint16_t* sXt = (uint16_t*)lds;
+  uint16_t* sH1t = (uint16_t*)(lds + R0);
+  unsigned char* r2 = lds + R0 + R1;
+  uint16_t* sX = (uint16_t*)r2;
+  float* sH2 = (float*)r2;
+  uint16_t* sdZ2 = (uint16_t*)r2;
+  uint16_t* sdZ2t = (uint16_t*)(r2 + ROWS * PH * 2);
+  uint16_t* sH1 = (uint16_t*)(lds + R0 + R1 + R2);
+  uint16_t* sdZ1t = sH1;
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6, r32 = lane & 31, hi = lane >> 5;
+  const int J = 32 * wave + r32;
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+  float* gp = gpart + (int64_t)blockIdx.x * kLearnedNParams;
+
+  // features -> sX (row-major) and sXt (transposed); entries 195.. are zero
+  for (int e = t; e < ROWS * (K1 / 8); e += NT) {
+    const int r = e / (K1 / 8), k0 = (e % (K1 / 8)) * 8;
+    uint16_t v[8];
+    if (k0 < FP) {
+      const uint4 q = *(const uint4*)(feat + (row0 + r) * FP + k0);
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (k0 + i >= NF) v[i] = 0;
+    *(uint4*)(sX + r * PX + k0) = make_uint4((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+                                             (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sXt[(k0 + i) * PT + r] = v[i];
+  }
+  for (int e = t; e < (224 - K1) * ROWS; e += NT) sXt[(K1 + e / ROWS) * PT + e % ROWS] = 0;
+  for (int e = t; e < NO * NH; e += NT) sW3[e] = params[oW3 + e];
+  bf16x8 bw1[13], bw2[8];
+  load_weight_frags(w1b, w2b, bw1, bw2);
+  const float bias1 = params[oB1 + J], bias2 = params[oB2 + J];
+  __syncthreads();
+
+  f32x16 ds1[2], ds2[2];
+  forward_hidden<true>(sX, sH1, sH1t, sH2, bw1, bw2, bias1, bias2, ds1, ds2);
+
+  // output layer, loss and dy = 2 (y - target) / (3 batch)
+  float se = 0.f;
+  if (t < ROWS * NO) {
+    const float y = output_layer(sH2, sW3, params + oB3, t);
+    const float d = y - target[(row0 + t / 3) * NO + t % 3];
+    se = d * d;
+    sdy[t] = 2.0f * d / (float)(NO * batch);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) se += __shfl_xor(se, o);
+  if (lane == 0) sred[wave] = se;
+  __syncthreads();
+  if (t == 0) lpart[blockIdx.x] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
+  // dW3[a][c] = sum_r dy[r][a] h2[r][c]; db3[a] = sum_r dy[r][a]
+  for (int o = t; o < NO * NH; o += NT) {
+    const int a = o / NH, c = o % NH;
+    float g = 0.f;
+    for (int r = 0; r < ROWS; ++r) g = fmaf(sdy[r * NO + a], sH2[r * PH2 + c], g);
+    gp[oW3 + o] = g;
+  }
+  if (t < NO) {
+    float g = 0.f;
+    for (int r = 0; r < ROWS; ++r) g += sdy[r * NO + t];
+    gp[oB3 + t] = g;
+  }
+  __syncthreads();  // every read of h2 is done: R2 now takes dz2
+
+  // dz2 = (dy W3) * silu'(z2), stored as BF16 row-major and transposed
+  {
+    float db = 0.f;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int v0 = 0; v0 < 16; v0 += 4) {
+        uint16_t hb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 32 * rt + acc_row(v0 + q, hi);
+          const float dh = sdy[r * NO] * sW3[J] + sdy[r * NO + 1] * sW3[NH + J] + sdy[r * NO + 2] * sW3[2 * NH + J];
+          const float dz = dh * ds2[rt][v0 + q];
+          db += dz;
+          hb[q] = f32_to_bf16_rne(dz);
+          sdZ2[r * PH + J] = hb[q];
+        }
+        *(uint2*)(sdZ2t + J * PT + 32 * rt + acc_row(v0, hi)) =
+            make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
+      }
+    db += __shfl_xor(db, 32);
+    if (hi == 0) gp[oB2 + J] = db;
+  }
+  __syncthreads();
+
+  // dh1 = dz2 W2 (unit J of layer 1), dz1 = dh1 * silu'(z1) -> transposed BF16
+  {
+    f32x16 acc[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[rt][v] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const bf16x8 b = frag(w2bt, NH, J, 16 * s + 8 * hi);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) acc[rt] = mfma(frag(sdZ2, PH, 32 * rt + r32, 16 * s + 8 * hi), b, acc[rt]);
+    }
+    float db = 0.f;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int v0 = 0; v0 < 16; v0 += 4) {
+        uint16_t hb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float dz = acc[rt][v0 + q] * ds1[rt][v0 + q];
+          db += dz;
+          hb[q] = f32_to_bf16_rne(dz);
+        }
+        *(uint2*)(sdZ1t + J * PT + 32 * rt + acc_row(v0, hi)) =
+            make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
+      }
+    db += __shfl_xor(db, 32);
+    if (hi == 0) gp[oB1 + J] = db;
+  }
+  // dW2[i][j] = sum_r dz2[r][i] h1[r][j]: rows i of tile `wave`, 4 column tiles
+  {
+    f32x16 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[nt][v] = 0.f;
+#pragma unroll
+    for (int s = 0; s < ROWS / 16; ++s) {
+      const bf16x8 a = frag(sdZ2t, PT, 32 * wave + r32, 16 * s + 8 * hi);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma(a, frag(sH1t, PT, 32 * nt + r32, 16 * s + 8 * hi), acc[nt]);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) gp[oW2 + (32 * wave + acc_row(v, hi)) * NH + 32 * nt + r32] = acc[nt][v];
+  }
+  __syncthreads();  // dz1 complete
+  // dW1[i][f] = sum_r dz1[r][i] x[r][f] for f < 195: 7 column tiles in two passes
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    constexpr int NTP = 4;
+    f32x16 acc[NTP];
+#pragma unroll
+    for (int q = 0; q < NTP; ++q)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
+    const int nt0 = pass * NTP;
+    const int ntn = pass == 0 ? NTP : 7 - NTP;
+#pragma unroll
+    for (int s = 0; s < ROWS / 16; ++s) {
+      const bf16x8 a = frag(sdZ1t, PT, 32 * wave + r32, 16 * s + 8 * hi);
+#pragma unroll
+      for (int q = 0; q < NTP; ++q)
+        if (q < ntn) acc[q] = mfma(a, frag(sXt, PT, 32 * (nt0 + q) + r32, 16 * s + 8 * hi), acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NTP; ++q) {
+      const int fcol = 32 * (nt0 + q) + r32;
+      if (q < ntn && fcol < NF)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) gp[oW1 + (32 * wave + acc_row(v, hi)) * NF + fcol] = acc[q][v];
+    }
+  }
+}
+
+// Sum of the workgroups' gradients, then (mode 1) one Adam step with BF16
+// copies of W1, W2 (and W2 transposed), (mode 0) the gradient and loss only,
+// (mode 2) the BF16 copies only.
+__global__ __launch_bounds__(NT) void k_update(float* params, float* m, float* v, const float* gpart,
+                                               const float* lpart, LearnedUpdate u, uint16_t* w1b, uint16_t* w2b,
+                                               uint16_t* w2bt) {
+  const int e = blockIdx.x * NT + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && u.loss_out && u.mode != 2) {
+    float l = 0.f;
+    for (int w = 0; w < u.nparts; ++w) l += lpart[w];
+    u.loss_out[0] = l * u.loss_scale;
+  }
+  if (e >= kLearnedNParams) return;
+  float p = params[e];
+  if (u.mode != 2) {
+    float g = 0.f;
+    for (int w = 0; w < u.nparts; ++w) g += gpart[(int64_t)w * kLearnedNParams + e];
+    if (u.mode == 0) {
+      u.grad_out[e] = g;
+      return;
+    }
+    const float mm = u.beta1 * m[e] + (1.0f - u.beta1) * g;
+    const float vv = u.beta2 * v[e] + (1.0f - u.beta2) * g * g;
+    m[e] = mm;
+    v[e] = vv;
+    p -= u.lr * (mm * u.c1) / (sqrtf(vv * u.c2) + u.eps);
+    params[e] = p;
+  }
+  const uint16_t b = f32_to_bf16_rne(p);
+  if (e < oB1) {
+    w1b[(e / NF) * K1 + e % NF] = b;
+  } else if (e >= oW2 && e < oB2) {
+    const int j = (e - oW2) / NH, k = (e - oW2) % NH;
+    w2b[j * NH + k] = b;
+    w2bt[k * NH + j] = b;
+  }
+}
+
+// ---------------------------------------------------------------- inference
+// Particles in bin order, 64 per chunk; every workgroup keeps its layer
+// weights in registers and walks chunks blockIdx.x, + gridDim.x, ...
+__global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X, int64_t n, const uint32_t* orig,
+                                                 const float* params, const uint16_t* w1b, const uint16_t* w2b,
+                                                 float* out, int* flag) {
+  constexpr int RX = ROWS * PH2 * 4;  // features, then h2
+  static_assert(RX >= ROWS * PX * 2, "feature tile");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[RX + ROWS * PH * 2];
+  __shared__ __attribute__((aligned(16))) float sW3[NO * NH];
+  __shared__ float sU[ROWS * NO];
+  __shared__ float sB3[NO];
+  uint16_t* sX = (uint16_t*)lds;
+  float* sH2 = (float*)lds;
+  uint16_t* sH1 = (uint16_t*)(lds + RX);
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int J = 32 * wave + (lane & 31);
+  for (int e = t; e < NO * NH; e += NT) sW3[e] = params[oW3 + e];
+  if (t < NO) sB3[t] = params[oB3 + t];
+  bf16x8 bw1[13], bw2[8];
+  load_weight_frags(w1b, w2b, bw1, bw2);
+  const float bias1 = params[oB1 + J], bias2 = params[oB2 + J];
+  f32x16 unused1[2], unused2[2];
+  const int64_t nchunks = (n + ROWS - 1) / ROWS;
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int pi = t >> 2, k3 = t & 3;
+    const int64_t p = min(ch * ROWS + pi, n - 1);
+    const bool active = ch * ROWS + pi < n;
+    const double x[3] = {X[3 * p], X[3 * p + 1], X[3 * p + 2]};
+    const bool ok = in_domain3(x[0], x[1], x[2]);
+    if (active && !ok && k3 == 0) atomicOr(flag, 1);
+    int c[3];
+    double td[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) locate(ok ? x[d] : 0.0, f.N, f.invd, &c[d], &td[d]);
+    uint16_t fe[48];
+    float u[3];
+    stencil_plane(f, c, td, k3, fe, u);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = quad_sum(u[a]);
+    uint16_t* row = sX + pi * PX;
+#pragma unroll
+    for (int q = 0; q < 12; ++q)
+      *(uint2*)(row + 48 * k3 + 4 * q) = make_uint2((uint32_t)fe[4 * q] | ((uint32_t)fe[4 * q + 1] << 16),
+                                                    (uint32_t)fe[4 * q + 2] | ((uint32_t)fe[4 * q + 3] << 16));
+    if (k3 == 0) {
+      row[192] = f32_to_bf16_rne((float)td[0]);
+      row[193] = f32_to_bf16_rne((float)td[1]);
+      row[194] = f32_to_bf16_rne((float)td[2]);
+      sU[pi * NO] = u[0];
+      sU[pi * NO + 1] = u[1];
+      sU[pi * NO + 2] = u[2];
+    } else if (k3 == 1) {
+#pragma unroll
+      for (int k = NF; k < PX; ++k) row[k] = 0;
+    }
+    __syncthreads();
+    forward_hidden<false>(sX, sH1, nullptr, sH2, bw1, bw2, bias1, bias2, unused1, unused2);
+    if (t < ROWS * NO) {
+      const int r = t / 3, a = t % 3;
+      const int64_t q = ch * ROWS + r;
+      const float y = output_layer(sH2, sW3, sB3, t);
+      if (q < n) out[3 * (int64_t)(orig ? orig[q] : (uint32_t)q) + a] = sU[r * NO + a] + y;
+    }
+    __syncthreads();  // h2 and sU are read before the next chunk overwrites them
+  }
+}
+
+// ---------------------------------------------------------------- audit
+__global__ void k_stride_gather(const double* X, int64_t stride, int64_t na, double* Xa) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= na) return;
+  const int64_t p = i * stride;
+  Xa[3 * i] = X[3 * p];
+  Xa[3 * i + 1] = X[3 * p + 1];
+  Xa[3 * i + 2] = X[3 * p + 2];
+}
+
+// sums[0] = sum |out[k i] - uw[i]|^2, sums[1] = sum |uw[i]|^2 in FP64; one block
+__global__ __launch_bounds__(1024) void k_audit(const float* out, int64_t stride, int64_t na, const float* uw,
+                                                double* sums) {
+  __shared__ double se[1024], sr[1024];
+  double e = 0.0, r = 0.0;
+  for (int64_t i = threadIdx.x; i < na; i += 1024)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double w = uw[3 * i + a];
+      const double d = (double)out[3 * (i * stride) + a] - w;
+      e += d * d;
+      r += w * w;
+    }
+  se[threadIdx.x] = e;
+  sr[threadIdx.x] = r;
+  __syncthreads();
+  for (int h = 512; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      se[threadIdx.x] += se[threadIdx.x + h];
+      sr[threadIdx.x] += sr[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sums[0] = se[0];
+    sums[1] = sr[0];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_learned_pairs(const LearnedField& f, const double* X, int64_t n, const float* uwide,
+                                uint16_t* feat, float* target, int* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (4 * n + NT - 1) / NT;
+  k_pairs<<<(unsigned)blocks, NT, 0, s>>>(f, X, n, uwide, feat, target, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_forward_backward(const uint16_t* feat, const float* target, int64_t batch,
+                                           const float* params, const uint16_t* w1b, const uint16_t* w2b,
+                                           const uint16_t* w2bt, float* gpart, float* lpart, hipStream_t s) {
+  if (batch <= 0 || batch % ROWS) return hipErrorInvalidValue;
+  k_forward_backward<<<(unsigned)(batch / ROWS), NT, 0, s>>>(feat, target, batch, params, w1b, w2b, w2bt, gpart,
+                                                             lpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_update(float* params, float* m, float* v, const float* gpart, const float* lpart,
+                                 const LearnedUpdate& u, uint16_t* w1b, uint16_t* w2b, uint16_t* w2bt,
+                                 hipStream_t s) {
+  const int blocks = (kLearnedNParams + NT - 1) / NT;
+  k_update<<<blocks, NT, 0, s>>>(params, m, v, gpart, lpart, u, w1b, w2b, w2bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_infer(const LearnedField& f, const double* X, int64_t n, const uint32_t* orig,
+                                const float* params, const uint16_t* w1b, const uint16_t* w2b, float* out,
+                                int* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nchunks = (n + ROWS - 1) / ROWS;
+  const int64_t grid = min(nchunks, (int64_t)256 * 2 * 4);
+  k_infer<<<(unsigned)grid, NT, 0, s>>>(f, X, n, orig, params, w1b, w2b, out, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_stride_gather(const double* X, int64_t stride, int64_t na, double* Xa, hipStream_t s) {
+  if (na <= 0) return hipSuccess;
+  k_stride_gather<<<(unsigned)((na + 255) / 256), 256, 0, s>>>(X, stride, na, Xa);
+  return hipGetLastError();
+}
+
+hipError_t launch_audit(const float* out, int64_t stride, int64_t na, const float* uw, double* sums,
+                        hipStream_t s) {
+  k_audit<<<1, 1024, 0, s>>>(out, stride, na, uw, sums);
+  return hipGetLastError();
+}
+
+}  // namespace ptk

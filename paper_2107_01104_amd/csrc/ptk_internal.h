@@ -17,6 +17,10 @@ constexpr int kTileF32 = 12;       // FP32, BF16, FP16 storage
 constexpr int kTileF64 = 8;        // FP64 storage
 constexpr int kWindow = 4;
 constexpr double kL = 6.283185307179586;  // fl64(2*pi)
+// learned correction form: features per particle, their row pitch, parameters
+constexpr int kLearnedNFeat = 195;
+constexpr int kLearnedPitch = 200;
+constexpr int kLearnedNParams = 41987;
 
 // Coefficients of beta_j (val) and d beta_j / dt (der) for node index
 // c = 0..I-1 (offset c - (I/2 - 1)), ascending powers of t.
@@ -43,7 +47,7 @@ struct FieldGeom {
 
 // Kernel timing (ptk_timing_enable / ptk_timing_read): event pairs recorded on
 // the call's stream around each instrumented launch sequence.
-constexpr int kTimerKinds = 6;
+constexpr int kTimerKinds = 7;
 struct TimedPair {
   hipEvent_t start, stop;
   int kind;
@@ -76,6 +80,11 @@ struct ptk_ctx {
   // scratch
   ptk::DevBuf keys_a, keys_b, vals_a, vals_b, offsets, hist, scan_tmp, flag;
   ptk::DevBuf xs, xn, orig, orig_b, k1, k2, h0, h1, h0b, h1b, gint, stage;
+  // learned form: FP32 master parameters, Adam moments, BF16 layer copies,
+  // per-workgroup gradient and loss partials, audit scratch
+  ptk::DevBuf lparams, lm, lv, lw1b, lw2b, lw2bt, lgpart, llpart, lwide, laudit_x, laudit_u, laudit_sums;
+  bool learned_ready = false;
+  int64_t learned_step = 0;
   size_t bytes_in_use = 0;
   size_t byte_cap = 0;      // 0 = unlimited (test hook PTK_TEST_MAX_BYTES)
   bool check = true;        // PTK_NO_CHECK clears it

@@ -22,11 +22,14 @@ F64, F32, BF16, F16 = 0, 1, 2, 3
 LAGRANGE, SPLINE = 0, 1
 EULER, HEUN, AB2 = 1, 2, 3
 OK, EINVAL, ENOFIELD, ENOMEM, EHIP, EDOMAIN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-TIMERS = ["interp", "interp_grad", "sort", "keys", "update", "permute"]
+TIMERS = ["interp", "interp_grad", "sort", "keys", "update", "permute", "learned"]
+LEARNED_NFEAT, LEARNED_FEAT_PITCH, LEARNED_NPARAMS = 195, 200, 41987
 
 EXPORTS = ["ptk_kernel_table", "ptk_create", "ptk_destroy", "ptk_last_error", "ptk_set_field", "ptk_get_field_scale",
            "ptk_locate", "ptk_interpolate", "ptk_interpolate_gradient", "ptk_advance_particles",
-           "ptk_binning_info", "ptk_get_binning", "ptk_timing_enable", "ptk_timing_read"]
+           "ptk_binning_info", "ptk_get_binning", "ptk_timing_enable", "ptk_timing_read",
+           "ptk_learned_make_pairs", "ptk_learned_set_params", "ptk_learned_get_params", "ptk_learned_loss_grad",
+           "ptk_learned_train", "ptk_interpolate_learned"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2107_01104_amd/build.py (or "
@@ -37,6 +40,11 @@ lib = ctypes.CDLL(LIB_PATH)
 
 class ptk_kernel(ctypes.Structure):
     _fields_ = [("family", ctypes.c_int), ("I", ctypes.c_int), ("m", ctypes.c_int)]
+
+
+class ptk_train_config(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
 _vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
@@ -57,6 +65,13 @@ lib.ptk_binning_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)
 lib.ptk_get_binning.argtypes = [_vp, _vp, _vp, _vp]
 lib.ptk_timing_enable.argtypes = [_vp, _int]
 lib.ptk_timing_read.argtypes = [_vp, _vp, _vp]
+lib.ptk_learned_make_pairs.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
+lib.ptk_learned_set_params.argtypes = [_vp, _vp]
+lib.ptk_learned_get_params.argtypes = [_vp, _vp]
+lib.ptk_learned_loss_grad.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp]
+lib.ptk_learned_train.argtypes = [_vp, _vp, _vp, _i64, ctypes.POINTER(ptk_train_config), _vp, _vp]
+lib.ptk_interpolate_learned.argtypes = [_vp, _vp, _i64, _vp, _dbl, _dbl, ctypes.POINTER(_dbl),
+                                        ctypes.POINTER(_int), _vp]
 for _name in EXPORTS:
     if _name not in ("ptk_destroy", "ptk_last_error"):
         getattr(lib, _name).restype = _int
@@ -76,6 +91,12 @@ ptk_binning_info = lib.ptk_binning_info
 ptk_get_binning = lib.ptk_get_binning
 ptk_timing_enable = lib.ptk_timing_enable
 ptk_timing_read = lib.ptk_timing_read
+ptk_learned_make_pairs = lib.ptk_learned_make_pairs
+ptk_learned_set_params = lib.ptk_learned_set_params
+ptk_learned_get_params = lib.ptk_learned_get_params
+ptk_learned_loss_grad = lib.ptk_learned_loss_grad
+ptk_learned_train = lib.ptk_learned_train
+ptk_interpolate_learned = lib.ptk_interpolate_learned
 
 
 def kernel_table(family: int, I: int, m: int = 0):
@@ -233,3 +254,64 @@ class Context:
         cnt = np.zeros(len(TIMERS), dtype=np.int64)
         self._check(lib.ptk_timing_read(self._h, ms.ctypes.data_as(_vp), cnt.ctypes.data_as(_vp)))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(TIMERS)}
+
+    # ---- learned correction form
+    def learned_make_pairs(self, X: torch.Tensor, features: bool = True, targets: bool = True):
+        """(feat uint16 [Np, 200] BF16 bits, target float32 [Np, 3]) at positions X."""
+        _dev_tensor(X, torch.float64, (3,), "X")
+        n = X.numel() // 3
+        feat = torch.empty((n, LEARNED_FEAT_PITCH), dtype=torch.int16, device=X.device) if features else None
+        tgt = torch.empty((n, 3), dtype=torch.float32, device=X.device) if targets else None
+        self._check(lib.ptk_learned_make_pairs(self._h, _ptr(X), n, _ptr(feat), _ptr(tgt), _stream(self.device)))
+        return feat, tgt
+
+    def learned_set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        if p.size != LEARNED_NPARAMS:
+            raise ValueError(f"expected {LEARNED_NPARAMS} parameters")
+        self._check(lib.ptk_learned_set_params(self._h, p.ctypes.data_as(_vp)))
+
+    def learned_get_params(self):
+        import numpy as np
+        p = np.empty(LEARNED_NPARAMS, dtype=np.float32)
+        self._check(lib.ptk_learned_get_params(self._h, p.ctypes.data_as(_vp)))
+        return p
+
+    def learned_loss_grad(self, feat: torch.Tensor, target: torch.Tensor):
+        """(loss float32 [1], grad float32 [41987]) of one batch, no update."""
+        _dev_tensor(feat, torch.int16, (LEARNED_FEAT_PITCH,), "feat")
+        _dev_tensor(target, torch.float32, (3,), "target")
+        n = feat.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+        grad = torch.empty(LEARNED_NPARAMS, dtype=torch.float32, device=feat.device)
+        self._check(lib.ptk_learned_loss_grad(self._h, _ptr(feat), _ptr(target), n, _ptr(loss), _ptr(grad),
+                                              _stream(self.device)))
+        return loss, grad
+
+    def learned_train(self, feat: torch.Tensor, target: torch.Tensor, epochs: int, batch: int = 4096,
+                      lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        """Adam over consecutive batches; returns the per-step loss curve (float32 tensor)."""
+        _dev_tensor(feat, torch.int16, (LEARNED_FEAT_PITCH,), "feat")
+        _dev_tensor(target, torch.float32, (3,), "target")
+        n = feat.shape[0]
+        steps = int(epochs) * (n // int(batch))
+        curve = torch.empty(max(steps, 1), dtype=torch.float32, device=feat.device)
+        cfg = ptk_train_config(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps))
+        self._check(lib.ptk_learned_train(self._h, _ptr(feat), _ptr(target), n, ctypes.byref(cfg), _ptr(curve),
+                                          _stream(self.device)))
+        return curve[:steps]
+
+    def interpolate_learned(self, X: torch.Tensor, audit_frac: float = 1e-3, tol_rel_rms: float = float("inf"),
+                            out=None):
+        """(out float32 [Np, 3], audit_rms, fell_back)."""
+        _dev_tensor(X, torch.float64, (3,), "X")
+        n = X.numel() // 3
+        if out is None:
+            out = torch.empty((n, 3), dtype=torch.float32, device=X.device)
+        a = _dbl()
+        fb = _int()
+        self._check(lib.ptk_interpolate_learned(self._h, _ptr(X), n, _ptr(out), float(audit_frac),
+                                                float(tol_rel_rms), ctypes.byref(a), ctypes.byref(fb),
+                                                _stream(self.device)))
+        return out, a.value, bool(fb.value)

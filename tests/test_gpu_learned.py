@@ -1,0 +1,264 @@
+"""GPU parity of the learned correction form against the oracle (marked gpu).
+
+Bars:
+* features: bit-exact (BF16 bits; entries 195..199 zero);
+* targets (u_wide - u_L4, two FP32 sums): per element within
+  64 * 2^-24 * (A_wide + A_L4), A the sums of |terms| (as for every FP32 sum);
+* one batch's loss and gradient: against the oracle with the same BF16
+  operand roundings -- relative Frobenius difference <= 1e-3 per tensor (FP32
+  summation order, the hardware exponential in silu, and the rare BF16
+  rounding of an activation that FP32 differences push across a rounding
+  boundary) -- and against plain FP64 within 2e-2 (the BF16 operands);
+* Adam steps: updates (params - start) within 1e-2 relative Frobenius of the
+  oracle's, per tensor; loss curves within 1e-3 relative;
+* inference: u_L4 part by the FP32 bound, network part RMS within 2e-4 and
+  max within 1e-2 of the RMS of the network output (same reasons);
+* audit and fallback as stated in the header.
+Every oracle input (features, targets, parameters) is built by the oracle.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import geometry, interp
+from oracle import kernels as K
+from oracle import learned as LN
+from oracle.precision import bf16_bits_to_f64
+from synthetic import fields, particles
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+F32_BOUND = 64 * 2.0 ** -24
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def fro(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def params_init(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    p = np.empty(LN.N_PARAMS)
+    o = 0
+    for _, shape in LN.SHAPES:
+        n = int(np.prod(shape))
+        fan_in = shape[1] if len(shape) == 2 else 1
+        p[o:o + n] = rng.standard_normal(n) * scale / math.sqrt(fan_in)
+        o += n
+    return p.astype(np.float32)
+
+
+@pytest.fixture(scope="module")
+def ptk():
+    from paper_2107_01104_amd import ptk as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def setup(ptk):
+    N = 32
+    u = fields.spectral_field(N, kc=10.0, seed=3).numpy().astype(np.float32)
+    ctx = ptk.Context(0)
+    ctx.set_field(torch.from_numpy(u).to(DEV), K.SPLINE, 8, 2, storage=ptk.F32)
+    yield ctx, u
+    ctx.close()
+
+
+def edge_positions(N):
+    invd = geometry.inv_delta(N)
+    L = geometry.L
+    xs = [0.0, -0.0, -1e-300, L, math.nextafter(L, 0.0), -L, 3 * L, 1e6, -0.5,
+          math.nextafter(0.0, -1.0)] + [j / invd for j in range(0, N, 3)]
+    xs = np.array(xs)
+    rng = np.random.default_rng(0)
+    return np.stack([xs, rng.permutation(xs), rng.permutation(xs)], axis=1)
+
+
+def test_pairs_features_and_targets(ptk, setup):
+    ctx, u = setup
+    say("[learned pairs] N=32, 3000 uniform + edge positions")
+    X = np.concatenate([edge_positions(32), particles.uniform_particles(3000, seed=21).numpy()])
+    feat, tgt = ctx.learned_make_pairs(torch.from_numpy(X).to(DEV))
+    feat = feat.cpu().numpy().view(np.uint16)
+    tgt = tgt.cpu().numpy().astype(np.float64)
+    ref_f = LN.features(u, X)
+    assert np.array_equal(feat[:, :195], ref_f)
+    assert not feat[:, 195:].any()
+    ref_t = LN.targets(u, X, K.SPLINE, 8, 2)
+    a_w = interp.interp_vec(u, X, K.SPLINE, 8, 2, absolute=True)
+    a_n = interp.interp_vec(u, X, K.LAGRANGE, 4, 0, absolute=True)
+    assert np.all(np.abs(tgt - ref_t) <= F32_BOUND * (a_w + a_n))
+    # either output alone
+    f2, t2 = ctx.learned_make_pairs(torch.from_numpy(X).to(DEV), targets=False)
+    assert t2 is None and np.array_equal(f2.cpu().numpy().view(np.uint16), feat)
+
+
+def _oracle_batch(u, n, seed):
+    X = particles.uniform_particles(n, seed=seed).numpy()
+    fb = LN.features(u, X)
+    tg = LN.targets(u, X, K.SPLINE, 8, 2)
+    feat = np.zeros((n, 200), dtype=np.uint16)
+    feat[:, :195] = fb
+    return X, fb, tg, feat
+
+
+def _dev_feat(feat):
+    return torch.from_numpy(feat.view(np.int16)).to(DEV)
+
+
+def test_loss_and_gradient(ptk, setup):
+    ctx, u = setup
+    say("[learned loss/grad] batch 512")
+    _, fb, tg, feat = _oracle_batch(u, 512, 22)
+    p = params_init(5)
+    ctx.learned_set_params(p)
+    np.testing.assert_array_equal(ctx.learned_get_params(), p)
+    tg32 = tg.astype(np.float32)
+    loss, grad = ctx.learned_loss_grad(_dev_feat(feat), torch.from_numpy(tg32).to(DEV))
+    loss = float(loss.cpu().numpy()[0])
+    grad = grad.cpu().numpy().astype(np.float64)
+    x = bf16_bits_to_f64(fb)
+    l_em, g_em = LN.loss_and_grads(p.astype(np.float64), x, tg32.astype(np.float64), emulate_bf16=True)
+    l_64, g_64 = LN.loss_and_grads(p.astype(np.float64), x, tg32.astype(np.float64))
+    assert abs(loss - l_em) <= 1e-4 * l_em
+    o = 0
+    for name, shape in LN.SHAPES:
+        n = int(np.prod(shape))
+        e_em = fro(grad[o:o + n], g_em[o:o + n])
+        e_64 = fro(grad[o:o + n], g_64[o:o + n])
+        say(f"  {name}: vs emulated {e_em:.2e}, vs fp64 {e_64:.2e}")
+        assert e_em <= 1e-3, name
+        assert e_64 <= 2e-2, name
+        o += n
+
+
+def test_adam_steps(ptk, setup):
+    ctx, u = setup
+    say("[learned train] 2 epochs x 4 batches of 128")
+    _, fb, tg, feat = _oracle_batch(u, 512, 23)
+    p0 = params_init(6)
+    ctx.learned_set_params(p0)
+    tg32 = tg.astype(np.float32)
+    curve = ctx.learned_train(_dev_feat(feat), torch.from_numpy(tg32).to(DEV), epochs=2, batch=128, lr=1e-3)
+    got = ctx.learned_get_params().astype(np.float64)
+    ref, losses = LN.train(p0.astype(np.float64), fb, tg32.astype(np.float64), epochs=2, batch=128, lr0=1e-3,
+                           emulate_bf16=True)
+    curve = curve.cpu().numpy().astype(np.float64)
+    assert curve.shape == (8,)
+    assert np.all(np.abs(curve - losses) <= 1e-3 * losses)
+    o = 0
+    for name, shape in LN.SHAPES:
+        n = int(np.prod(shape))
+        e = fro(got[o:o + n] - p0[o:o + n], ref[o:o + n] - p0[o:o + n])
+        say(f"  {name}: update difference {e:.2e}")
+        assert e <= 1e-2, name
+        o += n
+
+
+def test_inference_and_audit(ptk, setup):
+    ctx, u = setup
+    say("[learned infer] N=32, 4000 particles")
+    p = params_init(7, scale=0.3)
+    ctx.learned_set_params(p)
+    X = np.concatenate([edge_positions(32), particles.uniform_particles(4000, seed=24).numpy()])
+    out, audit, fell = ctx.interpolate_learned(torch.from_numpy(X).to(DEV), audit_frac=0.05)
+    out = out.cpu().numpy().astype(np.float64)
+    assert not fell
+    narrow = interp.interp_vec(u, X, K.LAGRANGE, 4, 0)
+    a_n = interp.interp_vec(u, X, K.LAGRANGE, 4, 0, absolute=True)
+    y, _ = LN.forward(p.astype(np.float64), bf16_bits_to_f64(LN.features(u, X)), emulate_bf16=True)
+    d = out - (narrow + y)
+    ry = float(np.sqrt(np.mean(y * y)))
+    say(f"  rms(y) {ry:.3e}  rms diff {np.sqrt(np.mean(d * d)):.3e}  max diff {np.max(np.abs(d)):.3e}")
+    assert np.sqrt(np.mean(d * d)) <= 2e-4 * ry
+    assert np.all(np.abs(d) <= 1e-2 * ry + F32_BOUND * a_n)
+    # audit: particles 0, 20, 40, ... against the wide kernel, on the oracle's output
+    _, ref_audit, ref_fell = LN.infer(p.astype(np.float64), u, X, K.SPLINE, 8, 2, audit_frac=0.05,
+                                      tol_rel_rms=np.inf, emulate_bf16=True)
+    assert not ref_fell
+    assert audit == pytest.approx(ref_audit, rel=1e-3)
+
+
+def test_fallback(ptk, setup):
+    ctx, u = setup
+    say("[learned fallback] tol 0")
+    ctx.learned_set_params(params_init(8, scale=0.3))
+    X = particles.uniform_particles(2000, seed=25).numpy()
+    Xd = torch.from_numpy(X).to(DEV)
+    out, audit, fell = ctx.interpolate_learned(Xd, audit_frac=0.01, tol_rel_rms=0.0)
+    assert fell and audit > 0
+    wide = interp.interp_vec(u, X, K.SPLINE, 8, 2)
+    a_w = interp.interp_vec(u, X, K.SPLINE, 8, 2, absolute=True)
+    out = out.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(out - wide) <= F32_BOUND * a_w)
+    # tolerance above the audit: no fallback
+    _, audit2, fell2 = ctx.interpolate_learned(Xd, audit_frac=0.01, tol_rel_rms=audit * 1.01)
+    assert not fell2 and audit2 == pytest.approx(audit, rel=1e-6)
+
+
+def test_errors_and_empty(ptk, setup):
+    ctx, u = setup
+    say("[learned errors]")
+    e = torch.empty((0, 3), dtype=torch.float64, device=DEV)
+    out, audit, fell = ctx.interpolate_learned(e)
+    assert out.shape == (0, 3) and audit == 0.0 and not fell
+    with pytest.raises(ptk.PtkError) as ei:
+        ctx.interpolate_learned(torch.tensor([[float("nan"), 0.0, 0.0]], dtype=torch.float64, device=DEV))
+    assert ei.value.code == ptk.EDOMAIN
+    feat = torch.zeros((100, 200), dtype=torch.int16, device=DEV)
+    tg = torch.zeros((100, 3), dtype=torch.float32, device=DEV)
+    with pytest.raises(ptk.PtkError) as ei:
+        ctx.learned_loss_grad(feat, tg)          # 100 is not a multiple of 64
+    assert ei.value.code == ptk.EINVAL
+    with pytest.raises(ptk.PtkError) as ei:
+        ctx.learned_train(feat[:64], tg[:64], epochs=1, batch=96)
+    assert ei.value.code == ptk.EINVAL
+    c2 = ptk.Context(0)
+    with pytest.raises(ptk.PtkError) as ei:
+        c2.learned_make_pairs(torch.zeros((4, 3), dtype=torch.float64, device=DEV))
+    assert ei.value.code == ptk.ENOFIELD
+    c2.set_field(torch.from_numpy(u.astype(np.float64)).to(DEV), K.SPLINE, 8, 2, storage=ptk.F64)
+    with pytest.raises(ptk.PtkError) as ei:
+        c2.learned_make_pairs(torch.zeros((4, 3), dtype=torch.float64, device=DEV))
+    assert ei.value.code == ptk.EUNSUPPORTED
+    c2.set_field(torch.from_numpy(u).to(DEV), K.SPLINE, 8, 2, storage=ptk.F32)
+    with pytest.raises(ptk.PtkError) as ei:
+        c2.interpolate_learned(torch.zeros((4, 3), dtype=torch.float64, device=DEV))
+    assert ei.value.code == ptk.EINVAL          # no parameters yet
+    c2.close()
+
+
+def test_learning_gain(ptk):
+    """Training on the library's own pairs reduces the error of u_L4 against
+    the wide kernel (evaluated by the oracle on held-out particles)."""
+    say("[learned gain] N=64 spectral field, 2^20 pairs, 8 epochs")
+    N = 64
+    u = fields.spectral_field(N, kc=340.0 * N / 1024, seed=100).numpy().astype(np.float32)
+    ctx = ptk.Context(0)
+    ctx.set_field(torch.from_numpy(u).to(DEV), K.SPLINE, 8, 2, storage=ptk.F32)
+    Xt = particles.uniform_particles(1 << 20, seed=101, device=DEV)
+    feat, tg = ctx.learned_make_pairs(Xt)
+    p0 = params_init(9, scale=0.5)
+    p0[LN.unpack(np.arange(LN.N_PARAMS))["W3"].reshape(-1)] = 0.0   # the correction starts at zero
+    p0[LN.unpack(np.arange(LN.N_PARAMS))["b3"]] = 0.0
+    ctx.learned_set_params(p0)
+    curve = ctx.learned_train(feat, tg, epochs=8, batch=4096, lr=1e-3).cpu().numpy()
+    Xe = particles.uniform_particles(4000, seed=102).numpy()
+    out, _, _ = ctx.interpolate_learned(torch.from_numpy(Xe).to(DEV), audit_frac=1.0)
+    wide = interp.interp_vec(u, Xe, K.SPLINE, 8, 2)
+    narrow = interp.interp_vec(u, Xe, K.LAGRANGE, 4, 0)
+    gap = float(np.sqrt(np.mean((narrow - wide) ** 2)))
+    res = float(np.sqrt(np.mean((out.cpu().numpy() - wide) ** 2)))
+    say(f"  loss {curve[0]:.3e} -> {curve[-1]:.3e}; rms(u_L4 - u_wide) {gap:.3e}, "
+        f"rms(learned - u_wide) {res:.3e}, gain {gap / res:.2f}")
+    assert curve[-1] < curve[0]
+    assert res < 0.8 * gap
+    ctx.close()
