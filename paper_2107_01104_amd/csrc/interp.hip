@@ -277,7 +277,10 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
   for (int e = 0; e < NV; ++e) r[e] = rowsum(r[e]);
 }
 
-template <int ST, int I, bool GRAD>
+// SPARSE: for launches with few particles per window -- visit only the
+// non-empty windows of each segment and fill the ring afresh for each,
+// instead of sweeping every plane.
+template <int ST, int I, bool GRAD, bool SPARSE>
 __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a) {
   using V = typename StoreT<ST>::acc;
   using Gm = Geom<ST, I>;
@@ -308,18 +311,6 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
   const int64_t x0 = (int64_t)tx * T, y0 = (int64_t)ty * T;
   const int tid = threadIdx.x;
 
-  // ---- initial fill: planes [W*w_begin, W*w_begin + W + I - 1)
-  {
-    const int64_t z_lo = W * w_begin;
-    constexpr int UNITS = (W + I - 1) * Gm::UNITS_PER_PLANE;
-    for (int u = tid; u < UNITS; u += NT) {
-      uint4 c[3];
-      const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
-      if (load_unit<ST, I>(a, x0, y0, z_lo + pl, uu, c)) store_unit<ST, I>(smem, z_lo + pl, uu, c);
-    }
-  }
-  __syncthreads();
-
   // ---- per-lane constants
   const int l16 = tid & 15;
   const int j = l16 & 7;              // x1 node offset
@@ -340,6 +331,17 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
   }
   const int N = a.N;
   const double invd = a.invd;
+
+  // ---- fill the ring with the planes window w touches: [W*w, W*w + W + I - 1)
+  auto fill = [&](int64_t w) {
+    const int64_t z_lo = W * w;
+    constexpr int UNITS = (W + I - 1) * Gm::UNITS_PER_PLANE;
+    for (int u = tid; u < UNITS; u += NT) {
+      uint4 c[3];
+      const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
+      if (load_unit<ST, I>(a, x0, y0, z_lo + pl, uu, c)) store_unit<ST, I>(smem, z_lo + pl, uu, c);
+    }
+  };
 
   // ---- software pipeline over windows: while window w is computed, the
   // positions of window w+1 and the planes window w+2 adds are in flight
@@ -492,6 +494,31 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
     if (more) write_rec(w + 1, n1, xv, qv);
   };
 
+  {
+    const int64_t bin0 = tile * a.nw;
+    if (a.offsets[bin0 + w_begin] == a.offsets[bin0 + w_end]) return;  // no particle in this segment
+    if constexpr (SPARSE) {
+      for (int64_t w = w_begin; w < w_end; ++w) {
+        const uint32_t start = a.offsets[bin0 + w], end = a.offsets[bin0 + w + 1];
+        if (start == end) continue;
+        fill(w);
+        for (uint32_t c0 = start; c0 < end; c0 += CH) {
+          const int m = (int)min((int64_t)CH, (int64_t)end - (int64_t)c0);
+          double xm;
+          uint32_t qm;
+          issue_pos(c0, m, xm, qm);
+          write_rec(w, m, xm, qm);
+          __syncthreads();  // ring and records complete
+          compute_chunk(m);
+          __syncthreads();  // every read done before the next fill
+        }
+      }
+      return;
+    }
+  }
+  fill(w_begin);
+  __syncthreads();
+
   // ---- prologue: records of the first window, planes of the second in flight
   {
     const int64_t bin = tile * a.nw + w_begin;
@@ -519,10 +546,19 @@ static hipError_t launch_one(const InterpArgs& a, hipStream_t s) {
   const int64_t grid = (nblk + 7) / 8 * 8;
   if (grid == 0) return hipSuccess;
   constexpr int NT = StoreT<ST>::THREADS;
-  if (a.grad)
-    k_interp<ST, I, true><<<(unsigned)grid, NT, 0, s>>>(a);
-  else
-    k_interp<ST, I, false><<<(unsigned)grid, NT, 0, s>>>(a);
+  // sparse when one fresh ring per particle loads fewer planes than the sweep
+  const bool sparse = a.np * (kWindow + I - 1) < a.n_tiles * a.nw * kWindow;
+  if (a.grad) {
+    if (sparse)
+      k_interp<ST, I, true, true><<<(unsigned)grid, NT, 0, s>>>(a);
+    else
+      k_interp<ST, I, true, false><<<(unsigned)grid, NT, 0, s>>>(a);
+  } else {
+    if (sparse)
+      k_interp<ST, I, false, true><<<(unsigned)grid, NT, 0, s>>>(a);
+    else
+      k_interp<ST, I, false, false><<<(unsigned)grid, NT, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 

@@ -40,7 +40,8 @@ __device__ __forceinline__ bf16x8 frag(const uint16_t* base, int pitch, int row,
 __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// logistic function through the hardware exponential and reciprocal
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float dsilu(float z) {
   const float s = sigm(z);
@@ -49,17 +50,52 @@ __device__ __forceinline__ float dsilu(float z) {
 // row of result register v of this lane within a 32-row tile
 __device__ __forceinline__ int acc_row(int v, int hi) { return 8 * (v >> 2) + 4 * hi + (v & 3); }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// two FP32 values rounded to BF16 (nearest even, one conversion instruction)
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, v);
+}
+__device__ __forceinline__ uint16_t to_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+
+// value of lane L of this lane's group of 4
+template <int L>
+__device__ __forceinline__ int quad_bcast(int v) {
+  return __builtin_amdgcn_mov_dpp(v, L * 0x55, 0xF, 0xF, true);
+}
+
 __device__ __forceinline__ float quad_sum(float v) {
   v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
   v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, true));
   return v;
 }
 
+typedef float f32x4a __attribute__((ext_vector_type(4), aligned(4)));
+
+// Steps 1-3 of Sec. 2.2 for the particle of this lane's group of 4: lane k
+// (k < 3) locates coordinate k, and the group shares cells and offsets.
+// Returns whether this lane's coordinate is inside the domain (lane 3: true).
+__device__ __forceinline__ bool locate_quad(const double* Xp, int k3, int N, double invd, int* c, double* td) {
+  const double x = Xp[k3 < 3 ? k3 : 2];
+  const bool ok = k3 == 3 || in_domain(x);
+  int cc;
+  double tt;
+  locate(ok ? x : 0.0, N, invd, &cc, &tt);
+  const long long tb = __double_as_longlong(tt);
+  int lo = (int)(tb & 0xFFFFFFFFll), hi = (int)(tb >> 32);
+#define PTK_Q(d)                                                                                   \
+  c[d] = quad_bcast<d>(cc);                                                                        \
+  td[d] = __longlong_as_double(((long long)(unsigned)quad_bcast<d>(hi) << 32) | (unsigned)quad_bcast<d>(lo));
+  PTK_Q(0) PTK_Q(1) PTK_Q(2)
+#undef PTK_Q
+  return ok;
+}
+
 // One quarter of a particle's 4 x 4 x 4 stencil (the x3 plane k3): its 48
-// BF16 features, written to feat[48*k3 ...], and its part of the Lagrange
-// I = 4 sum.  Offsets t (FP64, exact) and cells come from locate().
+// BF16 features, packed in pairs into fe[24] in feature order, and its part
+// of the Lagrange I = 4 sum.
 __device__ __forceinline__ void stencil_plane(const LearnedField& f, const int* c, const double* td, int k3,
-                                              uint16_t* feat, float* u) {
+                                              uint32_t* fe, float* u) {
   float w[3][4];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -78,18 +114,19 @@ __device__ __forceinline__ void stencil_plane(const LearnedField& f, const int* 
 #pragma unroll
   for (int k2 = 0; k2 < 4; ++k2) {
     const int64_t y = c[1] - 1 + k2 + f.halo_lo;
-    const float* row = (const float*)(plane + y * f.row_pitch) + 3 * (c[0] - 1 + f.halo_lo);
+    // the 4 nodes of the row: 12 consecutive floats, 4-byte aligned
+    const f32x4a* row = (const f32x4a*)((const float*)(plane + y * f.row_pitch) + 3 * (c[0] - 1 + f.halo_lo));
+    const f32x4a q0 = row[0], q1 = row[1], q2 = row[2];
+    const float v[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
     const float w23 = w[2][k3] * w[1][k2];
 #pragma unroll
     for (int k1 = 0; k1 < 4; ++k1) {
       const float ww = w23 * w[0][k1];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const float v = row[3 * k1 + a];
-        u[a] = fmaf(ww, v, u[a]);
-        feat[(k2 * 4 + k1) * 3 + a] = f32_to_bf16_rne(v);
-      }
+      for (int a = 0; a < 3; ++a) u[a] = fmaf(ww, v[3 * k1 + a], u[a]);
     }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) fe[6 * k2 + q] = pack_bf16(v[2 * q], v[2 * q + 1]);
   }
 }
 
@@ -101,14 +138,11 @@ __global__ __launch_bounds__(NT) void k_pairs(LearnedField f, const double* X, i
   const int64_t p = min(g >> 2, n - 1);
   const int k3 = (int)(g & 3);
   const bool active = (g >> 2) < n;
-  const double x[3] = {X[3 * p], X[3 * p + 1], X[3 * p + 2]};
-  const bool ok = in_domain3(x[0], x[1], x[2]);
-  if (active && !ok && k3 == 0) atomicOr(flag, 1);
   int c[3];
   double td[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) locate(ok ? x[d] : 0.0, f.N, f.invd, &c[d], &td[d]);
-  uint16_t fe[48];
+  const bool ok = locate_quad(X + 3 * p, k3, f.N, f.invd, c, td);
+  if (active && !ok) atomicOr(flag, 1);
+  uint32_t fe[24];
   float u[3];
   stencil_plane(f, c, td, k3, fe, u);
 #pragma unroll
@@ -117,15 +151,11 @@ __global__ __launch_bounds__(NT) void k_pairs(LearnedField f, const double* X, i
   if (feat) {
     uint2* dst = (uint2*)(feat + p * FP + 48 * k3);
 #pragma unroll
-    for (int q = 0; q < 12; ++q)
-      dst[q] = make_uint2((uint32_t)fe[4 * q] | ((uint32_t)fe[4 * q + 1] << 16),
-                          (uint32_t)fe[4 * q + 2] | ((uint32_t)fe[4 * q + 3] << 16));
+    for (int q = 0; q < 12; ++q) dst[q] = make_uint2(fe[2 * q], fe[2 * q + 1]);
     if (k3 == 0) {
       uint32_t* tail = (uint32_t*)(feat + p * FP + 192);
-      const uint16_t t0 = f32_to_bf16_rne((float)td[0]), t1 = f32_to_bf16_rne((float)td[1]),
-                     t2 = f32_to_bf16_rne((float)td[2]);
-      tail[0] = (uint32_t)t0 | ((uint32_t)t1 << 16);
-      tail[1] = (uint32_t)t2;
+      tail[0] = pack_bf16((float)td[0], (float)td[1]);
+      tail[1] = (uint32_t)to_bf16((float)td[2]);
       tail[2] = 0u;
       tail[3] = 0u;
     }
@@ -161,17 +191,20 @@ __device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
     for (int v0 = 0; v0 < 16; v0 += 4) {
-      uint16_t hb[4];
+      float h[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float z = acc[rt][v0 + q] + bias1;
-        hb[q] = f32_to_bf16_rne(silu(z));
+        h[q] = silu(z);
         if constexpr (TRAIN) ds1[rt][v0 + q] = dsilu(z);
-        sH1[(32 * rt + acc_row(v0 + q, hi)) * PH + J] = hb[q];
       }
-      if (sH1t)
-        *(uint2*)(sH1t + J * PT + 32 * rt + acc_row(v0, hi)) =
-            make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
+      const uint32_t p01 = pack_bf16(h[0], h[1]), p23 = pack_bf16(h[2], h[3]);
+      const int r0 = 32 * rt + acc_row(v0, hi);
+      sH1[r0 * PH + J] = (uint16_t)p01;
+      sH1[(r0 + 1) * PH + J] = (uint16_t)(p01 >> 16);
+      sH1[(r0 + 2) * PH + J] = (uint16_t)p23;
+      sH1[(r0 + 3) * PH + J] = (uint16_t)(p23 >> 16);
+      if (sH1t) *(uint2*)(sH1t + J * PT + r0) = make_uint2(p01, p23);
     }
   __syncthreads();  // h1 complete; sX is dead from here on
 #pragma unroll
@@ -325,18 +358,21 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
       for (int v0 = 0; v0 < 16; v0 += 4) {
-        uint16_t hb[4];
+        float dz[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = 32 * rt + acc_row(v0 + q, hi);
           const float dh = sdy[r * NO] * sW3[J] + sdy[r * NO + 1] * sW3[NH + J] + sdy[r * NO + 2] * sW3[2 * NH + J];
-          const float dz = dh * ds2[rt][v0 + q];
-          db += dz;
-          hb[q] = f32_to_bf16_rne(dz);
-          sdZ2[r * PH + J] = hb[q];
+          dz[q] = dh * ds2[rt][v0 + q];
+          db += dz[q];
         }
-        *(uint2*)(sdZ2t + J * PT + 32 * rt + acc_row(v0, hi)) =
-            make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
+        const uint32_t p01 = pack_bf16(dz[0], dz[1]), p23 = pack_bf16(dz[2], dz[3]);
+        const int r0 = 32 * rt + acc_row(v0, hi);
+        sdZ2[r0 * PH + J] = (uint16_t)p01;
+        sdZ2[(r0 + 1) * PH + J] = (uint16_t)(p01 >> 16);
+        sdZ2[(r0 + 2) * PH + J] = (uint16_t)p23;
+        sdZ2[(r0 + 3) * PH + J] = (uint16_t)(p23 >> 16);
+        *(uint2*)(sdZ2t + J * PT + r0) = make_uint2(p01, p23);
       }
     db += __shfl_xor(db, 32);
     if (hi == 0) gp[oB2 + J] = db;
@@ -361,15 +397,14 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
       for (int v0 = 0; v0 < 16; v0 += 4) {
-        uint16_t hb[4];
+        float dz[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float dz = acc[rt][v0 + q] * ds1[rt][v0 + q];
-          db += dz;
-          hb[q] = f32_to_bf16_rne(dz);
+          dz[q] = acc[rt][v0 + q] * ds1[rt][v0 + q];
+          db += dz[q];
         }
         *(uint2*)(sdZ1t + J * PT + 32 * rt + acc_row(v0, hi)) =
-            make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
+            make_uint2(pack_bf16(dz[0], dz[1]), pack_bf16(dz[2], dz[3]));
       }
     db += __shfl_xor(db, 32);
     if (hi == 0) gp[oB1 + J] = db;
@@ -449,7 +484,7 @@ __global__ __launch_bounds__(NT) void k_update(float* params, float* m, float* v
     p -= u.lr * (mm * u.c1) / (sqrtf(vv * u.c2) + u.eps);
     params[e] = p;
   }
-  const uint16_t b = f32_to_bf16_rne(p);
+  const uint16_t b = to_bf16(p);
   if (e < oB1) {
     w1b[(e / NF) * K1 + e % NF] = b;
   } else if (e >= oW2 && e < oB2) {
@@ -488,27 +523,21 @@ __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X
     const int pi = t >> 2, k3 = t & 3;
     const int64_t p = min(ch * ROWS + pi, n - 1);
     const bool active = ch * ROWS + pi < n;
-    const double x[3] = {X[3 * p], X[3 * p + 1], X[3 * p + 2]};
-    const bool ok = in_domain3(x[0], x[1], x[2]);
-    if (active && !ok && k3 == 0) atomicOr(flag, 1);
     int c[3];
     double td[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) locate(ok ? x[d] : 0.0, f.N, f.invd, &c[d], &td[d]);
-    uint16_t fe[48];
+    const bool ok = locate_quad(X + 3 * p, k3, f.N, f.invd, c, td);
+    if (active && !ok) atomicOr(flag, 1);
+    uint32_t fe[24];
     float u[3];
     stencil_plane(f, c, td, k3, fe, u);
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = quad_sum(u[a]);
     uint16_t* row = sX + pi * PX;
 #pragma unroll
-    for (int q = 0; q < 12; ++q)
-      *(uint2*)(row + 48 * k3 + 4 * q) = make_uint2((uint32_t)fe[4 * q] | ((uint32_t)fe[4 * q + 1] << 16),
-                                                    (uint32_t)fe[4 * q + 2] | ((uint32_t)fe[4 * q + 3] << 16));
+    for (int q = 0; q < 12; ++q) *(uint2*)(row + 48 * k3 + 4 * q) = make_uint2(fe[2 * q], fe[2 * q + 1]);
     if (k3 == 0) {
-      row[192] = f32_to_bf16_rne((float)td[0]);
-      row[193] = f32_to_bf16_rne((float)td[1]);
-      row[194] = f32_to_bf16_rne((float)td[2]);
+      *(uint32_t*)(row + 192) = pack_bf16((float)td[0], (float)td[1]);
+      row[194] = to_bf16((float)td[2]);
       sU[pi * NO] = u[0];
       sU[pi * NO + 1] = u[1];
       sU[pi * NO + 2] = u[2];

@@ -187,6 +187,43 @@ def test_interp_f32_storage(ptk, fam, I, m):
     ctx.close()
 
 
+def _check_storage(storage, uv, g, ru, rg, au, ag):
+    if storage == "f64":
+        assert rel_max(uv, ru) <= 1e-12 and rel_max(g, rg) <= 1e-12
+    else:
+        assert within_f32_bound(uv, ru, au) and within_f32_bound(g, rg, ag)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("N,Np,clustered", [(128, 1, False), (128, 37, False), (256, 3000, False),
+                                            (128, 600, True), (32, 20000, True)])
+def test_interp_sparse_and_clustered(ptk, storage, N, Np, clustered):
+    """Few particles per window select the sparse launch (a fresh ring for each
+    non-empty window); clustered particles put more than one chunk into a
+    window (both launch variants).  The (32, 20000) case is a dense launch."""
+    say(f"[interp sparse/clustered] {storage} N={N} Np={Np} clustered={clustered}")
+    rng = np.random.default_rng(N + Np)
+    u = rng.standard_normal((N, N, N, 3))
+    if storage == "f32":
+        u = u.astype(np.float32)
+    ctx = ptk.Context(0)
+    ctx.set_field(torch.from_numpy(u).to(DEV), K.SPLINE, 8, 2, storage=ptk.F64 if storage == "f64" else ptk.F32)
+    if clustered:
+        X = np.array([1.3, 2.9, 4.4]) + rng.uniform(0.0, 2.5 * L / N, (Np, 3))
+    else:
+        X = rng.uniform(-L, 2 * L, (Np, 3))
+    dt = torch.float64 if storage == "f64" else torch.float32
+    Xd = torch.from_numpy(X).to(DEV)
+    uv, g = ctx.interpolate_gradient(Xd, out_dtype=dt)
+    val = ctx.interpolate(Xd, out_dtype=dt)
+    ru, rg = interp.interp_vec(u.astype(np.float64), X, K.SPLINE, 8, 2, gradient=True)
+    au, ag = interp.interp_vec(u.astype(np.float64), X, K.SPLINE, 8, 2, gradient=True, absolute=True)
+    uv, g = uv.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+    _check_storage(storage, uv, g, ru, rg, au, ag)
+    _check_storage(storage, val.cpu().numpy().astype(np.float64), g, ru, rg, au, ag)
+    ctx.close()
+
+
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
 def test_interp_reduced_storage_tight(ptk, storage):
     say(f"[interp {storage}]")
