@@ -618,18 +618,16 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     const bool last = step == nsteps - 1;
     // u(X_n), and its gradient, at the bin-ordered positions
     {
+      // the last step writes the gradient straight to the caller's order
       InterpArgs a = base_args(c);
       a.X = xs;
       a.np = Np;
       a.out = k1;
-      a.grad = grad_out ? c->gint.ptr : nullptr;
+      a.grad = grad_out ? (last ? grad_out : c->gint.ptr) : nullptr;
+      a.grad_orig = grad_out && last ? orig : nullptr;
       a.out_f64 = vf64;
       Timed t(c, s, grad_out ? PTK_T_INTERP_GRAD : PTK_T_INTERP);
       PTK_HIP(c, launch_interp(c->storage, c->I, a, s), "interpolate");
-    }
-    if (grad_out && last) {
-      Timed t(c, s, PTK_T_PERMUTE);
-      PTK_HIP(c, scatter_v(c->gint.ptr, orig, 9, grad_out), "scatter gradient");
     }
     if (scheme == PTK_EULER) {
       PTK_TRY(update(kEulerOrPredict, k1, nullptr));

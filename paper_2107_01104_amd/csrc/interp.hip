@@ -93,6 +93,24 @@ template <int L, typename V>
 __device__ __forceinline__ V bcast(V v) {
   return dpp<0x150 + L>(v);
 }
+// lanes 0-7 of the row get lane L0's value, lanes 8-15 lane L1's: the second
+// move writes only DPP banks 2 and 3 (lanes 8-15) over the first
+template <int L0, int L1>
+__device__ __forceinline__ float bcast2(float v) {
+  const int a = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x150 + L0, 0xF, 0xF, true);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(a, __builtin_bit_cast(int, v), 0x150 + L1, 0xF, 0xC, false));
+}
+template <int L0, int L1>
+__device__ __forceinline__ double bcast2(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = (int)(b & 0xFFFFFFFFll), hi = (int)(b >> 32);
+  const int alo = __builtin_amdgcn_mov_dpp(lo, 0x150 + L0, 0xF, 0xF, true);
+  const int ahi = __builtin_amdgcn_mov_dpp(hi, 0x150 + L0, 0xF, 0xF, true);
+  const int rlo = __builtin_amdgcn_update_dpp(alo, lo, 0x150 + L1, 0xF, 0xC, false);
+  const int rhi = __builtin_amdgcn_update_dpp(ahi, hi, 0x150 + L1, 0xF, 0xC, false);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)rhi << 32) | (unsigned)rlo));
+}
+
 // sum over the 16 lanes of the row (every lane gets the total)
 template <typename V>
 __device__ __forceinline__ V rowsum(V v) {
@@ -206,8 +224,9 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
   using Gm = Geom<ST, I>;
   constexpr int NB = Gm::NB, RP = Gm::RP, PL = Gm::PL, R = Gm::R;
   constexpr int HALF = I / 2;
-  // planes of this lane: k = 2m + par, m = 0..I/2-1 (slot (z3 + k) mod R has parity h)
-  const int par = (z3 + h) & 1;
+  // planes of this lane: k = 2m + h, m = 0..I/2-1; the two halves read planes
+  // one ring slot apart (or R - 1 apart across the wrap; R is even), an odd
+  // number of plane pitches
   // weights: lanes 0-7 evaluate beta_j(t2), lanes 8-15 beta_j(t3); all lanes beta_j(t1)
   const V tsel = h ? t3 : t2;
   const V wsel = horner<I>(cv, tsel);
@@ -217,7 +236,7 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
 #define PTK_B2(k) if constexpr ((k) < I) w2[k] = bcast<k>(wsel);
   PTK_B2(0) PTK_B2(1) PTK_B2(2) PTK_B2(3) PTK_B2(4) PTK_B2(5) PTK_B2(6) PTK_B2(7)
 #undef PTK_B2
-#define PTK_B3(m) if constexpr ((m) < HALF) { const V e = bcast<8 + 2 * (m)>(wsel), o = bcast<9 + 2 * (m)>(wsel); w3[m] = par ? o : e; }
+#define PTK_B3(m) if constexpr ((m) < HALF) w3[m] = bcast2<8 + 2 * (m), 9 + 2 * (m)>(wsel);
   PTK_B3(0) PTK_B3(1) PTK_B3(2) PTK_B3(3)
 #undef PTK_B3
   V d1 = (V)0, dw2[I], dw3[HALF];
@@ -228,13 +247,13 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
 #define PTK_D2(k) if constexpr ((k) < I) dw2[k] = bcast<k>(dsel);
     PTK_D2(0) PTK_D2(1) PTK_D2(2) PTK_D2(3) PTK_D2(4) PTK_D2(5) PTK_D2(6) PTK_D2(7)
 #undef PTK_D2
-#define PTK_D3(m) if constexpr ((m) < HALF) { const V e = bcast<8 + 2 * (m)>(dsel), o = bcast<9 + 2 * (m)>(dsel); dw3[m] = par ? o : e; }
+#define PTK_D3(m) if constexpr ((m) < HALF) dw3[m] = bcast2<8 + 2 * (m), 9 + 2 * (m)>(dsel);
     PTK_D3(0) PTK_D3(1) PTK_D3(2) PTK_D3(3)
 #undef PTK_D3
   }
   // contraction: x2 over all rows per plane, x3 over this lane's planes
   const int noff = l2 * RP + (l1 + jj) * NB;
-  const int s0 = (z3 + par) % R;
+  const int s0 = (z3 + h) % R;
   V acc[3] = {0, 0, 0}, ad2[3] = {0, 0, 0}, ad3[3] = {0, 0, 0};
 #pragma unroll
   for (int m = 0; m < HALF; ++m) {
@@ -262,24 +281,47 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
       }
     }
   }
-  // x1 weight, then the sum over the group's 16 lanes
+  // x1 weight, then the sum over the group's 16 lanes.  Values: r[q] = u_q,
+  // r[3 + 3q + b] = d u_q / d x_b (before the 1/delta factor).
+  V e[GRAD ? 12 : 3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    r[q] = w1 * acc[q];
+    e[q] = w1 * acc[q];
     if constexpr (GRAD) {
-      r[3 + 3 * q + 0] = d1 * acc[q];
-      r[3 + 3 * q + 1] = w1 * ad2[q];
-      r[3 + 3 * q + 2] = w1 * ad3[q];
+      e[3 + 3 * q + 0] = d1 * acc[q];
+      e[3 + 3 * q + 1] = w1 * ad2[q];
+      e[3 + 3 * q + 2] = w1 * ad3[q];
     }
   }
-  constexpr int NV = GRAD ? 12 : 3;
+  if constexpr (!GRAD) {
+    // every lane gets the 3 totals
 #pragma unroll
-  for (int e = 0; e < NV; ++e) r[e] = rowsum(r[e]);
+    for (int q = 0; q < 3; ++q) r[q] = rowsum(e[q]);
+  } else {
+    // reduce-scatter: lanes l and l^8 split the 12 values 6/6, then lanes j and
+    // 7-j of each half split their 6 values 3/3, then each quad sums its 3.
+    // Lane l16 ends with the totals of values 6*(l16/8) + 3*((l16/4)&1) + k,
+    // k = 0..2, in r[k].
+    const int b2 = (j >> 2) & 1;
+    V f[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const V keep = h ? e[6 + k] : e[k];
+      const V send = h ? e[k] : e[6 + k];
+      f[k] = keep + dpp<0x128>(send);  // row_ror:8, the lane 8 away
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const V keep = b2 ? f[3 + k] : f[k];
+      const V send = b2 ? f[k] : f[3 + k];
+      V g = keep + dpp<0x141>(send);   // row_half_mirror, lane 7-j
+      g += dpp<0xB1>(g);
+      g += dpp<0x4E>(g);
+      r[k] = g;
+    }
+  }
 }
 
-// SPARSE: for launches with few particles per window -- visit only the
-// non-empty windows of each segment and fill the ring afresh for each,
-// instead of sweeping every plane.
 template <int ST, int I, bool GRAD, bool SPARSE>
 __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a) {
   using V = typename StoreT<ST>::acc;
@@ -291,7 +333,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
   constexpr int NV = GRAD ? 12 : 3;
   constexpr int CH = NT / 3 / GROUPS * GROUPS;  // particles located per chunk: one thread per coordinate
   // particle record: t1, t2, t3 (V) at 0; cells l1, l2, z3 (u16) at 32;
-  // destination index (u32) at 40
+  // destination indices (u32) of the values at 40 and of the gradient at 44
   constexpr int RECB = 48;
   __shared__ __attribute__((aligned(16))) unsigned char smem[Gm::LDS];
   __shared__ __attribute__((aligned(16))) unsigned char recs[CH * RECB];
@@ -376,7 +418,9 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
     const int pi = min(tid / 3, max(n - 1, 0));
     const int64_t p = min((int64_t)c0 + pi, (int64_t)a.np - 1);
     xv = a.X[3 * p + tid % 3];
-    qv = a.orig ? a.orig[p] : (uint32_t)p;
+    // axis-1 threads fetch the gradient destination, the others the value one
+    const uint32_t* src = (tid % 3 == 1 && a.grad_orig) ? a.grad_orig : a.orig;
+    qv = src ? src[p] : (uint32_t)p;
   };
   // steps 1-3 of Sec. 2.2 once per coordinate: one thread per (particle, axis)
   auto write_rec = [&](int64_t wr, int n, double xv, uint32_t qv) {
@@ -399,6 +443,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
         ((float*)rp)[ax] = (float)td;
       ((uint16_t*)(rp + 32))[ax] = (uint16_t)lc;
       if (ax == 0) *(uint32_t*)(rp + 40) = qv;
+      if (ax == 1) *(uint32_t*)(rp + 44) = qv;
     }
   };
   auto compute_chunk = [&](int n) {
@@ -423,33 +468,34 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
         asm volatile("" ::"v"(tf.w));  // keep the record reads 16 bytes wide
       }
       const uint4 lc = *(const uint4*)(rp + 32);
-      asm volatile("" ::"v"(lc.w));
       const int l1 = (int)(lc.x & 0xFFFFu), l2 = (int)(lc.x >> 16), z3 = (int)(lc.y & 0xFFFFu);
-      V r[NV];
+      V r[3];
       particle_sums<ST, I, GRAD>(smem, cv, cd, j, jj, h, t1, t2, t3, l1, l2, z3, r);
-      // lane e < NV writes result e: select it without branches
+      // which of its three totals this lane writes, and which value that is
+      const int sub = GRAD ? (l16 & 3) : l16;
+      const int ev = GRAD ? 6 * (l16 >> 3) + 3 * ((l16 >> 2) & 1) + (l16 & 3) : l16;
       V val = r[0];
-#pragma unroll
-      for (int e = 1; e < NV; ++e) val = (l16 == e) ? r[e] : val;
-      if (active && l16 < NV) {
-        const int64_t q = (int64_t)lc.z;
-        if (l16 < 3) {
+      val = sub == 1 ? r[1] : val;
+      val = sub == 2 ? r[2] : val;
+      if (active && sub < 3) {
+        const int64_t q = (int64_t)(ev < 3 ? lc.z : lc.w);
+        if (ev < 3) {
           if (ST == ST_BF16 || ST == ST_F16)
-            val *= (V)(l16 == 0 ? a.scale[0] : l16 == 1 ? a.scale[1] : a.scale[2]);
+            val *= (V)(ev == 0 ? a.scale[0] : ev == 1 ? a.scale[1] : a.scale[2]);
           if (a.out) {
             if (a.out_f64)
-              ((double*)a.out)[3 * q + l16] = (double)val;
+              ((double*)a.out)[3 * q + ev] = (double)val;
             else
-              ((float*)a.out)[3 * q + l16] = (float)val;
+              ((float*)a.out)[3 * q + ev] = (float)val;
           }
         } else {
           val *= (V)invd;
           if (ST == ST_BF16 || ST == ST_F16)
-            val *= (V)(l16 < 6 ? a.scale[0] : l16 < 9 ? a.scale[1] : a.scale[2]);
+            val *= (V)(ev < 6 ? a.scale[0] : ev < 9 ? a.scale[1] : a.scale[2]);
           if (a.out_f64)
-            ((double*)a.grad)[9 * q + (l16 - 3)] = (double)val;
+            ((double*)a.grad)[9 * q + (ev - 3)] = (double)val;
           else
-            ((float*)a.grad)[9 * q + (l16 - 3)] = (float)val;
+            ((float*)a.grad)[9 * q + (ev - 3)] = (float)val;
         }
       }
     }

@@ -53,6 +53,7 @@ struct InterpArgs {
   int64_t np;               // number of particles
   const uint32_t* offsets;  // [n_bins + 1]
   const uint32_t* orig;     // destination index of each bin-ordered particle, or NULL
+  const uint32_t* grad_orig;  // destination index of its gradient row, or NULL (= orig)
   void* out;                // [n][3] or NULL
   void* grad;               // [n][3][3] or NULL
   int out_f64;
