@@ -178,20 +178,35 @@ int ensure_binning(ptk_ctx* c, int64_t Np, int64_t n_bins) {
   PTK_TRY(ensure(c, c->vals_b, n4));
   const size_t hw = sort_hist_words(Np);
   PTK_TRY(ensure(c, c->hist, hw * 4));
-  PTK_TRY(ensure(c, c->scan_tmp, scan_tmp_words((int64_t)hw) * 4));
+  const int64_t scan_max = (int64_t)hw > n_bins + 1 ? (int64_t)hw : n_bins + 1;
+  PTK_TRY(ensure(c, c->scan_tmp, scan_tmp_words(scan_max) * 4));
   PTK_TRY(ensure(c, c->offsets, (size_t)(n_bins + 1) * 4));
   return PTK_OK;
 }
 
+// scratch of the incremental re-binning (in addition to ensure_binning's)
+int ensure_rebin(ptk_ctx* c, int64_t Np, int64_t n_bins) {
+  const size_t n4 = (size_t)Np * 4, b4 = (size_t)(n_bins + 1) * 4;
+  DevBuf* per_particle[] = {&c->skeys, &c->skeys2, &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b};
+  for (DevBuf* b : per_particle) PTK_TRY(ensure(c, *b, n4));
+  DevBuf* per_bin[] = {&c->offsets2, &c->rb_in, &c->rb_out, &c->rb_inc};
+  for (DevBuf* b : per_bin) PTK_TRY(ensure(c, *b, b4));
+  PTK_TRY(ensure(c, c->rb_block, rebin_block_words(Np) * 4));
+  return PTK_OK;
+}
+
 // keys -> stable sort -> offsets.  keys of the particles must be in keys_a.
-int bin_sorted(ptk_ctx* c, int64_t Np, int64_t n_bins, uint32_t** perm, hipStream_t s) {
+// *skeys (optional) receives the sorted keys' location.
+int bin_sorted(ptk_ctx* c, int64_t Np, int64_t n_bins, uint32_t** perm, hipStream_t s,
+               uint32_t** skeys = nullptr) {
   uint32_t* sk = nullptr;
   PTK_HIP(c,
           radix_sort_keys((uint32_t*)c->keys_a.ptr, (uint32_t*)c->keys_b.ptr, (uint32_t*)c->vals_a.ptr,
-                          (uint32_t*)c->vals_b.ptr, Np, bits_for(n_bins), (uint32_t*)c->hist.ptr,
+                          (uint32_t*)c->vals_b.ptr, Np, nullptr, false, bits_for(n_bins), (uint32_t*)c->hist.ptr,
                           (uint32_t*)c->scan_tmp.ptr, &sk, perm, s),
           "radix sort");
   PTK_HIP(c, launch_offsets(sk, Np, n_bins, (uint32_t*)c->offsets.ptr, s), "bin offsets");
+  if (skeys) *skeys = sk;
   return PTK_OK;
 }
 
@@ -374,7 +389,8 @@ void ptk_destroy(ptk_ctx* c) {
                       &c->hist, &c->scan_tmp, &c->flag, &c->xs, &c->xn, &c->orig, &c->orig_b, &c->k1,
                       &c->k2, &c->h0, &c->h1, &c->h0b, &c->h1b, &c->gint, &c->stage, &c->lparams,
                       &c->lm, &c->lv, &c->lw1b, &c->lw2b, &c->lw2bt, &c->lgpart, &c->llpart, &c->lwide,
-                      &c->laudit_x, &c->laudit_u, &c->laudit_sums};
+                      &c->laudit_x, &c->laudit_u, &c->laudit_sums, &c->skeys, &c->skeys2, &c->offsets2,
+                      &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->rb_in, &c->rb_out, &c->rb_inc, &c->rb_block};
     for (DevBuf* b : bufs) release(*b);
     for (TimedPair& p : c->pending) {
       (void)hipEventDestroy(p.start);
@@ -592,9 +608,34 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
             "position update");
     return PTK_OK;
   };
-  auto sort = [&](uint32_t** pm) -> int {
+  PTK_TRY(ensure_rebin(c, Np, n_bins));
+  // re-bin relative to the current (bin-ordered) state: new keys in `keys`;
+  // writes the permutation to vals_a and the new sorted keys / offsets to
+  // skeys2 / offsets2 (the current ones stay valid until swap_bins)
+  auto rebin = [&](uint32_t** pm) -> int {
     Timed t(c, s, PTK_T_SORT);
-    return bin_sorted(c, Np, n_bins, pm, s);
+    RebinScratch w;
+    w.in_start = (uint32_t*)c->rb_in.ptr;
+    w.out_before = (uint32_t*)c->rb_out.ptr;
+    w.inc_before = (uint32_t*)c->rb_inc.ptr;
+    w.blockoff = (uint32_t*)c->rb_block.ptr;
+    w.mk_a = (uint32_t*)c->mk_a.ptr;
+    w.mk_b = (uint32_t*)c->mk_b.ptr;
+    w.mv_a = (uint32_t*)c->mv_a.ptr;
+    w.mv_b = (uint32_t*)c->mv_b.ptr;
+    w.hist = (uint32_t*)c->hist.ptr;
+    w.scan_tmp = (uint32_t*)c->scan_tmp.ptr;
+    PTK_HIP(c,
+            rebin_incremental((const uint32_t*)c->skeys.ptr, (const uint32_t*)c->offsets.ptr, keys, Np, n_bins,
+                              bits_for(n_bins), w, (uint32_t*)c->vals_a.ptr, (uint32_t*)c->skeys2.ptr,
+                              (uint32_t*)c->offsets2.ptr, s),
+            "re-bin");
+    *pm = (uint32_t*)c->vals_a.ptr;
+    return PTK_OK;
+  };
+  auto swap_bins = [&]() {
+    std::swap(c->skeys, c->skeys2);
+    std::swap(c->offsets, c->offsets2);
   };
 
   PTK_HIP(c, hipMemsetAsync(flag, 0, sizeof(int), s), "flag clear");
@@ -604,7 +645,12 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     PTK_HIP(c, launch_keys(X, Np, (int)N, invd, bg, keys, flag, s), "keys");
   }
   uint32_t* perm = nullptr;
-  PTK_TRY(sort(&perm));
+  {
+    Timed t(c, s, PTK_T_SORT);
+    uint32_t* sk = nullptr;
+    PTK_TRY(bin_sorted(c, Np, n_bins, &perm, s, &sk));
+    PTK_HIP(c, hipMemcpyAsync(c->skeys.ptr, sk, (size_t)Np * 4, hipMemcpyDeviceToDevice, s), "sorted keys");
+  }
   {
     Timed t(c, s, PTK_T_PERMUTE);
     PTK_HIP(c, gather3_f64(X, perm, Np, xs, s), "gather positions");
@@ -635,13 +681,14 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
       // predictor, re-binned; u at the predictor is written back in xs order
       PTK_TRY(update(kEulerOrPredict, k1, nullptr));
       uint32_t* pp = nullptr;
-      PTK_TRY(sort(&pp));
+      PTK_TRY(rebin(&pp));
       {
         Timed t(c, s, PTK_T_PERMUTE);
         PTK_HIP(c, gather3_f64(xn, pp, Np, xp, s), "gather predictor");
       }
       {
         InterpArgs b = base_args(c);
+        b.offsets = (const uint32_t*)c->offsets2.ptr;  // the predictor's bins
         b.X = xp;
         b.np = Np;
         b.orig = pp;
@@ -670,7 +717,7 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
       break;
     }
     // re-bin the new positions and carry the per-particle state along
-    PTK_TRY(sort(&perm));
+    PTK_TRY(rebin(&perm));
     {
       Timed t(c, s, PTK_T_PERMUTE);
       PTK_HIP(c, gather3_f64(xn, perm, Np, xs, s), "gather positions");
@@ -680,6 +727,7 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
         if (hl >= 2) PTK_HIP(c, gather_v(h1, perm, h1b), "gather history");
       }
     }
+    swap_bins();
     uint32_t* to = orig;
     orig = orig_b;
     orig_b = to;

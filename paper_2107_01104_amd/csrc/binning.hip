@@ -64,9 +64,12 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kTile = kSortThreads * kSortItems;  // 2048
 
+// n_dev (optional): the element count held on the device; n is then an upper
+// bound that sized the grid, and tiles past the count contribute nothing.
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
-                                                    int shift, uint32_t mask,
+                                                    const uint32_t* __restrict__ n_dev, int shift, uint32_t mask,
                                                     uint32_t* __restrict__ hist, int64_t n_tiles) {
+  if (n_dev) n = min(n, (int64_t)*n_dev);
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -80,9 +83,11 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
 }
 
 __global__ __launch_bounds__(256) void k_radix_scatter(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, int64_t n, int shift,
-    uint32_t mask, int bits, const uint32_t* __restrict__ prefix, int64_t n_tiles,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, int64_t n,
+    const uint32_t* __restrict__ n_dev, int shift, uint32_t mask, int bits, const uint32_t* __restrict__ prefix,
+    int64_t n_tiles, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+  if (n_dev) n = min(n, (int64_t)*n_dev);
+  if ((int64_t)blockIdx.x * kTile >= n) return;
   __shared__ uint32_t wcount[4][256];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -236,6 +241,139 @@ __global__ __launch_bounds__(256) void k_gather_u32(const uint32_t* __restrict__
   out[k] = in[perm[k]];
 }
 
+
+// ---------------------------------------------------------------------------
+// incremental re-binning (particles move less than a cell per step, so few
+// change bins; only those are sorted, the rest keep their relative order)
+// ---------------------------------------------------------------------------
+// Tile of 2048 items: wave w owns items [512w, 512w + 512) of the tile in 8
+// rounds of 64.  For each item: whether its key changed ("mover") and the
+// number of movers before it in the tile.
+struct TileMovers {
+  uint32_t ok[kSortItems], nk[kSortItems], before[kSortItems];
+  bool valid[kSortItems], mover[kSortItems];
+  uint32_t total;
+};
+
+__device__ __forceinline__ void tile_movers(const uint32_t* okeys, const uint32_t* nkeys, int64_t n, TileMovers& t) {
+  __shared__ uint32_t wsum[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t wbase = (int64_t)blockIdx.x * kTile + wave * (64 * kSortItems);
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t run = 0;
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = wbase + r * 64 + lane;
+    t.valid[r] = i < n;
+    t.ok[r] = t.valid[r] ? okeys[i] : 0u;
+    t.nk[r] = t.valid[r] ? nkeys[i] : 0u;
+    t.mover[r] = t.valid[r] && t.ok[r] != t.nk[r];
+    const uint64_t bal = __ballot(t.mover[r]);
+    t.before[r] = run + (uint32_t)__popcll(bal & lt_mask);
+    run += (uint32_t)__popcll(bal);
+  }
+  if (lane == 0) wsum[wave] = run;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) pre += wsum[w];
+    tot += wsum[w];
+  }
+  for (int r = 0; r < kSortItems; ++r) t.before[r] += pre;
+  t.total = tot;
+}
+
+__device__ __forceinline__ int64_t tile_item(int r) {
+  return (int64_t)blockIdx.x * kTile + (threadIdx.x >> 6) * (64 * kSortItems) + r * 64 + (threadIdx.x & 63);
+}
+
+// movers per tile; per bin, movers in (by new key) and out (by old key)
+__global__ __launch_bounds__(256) void k_rebin_count(const uint32_t* __restrict__ okeys,
+                                                     const uint32_t* __restrict__ nkeys, int64_t n,
+                                                     uint32_t* __restrict__ in_cnt, uint32_t* __restrict__ out_cnt,
+                                                     uint32_t* __restrict__ tile_cnt) {
+  TileMovers t;
+  tile_movers(okeys, nkeys, n, t);
+  for (int r = 0; r < kSortItems; ++r)
+    if (t.mover[r]) {
+      atomicAdd(&in_cnt[t.nk[r]], 1u);
+      atomicAdd(&out_cnt[t.ok[r]], 1u);
+    }
+  if (threadIdx.x == 0) tile_cnt[blockIdx.x] = t.total;
+}
+
+// new bin sizes: old size - movers out + movers in; entry n_bins is 0
+__global__ __launch_bounds__(256) void k_rebin_newcnt(const uint32_t* __restrict__ ooff,
+                                                      const uint32_t* __restrict__ in_cnt,
+                                                      const uint32_t* __restrict__ out_cnt, int64_t n_bins,
+                                                      uint32_t* __restrict__ cnt) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b > n_bins) return;
+  cnt[b] = b == n_bins ? 0u : (ooff[b + 1] - ooff[b]) - out_cnt[b] + in_cnt[b];
+}
+
+// movers, in current order, to (mk, mv) = (new key, current index)
+__global__ __launch_bounds__(256) void k_rebin_compact(const uint32_t* __restrict__ okeys,
+                                                       const uint32_t* __restrict__ nkeys, int64_t n,
+                                                       const uint32_t* __restrict__ tile_off,
+                                                       uint32_t* __restrict__ mk, uint32_t* __restrict__ mv) {
+  TileMovers t;
+  tile_movers(okeys, nkeys, n, t);
+  const uint32_t base = tile_off[blockIdx.x];
+  for (int r = 0; r < kSortItems; ++r)
+    if (t.mover[r]) {
+      mk[base + t.before[r]] = t.nk[r];
+      mv[base + t.before[r]] = (uint32_t)tile_item(r);
+    }
+}
+
+// Place the movers, sorted by (new key, current index): in bin b they follow
+// the movers from earlier bins and, if they come from a later bin, the
+// particles that stay in b.  Also counts, per bin, the movers from earlier bins.
+__global__ __launch_bounds__(256) void k_rebin_movers(const uint32_t* __restrict__ sk, const uint32_t* __restrict__ sv,
+                                                      const uint32_t* __restrict__ m_dev,
+                                                      const uint32_t* __restrict__ ooff,
+                                                      const uint32_t* __restrict__ noff,
+                                                      const uint32_t* __restrict__ in_start,
+                                                      const uint32_t* __restrict__ out_before,
+                                                      uint32_t* __restrict__ inc_before, uint32_t* __restrict__ perm,
+                                                      uint32_t* __restrict__ skeys) {
+  const int64_t m = *m_dev;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < m; r += (int64_t)gridDim.x * 256) {
+    const uint32_t b = sk[r], i = sv[r];
+    const bool from_before = i < ooff[b];
+    if (from_before) atomicAdd(&inc_before[b], 1u);
+    const uint32_t stay = (ooff[b + 1] - ooff[b]) - (out_before[b + 1] - out_before[b]);
+    const uint32_t pos = noff[b] + (uint32_t)(r - in_start[b]) + (from_before ? 0u : stay);
+    perm[pos] = i;
+    skeys[pos] = b;
+  }
+}
+
+// Place the particles that stay in their bin b: after the movers from earlier
+// bins, in their current order.
+__global__ __launch_bounds__(256) void k_rebin_stayers(const uint32_t* __restrict__ okeys,
+                                                       const uint32_t* __restrict__ nkeys, int64_t n,
+                                                       const uint32_t* __restrict__ tile_off,
+                                                       const uint32_t* __restrict__ ooff,
+                                                       const uint32_t* __restrict__ noff,
+                                                       const uint32_t* __restrict__ out_before,
+                                                       const uint32_t* __restrict__ inc_before,
+                                                       uint32_t* __restrict__ perm, uint32_t* __restrict__ skeys) {
+  TileMovers t;
+  tile_movers(okeys, nkeys, n, t);
+  const uint32_t base = tile_off[blockIdx.x];
+  for (int r = 0; r < kSortItems; ++r) {
+    if (!t.valid[r] || t.mover[r]) continue;
+    const uint32_t b = t.nk[r];
+    const uint32_t i = (uint32_t)tile_item(r);
+    const uint32_t movers_before = base + t.before[r];         // movers at positions < i
+    const uint32_t out_in_seg = movers_before - out_before[b];  // of them, inside bin b's segment
+    const uint32_t pos = noff[b] + inc_before[b] + (i - ooff[b]) - out_in_seg;
+    perm[pos] = i;
+    skeys[pos] = b;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -271,11 +409,12 @@ hipError_t exclusive_scan_u32(uint32_t* a, int64_t m, uint32_t* tmp, hipStream_t
   return hipGetLastError();
 }
 
-// Stable sort of keys (values = input positions).  On return *keys_sorted and
-// *perm point into {ka, kb} / {va, vb}.
+// Stable sort of keys.  Values: those in va if vals_in_va, else the input
+// positions.  n_dev (optional) holds the element count on the device, n an
+// upper bound.  On return *keys_sorted and *perm point into {ka, kb} / {va, vb}.
 hipError_t radix_sort_keys(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* vb, int64_t n,
-                           int key_bits, uint32_t* hist, uint32_t* tmp, uint32_t** keys_sorted,
-                           uint32_t** perm, hipStream_t s) {
+                           const uint32_t* n_dev, bool vals_in_va, int key_bits, uint32_t* hist,
+                           uint32_t* tmp, uint32_t** keys_sorted, uint32_t** perm, hipStream_t s) {
   if (n == 0) {
     *keys_sorted = ka;
     *perm = va;
@@ -287,14 +426,15 @@ hipError_t radix_sort_keys(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* v
   const uint32_t mask = (1u << bits) - 1u;
   // pass p reads (kin, vin) and writes (kout, vout); the first pass takes the
   // input positions as values
-  uint32_t *kin = ka, *kout = kb, *vin = nullptr, *vout = va, *vspare = vb;
+  uint32_t *kin = ka, *kout = kb, *vin = vals_in_va ? va : nullptr, *vout = vals_in_va ? vb : va,
+           *vspare = vb;
   for (int p = 0; p < passes; ++p) {
     const int shift = p * bits;
-    k_radix_hist<<<(unsigned)n_tiles, 256, 0, s>>>(kin, n, shift, mask, hist, n_tiles);
+    k_radix_hist<<<(unsigned)n_tiles, 256, 0, s>>>(kin, n, n_dev, shift, mask, hist, n_tiles);
     hipError_t e = exclusive_scan_u32(hist, 256 * n_tiles, tmp, s);
     if (e != hipSuccess) return e;
-    k_radix_scatter<<<(unsigned)n_tiles, 256, 0, s>>>(kin, vin, n, shift, mask, bits, hist, n_tiles, kout,
-                                                      vout);
+    k_radix_scatter<<<(unsigned)n_tiles, 256, 0, s>>>(kin, vin, n, n_dev, shift, mask, bits, hist, n_tiles,
+                                                      kout, vout);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint32_t* t = kin;
@@ -307,6 +447,43 @@ hipError_t radix_sort_keys(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* v
   *keys_sorted = kin;
   *perm = vin;
   return hipSuccess;
+}
+
+size_t rebin_block_words(int64_t n) { return (size_t)((n + kTile - 1) / kTile + 2); }
+
+hipError_t rebin_incremental(const uint32_t* okeys, const uint32_t* ooff, const uint32_t* nkeys, int64_t n,
+                             int64_t n_bins, int key_bits, const RebinScratch& w, uint32_t* perm, uint32_t* skeys,
+                             uint32_t* noff, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t n_tiles = (n + kTile - 1) / kTile;
+  const size_t bin_bytes = (size_t)(n_bins + 1) * 4;
+  hipError_t e;
+  if ((e = hipMemsetAsync(w.in_start, 0, bin_bytes, s)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(w.out_before, 0, bin_bytes, s)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(w.inc_before, 0, bin_bytes, s)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(w.blockoff, 0, (size_t)(n_tiles + 1) * 4, s)) != hipSuccess) return e;
+  k_rebin_count<<<(unsigned)n_tiles, 256, 0, s>>>(okeys, nkeys, n, w.in_start, w.out_before, w.blockoff);
+  k_rebin_newcnt<<<blocks_for(n_bins + 1, 256), 256, 0, s>>>(ooff, w.in_start, w.out_before, n_bins, noff);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // noff, in_start, out_before, blockoff: exclusive scans (the last entries
+  // become the totals: n, movers in, movers out, movers)
+  if ((e = exclusive_scan_u32(noff, n_bins + 1, w.scan_tmp, s)) != hipSuccess) return e;
+  if ((e = exclusive_scan_u32(w.in_start, n_bins + 1, w.scan_tmp, s)) != hipSuccess) return e;
+  if ((e = exclusive_scan_u32(w.out_before, n_bins + 1, w.scan_tmp, s)) != hipSuccess) return e;
+  if ((e = exclusive_scan_u32(w.blockoff, n_tiles + 1, w.scan_tmp, s)) != hipSuccess) return e;
+  const uint32_t* m_dev = w.blockoff + n_tiles;
+  k_rebin_compact<<<(unsigned)n_tiles, 256, 0, s>>>(okeys, nkeys, n, w.blockoff, w.mk_a, w.mv_a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  uint32_t *sk = nullptr, *sv = nullptr;
+  if ((e = radix_sort_keys(w.mk_a, w.mk_b, w.mv_a, w.mv_b, n, m_dev, true, key_bits, w.hist, w.scan_tmp, &sk, &sv,
+                           s)) != hipSuccess)
+    return e;
+  const int64_t mgrid = min((int64_t)4096, (n + 255) / 256);
+  k_rebin_movers<<<(unsigned)mgrid, 256, 0, s>>>(sk, sv, m_dev, ooff, noff, w.in_start, w.out_before, w.inc_before,
+                                                 perm, skeys);
+  k_rebin_stayers<<<(unsigned)n_tiles, 256, 0, s>>>(okeys, nkeys, n, w.blockoff, ooff, noff, w.out_before,
+                                                    w.inc_before, perm, skeys);
+  return hipGetLastError();
 }
 
 hipError_t launch_offsets(const uint32_t* skeys, int64_t n, int64_t n_bins, uint32_t* offsets,

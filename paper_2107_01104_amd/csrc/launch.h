@@ -23,8 +23,23 @@ size_t sort_hist_words(int64_t n);
 size_t scan_tmp_words(int64_t m);
 hipError_t exclusive_scan_u32(uint32_t* a, int64_t m, uint32_t* tmp, hipStream_t s);
 hipError_t radix_sort_keys(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* vb, int64_t n,
-                           int key_bits, uint32_t* hist, uint32_t* tmp, uint32_t** keys_sorted,
-                           uint32_t** perm, hipStream_t s);
+                           const uint32_t* n_dev, bool vals_in_va, int key_bits, uint32_t* hist,
+                           uint32_t* tmp, uint32_t** keys_sorted, uint32_t** perm, hipStream_t s);
+// Stable re-sort after small moves.  okeys: the current keys, sorted, with
+// CSR offsets ooff[n_bins+1]; nkeys: new keys in the same order.  Produces
+// perm (new position -> current index), skeys (new sorted keys) and noff
+// (new offsets); the result equals a stable sort of nkeys.  Only the
+// particles whose key changed are sorted.
+struct RebinScratch {
+  uint32_t *in_start, *out_before, *inc_before;  // [n_bins + 1] each
+  uint32_t* blockoff;                            // [n/2048 + 2]
+  uint32_t *mk_a, *mk_b, *mv_a, *mv_b;           // [n] each
+  uint32_t *hist, *scan_tmp;                     // as for radix_sort_keys on n elements
+};
+size_t rebin_block_words(int64_t n);
+hipError_t rebin_incremental(const uint32_t* okeys, const uint32_t* ooff, const uint32_t* nkeys, int64_t n,
+                             int64_t n_bins, int key_bits, const RebinScratch& w, uint32_t* perm, uint32_t* skeys,
+                             uint32_t* noff, hipStream_t s);
 hipError_t launch_offsets(const uint32_t* skeys, int64_t n, int64_t n_bins, uint32_t* offsets,
                           hipStream_t s);
 hipError_t gather3_f64(const double* in, const uint32_t* perm, int64_t n, double* out, hipStream_t s);

@@ -80,6 +80,9 @@ struct ptk_ctx {
   // scratch
   ptk::DevBuf keys_a, keys_b, vals_a, vals_b, offsets, hist, scan_tmp, flag;
   ptk::DevBuf xs, xn, orig, orig_b, k1, k2, h0, h1, h0b, h1b, gint, stage;
+  // incremental re-binning inside advance: sorted keys and offsets of the
+  // current order and of the next, mover lists, per-bin counters
+  ptk::DevBuf skeys, skeys2, offsets2, mk_a, mk_b, mv_a, mv_b, rb_in, rb_out, rb_inc, rb_block;
   // learned form: FP32 master parameters, Adam moments, BF16 layer copies,
   // per-workgroup gradient and loss partials, audit scratch
   ptk::DevBuf lparams, lm, lv, lw1b, lw2b, lw2bt, lgpart, llpart, lwide, laudit_x, laudit_u, laudit_sums;

@@ -289,6 +289,34 @@ def test_multistep_f64_with_gradient(ptk, scheme):
     ctx.close()
 
 
+@pytest.mark.parametrize("scheme", ["euler", "heun", "ab2"])
+def test_multistep_many_movers(ptk, scheme):
+    """Large steps move about a quarter of the particles to another bin:
+    the incremental re-binning inside advance must still give the stable
+    order the kernel relies on (wrong bins would show as wrong velocities)."""
+    say(f"[advance many movers] {scheme}")
+    N = 16
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((N, N, N, 3))
+    ctx = ptk.Context(0)
+    ctx.set_field(torch.from_numpy(u).to(DEV), K.LAGRANGE, 4, 0, storage=ptk.F64)
+    X0 = np.concatenate([rng.uniform(0, L, (6000, 3)),
+                         np.array([2.0, 3.0, 4.0]) + rng.uniform(0, 0.05, (2000, 3))])  # a cluster
+    sc = {"euler": ptk.EULER, "heun": ptk.HEUN, "ab2": ptk.AB2}[scheme]
+    n = X0.shape[0]
+    Xd = torch.from_numpy(X0.copy()).to(DEV)
+    hist = torch.zeros((2, n, 3), dtype=torch.float64, device=DEV) if scheme == "ab2" else None
+    ctx.advance(Xd, sc, 0.3, 3, hist=hist, hist_len=0)
+    vel = lambda Y: interp.interp_vec(u, Y, K.LAGRANGE, 4, 0)
+    Xo, ho, hlo, _ = stepping.advance(X0, vel, sc, 0.3, 3)
+    keys0 = geometry.bin_keys(X0, N, 8, 4)
+    keys1 = geometry.bin_keys(Xo, N, 8, 4)
+    say(f"  particles that changed bin over the run: {np.mean(keys0 != keys1):.2f}")
+    assert np.mean(keys0 != keys1) > 0.2
+    assert np.max(circ(Xd.cpu().numpy(), Xo)) <= 1e-12 * L
+    ctx.close()
+
+
 def test_ab2_resume_matches_single_run(ptk):
     say("[ab2 resume]")
     N = 16
