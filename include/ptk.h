@@ -55,7 +55,7 @@ enum { PTK_F64 = 0, PTK_F32 = 1, PTK_BF16 = 2, PTK_F16 = 3 };
 enum { PTK_LAGRANGE = 0, PTK_SPLINE = 1 };
 
 /* Time-stepping schemes for ptk_advance_particles. */
-enum { PTK_EULER = 1, PTK_HEUN = 2, PTK_AB2 = 3 };
+enum { PTK_EULER = 1, PTK_HEUN = 2, PTK_AB2 = 3, PTK_AB3 = 4, PTK_AB4 = 5 };
 
 /* Return codes. */
 enum {
@@ -147,10 +147,15 @@ int ptk_interpolate_gradient(ptk_ctx *ctx, const double *X, int64_t Np, void *u_
  * scheme PTK_EULER: X <- W(X + dt u(X)).
  * scheme PTK_HEUN:  k1 = u(X); Xs = W(X + dt k1); k2 = u(Xs);
  *                   X <- W(X + (0.5 dt)(k1 + k2)).
- * scheme PTK_AB2:   X <- W(X + dt (1.5 u_n - 0.5 u_{n-1})), an Euler step while
- *    the history is empty.  rhs_hist: device [2][Np][3] holding u_n, u_{n-1}
- *    (binary64 for F64 storage, else FP32), in the order of X; *hist_len (host,
- *    0..2) says how many entries are valid and is updated, so a run can resume.
+ * schemes PTK_AB2, PTK_AB3, PTK_AB4 (Adams-Bashforth of order k = 2, 3, 4,
+ *    the paper's multi-step integration, Sec. 2.2):
+ *      X <- W(X + dt (b_0 u_n + b_1 u_{n-1} + ... + b_{k-1} u_{n-k+1})),
+ *    b = (3/2, -1/2), (23/12, -16/12, 5/12), (55/24, -59/24, 37/24, -9/24),
+ *    summed in that order; while fewer than k-1 past velocities are stored the
+ *    step uses the highest order they allow (Euler first).  rhs_hist: device
+ *    [k][Np][3] holding the last k velocities, most recent first (binary64
+ *    for F64 storage, else FP32), in the order of X; *hist_len (host, 0..k)
+ *    says how many entries are valid and is updated, so a run can resume.
  *    rhs_hist/hist_len may be NULL for Euler and Heun.
  * W is the wrap of ptk_locate; every update is separately rounded binary64.
  * grad_out: device [Np][3][3] (binary64 for F64 storage, else FP32) or NULL;

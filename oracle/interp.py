@@ -37,6 +37,23 @@ def weights_f64(family: int, I: int, m: int, t: np.ndarray, deriv: bool = False)
     return out
 
 
+def weights_abs(family: int, I: int, m: int, t: np.ndarray, deriv: bool = False) -> np.ndarray:
+    """H_j(t) = sum_p |c_jp| t^p (t >= 0) for the coefficients c_jp of beta_j
+    (or beta_j'): it bounds |beta_j(t)| and, times the number of Horner steps
+    and the unit roundoff, the rounding error of any Horner evaluation of
+    beta_j(t) (the standard bound for Horner's rule), so sums of |terms| built
+    from it bound reduced-precision evaluations of the kernel."""
+    tab = np.abs(kernels.coeff_table_f64(family, I, m, deriv))
+    t = np.asarray(t, dtype=np.float64)
+    out = np.empty(t.shape + (I,), dtype=np.float64)
+    for j in range(I):
+        acc = np.full(t.shape, tab[j, I - 1])
+        for p in range(I - 2, -1, -1):
+            acc = np.add(np.multiply(acc, np.abs(t)), tab[j, p])
+        out[..., j] = acc
+    return out
+
+
 def _gather(field: np.ndarray, c: np.ndarray, I: int) -> np.ndarray:
     """Stencil values [P, I(x3), I(x2), I(x1), 3] around cells c[P, 3]."""
     N = field.shape[0]
@@ -51,10 +68,11 @@ def interp_vec(field: np.ndarray, X: np.ndarray, family: int, I: int, m: int = 0
                gradient: bool = False, chunk: int = 4096, absolute: bool = False):
     """Vectorised triple sum; returns u[P,3] (and grad[P,3,3] if requested).
 
-    With ``absolute=True`` every weight and field value is replaced by its
-    absolute value: the result is the sum of |terms|, which bounds the rounding
-    error of any evaluation order of the same sum (used to derive tolerances
-    for reduced-precision arithmetic).
+    With ``absolute=True`` every field value is replaced by its absolute value
+    and every weight by ``weights_abs`` (the sum of the absolute values of its
+    polynomial's terms): the result bounds the size of every term and partial
+    sum and of the Horner rounding of the weights, for any evaluation order
+    (used to derive tolerances for reduced-precision arithmetic).
     """
     field = np.asarray(field)           # FP32 or FP64 values; gathered stencils become FP64
     if absolute:
@@ -68,15 +86,12 @@ def interp_vec(field: np.ndarray, X: np.ndarray, family: int, I: int, m: int = 0
     for s in range(0, P, chunk):
         e = min(P, s + chunk)
         c, t = geometry.cell_and_offset(X[s:e], N)
-        w = weights_f64(family, I, m, t)            # [p, axis, I]
-        if absolute:
-            w = np.abs(w)
+        w = weights_abs(family, I, m, t) if absolute else weights_f64(family, I, m, t)  # [p, axis, I]
         G = _gather(field, c, I).astype(np.float64)  # [p, k3, k2, k1, a]
         u[s:e] = np.einsum("pk,pj,pi,pkjia->pa", w[:, 2], w[:, 1], w[:, 0], G)
         if gradient:
-            d = weights_f64(family, I, m, t, deriv=True) * invd
-            if absolute:
-                d = np.abs(d)
+            d = (weights_abs(family, I, m, t, deriv=True) if absolute
+                 else weights_f64(family, I, m, t, deriv=True)) * invd
             g[s:e, :, 0] = np.einsum("pk,pj,pi,pkjia->pa", w[:, 2], w[:, 1], d[:, 0], G)
             g[s:e, :, 1] = np.einsum("pk,pj,pi,pkjia->pa", w[:, 2], d[:, 1], w[:, 0], G)
             g[s:e, :, 2] = np.einsum("pk,pj,pi,pkjia->pa", d[:, 2], w[:, 1], w[:, 0], G)

@@ -11,6 +11,13 @@ Readings (the paper gives neither the order nor the start-up):
 * Heun:   k1 = u(X); Xs = W(X + dt*k1); k2 = u(Xs); X <- W(X + (dt/2)*(k1 + k2)).
 * AB2:    X <- W(X + dt*(3/2*u_n - 1/2*u_{n-1})) with an Euler first step; the
   history holds [u_n, u_{n-1}] and its length (0, 1 or 2) so a run can resume.
+* AB3, AB4 (the paper's "multi-step" read as orders up to 4): the textbook
+  Adams-Bashforth weights (from integrating the interpolant of the last k
+  velocities over one step) -- AB3: 23/12, -16/12, 5/12; AB4: 55/24, -59/24,
+  37/24, -9/24 -- applied as X + dt*sum_j b_j*u_{n-j} in the order j = 0, 1, ...
+  While the history is shorter, the step uses the highest order it allows
+  (Euler, then AB2, AB3).  The history holds the last k velocities, most
+  recent first, and its length (0..k).
 * W is the periodic wrap of ``geometry.wrap``: the state is stored wrapped.
 * Every operation is a separately rounded binary64 operation in the order
   written (``dt/2`` is formed once as 0.5*dt).
@@ -24,7 +31,12 @@ import numpy as np
 
 from .geometry import wrap
 
-EULER, HEUN, AB2 = 1, 2, 3
+EULER, HEUN, AB2, AB3, AB4 = 1, 2, 3, 4, 5
+
+# Adams-Bashforth weights b_j of u_{n-j}, by order
+AB_WEIGHTS = {1: (1.0,), 2: (1.5, -0.5), 3: (23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0),
+              4: (55.0 / 24.0, -59.0 / 24.0, 37.0 / 24.0, -9.0 / 24.0)}
+AB_ORDER = {AB2: 2, AB3: 3, AB4: 4}
 
 
 def euler_update(X, dt, u):
@@ -44,6 +56,15 @@ def ab2_update(X, dt, u_n, u_prev):
     return wrap(np.add(X, np.multiply(dt, inc)))
 
 
+def ab_update(X, dt, us, order: int):
+    """X + dt*sum_j b_j*us[j] for us = [u_n, u_{n-1}, ...] (j = 0..order-1)."""
+    b = AB_WEIGHTS[order]
+    inc = np.multiply(b[0], us[0])
+    for j in range(1, order):
+        inc = np.add(inc, np.multiply(b[j], us[j]))
+    return wrap(np.add(X, np.multiply(dt, inc)))
+
+
 def advance(X, velocity, scheme: int, dt: float, nsteps: int, hist=None, hist_len: int = 0,
             gradient=None):
     """Advance positions X[Np][3] by nsteps.
@@ -54,7 +75,7 @@ def advance(X, velocity, scheme: int, dt: float, nsteps: int, hist=None, hist_le
     X = np.array(X, dtype=np.float64)
     grad_last = None
     if hist is None:
-        hist = np.zeros((2,) + X.shape)
+        hist = np.zeros((AB_ORDER.get(scheme, 2),) + X.shape)
     hist = np.array(hist, dtype=np.float64)
     for _ in range(nsteps):
         if gradient is not None:
@@ -75,6 +96,15 @@ def advance(X, velocity, scheme: int, dt: float, nsteps: int, hist=None, hist_le
             hist[1] = hist[0]
             hist[0] = u0
             hist_len = min(hist_len + 1, 2)
+            X = Xn
+        elif scheme in (AB3, AB4):
+            K = AB_ORDER[scheme]
+            q = min(K, hist_len + 1)
+            Xn = ab_update(X, dt, [u0] + [hist[j] for j in range(q - 1)], q)
+            for j in range(K - 1, 0, -1):
+                hist[j] = hist[j - 1]
+            hist[0] = u0
+            hist_len = min(hist_len + 1, K)
             X = Xn
         else:
             raise ValueError("unknown scheme")

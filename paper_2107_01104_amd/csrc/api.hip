@@ -387,7 +387,8 @@ void ptk_destroy(ptk_ctx* c) {
     (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->field, &c->coef, &c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->offsets,
                       &c->hist, &c->scan_tmp, &c->flag, &c->xs, &c->xn, &c->orig, &c->orig_b, &c->k1,
-                      &c->k2, &c->h0, &c->h1, &c->h0b, &c->h1b, &c->gint, &c->stage, &c->lparams,
+                      &c->k2, &c->abh[0], &c->abh[1], &c->abh[2], &c->abh[3], &c->abh_b[0], &c->abh_b[1],
+                      &c->abh_b[2], &c->abh_b[3], &c->gint, &c->stage, &c->lparams,
                       &c->lm, &c->lv, &c->lw1b, &c->lw2b, &c->lw2bt, &c->lgpart, &c->llpart, &c->lwide,
                       &c->laudit_x, &c->laudit_u, &c->laudit_sums, &c->skeys, &c->skeys2, &c->offsets2,
                       &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->rb_in, &c->rb_out, &c->rb_inc, &c->rb_block};
@@ -545,13 +546,15 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
   if (!c) return PTK_EINVAL;
   c->err.clear();
   if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
-  if (scheme != PTK_EULER && scheme != PTK_HEUN && scheme != PTK_AB2) return fail(c, PTK_EINVAL, "bad scheme");
+  if (scheme < PTK_EULER || scheme > PTK_AB4) return fail(c, PTK_EINVAL, "bad scheme");
+  // Adams-Bashforth order and history depth
+  const int K = scheme == PTK_AB2 ? 2 : scheme == PTK_AB3 ? 3 : scheme == PTK_AB4 ? 4 : 0;
   if (Np < 0 || Np > (int64_t)0xFFFFFFFF) return fail(c, PTK_EINVAL, "Np out of range [0, 2^32)");
   if (nsteps < 0) return fail(c, PTK_EINVAL, "nsteps must be >= 0");
   if (!std::isfinite(dt)) return fail(c, PTK_EINVAL, "dt must be finite");
-  if (scheme == PTK_AB2) {
-    if (!rhs_hist || !hist_len) return fail(c, PTK_EINVAL, "AB2 needs rhs_hist and hist_len");
-    if (*hist_len < 0 || *hist_len > 2) return fail(c, PTK_EINVAL, "hist_len must be 0, 1 or 2");
+  if (K) {
+    if (!rhs_hist || !hist_len) return fail(c, PTK_EINVAL, "Adams-Bashforth needs rhs_hist and hist_len");
+    if (*hist_len < 0 || *hist_len > K) return fail(c, PTK_EINVAL, "hist_len must be in [0, order]");
   }
   if (Np > 0 && !X) return fail(c, PTK_EINVAL, "NULL positions");
   if (Np == 0 || nsteps == 0) return PTK_OK;
@@ -574,11 +577,9 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
   PTK_TRY(ensure(c, c->orig_b, (size_t)Np * 4));
   PTK_TRY(ensure(c, c->k1, v3));
   if (scheme == PTK_HEUN) PTK_TRY(ensure(c, c->k2, v3));
-  if (scheme == PTK_AB2) {
-    PTK_TRY(ensure(c, c->h0, v3));
-    PTK_TRY(ensure(c, c->h1, v3));
-    PTK_TRY(ensure(c, c->h0b, v3));
-    PTK_TRY(ensure(c, c->h1b, v3));
+  for (int j = 0; j < K; ++j) {
+    PTK_TRY(ensure(c, c->abh[j], v3));
+    PTK_TRY(ensure(c, c->abh_b[j], v3));
   }
   if (grad_out) PTK_TRY(ensure(c, c->gint, (size_t)Np * 9 * vb));
   c->bin_valid = false;
@@ -592,8 +593,12 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
   int* flag = (int*)c->flag.ptr;
   void* k1 = c->k1.ptr;
   void* k2 = c->k2.ptr;
-  void *h0 = c->h0.ptr, *h1 = c->h1.ptr, *h0b = c->h0b.ptr, *h1b = c->h1b.ptr;
-  int hl = scheme == PTK_AB2 ? *hist_len : 0;
+  void *h[4] = {nullptr, nullptr, nullptr, nullptr}, *hb[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int j = 0; j < K; ++j) {
+    h[j] = c->abh[j].ptr;
+    hb[j] = c->abh_b[j].ptr;
+  }
+  int hl = K ? *hist_len : 0;
   auto gather_v = [&](const void* in, const uint32_t* pm, void* out) -> hipError_t {
     return vf64 ? gather3_f64((const double*)in, pm, Np, (double*)out, s)
                 : gather3_f32((const float*)in, pm, Np, (float*)out, s);
@@ -602,12 +607,25 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     return vf64 ? scatter_f64((const double*)in, idx, Np, width, (double*)out, s)
                 : scatter_f32((const float*)in, idx, Np, width, (float*)out, s);
   };
-  auto update = [&](int kind, const void* ka, const void* kb) -> int {
+  auto update = [&](int kind, const UpdateVel& v) -> int {
     Timed t(c, s, PTK_T_UPDATE);
-    PTK_HIP(c, launch_update(kind, vf64, xs, ka, kb, dt, Np, xn, keys, (int)N, invd, bg, flag, s),
-            "position update");
+    PTK_HIP(c, launch_update(kind, vf64, xs, v, dt, Np, xn, keys, (int)N, invd, bg, flag, s), "position update");
     return PTK_OK;
   };
+  auto vel = [](const void* a, const void* b) {
+    UpdateVel v;
+    std::memset(&v, 0, sizeof(v));
+    v.k[0] = a;
+    v.k[1] = b;
+    v.nk = b ? 2 : 1;
+    return v;
+  };
+  // Adams-Bashforth weights of u_{n-j} by order (order 1 is Euler)
+  static const double kABW[5][4] = {{0, 0, 0, 0},
+                                    {1.0, 0, 0, 0},
+                                    {1.5, -0.5, 0, 0},
+                                    {23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0, 0},
+                                    {55.0 / 24.0, -59.0 / 24.0, 37.0 / 24.0, -9.0 / 24.0}};
   PTK_TRY(ensure_rebin(c, Np, n_bins));
   // re-bin relative to the current (bin-ordered) state: new keys in `keys`;
   // writes the permutation to vals_a and the new sorted keys / offsets to
@@ -655,10 +673,8 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     Timed t(c, s, PTK_T_PERMUTE);
     PTK_HIP(c, gather3_f64(X, perm, Np, xs, s), "gather positions");
     PTK_HIP(c, hipMemcpyAsync(orig, perm, (size_t)Np * 4, hipMemcpyDeviceToDevice, s), "copy order");
-    if (scheme == PTK_AB2) {
-      if (hl >= 1) PTK_HIP(c, gather_v(rhs_hist, perm, h0), "gather history");
-      if (hl >= 2) PTK_HIP(c, gather_v((const char*)rhs_hist + v3, perm, h1), "gather history");
-    }
+    for (int j = 0; j < hl; ++j)
+      PTK_HIP(c, gather_v((const char*)rhs_hist + j * v3, perm, h[j]), "gather history");
   }
   for (int step = 0; step < nsteps; ++step) {
     const bool last = step == nsteps - 1;
@@ -676,10 +692,10 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
       PTK_HIP(c, launch_interp(c->storage, c->I, a, s), "interpolate");
     }
     if (scheme == PTK_EULER) {
-      PTK_TRY(update(kEulerOrPredict, k1, nullptr));
+      PTK_TRY(update(kEulerOrPredict, vel(k1, nullptr)));
     } else if (scheme == PTK_HEUN) {
       // predictor, re-binned; u at the predictor is written back in xs order
-      PTK_TRY(update(kEulerOrPredict, k1, nullptr));
+      PTK_TRY(update(kEulerOrPredict, vel(k1, nullptr)));
       uint32_t* pp = nullptr;
       PTK_TRY(rebin(&pp));
       {
@@ -697,23 +713,30 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
         Timed t(c, s, PTK_T_INTERP);
         PTK_HIP(c, launch_interp(c->storage, c->I, b, s), "interpolate predictor");
       }
-      PTK_TRY(update(kHeunCorrect, k1, k2));
+      PTK_TRY(update(kHeunCorrect, vel(k1, k2)));
     } else {
-      PTK_TRY(update(hl == 0 ? kEulerOrPredict : kAB2, k1, h0));
-      // history rotation: u_{n-1} <- u_n, u_n <- k1
-      void* t = h1;
-      h1 = h0;
-      h0 = k1;
+      // order min(K, hl + 1): u_n = k1 and the hl stored velocities
+      const int q = hl + 1 < K ? hl + 1 : K;
+      UpdateVel v;
+      std::memset(&v, 0, sizeof(v));
+      v.k[0] = k1;
+      for (int j = 1; j < q; ++j) v.k[j] = h[j - 1];
+      for (int j = 0; j < q; ++j) v.b[j] = kABW[q][j];
+      v.nk = q;
+      PTK_TRY(update(q == 1 ? kEulerOrPredict : kAB, v));
+      // history rotation: u_{n-j-1} <- u_{n-j}, u_n <- k1; the dropped buffer
+      // takes the next step's velocity
+      void* t = h[K - 1];
+      for (int j = K - 1; j > 0; --j) h[j] = h[j - 1];
+      h[0] = k1;
       k1 = t;
-      hl = hl < 2 ? hl + 1 : 2;
+      hl = hl < K ? hl + 1 : K;
     }
     if (last) {
       Timed t(c, s, PTK_T_PERMUTE);
       PTK_HIP(c, scatter_f64(xn, orig, Np, 3, X, s), "scatter positions");
-      if (scheme == PTK_AB2) {
-        PTK_HIP(c, scatter_v(h0, orig, 3, rhs_hist), "scatter history");
-        if (hl >= 2) PTK_HIP(c, scatter_v(h1, orig, 3, (char*)rhs_hist + v3), "scatter history");
-      }
+      for (int j = 0; j < hl; ++j)
+        PTK_HIP(c, scatter_v(h[j], orig, 3, (char*)rhs_hist + j * v3), "scatter history");
       break;
     }
     // re-bin the new positions and carry the per-particle state along
@@ -722,25 +745,15 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
       Timed t(c, s, PTK_T_PERMUTE);
       PTK_HIP(c, gather3_f64(xn, perm, Np, xs, s), "gather positions");
       PTK_HIP(c, gather_u32(orig, perm, Np, orig_b, s), "gather order");
-      if (scheme == PTK_AB2) {
-        PTK_HIP(c, gather_v(h0, perm, h0b), "gather history");
-        if (hl >= 2) PTK_HIP(c, gather_v(h1, perm, h1b), "gather history");
-      }
+      for (int j = 0; j < hl; ++j) PTK_HIP(c, gather_v(h[j], perm, hb[j]), "gather history");
     }
     swap_bins();
     uint32_t* to = orig;
     orig = orig_b;
     orig_b = to;
-    if (scheme == PTK_AB2) {
-      void* t0 = h0;
-      h0 = h0b;
-      h0b = t0;
-      void* t1 = h1;
-      h1 = h1b;
-      h1b = t1;
-    }
+    for (int j = 0; j < hl; ++j) std::swap(h[j], hb[j]);
   }
-  if (scheme == PTK_AB2) *hist_len = hl;
+  if (K) *hist_len = hl;
   return check_flag(c, s);
 }
 

@@ -322,6 +322,74 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
   }
 }
 
+// Value only, FP32/BF16/FP16 storage, I = 4 or 8: one particle per 32 lanes
+// (two rows of 16).  Row q (q = 0, 1) of the pair and half h of the row take
+// the planes k = 4m + 2q + h; the two rows of a half-wave then read planes
+// two ring slots apart (2 plane pitches = 0 mod 256 bytes), i.e. the same
+// banks at the same offsets, which the LDS serves at its full 16-byte rate.
+// Each row evaluates its own x2/x3 weights; the rows' partial sums meet with
+// a row broadcast.  Leaves the 3 totals in r on the odd rows.
+template <int ST, int I, typename V>
+__device__ __forceinline__ void particle_sums32(const unsigned char* smem, const V* cv, int j, int jj, int h,
+                                                V t1, V t2, V t3, int l1, int l2, int z3, V* r) {
+  using Gm = Geom<ST, I>;
+  constexpr int NB = Gm::NB, RP = Gm::RP, PL = Gm::PL, R = Gm::R;
+  constexpr int NM = I / 4;  // planes per lane
+  static_assert(I % 4 == 0, "32-lane groups need I divisible by 4");
+  const int q = (threadIdx.x >> 4) & 1;
+  const V tsel = h ? t3 : t2;
+  const V wsel = horner<I>(cv, tsel);
+  V w1 = horner<I>(cv, t1);
+  if (j >= I) w1 = (V)0;
+  V w2[I], w3[NM];
+#define PTK_B2(k) if constexpr ((k) < I) w2[k] = bcast<k>(wsel);
+  PTK_B2(0) PTK_B2(1) PTK_B2(2) PTK_B2(3) PTK_B2(4) PTK_B2(5) PTK_B2(6) PTK_B2(7)
+#undef PTK_B2
+  // w3[m] = beta_{4m + 2q + h}(t3), held by lane 8 + 4m + 2q + h of the row:
+  // row_mask 0x5 / 0xA picks the even / odd rows, bank_mask 0x3 / 0xC the halves
+#define PTK_B3(m)                                                                                        \
+  if constexpr ((m) < NM) {                                                                              \
+    const int src = __builtin_bit_cast(int, wsel);                                                       \
+    int x = __builtin_amdgcn_update_dpp(0, src, 0x150 + 8 + 4 * (m), 0x5, 0x3, false);                   \
+    x = __builtin_amdgcn_update_dpp(x, src, 0x150 + 9 + 4 * (m), 0x5, 0xC, false);                       \
+    x = __builtin_amdgcn_update_dpp(x, src, 0x150 + 10 + 4 * (m), 0xA, 0x3, false);                      \
+    x = __builtin_amdgcn_update_dpp(x, src, 0x150 + 11 + 4 * (m), 0xA, 0xC, false);                      \
+    w3[m] = __builtin_bit_cast(V, x);                                                                    \
+  }
+  PTK_B3(0) PTK_B3(1)
+#undef PTK_B3
+  const int noff = l2 * RP + (l1 + jj) * NB;
+  const int s0 = (z3 + 2 * q + h) % R;
+  V acc[3] = {0, 0, 0};
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    const int slot = s0 + 4 * m < R ? s0 + 4 * m : s0 + 4 * m - R;
+    const int base = slot * PL + noff;
+    V sum[3] = {0, 0, 0};
+#pragma unroll
+    for (int i2 = 0; i2 < I; ++i2) {
+      V v[3];
+      uint32_t keep;
+      lds_get<ST>(smem, base + i2 * RP, v, keep);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sum[c] = fma(w2[i2], v[c], sum[c]);
+      asm volatile("" ::"v"(keep));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = fma(w3[m], sum[c], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    V v = rowsum(w1 * acc[c]);
+    // odd rows add the even row's total: row_bcast:15 into rows 1 and 3
+    v += __builtin_bit_cast(V, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
+    r[c] = v;
+  }
+}
+
+// SPARSE: for launches with few particles per window -- visit only the
+// non-empty windows of each segment and fill the ring afresh for each,
+// instead of sweeping every plane.
 template <int ST, int I, bool GRAD, bool SPARSE>
 __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a) {
   using V = typename StoreT<ST>::acc;
@@ -329,7 +397,9 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
   constexpr int T = Gm::T;
   constexpr int W = kWindow;
   constexpr int NT = Gm::THREADS;
-  constexpr int GROUPS = NT / 16;        // particles per round
+  // lanes per particle: 32 for the FP32/16-bit value kernels with I = 4 or 8
+  constexpr int GL = (!GRAD && ST != ST_F64 && I % 4 == 0) ? 32 : 16;
+  constexpr int GROUPS = NT / GL;        // particles per round
   constexpr int NV = GRAD ? 12 : 3;
   constexpr int CH = NT / 3 / GROUPS * GROUPS;  // particles located per chunk: one thread per coordinate
   // particle record: t1, t2, t3 (V) at 0; cells l1, l2, z3 (u16) at 32;
@@ -358,7 +428,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
   const int j = l16 & 7;              // x1 node offset
   const int h = l16 >> 3;             // plane half
   const int jj = j < I ? j : I - 1;
-  const int grp = tid >> 4;
+  const int grp = tid / GL;
   const KernelTables* tab = (const KernelTables*)a.coef;
   V cv[I], cd[I];
 #pragma unroll
@@ -447,7 +517,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
     }
   };
   auto compute_chunk = [&](int n) {
-    const int wave_grp0 = __builtin_amdgcn_readfirstlane(grp & ~3);  // first group of this wave
+    const int wave_grp0 = __builtin_amdgcn_readfirstlane(grp & ~(64 / GL - 1));  // first group of this wave
     for (int r0 = 0; r0 < n; r0 += GROUPS) {
       if (r0 + wave_grp0 >= n) break;  // nothing left for this wave: its SIMD serves other waves
       const int pi = r0 + grp;
@@ -470,9 +540,13 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
       const uint4 lc = *(const uint4*)(rp + 32);
       const int l1 = (int)(lc.x & 0xFFFFu), l2 = (int)(lc.x >> 16), z3 = (int)(lc.y & 0xFFFFu);
       V r[3];
-      particle_sums<ST, I, GRAD>(smem, cv, cd, j, jj, h, t1, t2, t3, l1, l2, z3, r);
+      if constexpr (GL == 32)
+        particle_sums32<ST, I>(smem, cv, j, jj, h, t1, t2, t3, l1, l2, z3, r);
+      else
+        particle_sums<ST, I, GRAD>(smem, cv, cd, j, jj, h, t1, t2, t3, l1, l2, z3, r);
       // which of its three totals this lane writes, and which value that is
-      const int sub = GRAD ? (l16 & 3) : l16;
+      // (32-lane groups: the totals are on the odd row)
+      const int sub = GRAD ? (l16 & 3) : (GL == 32 && ((tid >> 4) & 1) == 0) ? 3 : l16;
       const int ev = GRAD ? 6 * (l16 >> 3) + 3 * ((l16 >> 2) & 1) + (l16 & 3) : l16;
       V val = r[0];
       val = sub == 1 ? r[1] : val;

@@ -78,10 +78,17 @@ struct InterpArgs {
 hipError_t launch_interp(int storage, int I, const InterpArgs& a, hipStream_t s);
 
 // step.hip
-enum UpdateKind { kEulerOrPredict = 0, kHeunCorrect = 1, kAB2 = 2 };
-hipError_t launch_update(int kind, int vel_f64, const double* X, const void* ka, const void* kb, double dt,
-                         int64_t n, double* Xout, uint32_t* keys, int N, double invd, const BinGeom& g,
-                         int* flag, hipStream_t s);
+enum UpdateKind { kEulerOrPredict = 0, kHeunCorrect = 1, kAB = 2 };
+// velocities k[j] (FP64 or FP32, [n][3], unused ones NULL) and, for kAB, the
+// weights b[j] of the nk of them
+struct UpdateVel {
+  const void* k[4];
+  double b[4];
+  int nk;
+};
+hipError_t launch_update(int kind, int vel_f64, const double* X, const UpdateVel& v, double dt, int64_t n,
+                         double* Xout, uint32_t* keys, int N, double invd, const BinGeom& g, int* flag,
+                         hipStream_t s);
 
 // learned.hip
 struct LearnedField {

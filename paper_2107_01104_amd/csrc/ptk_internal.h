@@ -79,7 +79,8 @@ struct ptk_ctx {
   bool bin_valid = false;
   // scratch
   ptk::DevBuf keys_a, keys_b, vals_a, vals_b, offsets, hist, scan_tmp, flag;
-  ptk::DevBuf xs, xn, orig, orig_b, k1, k2, h0, h1, h0b, h1b, gint, stage;
+  ptk::DevBuf xs, xn, orig, orig_b, k1, k2, gint, stage;
+  ptk::DevBuf abh[4], abh_b[4];  // Adams-Bashforth history in bin order, and its permuted copy
   // incremental re-binning inside advance: sorted keys and offsets of the
   // current order and of the next, mover lists, per-bin counters
   ptk::DevBuf skeys, skeys2, offsets2, mk_a, mk_b, mv_a, mv_b, rb_in, rb_out, rb_inc, rb_block;

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libptk.so")
 
 F64, F32, BF16, F16 = 0, 1, 2, 3
 LAGRANGE, SPLINE = 0, 1
-EULER, HEUN, AB2 = 1, 2, 3
+EULER, HEUN, AB2, AB3, AB4 = 1, 2, 3, 4, 5
+AB_ORDER = {AB2: 2, AB3: 3, AB4: 4}
 OK, EINVAL, ENOFIELD, ENOMEM, EHIP, EDOMAIN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 TIMERS = ["interp", "interp_grad", "sort", "keys", "update", "permute", "learned"]
 LEARNED_NFEAT, LEARNED_FEAT_PITCH, LEARNED_NPARAMS = 195, 200, 41987
@@ -218,14 +219,15 @@ class Context:
 
     def advance(self, X: torch.Tensor, scheme: int, dt: float, nsteps: int, hist=None, hist_len: int = 0,
                 grad_out=None):
-        """Advance X in place; returns the new history length (AB2) or 0."""
+        """Advance X in place; returns the new history length (Adams-Bashforth) or 0."""
         _dev_tensor(X, torch.float64, (3,), "X")
         n = X.numel() // 3
         hl = ctypes.c_int(int(hist_len))
         if hist is not None:
             _dev_tensor(hist, self.vel_dtype(), (3,), "rhs_hist")
-            if tuple(hist.shape) != (2, n, 3):
-                raise ValueError("rhs_hist must have shape (2, Np, 3)")
+            k = AB_ORDER.get(int(scheme), 2)
+            if tuple(hist.shape) != (k, n, 3):
+                raise ValueError(f"rhs_hist must have shape ({k}, Np, 3)")
         if grad_out is not None:
             _dev_tensor(grad_out, self.vel_dtype(), (3, 3), "grad_out")
         self._check(lib.ptk_advance_particles(self._h, _ptr(X), n, _ptr(hist),

@@ -5,15 +5,17 @@ within 1e-12 of the oracle (max |diff| / rms of the reference); positions after
 time steps within 1e-12 * 2*pi (FP64 path).
 
 FP32 sums (FP32, BF16 and FP16 storage, compared on the same stored field): per
-element |gpu - oracle| <= F32_BOUND * A, where A is the sum of the absolute
-values of the terms of that element's triple sum (oracle, absolute=True).
+element |gpu - oracle| <= F32_BOUND * A, where A is the oracle's absolute sum
+(absolute=True): every field value by its absolute value and every weight by
+the sum of the absolute values of its polynomial's terms, sum_p |c_p| t^p.
 Derivation: the kernel forms each result through FP32 sums of depth
-I (x2) + I (x3) + log2(8) (x1 lanes) <= 19 plus FP32 Horner weights (<= 8 fused
-steps each, three factors) and the FP32 rounding of t (relative 2^-24 in the
-offset, amplified by the weight derivative); a first-order bound of every term
-is below 64 ulp(1) = 64 * 2^-24 times A.  Relative RMS differences are also
-required to stay below 1e-6 for values and 4e-6 for gradients (typical FP32
-accumulation error, reported beside the bound).
+I (x2) + I (x3) + 4 (lane reduction) <= 20 and FP32 Horner weights (<= 7 steps
+each, three factors); Horner's rule has the error bound 2*steps*u*sum_p |c_p|
+t^p (u = 2^-24), so every first-order term is below 64 u times A.  The FP32
+rounding of the offset t adds |beta'| 2^-24 per weight, a few per cent of the
+bound.  Relative RMS differences are also required to stay below 1e-6 for
+values and 4e-6 for gradients (typical FP32 accumulation error, reported
+beside the bound).
 """
 import math
 import sys
@@ -184,6 +186,9 @@ def test_interp_f32_storage(ptk, fam, I, m):
     say(f"  rel rms value {rel_rms(uv, ru):.2e} grad {rel_rms(g, rg):.2e}")
     assert within_f32_bound(uv, ru, au) and within_f32_bound(g, rg, ag)
     assert rel_rms(uv, ru) <= 1e-6 and rel_rms(g, rg) <= 4e-6
+    # the value-only kernel (its own lane layout)
+    val = ctx.interpolate(torch.from_numpy(X).to(DEV)).cpu().numpy().astype(np.float64)
+    assert within_f32_bound(val, ru, au) and rel_rms(val, ru) <= 1e-6
     ctx.close()
 
 
@@ -225,19 +230,20 @@ def test_interp_sparse_and_clustered(ptk, storage, N, Np, clustered):
 
 
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
-def test_interp_reduced_storage_tight(ptk, storage):
-    say(f"[interp {storage}]")
+@pytest.mark.parametrize("fam,I,m", [(K.LAGRANGE, 4, 0), (K.SPLINE, 6, 1), (K.SPLINE, 8, 2)])
+def test_interp_reduced_storage_tight(ptk, storage, fam, I, m):
+    say(f"[interp {storage}] I={I}")
     code = ptk.BF16 if storage == "bf16" else ptk.F16
     N = 64
     u = fields.spectral_field(N, kc=20.0, seed=1, dtype=torch.float32).numpy()
     ctx = ptk.Context(0)
-    ctx.set_field(torch.from_numpy(u).to(DEV), K.SPLINE, 8, 2, storage=code)
+    ctx.set_field(torch.from_numpy(u).to(DEV), fam, I, m, storage=code)
     vals, s = precision.store(u, code)
     assert np.allclose(ctx.field_scale(), s, rtol=2e-7, atol=0)
     X = particles.uniform_particles(20000, seed=12, device="cpu").numpy()
     uv, g = ctx.interpolate_gradient(torch.from_numpy(X).to(DEV), out_dtype=torch.float32)
-    ru, rg = interp.interp_vec(vals, X, K.SPLINE, 8, 2, gradient=True)
-    au, ag = interp.interp_vec(vals, X, K.SPLINE, 8, 2, gradient=True, absolute=True)
+    ru, rg = interp.interp_vec(vals, X, fam, I, m, gradient=True)
+    au, ag = interp.interp_vec(vals, X, fam, I, m, gradient=True, absolute=True)
     ru, rg = ru * s, rg * s[None, :, None]
     au, ag = au * s, ag * s[None, :, None]
     uv, g = uv.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
@@ -245,6 +251,8 @@ def test_interp_reduced_storage_tight(ptk, storage):
     # one more FP32 rounding: the product with the scale s_a
     assert within_f32_bound(uv, ru, au * 1.0625) and within_f32_bound(g, rg, ag * 1.0625)
     assert rel_rms(uv, ru) <= 1e-6 and rel_rms(g, rg) <= 4e-6
+    val = ctx.interpolate(torch.from_numpy(X).to(DEV)).cpu().numpy().astype(np.float64)
+    assert within_f32_bound(val, ru, au * 1.0625) and rel_rms(val, ru) <= 1e-6
     ctx.close()
 
 
@@ -264,7 +272,11 @@ def test_heun_step_f64(ptk, f0):
     ctx.close()
 
 
-@pytest.mark.parametrize("scheme", ["euler", "heun", "ab2"])
+SCHEMES = {"euler": 1, "heun": 2, "ab2": 3, "ab3": 4, "ab4": 5}
+AB_DEPTH = {"ab2": 2, "ab3": 3, "ab4": 4}
+
+
+@pytest.mark.parametrize("scheme", ["euler", "heun", "ab2", "ab3", "ab4"])
 def test_multistep_f64_with_gradient(ptk, scheme):
     say(f"[advance f64] {scheme}")
     N = 16
@@ -273,9 +285,9 @@ def test_multistep_f64_with_gradient(ptk, scheme):
     ctx = ptk.Context(0)
     ctx.set_field(torch.from_numpy(u).to(DEV), K.SPLINE, 6, 1, storage=ptk.F64)
     X0 = rng.uniform(0, L, (5000, 3))
-    sc = {"euler": ptk.EULER, "heun": ptk.HEUN, "ab2": ptk.AB2}[scheme]
+    sc = SCHEMES[scheme]
     Xd = torch.from_numpy(X0.copy()).to(DEV)
-    hist = torch.zeros((2, 5000, 3), dtype=torch.float64, device=DEV) if scheme == "ab2" else None
+    hist = torch.zeros((AB_DEPTH[scheme], 5000, 3), dtype=torch.float64, device=DEV) if scheme in AB_DEPTH else None
     grad = torch.zeros((5000, 3, 3), dtype=torch.float64, device=DEV)
     hl = ctx.advance(Xd, sc, 2e-3, 7, hist=hist, hist_len=0, grad_out=grad)
     vel = lambda Y: interp.interp_vec(u, Y, K.SPLINE, 6, 1)
@@ -283,13 +295,13 @@ def test_multistep_f64_with_gradient(ptk, scheme):
     Xo, ho, hlo, go = stepping.advance(X0, vel, sc, 2e-3, 7, gradient=gfn)
     assert np.max(circ(Xd.cpu().numpy(), Xo)) <= 1e-12 * L
     assert rel_max(grad.cpu().numpy(), go) <= 1e-11
-    if scheme == "ab2":
-        assert hl == hlo == 2
+    if scheme in AB_DEPTH:
+        assert hl == hlo == AB_DEPTH[scheme]
         assert rel_max(hist.cpu().numpy(), ho) <= 1e-12
     ctx.close()
 
 
-@pytest.mark.parametrize("scheme", ["euler", "heun", "ab2"])
+@pytest.mark.parametrize("scheme", ["euler", "heun", "ab2", "ab4"])
 def test_multistep_many_movers(ptk, scheme):
     """Large steps move about a quarter of the particles to another bin:
     the incremental re-binning inside advance must still give the stable
@@ -302,10 +314,10 @@ def test_multistep_many_movers(ptk, scheme):
     ctx.set_field(torch.from_numpy(u).to(DEV), K.LAGRANGE, 4, 0, storage=ptk.F64)
     X0 = np.concatenate([rng.uniform(0, L, (6000, 3)),
                          np.array([2.0, 3.0, 4.0]) + rng.uniform(0, 0.05, (2000, 3))])  # a cluster
-    sc = {"euler": ptk.EULER, "heun": ptk.HEUN, "ab2": ptk.AB2}[scheme]
+    sc = SCHEMES[scheme]
     n = X0.shape[0]
     Xd = torch.from_numpy(X0.copy()).to(DEV)
-    hist = torch.zeros((2, n, 3), dtype=torch.float64, device=DEV) if scheme == "ab2" else None
+    hist = torch.zeros((AB_DEPTH[scheme], n, 3), dtype=torch.float64, device=DEV) if scheme in AB_DEPTH else None
     ctx.advance(Xd, sc, 0.3, 3, hist=hist, hist_len=0)
     vel = lambda Y: interp.interp_vec(u, Y, K.LAGRANGE, 4, 0)
     Xo, ho, hlo, _ = stepping.advance(X0, vel, sc, 0.3, 3)
@@ -317,22 +329,25 @@ def test_multistep_many_movers(ptk, scheme):
     ctx.close()
 
 
-def test_ab2_resume_matches_single_run(ptk):
-    say("[ab2 resume]")
+@pytest.mark.parametrize("scheme", ["ab2", "ab4"])
+def test_ab_resume_matches_single_run(ptk, scheme):
+    say(f"[{scheme} resume]")
     N = 16
+    depth = AB_DEPTH[scheme]
+    sc = SCHEMES[scheme]
     rng = np.random.default_rng(4)
     u = rng.standard_normal((N, N, N, 3)) * 0.3
     ctx = ptk.Context(0)
     ctx.set_field(torch.from_numpy(u).to(DEV), K.LAGRANGE, 4, 0, storage=ptk.F64)
     X0 = torch.from_numpy(rng.uniform(0, L, (3000, 3))).to(DEV)
-    Xa, ha = X0.clone(), torch.zeros((2, 3000, 3), dtype=torch.float64, device=DEV)
-    la = ctx.advance(Xa, ptk.AB2, 2e-3, 12, hist=ha, hist_len=0)
-    Xb, hb = X0.clone(), torch.zeros((2, 3000, 3), dtype=torch.float64, device=DEV)
-    lb = ctx.advance(Xb, ptk.AB2, 2e-3, 5, hist=hb, hist_len=0)
+    Xa, ha = X0.clone(), torch.zeros((depth, 3000, 3), dtype=torch.float64, device=DEV)
+    la = ctx.advance(Xa, sc, 2e-3, 12, hist=ha, hist_len=0)
+    Xb, hb = X0.clone(), torch.zeros((depth, 3000, 3), dtype=torch.float64, device=DEV)
+    lb = ctx.advance(Xb, sc, 2e-3, 2, hist=hb, hist_len=0)
     Xb_host, hb_host = Xb.cpu(), hb.cpu()               # host round-trip of the state
     Xb, hb = Xb_host.to(DEV), hb_host.to(DEV)
-    lb = ctx.advance(Xb, ptk.AB2, 2e-3, 7, hist=hb, hist_len=lb)
-    assert la == lb == 2
+    lb = ctx.advance(Xb, sc, 2e-3, 10, hist=hb, hist_len=lb)
+    assert la == lb == depth
     assert torch.equal(Xa, Xb) and torch.equal(ha, hb)
     ctx.close()
 

@@ -169,3 +169,22 @@ def test_fourier_field_interpolation_error_drops():
         val = interp.interp_vec(u, X, K.SPLINE, 8, 2)
         errs.append(np.sqrt(np.mean((val - ex) ** 2)) / np.sqrt(np.mean(ex ** 2)))
     assert errs[1] < errs[0] / 30 and errs[1] < 1e-5
+
+
+@pytest.mark.parametrize("fam,I,m", [(K.LAGRANGE, 4, 0), (K.SPLINE, 6, 1), (K.SPLINE, 8, 2)])
+def test_absolute_weights_bound_the_weights(fam, I, m):
+    """weights_abs (sum of |terms| of each kernel polynomial) is >= |beta|
+    everywhere, equals |c_0| at t = 0, and the absolute interpolation sum
+    bounds the value itself."""
+    t = np.linspace(0.0, 0.999, 101)
+    for deriv in (False, True):
+        w = interp.weights_f64(fam, I, m, t, deriv)
+        h = interp.weights_abs(fam, I, m, t, deriv)
+        assert np.all(h >= np.abs(w) - 1e-15)
+        c0 = np.abs(K.coeff_table_f64(fam, I, m, deriv)[:, 0])
+        assert np.array_equal(h[0], c0)
+    u = np.random.default_rng(1).standard_normal((12, 12, 12, 3))
+    X = np.random.default_rng(2).uniform(0, 2 * np.pi, (300, 3))
+    v, g = interp.interp_vec(u, X, fam, I, m, gradient=True)
+    av, ag = interp.interp_vec(u, X, fam, I, m, gradient=True, absolute=True)
+    assert np.all(av >= np.abs(v)) and np.all(ag >= np.abs(g))

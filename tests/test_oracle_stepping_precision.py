@@ -35,7 +35,10 @@ def rk4(X, f, dt, n):
     return X
 
 
-@pytest.mark.parametrize("scheme", [stepping.EULER, stepping.HEUN, stepping.AB2])
+ALL = [stepping.EULER, stepping.HEUN, stepping.AB2, stepping.AB3, stepping.AB4]
+
+
+@pytest.mark.parametrize("scheme", ALL)
 def test_shear_flow_exact(scheme):
     X0 = np.random.default_rng(0).uniform(0, L, (500, 3))
     dt, n = 1e-2, 37
@@ -46,7 +49,7 @@ def test_shear_flow_exact(scheme):
     assert np.all((X >= 0) & (X < L))
 
 
-@pytest.mark.parametrize("scheme", [stepping.EULER, stepping.HEUN, stepping.AB2])
+@pytest.mark.parametrize("scheme", ALL)
 def test_constant_velocity(scheme):
     X0 = np.random.default_rng(1).uniform(0, L, (100, 3))
     c = np.array([0.7, -1.3, 2.1])
@@ -67,12 +70,65 @@ def test_convergence_order_in_dt(scheme, order):
     assert np.all(np.abs(rates - order) < 0.25), rates
 
 
+def test_ab_weights_consistent():
+    """Each Adams-Bashforth rule integrates polynomials of degree < k exactly:
+    sum_j b_j (-j)^p = 1/(p+1) for p < k (exact rationals)."""
+    from fractions import Fraction as F
+    exact = {2: (F(3, 2), F(-1, 2)), 3: (F(23, 12), F(-16, 12), F(5, 12)),
+             4: (F(55, 24), F(-59, 24), F(37, 24), F(-9, 24))}
+    for k, b in exact.items():
+        for p in range(k):
+            assert sum(bj * F(-j) ** p for j, bj in enumerate(b)) == F(1, p + 1)
+        assert all(abs(float(bj) - w) == 0.0 for bj, w in zip(b, stepping.AB_WEIGHTS[k]))
+
+
+@pytest.mark.parametrize("scheme,order", [(stepping.AB3, 3), (stepping.AB4, 4)])
+def test_ab_high_order_convergence_with_exact_history(scheme, order):
+    """With the history taken from the exact trajectory (RK4 with a fine step,
+    run backwards), AB3 and AB4 converge at their full order."""
+    X0 = np.random.default_rng(2).uniform(0, L, (200, 3))
+    T = 0.5
+    ref = rk4(X0.copy(), abc, T / 4000, 4000)
+    K = stepping.AB_ORDER[scheme]
+    errs = []
+    for n in [40, 80, 160]:
+        dt = T / n
+        hist = np.zeros((K, 200, 3))
+        for j in range(1, K):
+            Xj = rk4(X0.copy(), abc, -dt * j / 200, 200)
+            hist[j - 1] = abc(Xj)
+        X, _, _, _ = stepping.advance(X0, abc, scheme, dt, n, hist=hist, hist_len=K - 1)
+        errs.append(np.max(_circ(X, ref)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - order) < 0.3), rates
+
+
+@pytest.mark.parametrize("scheme", [stepping.AB3, stepping.AB4])
+def test_ab_startup_lowers_order(scheme):
+    """From an empty history the first steps use Euler, AB2, ...: the first
+    step equals an Euler step and the second an AB2 step."""
+    X0 = np.random.default_rng(5).uniform(0, L, (50, 3))
+    dt = 1e-2
+    X1, h1, l1, _ = stepping.advance(X0, abc, scheme, dt, 1)
+    assert np.array_equal(X1, stepping.euler_update(X0, dt, abc(X0))) and l1 == 1
+    X2, h2, l2, _ = stepping.advance(X1, abc, scheme, dt, 1, hist=h1, hist_len=l1)
+    assert np.array_equal(X2, stepping.ab2_update(X1, dt, abc(X1), abc(X0))) and l2 == 2
+
+
 def test_ab2_resume_bitwise():
     X0 = np.random.default_rng(3).uniform(0, L, (300, 3))
     Xa, ha, la, _ = stepping.advance(X0, abc, stepping.AB2, 2e-3, 40)
     Xb, hb, lb, _ = stepping.advance(X0, abc, stepping.AB2, 2e-3, 17)
     Xb, hb, lb, _ = stepping.advance(Xb, abc, stepping.AB2, 2e-3, 23, hist=hb, hist_len=lb)
     assert np.array_equal(Xa, Xb) and np.array_equal(ha, hb) and la == lb == 2
+
+
+def test_ab4_resume_bitwise():
+    X0 = np.random.default_rng(3).uniform(0, L, (300, 3))
+    Xa, ha, la, _ = stepping.advance(X0, abc, stepping.AB4, 2e-3, 40)
+    Xb, hb, lb, _ = stepping.advance(X0, abc, stepping.AB4, 2e-3, 2)
+    Xb, hb, lb, _ = stepping.advance(Xb, abc, stepping.AB4, 2e-3, 38, hist=hb, hist_len=lb)
+    assert np.array_equal(Xa, Xb) and np.array_equal(ha, hb) and la == lb == 4
 
 
 def test_bf16_rounding_matches_torch():
