@@ -268,7 +268,8 @@ def main():
 
 
 def run_forms(ctx, ptk, u_host, X0, N, Np):
-    """Interpolation-only timings (velocity) for FP32/BF16/FP16 storage and their errors."""
+    """Interpolation-only timings (velocity) for FP64/FP32/BF16/FP16 storage and the learned
+    form, their errors against the FP64 oracle, and their speed against the FP64 path."""
     import numpy as np
     import torch
     from oracle import interp
@@ -280,25 +281,27 @@ def run_forms(ctx, ptk, u_host, X0, N, Np):
     out = torch.empty((Np, 3), dtype=torch.float32, device=dev)
     res = {}
     u_dev = torch.from_numpy(u_host).to(dev)
-    for name, code in (("f32", ptk.F32), ("bf16", ptk.BF16), ("f16", ptk.F16)):
+    out64 = torch.empty((Np, 3), dtype=torch.float64, device=dev)
+    for name, code in (("f64", ptk.F64), ("f32", ptk.F32), ("bf16", ptk.BF16), ("f16", ptk.F16)):
         ctx.set_field(u_dev, ptk.SPLINE, 8, 2, storage=code)
-        ctx.interpolate(X0, out=out)
+        o = out64 if code == ptk.F64 else out
+        ctx.interpolate(X0, out=o)
         torch.cuda.synchronize()
         ctx.timing(True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(3):
-            ctx.interpolate(X0, out=out)
+            ctx.interpolate(X0, out=o)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 3
         t = ctx.timing_read()
         ctx.timing(False)
         kms = t["interp"][0] / max(t["interp"][1], 1)
-        got = ctx.interpolate(torch.from_numpy(sample).to(dev)).cpu().numpy().astype(np.float64)
+        got = ctx.interpolate(torch.from_numpy(sample).to(dev), out_dtype=o.dtype).cpu().numpy().astype(np.float64)
         err = got - ref
-        node_b = 12 if code == ptk.F32 else 6
-        alg = algorithmic_bytes(N, Np, node_b, 12)
+        node_b = {ptk.F64: 24, ptk.F32: 12}.get(code, 6)
+        alg = algorithmic_bytes(N, Np, node_b, 24 if code == ptk.F64 else 12)
         res[name] = {"end_to_end_ms": round(ms, 3), "interp_kernel_ms": round(kms, 3),
                      "interp_per_s_end_to_end": Np / (ms * 1e-3),
                      "interp_per_s_kernel": Np / (kms * 1e-3),
@@ -306,8 +309,15 @@ def run_forms(ctx, ptk, u_host, X0, N, Np):
                      "rms_err_rel": float(np.sqrt(np.mean(err ** 2)) / rms_ref),
                      "max_err_rel": float(np.max(np.abs(err)) / rms_ref)}
         log(f"form {name}: {res[name]}")
+    del out64
     res["learned"] = run_learned(ctx, ptk, u_dev, u_host, X0, Np, sample, ref, rms_ref, out)
     log(f"form learned: {res['learned']}")
+    # throughput against the plain FP64 I=8 path on the same GPU
+    f64 = res["f64"]
+    for name in ("f32", "bf16", "f16"):
+        res[name]["speedup_vs_f64_kernel"] = round(f64["interp_kernel_ms"] / res[name]["interp_kernel_ms"], 3)
+        res[name]["speedup_vs_f64_end_to_end"] = round(f64["end_to_end_ms"] / res[name]["end_to_end_ms"], 3)
+    res["learned"]["speedup_vs_f64_end_to_end"] = round(f64["end_to_end_ms"] / res["learned"]["end_to_end_ms"], 3)
     del u_dev
     ctx.set_field(torch.zeros((8, 8, 8, 3), dtype=torch.float32, device=dev), ptk.SPLINE, 8, 2)
     return res

@@ -187,7 +187,7 @@ int ensure_binning(ptk_ctx* c, int64_t Np, int64_t n_bins) {
 // scratch of the incremental re-binning (in addition to ensure_binning's)
 int ensure_rebin(ptk_ctx* c, int64_t Np, int64_t n_bins) {
   const size_t n4 = (size_t)Np * 4, b4 = (size_t)(n_bins + 1) * 4;
-  DevBuf* per_particle[] = {&c->skeys, &c->skeys2, &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b};
+  DevBuf* per_particle[] = {&c->skeys, &c->skeys2, &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->mo};
   for (DevBuf* b : per_particle) PTK_TRY(ensure(c, *b, n4));
   DevBuf* per_bin[] = {&c->offsets2, &c->rb_in, &c->rb_out, &c->rb_inc};
   for (DevBuf* b : per_bin) PTK_TRY(ensure(c, *b, b4));
@@ -391,7 +391,8 @@ void ptk_destroy(ptk_ctx* c) {
                       &c->abh_b[2], &c->abh_b[3], &c->gint, &c->stage, &c->lparams,
                       &c->lm, &c->lv, &c->lw1b, &c->lw2b, &c->lw2bt, &c->lgpart, &c->llpart, &c->lwide,
                       &c->laudit_x, &c->laudit_u, &c->laudit_sums, &c->skeys, &c->skeys2, &c->offsets2,
-                      &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->rb_in, &c->rb_out, &c->rb_inc, &c->rb_block};
+                      &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->mo, &c->rb_in, &c->rb_out, &c->rb_inc,
+                      &c->rb_block};
     for (DevBuf* b : bufs) release(*b);
     for (TimedPair& p : c->pending) {
       (void)hipEventDestroy(p.start);
@@ -641,6 +642,7 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     w.mk_b = (uint32_t*)c->mk_b.ptr;
     w.mv_a = (uint32_t*)c->mv_a.ptr;
     w.mv_b = (uint32_t*)c->mv_b.ptr;
+    w.mo = (uint32_t*)c->mo.ptr;
     w.hist = (uint32_t*)c->hist.ptr;
     w.scan_tmp = (uint32_t*)c->scan_tmp.ptr;
     PTK_HIP(c,

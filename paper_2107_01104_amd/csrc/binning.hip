@@ -286,36 +286,21 @@ __device__ __forceinline__ int64_t tile_item(int r) {
   return (int64_t)blockIdx.x * kTile + (threadIdx.x >> 6) * (64 * kSortItems) + r * 64 + (threadIdx.x & 63);
 }
 
-// movers per tile; per bin, movers in (by new key) and out (by old key)
+// movers per tile
 __global__ __launch_bounds__(256) void k_rebin_count(const uint32_t* __restrict__ okeys,
                                                      const uint32_t* __restrict__ nkeys, int64_t n,
-                                                     uint32_t* __restrict__ in_cnt, uint32_t* __restrict__ out_cnt,
                                                      uint32_t* __restrict__ tile_cnt) {
   TileMovers t;
   tile_movers(okeys, nkeys, n, t);
-  for (int r = 0; r < kSortItems; ++r)
-    if (t.mover[r]) {
-      atomicAdd(&in_cnt[t.nk[r]], 1u);
-      atomicAdd(&out_cnt[t.ok[r]], 1u);
-    }
   if (threadIdx.x == 0) tile_cnt[blockIdx.x] = t.total;
 }
 
-// new bin sizes: old size - movers out + movers in; entry n_bins is 0
-__global__ __launch_bounds__(256) void k_rebin_newcnt(const uint32_t* __restrict__ ooff,
-                                                      const uint32_t* __restrict__ in_cnt,
-                                                      const uint32_t* __restrict__ out_cnt, int64_t n_bins,
-                                                      uint32_t* __restrict__ cnt) {
-  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (b > n_bins) return;
-  cnt[b] = b == n_bins ? 0u : (ooff[b + 1] - ooff[b]) - out_cnt[b] + in_cnt[b];
-}
-
-// movers, in current order, to (mk, mv) = (new key, current index)
+// movers, in current order, to (mk, mv, mo) = (new key, current index, old key)
 __global__ __launch_bounds__(256) void k_rebin_compact(const uint32_t* __restrict__ okeys,
                                                        const uint32_t* __restrict__ nkeys, int64_t n,
                                                        const uint32_t* __restrict__ tile_off,
-                                                       uint32_t* __restrict__ mk, uint32_t* __restrict__ mv) {
+                                                       uint32_t* __restrict__ mk, uint32_t* __restrict__ mv,
+                                                       uint32_t* __restrict__ mo) {
   TileMovers t;
   tile_movers(okeys, nkeys, n, t);
   const uint32_t base = tile_off[blockIdx.x];
@@ -323,7 +308,39 @@ __global__ __launch_bounds__(256) void k_rebin_compact(const uint32_t* __restric
     if (t.mover[r]) {
       mk[base + t.before[r]] = t.nk[r];
       mv[base + t.before[r]] = (uint32_t)tile_item(r);
+      mo[base + t.before[r]] = t.ok[r];
     }
+}
+
+// first[b] = first index i < m with keys[i] >= b (m if none), for sorted keys
+// and b = 0..n_bins, by binary search (one thread per bin, so the cost does
+// not depend on how the keys are spread); m is read on the device
+__global__ __launch_bounds__(256) void k_first_ge(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ m_dev,
+                                                  int64_t n_bins, uint32_t* __restrict__ first) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b > n_bins) return;
+  uint32_t lo = 0, hi = *m_dev;
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if (keys[mid] < (uint32_t)b)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  first[b] = lo;
+}
+
+// new offsets: elements with new key < b = (old key < b) - (movers whose old
+// key < b) + (movers whose new key < b); also clears the per-bin count of
+// movers that come from earlier bins
+__global__ __launch_bounds__(256) void k_rebin_offsets(const uint32_t* __restrict__ ooff,
+                                                       const uint32_t* __restrict__ out_before,
+                                                       const uint32_t* __restrict__ in_start, int64_t n_bins,
+                                                       uint32_t* __restrict__ noff, uint32_t* __restrict__ inc_before) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b > n_bins) return;
+  noff[b] = ooff[b] - out_before[b] + in_start[b];
+  inc_before[b] = 0u;
 }
 
 // Place the movers, sorted by (new key, current index): in bin b they follow
@@ -456,28 +473,25 @@ hipError_t rebin_incremental(const uint32_t* okeys, const uint32_t* ooff, const 
                              uint32_t* noff, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int64_t n_tiles = (n + kTile - 1) / kTile;
-  const size_t bin_bytes = (size_t)(n_bins + 1) * 4;
   hipError_t e;
-  if ((e = hipMemsetAsync(w.in_start, 0, bin_bytes, s)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(w.out_before, 0, bin_bytes, s)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(w.inc_before, 0, bin_bytes, s)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(w.blockoff, 0, (size_t)(n_tiles + 1) * 4, s)) != hipSuccess) return e;
-  k_rebin_count<<<(unsigned)n_tiles, 256, 0, s>>>(okeys, nkeys, n, w.in_start, w.out_before, w.blockoff);
-  k_rebin_newcnt<<<blocks_for(n_bins + 1, 256), 256, 0, s>>>(ooff, w.in_start, w.out_before, n_bins, noff);
+  // movers per tile, exclusive scan: the last entry becomes the mover count m
+  if ((e = hipMemsetAsync(w.blockoff + n_tiles, 0, 4, s)) != hipSuccess) return e;
+  k_rebin_count<<<(unsigned)n_tiles, 256, 0, s>>>(okeys, nkeys, n, w.blockoff);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // noff, in_start, out_before, blockoff: exclusive scans (the last entries
-  // become the totals: n, movers in, movers out, movers)
-  if ((e = exclusive_scan_u32(noff, n_bins + 1, w.scan_tmp, s)) != hipSuccess) return e;
-  if ((e = exclusive_scan_u32(w.in_start, n_bins + 1, w.scan_tmp, s)) != hipSuccess) return e;
-  if ((e = exclusive_scan_u32(w.out_before, n_bins + 1, w.scan_tmp, s)) != hipSuccess) return e;
   if ((e = exclusive_scan_u32(w.blockoff, n_tiles + 1, w.scan_tmp, s)) != hipSuccess) return e;
   const uint32_t* m_dev = w.blockoff + n_tiles;
-  k_rebin_compact<<<(unsigned)n_tiles, 256, 0, s>>>(okeys, nkeys, n, w.blockoff, w.mk_a, w.mv_a);
+  // movers in current order (their old keys are then sorted), then sorted by new key
+  k_rebin_compact<<<(unsigned)n_tiles, 256, 0, s>>>(okeys, nkeys, n, w.blockoff, w.mk_a, w.mv_a, w.mo);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_first_ge<<<blocks_for(n_bins + 1, 256), 256, 0, s>>>(w.mo, m_dev, n_bins, w.out_before);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   uint32_t *sk = nullptr, *sv = nullptr;
   if ((e = radix_sort_keys(w.mk_a, w.mk_b, w.mv_a, w.mv_b, n, m_dev, true, key_bits, w.hist, w.scan_tmp, &sk, &sv,
                            s)) != hipSuccess)
     return e;
+  k_first_ge<<<blocks_for(n_bins + 1, 256), 256, 0, s>>>(sk, m_dev, n_bins, w.in_start);
+  k_rebin_offsets<<<blocks_for(n_bins + 1, 256), 256, 0, s>>>(ooff, w.out_before, w.in_start, n_bins, noff,
+                                                             w.inc_before);
   const int64_t mgrid = min((int64_t)4096, (n + 255) / 256);
   k_rebin_movers<<<(unsigned)mgrid, 256, 0, s>>>(sk, sv, m_dev, ooff, noff, w.in_start, w.out_before, w.inc_before,
                                                  perm, skeys);

@@ -25,6 +25,8 @@
 // Weights: every lane evaluates its own node of beta (and beta') by Horner from
 // its row of the coefficient table; the group shares them with DPP
 // row_newbcast.  Sums are FP64 for FP64 storage and FP32 otherwise.
+#include <type_traits>
+
 #include "device_common.h"
 #include "launch.h"
 #include "ptk_internal.h"
@@ -169,6 +171,15 @@ __device__ __forceinline__ void lds_get(const unsigned char* smem, int off, V* v
     v[1] = __half2float(__ushort_as_half((unsigned short)(u.x >> 16)));
     v[2] = __half2float(__ushort_as_half((unsigned short)(u.y & 0xFFFFu)));
     keep = 0;
+  }
+}
+
+// f(integral_constant<int, K>) for K = B .. E-1
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
   }
 }
 
@@ -458,9 +469,12 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
   // ---- software pipeline over windows: while window w is computed, the
   // positions of window w+1 and the planes window w+2 adds are in flight
   // (issued in that order, so each wait only covers older loads).
-  constexpr int DEPTH = GRAD ? 1 : 2;  // windows of plane prefetch
-  uint4 preA[Gm::PRE][3], preB[DEPTH == 2 ? Gm::PRE : 1][3];
-  bool okA[Gm::PRE], okB[DEPTH == 2 ? Gm::PRE : 1];
+  // windows of plane prefetch: the planes of window v are loaded into buffer
+  // v mod DEPTH, DEPTH windows ahead (one for the gradient kernels, which
+  // need the registers)
+  constexpr int DEPTH = GRAD ? 1 : 3;
+  uint4 pre[DEPTH][Gm::PRE][3];
+  bool pok[DEPTH][Gm::PRE];
 
   auto issue_planes = [&](int64_t wn, uint4 (&pre)[Gm::PRE][3], bool (&ok)[Gm::PRE]) {
     const int64_t zn = W * wn + I - 1;  // planes window wn adds: [zn, zn + W)
@@ -574,13 +588,12 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
       }
     }
   };
-  // one window: records of w are in LDS, the ring holds w's planes.  With a
-  // two-window plane pipeline (value kernels), `cur` holds the planes of w+1
-  // (loaded during the previous window) and `nxt` receives w+2's; with a
-  // one-window pipeline (gradient kernels, which need the registers) `cur`
-  // receives w+1's planes in this window.
-  auto window = [&](int64_t w, uint4 (&cur)[Gm::PRE][3], bool (&cok)[Gm::PRE], uint4 (&nxt)[Gm::PRE][3],
-                    bool (&nok)[Gm::PRE]) {
+  // one window: records of w are in LDS, the ring holds w's planes, buffers
+  // hold the planes of w+1 .. w+DEPTH-1; B is w's buffer (w - w_begin mod
+  // DEPTH), which receives the planes of w+DEPTH
+  auto window = [&](int64_t w, auto B_) {
+    constexpr int B = decltype(B_)::value;
+    constexpr int B1 = (B + 1) % DEPTH;
     const int64_t bin = tile * a.nw + w;
     const uint32_t start = a.offsets[bin], end = a.offsets[bin + 1];
     const bool more = w + 1 < w_end;
@@ -589,10 +602,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
     double xv = 0.0;
     uint32_t qv = 0;
     if (more && a.np > 0) issue_pos(end, n1, xv, qv);
-    if constexpr (DEPTH == 2)
-      issue_planes(w + 2, nxt, nok);
-    else
-      issue_planes(w + 1, cur, cok);
+    issue_planes(w + DEPTH, pre[B], pok[B]);
     __syncthreads();  // records of w and the ring are complete
     int n = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
     compute_chunk(n);
@@ -610,7 +620,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
     __syncthreads();  // every read of this window's ring slots and records is done
     // the ring holds at least the planes one window touches: w+1's new planes
     // replace planes no later window reads; then w+1's records
-    store_planes(w + 1, cur, cok);
+    store_planes(w + 1, pre[B1], pok[B1]);
     if (more) write_rec(w + 1, n1, xv, qv);
   };
 
@@ -649,14 +659,15 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
     if (a.np > 0) issue_pos(start, n0, xv, qv);
     write_rec(w_begin, n0, xv, qv);
   }
-  if constexpr (DEPTH == 2) {
-    issue_planes(w_begin + 1, preA, okA);
-    for (int64_t w = w_begin; w < w_end; w += 2) {
-      window(w, preA, okA, preB, okB);
-      if (w + 1 < w_end) window(w + 1, preB, okB, preA, okA);
-    }
-  } else {
-    for (int64_t w = w_begin; w < w_end; ++w) window(w, preA, okA, preA, okA);
+  // planes of w_begin+1 .. w_begin+DEPTH-1 in flight, then windows in groups
+  // of DEPTH so that every buffer index is a constant
+  static_for<1, DEPTH>([&](auto K) { issue_planes(w_begin + decltype(K)::value, pre[decltype(K)::value], pok[decltype(K)::value]); });
+  for (int64_t w = w_begin; w < w_end; w += DEPTH) {
+    window(w, std::integral_constant<int, 0>{});
+    if constexpr (DEPTH > 1)
+      if (w + 1 < w_end) window(w + 1, std::integral_constant<int, 1 % DEPTH>{});
+    if constexpr (DEPTH > 2)
+      if (w + 2 < w_end) window(w + 2, std::integral_constant<int, 2 % DEPTH>{});
   }
 }
 

@@ -33,7 +33,7 @@ hipError_t radix_sort_keys(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* v
 struct RebinScratch {
   uint32_t *in_start, *out_before, *inc_before;  // [n_bins + 1] each
   uint32_t* blockoff;                            // [n/2048 + 2]
-  uint32_t *mk_a, *mk_b, *mv_a, *mv_b;           // [n] each
+  uint32_t *mk_a, *mk_b, *mv_a, *mv_b, *mo;      // [n] each
   uint32_t *hist, *scan_tmp;                     // as for radix_sort_keys on n elements
 };
 size_t rebin_block_words(int64_t n);

@@ -83,7 +83,7 @@ struct ptk_ctx {
   ptk::DevBuf abh[4], abh_b[4];  // Adams-Bashforth history in bin order, and its permuted copy
   // incremental re-binning inside advance: sorted keys and offsets of the
   // current order and of the next, mover lists, per-bin counters
-  ptk::DevBuf skeys, skeys2, offsets2, mk_a, mk_b, mv_a, mv_b, rb_in, rb_out, rb_inc, rb_block;
+  ptk::DevBuf skeys, skeys2, offsets2, mk_a, mk_b, mv_a, mv_b, mo, rb_in, rb_out, rb_inc, rb_block;
   // learned form: FP32 master parameters, Adam moments, BF16 layer copies,
   // per-workgroup gradient and loss partials, audit scratch
   ptk::DevBuf lparams, lm, lv, lw1b, lw2b, lw2bt, lgpart, llpart, lwide, laudit_x, laudit_u, laudit_sums;
