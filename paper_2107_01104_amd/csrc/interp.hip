@@ -400,9 +400,10 @@ __device__ __forceinline__ void particle_sums32(const unsigned char* smem, const
 
 // SPARSE: for launches with few particles per window -- visit only the
 // non-empty windows of each segment and fill the ring afresh for each,
-// instead of sweeping every plane.
+// instead of sweeping every plane.  Two workgroups per CU for FP32 and 16-bit
+// storage; FP64 nodes fill the LDS of one.
 template <int ST, int I, bool GRAD, bool SPARSE>
-__global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a) {
+__global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_interp(InterpArgs a) {
   using V = typename StoreT<ST>::acc;
   using Gm = Geom<ST, I>;
   constexpr int T = Gm::T;
@@ -471,10 +472,18 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
   // (issued in that order, so each wait only covers older loads).
   // windows of plane prefetch: the planes of window v are loaded into buffer
   // v mod DEPTH, DEPTH windows ahead (one for the gradient kernels, which
-  // need the registers)
-  constexpr int DEPTH = GRAD ? 1 : 3;
+  // need the registers).  Positions and destination indices are loaded two
+  // windows ahead into buffer v mod 2, so that a window with few particles
+  // does not wait for memory.
+  constexpr int DEPTH = GRAD ? 1 : 2;
+  // positions two windows ahead, except where the registers would spill
+  // (FP64 nodes; gradients of 16-bit storage)
+  constexpr bool POS2 = ST == ST_F32 || (!GRAD && ST != ST_F64);
   uint4 pre[DEPTH][Gm::PRE][3];
   bool pok[DEPTH][Gm::PRE];
+  double pos_x[2] = {0.0, 0.0};
+  uint32_t pos_q[2] = {0u, 0u};
+  int pos_n[2] = {0, 0};
 
   auto issue_planes = [&](int64_t wn, uint4 (&pre)[Gm::PRE][3], bool (&ok)[Gm::PRE]) {
     const int64_t zn = W * wn + I - 1;  // planes window wn adds: [zn, zn + W)
@@ -588,20 +597,30 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
       }
     }
   };
-  // one window: records of w are in LDS, the ring holds w's planes, buffers
-  // hold the planes of w+1 .. w+DEPTH-1; B is w's buffer (w - w_begin mod
-  // DEPTH), which receives the planes of w+DEPTH
-  auto window = [&](int64_t w, auto B_) {
+  // positions (up to CH particles) of window v into position buffer P
+  auto issue_window_pos = [&](int64_t v, double& xv, uint32_t& qv, int& nv) {
+    nv = 0;
+    if (v < w_end) {
+      const int64_t bin = tile * a.nw + v;
+      const uint32_t start = a.offsets[bin], end = a.offsets[bin + 1];
+      nv = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
+      if (nv > 0) issue_pos(start, nv, xv, qv);
+    }
+  };
+  // one window: records of w are in LDS, the ring holds w's planes; plane
+  // buffer B (w - w_begin mod DEPTH) receives the planes of w+DEPTH, position
+  // buffer P (w - w_begin mod 2) the positions of w+2
+  auto window = [&](int64_t w, auto B_, auto P_) {
     constexpr int B = decltype(B_)::value;
     constexpr int B1 = (B + 1) % DEPTH;
+    constexpr int P = decltype(P_)::value;
+    constexpr int P1 = (P + 1) % 2;
     const int64_t bin = tile * a.nw + w;
     const uint32_t start = a.offsets[bin], end = a.offsets[bin + 1];
-    const bool more = w + 1 < w_end;
-    const uint32_t end1 = more ? a.offsets[bin + 2] : end;
-    const int n1 = (int)min((int64_t)CH, (int64_t)end1 - (int64_t)end);
-    double xv = 0.0;
-    uint32_t qv = 0;
-    if (more && a.np > 0) issue_pos(end, n1, xv, qv);
+    if constexpr (!POS2)  // registers are short: positions one window ahead
+      issue_window_pos(w + 1, pos_x[0], pos_q[0], pos_n[0]);
+    else
+      issue_window_pos(w + 2, pos_x[P], pos_q[P], pos_n[P]);
     issue_planes(w + DEPTH, pre[B], pok[B]);
     __syncthreads();  // records of w and the ring are complete
     int n = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
@@ -621,7 +640,8 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
     // the ring holds at least the planes one window touches: w+1's new planes
     // replace planes no later window reads; then w+1's records
     store_planes(w + 1, pre[B1], pok[B1]);
-    if (more) write_rec(w + 1, n1, xv, qv);
+    constexpr int PR = POS2 ? P1 : 0;
+    if (w + 1 < w_end) write_rec(w + 1, pos_n[PR], pos_x[PR], pos_q[PR]);
   };
 
   {
@@ -649,25 +669,28 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, 2) void k_interp(InterpArgs a)
   fill(w_begin);
   __syncthreads();
 
-  // ---- prologue: records of the first window, planes of the second in flight
+  // ---- prologue: records of the first window, positions of the second and
+  // planes of w_begin+1 .. w_begin+DEPTH-1 in flight
   {
-    const int64_t bin = tile * a.nw + w_begin;
-    const uint32_t start = a.offsets[bin], end = a.offsets[bin + 1];
-    const int n0 = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
     double xv = 0.0;
     uint32_t qv = 0;
-    if (a.np > 0) issue_pos(start, n0, xv, qv);
-    write_rec(w_begin, n0, xv, qv);
+    int nv = 0;
+    issue_window_pos(w_begin, xv, qv, nv);
+    write_rec(w_begin, nv, xv, qv);
   }
-  // planes of w_begin+1 .. w_begin+DEPTH-1 in flight, then windows in groups
-  // of DEPTH so that every buffer index is a constant
+  if constexpr (POS2) issue_window_pos(w_begin + 1, pos_x[1], pos_q[1], pos_n[1]);
   static_for<1, DEPTH>([&](auto K) { issue_planes(w_begin + decltype(K)::value, pre[decltype(K)::value], pok[decltype(K)::value]); });
-  for (int64_t w = w_begin; w < w_end; w += DEPTH) {
-    window(w, std::integral_constant<int, 0>{});
-    if constexpr (DEPTH > 1)
-      if (w + 1 < w_end) window(w + 1, std::integral_constant<int, 1 % DEPTH>{});
-    if constexpr (DEPTH > 2)
-      if (w + 2 < w_end) window(w + 2, std::integral_constant<int, 2 % DEPTH>{});
+  // windows in pairs so that every buffer index is a constant (single
+  // windows when every buffer is the same)
+  static_assert(DEPTH == 1 || DEPTH == 2, "window pairs cover plane depths 1 and 2");
+  if constexpr (POS2 || DEPTH == 2) {
+    for (int64_t w = w_begin; w < w_end; w += 2) {
+      window(w, std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+      if (w + 1 < w_end) window(w + 1, std::integral_constant<int, 1 % DEPTH>{}, std::integral_constant<int, 1>{});
+    }
+  } else {
+    for (int64_t w = w_begin; w < w_end; ++w)
+      window(w, std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
   }
 }
 

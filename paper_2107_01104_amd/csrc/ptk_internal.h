@@ -15,7 +15,7 @@ constexpr int kMaxI = 8;           // largest kernel size built into the library
 // kWindow cell layers; T depends on the storage type (LDS budget per node).
 constexpr int kTileF32 = 12;       // FP32, BF16, FP16 storage
 constexpr int kTileF64 = 8;        // FP64 storage
-constexpr int kWindow = 4;
+constexpr int kWindow = 5;
 constexpr double kL = 6.283185307179586;  // fl64(2*pi)
 // learned correction form: features per particle, their row pitch, parameters
 constexpr int kLearnedNFeat = 195;

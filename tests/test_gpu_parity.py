@@ -112,7 +112,7 @@ def test_binning_bit_exact(ptk, N, Np):
     out = ctx.interpolate(Xd)
     torch.cuda.synchronize()
     perm, off, T, W = ctx.binning()
-    assert (T, W) == (12, 4)
+    assert (T, W) == (12, 5)
     keys = geometry.bin_keys(X, N, T, W)
     nbins = geometry.n_bins(N, T, W)
     assert off.numel() == nbins + 1
@@ -130,7 +130,7 @@ def test_binning_bit_exact_f64_tiles(ptk):
     ctx.interpolate(torch.from_numpy(X).to(DEV), out_dtype=torch.float64)
     torch.cuda.synchronize()
     perm, off, T, W = ctx.binning()
-    assert (T, W) == (8, 4)
+    assert (T, W) == (8, 5)
     keys = geometry.bin_keys(X, N, T, W)
     assert np.array_equal(perm.cpu().numpy().astype(np.int64), geometry.stable_order(keys))
     assert np.array_equal(off.cpu().numpy().astype(np.int64), geometry.offsets_from_keys(keys, geometry.n_bins(N, T, W)))
@@ -321,8 +321,8 @@ def test_multistep_many_movers(ptk, scheme):
     ctx.advance(Xd, sc, 0.3, 3, hist=hist, hist_len=0)
     vel = lambda Y: interp.interp_vec(u, Y, K.LAGRANGE, 4, 0)
     Xo, ho, hlo, _ = stepping.advance(X0, vel, sc, 0.3, 3)
-    keys0 = geometry.bin_keys(X0, N, 8, 4)
-    keys1 = geometry.bin_keys(Xo, N, 8, 4)
+    keys0 = geometry.bin_keys(X0, N, 8, 5)
+    keys1 = geometry.bin_keys(Xo, N, 8, 5)
     say(f"  particles that changed bin over the run: {np.mean(keys0 != keys1):.2f}")
     assert np.mean(keys0 != keys1) > 0.2
     assert np.max(circ(Xd.cpu().numpy(), Xo)) <= 1e-12 * L
