@@ -484,6 +484,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
   double pos_x[2] = {0.0, 0.0};
   uint32_t pos_q[2] = {0u, 0u};
   int pos_n[2] = {0, 0};
+  uint32_t pos_s[2] = {0u, 0u}, pos_e[2] = {0u, 0u};  // particle range of the buffered window
 
   auto issue_planes = [&](int64_t wn, uint4 (&pre)[Gm::PRE][3], bool (&ok)[Gm::PRE]) {
     const int64_t zn = W * wn + I - 1;  // planes window wn adds: [zn, zn + W)
@@ -597,15 +598,16 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
       }
     }
   };
-  // positions (up to CH particles) of window v into position buffer P
-  auto issue_window_pos = [&](int64_t v, double& xv, uint32_t& qv, int& nv) {
-    nv = 0;
-    if (v < w_end) {
-      const int64_t bin = tile * a.nw + v;
-      const uint32_t start = a.offsets[bin], end = a.offsets[bin + 1];
-      nv = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
-      if (nv > 0) issue_pos(start, nv, xv, qv);
-    }
+  // positions (up to CH particles) of window v, whose particles start at
+  // `start` (the end of window v-1), into a position buffer; only the end of
+  // its range is read from the offsets
+  auto issue_window_pos = [&](int64_t v, uint32_t start, double& xv, uint32_t& qv, int& nv, uint32_t& s_out,
+                              uint32_t& e_out) {
+    const uint32_t end = v < w_end ? a.offsets[tile * a.nw + v + 1] : start;
+    s_out = start;
+    e_out = end;
+    nv = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
+    if (nv > 0) issue_pos(start, nv, xv, qv);
   };
   // one window: records of w are in LDS, the ring holds w's planes; plane
   // buffer B (w - w_begin mod DEPTH) receives the planes of w+DEPTH, position
@@ -615,12 +617,12 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
     constexpr int B1 = (B + 1) % DEPTH;
     constexpr int P = decltype(P_)::value;
     constexpr int P1 = (P + 1) % 2;
-    const int64_t bin = tile * a.nw + w;
-    const uint32_t start = a.offsets[bin], end = a.offsets[bin + 1];
+    constexpr int PW = POS2 ? P : 0;  // buffer holding w's range
+    const uint32_t start = pos_s[PW], end = pos_e[PW];
     if constexpr (!POS2)  // registers are short: positions one window ahead
-      issue_window_pos(w + 1, pos_x[0], pos_q[0], pos_n[0]);
+      issue_window_pos(w + 1, end, pos_x[0], pos_q[0], pos_n[0], pos_s[0], pos_e[0]);
     else
-      issue_window_pos(w + 2, pos_x[P], pos_q[P], pos_n[P]);
+      issue_window_pos(w + 2, pos_e[P1], pos_x[P], pos_q[P], pos_n[P], pos_s[P], pos_e[P]);
     issue_planes(w + DEPTH, pre[B], pok[B]);
     __syncthreads();  // records of w and the ring are complete
     int n = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
@@ -675,10 +677,11 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
     double xv = 0.0;
     uint32_t qv = 0;
     int nv = 0;
-    issue_window_pos(w_begin, xv, qv, nv);
+    issue_window_pos(w_begin, a.offsets[tile * a.nw + w_begin], xv, qv, nv, pos_s[0], pos_e[0]);
     write_rec(w_begin, nv, xv, qv);
   }
-  if constexpr (POS2) issue_window_pos(w_begin + 1, pos_x[1], pos_q[1], pos_n[1]);
+  if constexpr (POS2)
+    issue_window_pos(w_begin + 1, pos_e[0], pos_x[1], pos_q[1], pos_n[1], pos_s[1], pos_e[1]);
   static_for<1, DEPTH>([&](auto K) { issue_planes(w_begin + decltype(K)::value, pre[decltype(K)::value], pok[decltype(K)::value]); });
   // windows in pairs so that every buffer index is a constant (single
   // windows when every buffer is the same)
