@@ -35,9 +35,11 @@ N_PART = 100_000_000
 KC = 340.0
 DT = 1e-3
 HBM_PEAK_GBS = 8000.0
-# FP32 FMA issue rate without packed-FP32 instructions (which this library does
-# not emit): 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz.  The packed rate is 157.3.
-FP32_VALU_PEAK_TFLOPS = 78.6
+# FP32 vector peak: 256 CUs x 4 SIMDs x 32 FMA lanes per clock x 2 FLOP x 2.4 GHz.
+# A wave64 v_fmac_f32 issues in two clocks on gfx950 without packed
+# instructions (measured: as fast as v_mov_b32), so the full vector rate is the
+# ceiling; DPP and FP64 forms issue in four.
+FP32_VALU_PEAK_TFLOPS = 157.3
 # algorithmic FLOP per particle of the separable I=8 sum: value 1920 FMA,
 # value + gradient 4080 FMA (x3 stage, x2 stage, x1 stage, Horner weights)
 FLOP_VALUE_I8 = 2 * 1920

@@ -573,7 +573,6 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
   PTK_TRY(ensure_binning(c, Np, n_bins));
   PTK_TRY(ensure(c, c->xs, (size_t)Np * 24));
   PTK_TRY(ensure(c, c->xn, (size_t)Np * 24));
-  PTK_TRY(ensure(c, c->stage, (size_t)Np * 24));
   PTK_TRY(ensure(c, c->orig, (size_t)Np * 4));
   PTK_TRY(ensure(c, c->orig_b, (size_t)Np * 4));
   PTK_TRY(ensure(c, c->k1, v3));
@@ -587,7 +586,6 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
 
   double* xs = (double*)c->xs.ptr;
   double* xn = (double*)c->xn.ptr;
-  double* xp = (double*)c->stage.ptr;
   uint32_t* orig = (uint32_t*)c->orig.ptr;
   uint32_t* orig_b = (uint32_t*)c->orig_b.ptr;
   uint32_t* keys = (uint32_t*)c->keys_a.ptr;
@@ -701,13 +699,12 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
       uint32_t* pp = nullptr;
       PTK_TRY(rebin(&pp));
       {
-        Timed t(c, s, PTK_T_PERMUTE);
-        PTK_HIP(c, gather3_f64(xn, pp, Np, xp, s), "gather predictor");
-      }
-      {
+        // the kernel reads the predictor positions through pp, the order it
+        // also writes u in: no gathered copy
         InterpArgs b = base_args(c);
         b.offsets = (const uint32_t*)c->offsets2.ptr;  // the predictor's bins
-        b.X = xp;
+        b.X = xn;
+        b.x_by_orig = 1;
         b.np = Np;
         b.orig = pp;
         b.out = k2;

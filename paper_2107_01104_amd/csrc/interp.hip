@@ -4,27 +4,28 @@
 //
 // Work decomposition: a workgroup owns one tile column -- T x T cells in
 // (x1, x2), a run of x3 -- and sweeps it along x3, the paper's slice
-// direction, in windows of W = 4 cell layers.  Particles are binned by (tile,
+// direction, in windows of W = 5 cell layers.  Particles are binned by (tile,
 // window) with x3 fastest, so a window's particles are contiguous.  The
 // (T+I-1)^2 halo nodes of the W+I-1 x3 planes a window touches live in an LDS
 // ring; each plane is read from HBM once per tile column (halo over-fetch
-// ((T+I-1)/T)^2, 2.5 for T = 12, I = 8), and the planes the next window adds
+// ((T+I-1)/T)^2, 2.5 for T = 12, I = 8), and the planes the next windows add
 // are loaded into registers while the current window is computed.  The ring is
 // small enough for two workgroups per CU (16 waves) to hide latency.
 //
-// Per particle: a group of 16 lanes.  Lane j = lane & 7 owns the x1 node
-// offset j; the two half-rows split the particle's I planes by ring-slot
-// parity (the ring has an even number of slots, so consecutive planes
-// alternate).  Each lane contracts x2 for each of its planes and x3 over
-// them, scales by its x1 weight, and the group sums over its 16 lanes with
-// DPP: the paper's split of the triple sum into partial sums finished along
-// the remaining direction (Sec. 3.3), inside one wavefront.  The plane pitch
-// is 128 mod 256 bytes, so the two half-rows of a quarter-wave -- an odd
-// number of planes apart -- read complementary halves of the 64 banks.
+// Per particle: a group of 16 lanes (32 for the FP32/16-bit value kernels with
+// I = 4 or 8).  Lane j = lane & 7 owns the x1 node offset j; the half-rows
+// (and rows) split the particle's I planes between them.  Each lane contracts
+// x2 for each of its planes and x3 over them, scales by its x1 weight, and the
+// group sums over its lanes with DPP: the paper's split of the triple sum into
+// partial sums finished along the remaining direction (Sec. 3.3), inside one
+// wavefront.  Plane pitches are 128 mod 256 bytes and the lanes of a
+// half-wave read planes whose offsets make the 16-byte reads conflict-free.
 //
 // Weights: every lane evaluates its own node of beta (and beta') by Horner from
 // its row of the coefficient table; the group shares them with DPP
-// row_newbcast.  Sums are FP64 for FP64 storage and FP32 otherwise.
+// row_newbcast.  (Folding the broadcast into the FMAs as their DPP operand
+// issues fewer instructions but measures slower.)  Sums are FP64 for FP64
+// storage and FP32 otherwise.
 #include <type_traits>
 
 #include "device_common.h"
@@ -511,7 +512,8 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
   auto issue_pos = [&](uint32_t c0, int n, double& xv, uint32_t& qv) {
     const int pi = min(tid / 3, max(n - 1, 0));
     const int64_t p = min((int64_t)c0 + pi, (int64_t)a.np - 1);
-    xv = a.X[3 * p + tid % 3];
+    const int64_t xi = a.x_by_orig ? (int64_t)a.orig[p] : p;
+    xv = a.X[3 * xi + tid % 3];
     // axis-1 threads fetch the gradient destination, the others the value one
     const uint32_t* src = (tid % 3 == 1 && a.grad_orig) ? a.grad_orig : a.orig;
     qv = src ? src[p] : (uint32_t)p;
@@ -540,7 +542,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
       if (ax == 1) *(uint32_t*)(rp + 44) = qv;
     }
   };
-  auto compute_chunk = [&](int n) {
+  auto compute_chunk = [&](int n) __attribute__((always_inline)) {
     const int wave_grp0 = __builtin_amdgcn_readfirstlane(grp & ~(64 / GL - 1));  // first group of this wave
     for (int r0 = 0; r0 < n; r0 += GROUPS) {
       if (r0 + wave_grp0 >= n) break;  // nothing left for this wave: its SIMD serves other waves

@@ -64,7 +64,8 @@ struct InterpArgs {
   double invd;
   int64_t ntx, n_tiles, nw;  // tile columns per axis, columns, x3 windows per column
   int64_t nseg, wps;         // x3 segments per column (one workgroup each), windows per segment
-  const double* X;          // positions in bin order
+  const double* X;          // positions in bin order, or indexed by orig (x_by_orig)
+  int x_by_orig;            // particle p's position is X[orig[p]] rather than X[p]
   int64_t np;               // number of particles
   const uint32_t* offsets;  // [n_bins + 1]
   const uint32_t* orig;     // destination index of each bin-ordered particle, or NULL
