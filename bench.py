@@ -138,7 +138,7 @@ def summarize_pmc(fetch_dir, write_dir):
         out[f"copy_{key}_factor"] = factor
         lines.append(f"| calibration copy (1 GiB) | {counter} | {statistics.mean(copy_kib):.0f} KiB | "
                      f"factor {factor:.4f} |")
-        for kind, needle in (("interp_grad", "k_interp<1, 8, true>"), ("interp", "k_interp<1, 8, false>")):
+        for kind, needle in (("interp_grad", "k_interp<1, 8, true, false>"), ("interp", "k_interp<1, 8, false, false>")):
             kib = pick(vals, needle)
             b = statistics.mean(kib) * 1024.0 / factor
             out[f"{kind}_{key}"] = b
