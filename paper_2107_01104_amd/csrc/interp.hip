@@ -473,13 +473,14 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
   // (issued in that order, so each wait only covers older loads).
   // windows of plane prefetch: the planes of window v are loaded into buffer
   // v mod DEPTH, DEPTH windows ahead (one for the gradient kernels, which
-  // need the registers).  Positions and destination indices are loaded two
-  // windows ahead into buffer v mod 2, so that a window with few particles
-  // does not wait for memory.
+  // need the registers).  Positions and destination indices are loaded one
+  // window ahead, or two (into buffer v mod 2) where registers allow, so that
+  // a window with few particles does not wait for memory.
   constexpr int DEPTH = GRAD ? 1 : 2;
-  // positions two windows ahead, except where the registers would spill
-  // (FP64 nodes; gradients of 16-bit storage)
-  constexpr bool POS2 = ST == ST_F32 || (!GRAD && ST != ST_F64);
+  // positions two windows ahead for the FP32 gradient kernel; one window
+  // ahead elsewhere (FP64 nodes and 16-bit gradients would spill; the value
+  // kernels measure faster with the registers left to the sums)
+  constexpr bool POS2 = GRAD && ST == ST_F32;
   uint4 pre[DEPTH][Gm::PRE][3];
   bool pok[DEPTH][Gm::PRE];
   double pos_x[2] = {0.0, 0.0};
