@@ -66,10 +66,21 @@ constexpr int kTile = kSortThreads * kSortItems;  // 2048
 
 // n_dev (optional): the element count held on the device; n is then an upper
 // bound that sized the grid, and tiles past the count contribute nothing.
+// tiles of a sort of n elements, or of min(n, *n_dev) when the count lives on
+// the device; the digit histograms are laid out [digit][tiles]
+__device__ __forceinline__ int64_t sort_tiles(int64_t n, const uint32_t* n_dev) {
+  if (n_dev) n = min(n, (int64_t)*n_dev);
+  return (n + kTile - 1) / kTile;
+}
+
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
                                                     const uint32_t* __restrict__ n_dev, int shift, uint32_t mask,
                                                     uint32_t* __restrict__ hist, int64_t n_tiles) {
-  if (n_dev) n = min(n, (int64_t)*n_dev);
+  if (n_dev) {
+    n_tiles = sort_tiles(n, n_dev);
+    if ((int64_t)blockIdx.x >= n_tiles) return;
+    n = min(n, (int64_t)*n_dev);
+  }
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -86,7 +97,10 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, int64_t n,
     const uint32_t* __restrict__ n_dev, int shift, uint32_t mask, int bits, const uint32_t* __restrict__ prefix,
     int64_t n_tiles, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
-  if (n_dev) n = min(n, (int64_t)*n_dev);
+  if (n_dev) {
+    n_tiles = sort_tiles(n, n_dev);
+    n = min(n, (int64_t)*n_dev);
+  }
   if ((int64_t)blockIdx.x * kTile >= n) return;
   __shared__ uint32_t wcount[4][256];
   const int lane = threadIdx.x & 63;
@@ -160,8 +174,17 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* sh
   return wpre + x - v;
 }
 
+// length of a scan over sort histograms whose tile count lives on the device
+// (cnt != NULL: 256 digits x sort_tiles(cap, cnt)), else n
+__device__ __forceinline__ int64_t scan_len(int64_t n, const uint32_t* cnt, int64_t cap) {
+  return cnt ? 256 * sort_tiles(cap, cnt) : n;
+}
+
 __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ a, int64_t n,
-                                                     uint32_t* __restrict__ sums) {
+                                                     uint32_t* __restrict__ sums, const uint32_t* __restrict__ cnt,
+                                                     int64_t cap) {
+  n = scan_len(n, cnt, cap);
+  if ((int64_t)blockIdx.x * kScanBlock >= n) return;
   __shared__ uint32_t sh[4];
   int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
   uint32_t s = 0;
@@ -172,7 +195,9 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict_
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ sums, int64_t nb) {
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ sums, int64_t nb,
+                                                  const uint32_t* __restrict__ cnt, int64_t cap) {
+  if (cnt) nb = (scan_len(0, cnt, cap) + kScanBlock - 1) / kScanBlock;
   __shared__ uint32_t sh[4];
   uint32_t carry = 0;
   for (int64_t base = 0; base < nb; base += 256) {
@@ -186,7 +211,10 @@ __global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ sums, i
 }
 
 __global__ __launch_bounds__(256) void k_scan_apply(uint32_t* __restrict__ a, int64_t n,
-                                                    const uint32_t* __restrict__ sums) {
+                                                    const uint32_t* __restrict__ sums,
+                                                    const uint32_t* __restrict__ cnt, int64_t cap) {
+  n = scan_len(n, cnt, cap);
+  if ((int64_t)blockIdx.x * kScanBlock >= n) return;
   __shared__ uint32_t sh[4];
   int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
   uint32_t v[4], s = 0;
@@ -417,13 +445,20 @@ size_t sort_hist_words(int64_t n) {
 
 size_t scan_tmp_words(int64_t m) { return (size_t)((m + kScanBlock - 1) / kScanBlock + 1); }
 
-hipError_t exclusive_scan_u32(uint32_t* a, int64_t m, uint32_t* tmp, hipStream_t s) {
+// exclusive scan of a[0, m); with cnt != NULL the length is the histogram
+// size of a sort of min(cap, *cnt) elements (m is then its upper bound)
+static hipError_t scan_u32(uint32_t* a, int64_t m, uint32_t* tmp, const uint32_t* cnt, int64_t cap,
+                           hipStream_t s) {
   if (m == 0) return hipSuccess;
   int64_t nb = (m + kScanBlock - 1) / kScanBlock;
-  k_scan_reduce<<<(unsigned)nb, 256, 0, s>>>(a, m, tmp);
-  k_scan_top<<<1, 256, 0, s>>>(tmp, nb);
-  k_scan_apply<<<(unsigned)nb, 256, 0, s>>>(a, m, tmp);
+  k_scan_reduce<<<(unsigned)nb, 256, 0, s>>>(a, m, tmp, cnt, cap);
+  k_scan_top<<<1, 256, 0, s>>>(tmp, nb, cnt, cap);
+  k_scan_apply<<<(unsigned)nb, 256, 0, s>>>(a, m, tmp, cnt, cap);
   return hipGetLastError();
+}
+
+hipError_t exclusive_scan_u32(uint32_t* a, int64_t m, uint32_t* tmp, hipStream_t s) {
+  return scan_u32(a, m, tmp, nullptr, 0, s);
 }
 
 // Stable sort of keys.  Values: those in va if vals_in_va, else the input
@@ -448,7 +483,8 @@ hipError_t radix_sort_keys(uint32_t* ka, uint32_t* kb, uint32_t* va, uint32_t* v
   for (int p = 0; p < passes; ++p) {
     const int shift = p * bits;
     k_radix_hist<<<(unsigned)n_tiles, 256, 0, s>>>(kin, n, n_dev, shift, mask, hist, n_tiles);
-    hipError_t e = exclusive_scan_u32(hist, 256 * n_tiles, tmp, s);
+    // with the count on the device, every kernel sizes the histogram from it
+    hipError_t e = scan_u32(hist, 256 * n_tiles, tmp, n_dev, n, s);
     if (e != hipSuccess) return e;
     k_radix_scatter<<<(unsigned)n_tiles, 256, 0, s>>>(kin, vin, n, n_dev, shift, mask, bits, hist, n_tiles,
                                                       kout, vout);
