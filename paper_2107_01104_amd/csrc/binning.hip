@@ -60,6 +60,25 @@ __global__ __launch_bounds__(256) void k_locate(const double* __restrict__ X, in
 //   tile = 256 threads x 8 items; each wave owns 512 consecutive items and
 //   ranks them in 8 rounds of 64 with a ballot-built "same digit" lane mask.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  uint32_t wpre = 0, tot = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) wpre += sh[w];
+    tot += sh[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return wpre + x - v;
+}
+
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kTile = kSortThreads * kSortItems;  // 2048
@@ -103,6 +122,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
   }
   if ((int64_t)blockIdx.x * kTile >= n) return;
   __shared__ uint32_t wcount[4][256];
+  __shared__ uint32_t dstart[256];
+  __shared__ uint32_t scan_sh[4];
+  __shared__ uint32_t skey[kTile], sval[kTile];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   for (int d = threadIdx.x; d < 4 * 256; d += 256) (&wcount[0][0])[d] = 0;
@@ -133,46 +155,42 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     rank[r] = valid ? base + before : 0xFFFFFFFFu;
   }
   __syncthreads();
-  // exclusive prefix of the per-wave counts over waves, per digit
+  // exclusive prefix of the per-wave counts over waves, per digit, and the
+  // start of each digit's run inside the tile
+  uint32_t tile_count = 0;
   {
-    uint32_t run = 0;
     for (int w = 0; w < 4; ++w) {
       uint32_t c = wcount[w][threadIdx.x];
-      wcount[w][threadIdx.x] = run;
-      run += c;
+      wcount[w][threadIdx.x] = tile_count;
+      tile_count += c;
     }
   }
+  uint32_t ntile;
+  const uint32_t my_start = block_excl_scan_256(tile_count, scan_sh, &ntile);
+  dstart[threadIdx.x] = my_start;
   __syncthreads();
+  // the tile in digit order in LDS, then written out run by run: consecutive
+  // threads write consecutive addresses of a digit's run
   for (int r = 0; r < kSortItems; ++r) {
     if (rank[r] == 0xFFFFFFFFu) continue;
-    uint32_t d = (key[r] >> shift) & mask;
-    uint64_t pos = (uint64_t)prefix[(int64_t)d * n_tiles + blockIdx.x] + wcount[wave][d] + rank[r];
-    keys_out[pos] = key[r];
-    vals_out[pos] = val[r];
+    const uint32_t d = (key[r] >> shift) & mask;
+    const uint32_t lp = dstart[d] + wcount[wave][d] + rank[r];
+    skey[lp] = key[r];
+    sval[lp] = val[r];
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < ntile; j += kSortThreads) {
+    const uint32_t k = skey[j];
+    const uint32_t d = (k >> shift) & mask;
+    const uint64_t pos = (uint64_t)prefix[(int64_t)d * n_tiles + blockIdx.x] + (j - dstart[d]);
+    keys_out[pos] = k;
+    vals_out[pos] = sval[j];
   }
 }
 
 // exclusive scan of n uint32 (in place): block sums, scan of sums, apply
 constexpr int kScanBlock = 1024;  // elements per block (256 threads x 4)
 
-__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* sh, uint32_t* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t x = v;
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wave] = x;
-  __syncthreads();
-  uint32_t wpre = 0, tot = 0;
-  for (int w = 0; w < 4; ++w) {
-    if (w < wave) wpre += sh[w];
-    tot += sh[w];
-  }
-  __syncthreads();
-  *total = tot;
-  return wpre + x - v;
-}
 
 // length of a scan over sort histograms whose tile count lives on the device
 // (cnt != NULL: 256 digits x sort_tiles(cap, cnt)), else n
