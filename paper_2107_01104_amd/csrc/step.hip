@@ -12,46 +12,58 @@
 
 namespace ptk {
 
-// One block: 256 particles.  Positions and velocities are [n][3] rows; the
-// block stages its 768 consecutive entries of each through LDS so that every
-// global access is a unit-stride wave access, then each thread updates one
-// particle.
-constexpr int kUpdBlock = 256;
+// One block: 512 particles, 256 threads.  Positions and velocities are [n][3]
+// rows; the block stages its consecutive rows of each through LDS (16-byte
+// loads and stores where the block is full and the arrays are 16-byte
+// aligned), so every global access is a unit-stride wave access, then each
+// thread updates two particles.
+constexpr int kUpdThreads = 256;
+constexpr int kUpdParts = 512;
+
 template <typename V>
-__global__ __launch_bounds__(kUpdBlock) void k_update(int kind, const double* __restrict__ X, UpdateVel v, double dt,
-                                                      int64_t n, double* __restrict__ Xout, uint32_t* __restrict__ keys,
-                                                      int N, double invd, BinGeom g, int* __restrict__ flag) {
-  __shared__ double sx[3 * kUpdBlock];
-  __shared__ V sk[4][3 * kUpdBlock];
-  const int64_t base = (int64_t)blockIdx.x * kUpdBlock;
-  const int nb = (int)min((int64_t)kUpdBlock, n - base);
-  const int ne = 3 * nb;
-  const int nk = kind == kEulerOrPredict ? 1 : kind == kHeunCorrect ? 2 : v.nk;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < ne; e += kUpdBlock) {
-    sx[e] = X[3 * base + e];
-    for (int j = 0; j < nk; ++j) sk[j][e] = ((const V*)v.k[j])[3 * base + e];
+__device__ __forceinline__ void stage_in(void* dst, const void* src, int nbytes, bool vec) {
+  if (vec) {
+    for (int e = threadIdx.x; e < nbytes / 16; e += kUpdThreads) ((uint4*)dst)[e] = ((const uint4*)src)[e];
+  } else {
+    for (int e = threadIdx.x; e < nbytes / (int)sizeof(V); e += kUpdThreads) ((V*)dst)[e] = ((const V*)src)[e];
   }
+}
+
+template <typename V>
+__global__ __launch_bounds__(kUpdThreads) void k_update(int kind, const double* __restrict__ X, UpdateVel v,
+                                                        double dt, int64_t n, double* __restrict__ Xout,
+                                                        uint32_t* __restrict__ keys, int N, double invd, BinGeom g,
+                                                        int* __restrict__ flag, int aligned) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char upd_smem[];
+  double* sx = (double*)upd_smem;                         // [3 * kUpdParts]
+  V* sk = (V*)(upd_smem + 3 * kUpdParts * sizeof(double));  // [nk][3 * kUpdParts]
+  const int64_t base = (int64_t)blockIdx.x * kUpdParts;
+  const int nb = (int)min((int64_t)kUpdParts, n - base);
+  const int nk = kind == kEulerOrPredict ? 1 : kind == kHeunCorrect ? 2 : v.nk;
+  const bool vec = aligned && nb == kUpdParts;
+  stage_in<double>(sx, X + 3 * base, 3 * nb * (int)sizeof(double), vec);
+  for (int j = 0; j < nk; ++j)
+    stage_in<V>(sk + j * 3 * kUpdParts, (const V*)v.k[j] + 3 * base, 3 * nb * (int)sizeof(V), vec);
   __syncthreads();
-  if (tid < nb) {
+  const double hdt = 0.5 * dt;
+  for (int p = threadIdx.x; p < nb; p += kUpdThreads) {
     int c[3];
     bool ok = true;
-    const double hdt = 0.5 * dt;
     for (int d = 0; d < 3; ++d) {
-      const int e = 3 * tid + d;
+      const int e = 3 * p + d;
       const double x = sx[e];
-      const double a = (double)sk[0][e];
+      const double a = (double)sk[e];
       double xn;
       if (kind == kEulerOrPredict) {
         xn = x + dt * a;
       } else if (kind == kHeunCorrect) {
-        const double b = (double)sk[1][e];
+        const double b = (double)sk[3 * kUpdParts + e];
         xn = x + hdt * (a + b);
       } else {
         double inc = v.b[0] * a;
-        if (nk > 1) inc = inc + v.b[1] * (double)sk[1][e];
-        if (nk > 2) inc = inc + v.b[2] * (double)sk[2][e];
-        if (nk > 3) inc = inc + v.b[3] * (double)sk[3][e];
+        if (nk > 1) inc = inc + v.b[1] * (double)sk[3 * kUpdParts + e];
+        if (nk > 2) inc = inc + v.b[2] * (double)sk[6 * kUpdParts + e];
+        if (nk > 3) inc = inc + v.b[3] * (double)sk[9 * kUpdParts + e];
         xn = x + dt * inc;
       }
       if (!in_domain(xn)) {
@@ -62,22 +74,34 @@ __global__ __launch_bounds__(kUpdBlock) void k_update(int kind, const double* __
       sx[e] = locate(xn, N, invd, &c[d], &t);  // only this thread touches its three entries
     }
     if (!ok) flag[0] = 1;
-    keys[base + tid] = bin_key(c[0], c[1], c[2], g);
+    keys[base + p] = bin_key(c[0], c[1], c[2], g);
   }
   __syncthreads();
-  for (int e = tid; e < ne; e += kUpdBlock) Xout[3 * base + e] = sx[e];
+  if (vec) {
+    for (int e = threadIdx.x; e < 3 * kUpdParts * 8 / 16; e += kUpdThreads)
+      ((uint4*)(Xout + 3 * base))[e] = ((const uint4*)sx)[e];
+  } else {
+    for (int e = threadIdx.x; e < 3 * nb; e += kUpdThreads) Xout[3 * base + e] = sx[e];
+  }
 }
 
 hipError_t launch_update(int kind, int vel_f64, const double* X, const UpdateVel& v, double dt, int64_t n,
                          double* Xout, uint32_t* keys, int N, double invd, const BinGeom& g, int* flag,
                          hipStream_t s) {
   if (n == 0) return hipSuccess;
-  if (kind == kAB && (v.nk < 1 || v.nk > 4)) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)((n + kUpdBlock - 1) / kUpdBlock);
+  const int nk = kind == kEulerOrPredict ? 1 : kind == kHeunCorrect ? 2 : v.nk;
+  if (nk < 1 || nk > 4) return hipErrorInvalidValue;
+  for (int j = 0; j < nk; ++j)
+    if (!v.k[j]) return hipErrorInvalidValue;
+  bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)Xout % 16 == 0);
+  for (int j = 0; j < nk; ++j) aligned = aligned && ((uintptr_t)v.k[j] % 16 == 0);
+  const unsigned blocks = (unsigned)((n + kUpdParts - 1) / kUpdParts);
+  const size_t vb = vel_f64 ? sizeof(double) : sizeof(float);
+  const size_t lds = 3 * kUpdParts * sizeof(double) + (size_t)nk * 3 * kUpdParts * vb;
   if (vel_f64)
-    k_update<double><<<blocks, kUpdBlock, 0, s>>>(kind, X, v, dt, n, Xout, keys, N, invd, g, flag);
+    k_update<double><<<blocks, kUpdThreads, lds, s>>>(kind, X, v, dt, n, Xout, keys, N, invd, g, flag, aligned);
   else
-    k_update<float><<<blocks, kUpdBlock, 0, s>>>(kind, X, v, dt, n, Xout, keys, N, invd, g, flag);
+    k_update<float><<<blocks, kUpdThreads, lds, s>>>(kind, X, v, dt, n, Xout, keys, N, invd, g, flag, aligned);
   return hipGetLastError();
 }
 
