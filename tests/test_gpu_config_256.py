@@ -1,0 +1,126 @@
+"""Parity at the mid-size workload (marked gpu): 256^3 FP32 spectral field
+(k <= 80, seed 3), 10^7 uniform particles (seed 13), C1 spline with I = 6, AB2
+with dt = 2e-3 and re-binning every step.
+
+The oracle computes a seeded sample of particles one by one: values and
+gradients, and the first two steps (Euler start-up, then AB2) of the sample's
+trajectories on the same stored FP32 values.  The 100-step run is checked by
+properties that hold at any size: positions stay in [0, 2 pi), the history
+depth is 2, and 100 steps equal 40 + 60 steps resumed from the returned state
+bit for bit.  Bars as in test_gpu_parity (FP32 sums within 64 * 2^-24 * A).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import geometry, interp, stepping
+from oracle import kernels as K
+from synthetic import fields, particles
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+L = geometry.L
+N, NP, NS = 256, 10_000_000, 2048
+DT = 2e-3
+FAM, I, M = K.SPLINE, 6, 1
+F32_BOUND = 64 * 2.0 ** -24
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def within(gpu, ref, absum):
+    return bool(np.all(np.abs(gpu - ref) <= F32_BOUND * absum))
+
+
+def circ(a, b):
+    d = np.abs(a - b) % L
+    return np.minimum(d, L - d)
+
+
+@pytest.fixture(scope="module")
+def ptk():
+    from paper_2107_01104_amd import ptk as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def setup(ptk):
+    say("[256^3] field k<=80 seed 3; 1e7 particles seed 13; C1 spline I=6")
+    u = fields.spectral_field(N, kc=80.0, seed=3, device=DEV, dtype=torch.float32)
+    ctx = ptk.Context(0)
+    ctx.set_field(u, FAM, I, M, storage=ptk.F32)
+    uh = u.cpu().numpy()
+    del u
+    X = particles.uniform_particles(NP, seed=13, device=DEV)
+    rng = np.random.default_rng(256)
+    idx = np.unique(np.concatenate([[0, NP - 1], rng.choice(NP, NS, replace=False)]))
+    yield ctx, uh, X, idx
+    ctx.close()
+
+
+def test_values_and_gradients_sampled(ptk, setup):
+    ctx, uh, X, idx = setup
+    say("[256^3] value + gradient and value kernels on all 1e7")
+    idx_d = torch.from_numpy(idx).to(DEV)
+    Xs = X[idx_d].cpu().numpy()
+    uv, g = ctx.interpolate_gradient(X, out_dtype=torch.float32)
+    val = ctx.interpolate(X)
+    ru, rg = interp.interp_vec(uh, Xs, FAM, I, M, gradient=True)
+    au, ag = interp.interp_vec(uh, Xs, FAM, I, M, gradient=True, absolute=True)
+    assert within(uv[idx_d].cpu().numpy().astype(np.float64), ru, au)
+    assert within(g[idx_d].cpu().numpy().astype(np.float64), rg, ag)
+    assert within(val[idx_d].cpu().numpy().astype(np.float64), ru, au)
+
+
+def test_ab2_first_steps_sampled(ptk, setup):
+    """Two steps (Euler start-up, then AB2) on all 1e7 particles; the sample's
+    trajectories against the oracle's.  Each step moves a position by dt times
+    a velocity whose FP32 error is below the bound, and the second step's
+    velocity is taken at positions that differ by that much (a second-order
+    effect, covered by the factor 1.1)."""
+    ctx, uh, X, idx = setup
+    say("[256^3] 2 AB2 steps")
+    idx_d = torch.from_numpy(idx).to(DEV)
+    Xs = X[idx_d].cpu().numpy()
+    Xa = X.clone()
+    hist = torch.zeros((2, NP, 3), dtype=torch.float32, device=DEV)
+    hl = ctx.advance(Xa, stepping.AB2, DT, 2, hist=hist, hist_len=0)
+    assert hl == 2
+    X2 = Xa[idx_d].cpu().numpy()
+    vel = lambda Y: interp.interp_vec(uh, Y, FAM, I, M)
+    Xo, ho, hlo, _ = stepping.advance(Xs, vel, stepping.AB2, DT, 2)
+    assert hlo == 2
+    X1o = stepping.advance(Xs, vel, stepping.AB2, DT, 1)[0]
+    a0 = interp.interp_vec(uh, Xs, FAM, I, M, absolute=True).max(axis=1)
+    a1 = interp.interp_vec(uh, X1o, FAM, I, M, absolute=True).max(axis=1)
+    # step 1: dt * e0; step 2: dt * (1.5 e1 + 0.5 e0)
+    tol = DT * F32_BOUND * (1.5 * a0 + 1.5 * a1) * 1.1 + 8 * np.spacing(L)
+    d = circ(X2, Xo).max(axis=1)
+    say(f"  max position difference {d.max():.3e} (tolerance min {tol.min():.3e})")
+    assert np.all(d <= tol)
+    # the returned history is u at the sample's previous positions, in caller order
+    hv = hist[:, idx_d].cpu().numpy().astype(np.float64)
+    a_hist = np.stack([a1, a0])[:, :, None]
+    assert np.all(np.abs(hv - ho) <= F32_BOUND * a_hist * 1.1)
+
+
+def test_ab2_100_steps_resume_and_domain(ptk, setup):
+    ctx, uh, X, idx = setup
+    say("[256^3] 100 AB2 steps = 40 + 60 resumed")
+    Xa = X.clone()
+    ha = torch.zeros((2, NP, 3), dtype=torch.float32, device=DEV)
+    la = ctx.advance(Xa, stepping.AB2, DT, 100, hist=ha, hist_len=0)
+    Xb = X.clone()
+    hb = torch.zeros((2, NP, 3), dtype=torch.float32, device=DEV)
+    lb = ctx.advance(Xb, stepping.AB2, DT, 40, hist=hb, hist_len=0)
+    lb = ctx.advance(Xb, stepping.AB2, DT, 60, hist=hb, hist_len=lb)
+    assert la == lb == 2
+    assert torch.equal(Xa, Xb) and torch.equal(ha, hb)
+    assert bool(torch.all((Xa >= 0) & (Xa < L)))
+    assert bool(torch.all(torch.isfinite(ha)))
