@@ -172,7 +172,7 @@ def main():
         summarize_pmc(*args.summarize_pmc)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus above 1 is not supported "
+        print(json.dumps({"error": "the library runs on one GPU; --gpus above 1 is not supported "
                                    "(x3-slab sharding over several GPUs is a design, not built)"}))
         sys.exit(2)
 
