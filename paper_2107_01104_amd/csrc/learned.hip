@@ -518,8 +518,15 @@ __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X
   load_weight_frags(w1b, w2b, bw1, bw2);
   const float bias1 = params[oB1 + J], bias2 = params[oB2 + J];
   f32x16 unused1[2], unused2[2];
+  // each block walks a contiguous range of chunks (neighbouring bins, so its
+  // stencil reads stay in L2 and in the translation caches); consecutive
+  // blocks go round-robin to the 8 XCDs, so XCD x is given a contiguous range
   const int64_t nchunks = (n + ROWS - 1) / ROWS;
-  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  const int64_t per_xcd = gridDim.x / 8;
+  const int64_t bid = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int64_t per_block = (nchunks + gridDim.x - 1) / gridDim.x;
+  const int64_t ch_end = min(nchunks, (bid + 1) * per_block);
+  for (int64_t ch = bid * per_block; ch < ch_end; ++ch) {
     const int pi = t >> 2, k3 = t & 3;
     const int64_t p = min(ch * ROWS + pi, n - 1);
     const bool active = ch * ROWS + pi < n;
@@ -628,7 +635,7 @@ hipError_t launch_learned_infer(const LearnedField& f, const double* X, int64_t 
                                 int* flag, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t nchunks = (n + ROWS - 1) / ROWS;
-  const int64_t grid = min(nchunks, (int64_t)256 * 2 * 4);
+  const int64_t grid = min((nchunks + 7) / 8 * 8, (int64_t)256 * 2 * 4);  // a multiple of the 8 XCDs
   k_infer<<<(unsigned)grid, NT, 0, s>>>(f, X, n, orig, params, w1b, w2b, out, flag);
   return hipGetLastError();
 }
