@@ -210,6 +210,13 @@ int bin_sorted(ptk_ctx* c, int64_t Np, int64_t n_bins, uint32_t** perm, hipStrea
   return PTK_OK;
 }
 
+// positions gathered into bin order in c->xs, which is grown to fit first
+int gather_positions(ptk_ctx* c, const double* X, const uint32_t* perm, int64_t Np, hipStream_t s) {
+  PTK_TRY(ensure(c, c->xs, (size_t)Np * 24));
+  PTK_HIP(c, gather3_f64(X, perm, Np, (double*)c->xs.ptr, s), "gather positions");
+  return PTK_OK;
+}
+
 InterpArgs base_args(const ptk_ctx* c) {
   InterpArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -263,7 +270,6 @@ int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* gr
     return PTK_OK;
   }
   PTK_TRY(ensure_binning(c, Np, n_bins));
-  PTK_TRY(ensure(c, c->xs, (size_t)Np * 24));
   PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
   {
     Timed t(c, s, PTK_T_KEYS);
@@ -277,12 +283,11 @@ int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* gr
     Timed t(c, s, PTK_T_SORT);
     PTK_TRY(bin_sorted(c, Np, n_bins, &perm, s));
   }
-  {
-    Timed t(c, s, PTK_T_PERMUTE);
-    PTK_HIP(c, gather3_f64(X, perm, Np, (double*)c->xs.ptr, s), "gather positions");
-  }
+  // the kernel reads the caller's positions through the bin permutation (the
+  // order it also writes the results in): no gathered copy
   InterpArgs a = base_args(c);
-  a.X = (const double*)c->xs.ptr;
+  a.X = X;
+  a.x_by_orig = 1;
   a.np = Np;
   a.orig = perm;
   a.out = u_out;
@@ -955,7 +960,6 @@ int ptk_interpolate_learned(ptk_ctx* c, const double* X, int64_t Np, float* out,
   const int64_t n_bins = n_bins_of(bg);
   c->bin_valid = false;
   PTK_TRY(ensure_binning(c, Np, n_bins));
-  PTK_TRY(ensure(c, c->xs, (size_t)Np * 24));
   PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
   {
     Timed t(c, s, PTK_T_KEYS);
@@ -969,7 +973,7 @@ int ptk_interpolate_learned(ptk_ctx* c, const double* X, int64_t Np, float* out,
   }
   {
     Timed t(c, s, PTK_T_PERMUTE);
-    PTK_HIP(c, gather3_f64(X, perm, Np, (double*)c->xs.ptr, s), "gather positions");
+    PTK_TRY(gather_positions(c, X, perm, Np, s));
   }
   {
     Timed t(c, s, PTK_T_LEARNED);
