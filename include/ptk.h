@@ -8,8 +8,8 @@
  * particle positions with I-point tensor-product kernels (Sec. 2.2, the four
  * enumerated steps and Eq. "triple_sum"), its gradient through derivative
  * kernels, and the tracer ODE dX/dt = u(X) (Eq. "tracers") advanced with
- * Euler, Heun or two-step Adams-Bashforth using a per-particle rhs history
- * (Sec. 2.2; Sec. 3.3.1 "Particle data structure").
+ * Euler, Heun or Adams-Bashforth of order 2 to 4 using a per-particle rhs
+ * history (Sec. 2.2; Sec. 3.3.1 "Particle data structure").
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -161,8 +161,10 @@ int ptk_interpolate_gradient(ptk_ctx *ctx, const double *X, int64_t Np, void *u_
  * grad_out: device [Np][3][3] (binary64 for F64 storage, else FP32) or NULL;
  *    if given, every step also evaluates the gradient at its start position,
  *    and on return grad_out holds the one of the last step.
- * Particles are re-binned (stable sort by bin) after every position update
- * and kept in bin order internally; results are returned in the order of X. */
+ * Particles are re-binned after every position update to the stable order of
+ * their new bins (only the particles whose bin changed are sorted, then merged
+ * with the others) and kept in bin order internally; results are returned in
+ * the order of X. */
 int ptk_advance_particles(ptk_ctx *ctx, double *X, int64_t Np, void *rhs_hist, int *hist_len,
                           int scheme, double dt, int nsteps, void *grad_out, void *stream);
 
