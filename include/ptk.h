@@ -174,8 +174,8 @@ int ptk_advance_particles(ptk_ctx *ctx, double *X, int64_t Np, void *rhs_hist, i
  * windows of W cell layers; bin of cell c:
  *   key = ((c2/T) * ntx + c1/T) * nw + c3/W,  ntx = ceil(N/T), nw = ceil(N/W),
  * so within a column particles are ordered along x3 like the paper's slices.
- * T is 12 for FP32/BF16/FP16 storage and 8 for FP64 storage; W is 5 (with
- * I = 8 the W + I - 1 = 12 planes a window touches fill the LDS ring). */
+ * T is 12 and W is 5 for every storage type (with I = 8 the W + I - 1 = 12
+ * planes a window touches fill the LDS ring). */
 int ptk_binning_info(const ptk_ctx *ctx, int64_t *np, int64_t *n_bins, int *tile, int *window);
 
 /* Copy that binning to device buffers: perm[k] (uint32 [np]) = index in X of

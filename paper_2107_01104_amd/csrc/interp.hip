@@ -58,7 +58,7 @@ struct StoreT<ST_F64> {
   static constexpr int T = kTileF64;
   static constexpr int NB = 32;
   static constexpr int GB = 24;
-  static constexpr int THREADS = 256;
+  static constexpr int THREADS = 512;
 };
 
 template <int ST, int I>

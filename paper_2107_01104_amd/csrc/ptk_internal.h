@@ -12,9 +12,10 @@ namespace ptk {
 
 constexpr int kMaxI = 8;           // largest kernel size built into the library
 // Bins: tile columns of T x T cells in (x1, x2), cut along x3 into windows of
-// kWindow cell layers; T depends on the storage type (LDS budget per node).
+// kWindow cell layers.  T per storage type: FP32 and 16-bit nodes leave room
+// for two workgroups per CU; FP64 nodes (32 bytes in LDS) fill one.
 constexpr int kTileF32 = 12;       // FP32, BF16, FP16 storage
-constexpr int kTileF64 = 8;        // FP64 storage
+constexpr int kTileF64 = 12;       // FP64 storage
 constexpr int kWindow = 5;
 constexpr double kL = 6.283185307179586;  // fl64(2*pi)
 // learned correction form: features per particle, their row pitch, parameters

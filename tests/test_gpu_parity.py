@@ -130,7 +130,7 @@ def test_binning_bit_exact_f64_tiles(ptk):
     ctx.interpolate(torch.from_numpy(X).to(DEV), out_dtype=torch.float64)
     torch.cuda.synchronize()
     perm, off, T, W = ctx.binning()
-    assert (T, W) == (8, 5)
+    assert (T, W) == (12, 5)
     keys = geometry.bin_keys(X, N, T, W)
     assert np.array_equal(perm.cpu().numpy().astype(np.int64), geometry.stable_order(keys))
     assert np.array_equal(off.cpu().numpy().astype(np.int64), geometry.offsets_from_keys(keys, geometry.n_bins(N, T, W)))
