@@ -139,3 +139,87 @@ def test_odd_sizes_rejected():
         K.nodes(5)
     with pytest.raises(ValueError):
         K.spline_kernel(6, 3)
+
+
+# ---- the spline reading rebuilt by a second, independent construction: Hermite
+# interpolation in Newton form (confluent divided differences) of the data
+# e_j, with the end derivatives taken from centred Lagrange interpolants built
+# by ordinary divided differences.  The oracle solves a linear system in the
+# monomial basis instead; the two share no code.
+
+def _newton(xs, ys):
+    """Divided-difference coefficients on distinct nodes xs."""
+    c = list(ys)
+    for k in range(1, len(xs)):
+        for i in range(len(xs) - 1, k - 1, -1):
+            c[i] = (c[i] - c[i - 1]) / (xs[i] - xs[i - k])
+    return c
+
+
+def _newton_deriv_at(xs, c, x, k):
+    """k-th derivative at x of sum_i c_i prod_{l<i} (t - xs_l), by expanding the
+    products into ascending coefficients."""
+    poly = [Fr(0)] * len(c)
+    basis = [Fr(1)]
+    for i, ci in enumerate(c):
+        for p, b in enumerate(basis):
+            poly[p] += ci * b
+        nxt = [Fr(0)] * (len(basis) + 1)
+        for p, b in enumerate(basis):
+            nxt[p + 1] += b
+            nxt[p] -= xs[i] * b
+        basis = nxt
+    tot = Fr(0)
+    for p in range(k, len(poly)):
+        fall = 1
+        for q in range(k):
+            fall *= p - q
+        tot += poly[p] * fall * Fr(x) ** (p - k)
+    return tot
+
+
+def _hermite_eval(zs, derivs, t):
+    """Hermite interpolant in Newton form: zs sorted with repeats, derivs[z][k]
+    the k-th derivative at node z; evaluated at t."""
+    n = len(zs)
+    table = [[Fr(0)] * n for _ in range(n)]
+    for i in range(n):
+        table[i][0] = derivs[zs[i]][0]
+    for k in range(1, n):
+        for i in range(n - k):
+            if zs[i + k] == zs[i]:
+                f = 1
+                for q in range(2, k + 1):
+                    f *= q
+                table[i][k] = derivs[zs[i]][k] / f
+            else:
+                table[i][k] = (table[i + 1][k - 1] - table[i][k - 1]) / (zs[i + k] - zs[i])
+    val, prod = Fr(0), Fr(1)
+    for k in range(n):
+        val += table[0][k] * prod
+        prod *= (t - zs[k])
+    return val
+
+
+def _spline_weight_hermite(I, m, j, t):
+    n = I // 2 - 1
+    data = {x: Fr(int(x == j)) for x in range(-n - 1, n + 3)}
+    left = list(range(-n, n + 1))
+    right = list(range(1 - n, n + 2))
+    cl = _newton(left, [data[x] for x in left])
+    cr = _newton(right, [data[x] for x in right])
+    derivs = {0: [data[0]] + [_newton_deriv_at(left, cl, 0, k) for k in range(1, m + 1)],
+              1: [data[1]] + [_newton_deriv_at(right, cr, 1, k) for k in range(1, m + 1)]}
+    extra = list(range(-(n - m), 0)) + list(range(2, n - m + 2))
+    for r in extra:
+        derivs[r] = [data[r]]
+    zs = sorted(extra + [0] * (m + 1) + [1] * (m + 1))
+    return _hermite_eval(zs, derivs, Fr(t))
+
+
+@pytest.mark.parametrize("I,m", [(4, 1), (6, 1), (6, 2), (8, 1), (8, 2), (8, 3)])
+def test_spline_matches_hermite_newton_construction(I, m):
+    for t in [Fr(1, 4), Fr(2, 3), Fr(9, 10)]:
+        got = K.weights_exact(K.SPLINE, I, m, t)
+        want = [_spline_weight_hermite(I, m, j, t) for j in K.nodes(I)]
+        assert got == want
