@@ -9,8 +9,9 @@
 // (T+I-1)^2 halo nodes of the W+I-1 x3 planes a window touches live in an LDS
 // ring; each plane is read from HBM once per tile column (halo over-fetch
 // ((T+I-1)/T)^2, 2.5 for T = 12, I = 8), and the planes the next windows add
-// are loaded into registers while the current window is computed.  The ring is
-// small enough for two workgroups per CU (16 waves) to hide latency.
+// are loaded into registers while the current window is computed.  With FP32
+// and 16-bit nodes the ring leaves room for two 512-thread workgroups per CU
+// (16 waves); FP64 nodes fill the LDS with one.
 //
 // Per particle: a group of 16 lanes (32 for the FP32/16-bit value kernels with
 // I = 4 or 8).  Lane j = lane & 7 owns the x1 node offset j; the half-rows
