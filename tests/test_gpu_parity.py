@@ -13,9 +13,9 @@ I (x2) + I (x3) + 4 (lane reduction) <= 20 and FP32 Horner weights (<= 7 steps
 each, three factors); Horner's rule has the error bound 2*steps*u*sum_p |c_p|
 t^p (u = 2^-24), so every first-order term is below 64 u times A.  The FP32
 rounding of the offset t adds |beta'| 2^-24 per weight, a few per cent of the
-bound.  Relative RMS differences are also required to stay below 1e-6 for
-values and 4e-6 for gradients (typical FP32 accumulation error, reported
-beside the bound).
+bound.  The RMS difference is also required to stay below a quarter of the
+RMS of that bound (rounding errors add up like a random walk, far from the
+worst case), and the relative RMS is reported beside it.
 """
 import math
 import sys
@@ -54,6 +54,13 @@ F32_BOUND = 64 * 2.0 ** -24
 
 def within_f32_bound(gpu, ref, absum):
     return bool(np.all(np.abs(gpu - ref) <= F32_BOUND * absum))
+
+
+def typical_below_bound(gpu, ref, absum):
+    """The RMS difference stays well below the RMS of the per-element bound:
+    first-order rounding errors of a depth-20 sum add up like a random walk
+    (about sqrt(20) u |terms|), a small fraction of the worst case 64 u A."""
+    return float(np.sqrt(np.mean((gpu - ref) ** 2))) <= 0.25 * F32_BOUND * float(np.sqrt(np.mean(absum ** 2)))
 
 
 def circ(a, b):
@@ -171,7 +178,7 @@ def test_interp_f64_small_and_ragged_grids(ptk, fam, I, m, N):
     ctx.close()
 
 
-@pytest.mark.parametrize("fam,I,m", [(K.LAGRANGE, 4, 0), (K.SPLINE, 6, 1), (K.SPLINE, 8, 2)])
+@pytest.mark.parametrize("fam,I,m", KERNELS)
 def test_interp_f32_storage(ptk, fam, I, m):
     say(f"[interp f32] I={I}")
     N = 64
@@ -185,10 +192,10 @@ def test_interp_f32_storage(ptk, fam, I, m):
     uv, g = uv.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
     say(f"  rel rms value {rel_rms(uv, ru):.2e} grad {rel_rms(g, rg):.2e}")
     assert within_f32_bound(uv, ru, au) and within_f32_bound(g, rg, ag)
-    assert rel_rms(uv, ru) <= 1e-6 and rel_rms(g, rg) <= 4e-6
+    assert typical_below_bound(uv, ru, au) and typical_below_bound(g, rg, ag)
     # the value-only kernel (its own lane layout)
     val = ctx.interpolate(torch.from_numpy(X).to(DEV)).cpu().numpy().astype(np.float64)
-    assert within_f32_bound(val, ru, au) and rel_rms(val, ru) <= 1e-6
+    assert within_f32_bound(val, ru, au) and typical_below_bound(val, ru, au)
     ctx.close()
 
 
@@ -230,7 +237,7 @@ def test_interp_sparse_and_clustered(ptk, storage, N, Np, clustered):
 
 
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
-@pytest.mark.parametrize("fam,I,m", [(K.LAGRANGE, 4, 0), (K.SPLINE, 6, 1), (K.SPLINE, 8, 2)])
+@pytest.mark.parametrize("fam,I,m", KERNELS)
 def test_interp_reduced_storage_tight(ptk, storage, fam, I, m):
     say(f"[interp {storage}] I={I}")
     code = ptk.BF16 if storage == "bf16" else ptk.F16
@@ -250,9 +257,9 @@ def test_interp_reduced_storage_tight(ptk, storage, fam, I, m):
     say(f"  rel rms value {rel_rms(uv, ru):.2e} grad {rel_rms(g, rg):.2e}")
     # one more FP32 rounding: the product with the scale s_a
     assert within_f32_bound(uv, ru, au * 1.0625) and within_f32_bound(g, rg, ag * 1.0625)
-    assert rel_rms(uv, ru) <= 1e-6 and rel_rms(g, rg) <= 4e-6
+    assert typical_below_bound(uv, ru, au * 1.0625) and typical_below_bound(g, rg, ag * 1.0625)
     val = ctx.interpolate(torch.from_numpy(X).to(DEV)).cpu().numpy().astype(np.float64)
-    assert within_f32_bound(val, ru, au * 1.0625) and rel_rms(val, ru) <= 1e-6
+    assert within_f32_bound(val, ru, au * 1.0625) and typical_below_bound(val, ru, au * 1.0625)
     ctx.close()
 
 
@@ -298,6 +305,43 @@ def test_multistep_f64_with_gradient(ptk, scheme):
     if scheme in AB_DEPTH:
         assert hl == hlo == AB_DEPTH[scheme]
         assert rel_max(hist.cpu().numpy(), ho) <= 1e-12
+    ctx.close()
+
+
+AB_SUM = {"euler": 1.0, "heun": 1.0, "ab2": 2.0, "ab3": 46.0 / 12.0, "ab4": 160.0 / 24.0}
+
+
+@pytest.mark.parametrize("scheme", ["euler", "heun", "ab2", "ab3", "ab4"])
+def test_multistep_f32_storage(ptk, scheme):
+    """Four steps with gradient on FP32 storage (C2 spline, I = 8) against the
+    oracle on the same stored values.  Each step moves a position by dt times
+    a weighted sum of velocities (weights summing in absolute value to
+    AB_SUM), each within the FP32 bound; over a few steps at dt = 2e-3 on this
+    smooth field the propagated differences stay far below the factor 1.5."""
+    say(f"[advance f32] {scheme}")
+    N, Np, steps, dt = 32, 4000, 4, 2e-3
+    u = fields.spectral_field(N, kc=6.0, seed=5, dtype=torch.float32).numpy()
+    ctx = ptk.Context(0)
+    ctx.set_field(torch.from_numpy(u).to(DEV), K.SPLINE, 8, 2, storage=ptk.F32)
+    X0 = particles.uniform_particles(Np, seed=21, device="cpu").numpy()
+    sc = SCHEMES[scheme]
+    Xd = torch.from_numpy(X0.copy()).to(DEV)
+    hist = torch.zeros((AB_DEPTH[scheme], Np, 3), dtype=torch.float32, device=DEV) if scheme in AB_DEPTH else None
+    grad = torch.zeros((Np, 3, 3), dtype=torch.float32, device=DEV)
+    ctx.advance(Xd, sc, dt, steps, hist=hist, hist_len=0, grad_out=grad)
+    vel = lambda Y: interp.interp_vec(u, Y, K.SPLINE, 8, 2)
+    gfn = lambda Y: interp.interp_vec(u, Y, K.SPLINE, 8, 2, gradient=True)
+    Xo, _, _, go = stepping.advance(X0, vel, sc, dt, steps, gradient=gfn)
+    amax = float(interp.interp_vec(u, X0, K.SPLINE, 8, 2, absolute=True).max())
+    tol = steps * dt * AB_SUM[scheme] * (2 if scheme == "heun" else 1) * F32_BOUND * amax * 1.5 + 8 * np.spacing(L)
+    d = circ(Xd.cpu().numpy(), Xo).max()
+    say(f"  max position difference {d:.3e} (tolerance {tol:.3e})")
+    assert d <= tol
+    # gradient at the last step's start, where the two trajectories differ by
+    # far less than the field's scale
+    Xl = stepping.advance(X0, vel, sc, dt, steps - 1)[0]
+    _, ag = interp.interp_vec(u, Xl, K.SPLINE, 8, 2, gradient=True, absolute=True)
+    assert within_f32_bound(grad.cpu().numpy().astype(np.float64), go, ag * 1.1)
     ctx.close()
 
 
