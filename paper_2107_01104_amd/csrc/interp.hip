@@ -423,13 +423,29 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
   __shared__ __attribute__((aligned(16))) unsigned char recs[CH * RECB];
 
   // ---- block -> (tile column, x3 segment); consecutive blocks go round-robin
-  // to the 8 XCDs, so XCD x is given a contiguous range of columns
+  // to the 8 XCDs, so XCD x is given a contiguous range of an ordering of the
+  // columns by 8 x 8 blocks of columns: the columns an XCD sweeps at the same
+  // time are neighbours in x1 and x2, and the halo planes they share are read
+  // from its L2
   const int64_t nblk = a.n_tiles * a.nseg;
   const int64_t per_xcd = (nblk + 7) / 8;
   const int64_t b = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (b >= nblk) return;
-  const int64_t tile = b / a.nseg;
+  const int64_t ord = b / a.nseg;  // position of the column in the blocked order
   const int seg = (int)(b % a.nseg);
+  int64_t tile;
+  {
+    // 32-bit arithmetic: columns per axis and their count are small
+    constexpr uint32_t S = 8;
+    const uint32_t ntx = (uint32_t)a.ntx, o = (uint32_t)ord;
+    const uint32_t band = o / (S * ntx);                // band of S rows of columns
+    const uint32_t rows = min(S, ntx - band * S);
+    const uint32_t off = o - band * S * ntx;
+    const uint32_t sc = off / (rows * S);               // S-wide block within the band
+    const uint32_t cols = min(S, ntx - sc * S);
+    const uint32_t inner = off - sc * rows * S;
+    tile = (int64_t)((band * S + inner / cols) * ntx + sc * S + inner % cols);
+  }
   const int64_t w_begin = (int64_t)seg * a.wps;
   const int64_t w_end = min(a.nw, w_begin + a.wps);
   if (w_begin >= w_end) return;
