@@ -210,13 +210,6 @@ int bin_sorted(ptk_ctx* c, int64_t Np, int64_t n_bins, uint32_t** perm, hipStrea
   return PTK_OK;
 }
 
-// positions gathered into bin order in c->xs, which is grown to fit first
-int gather_positions(ptk_ctx* c, const double* X, const uint32_t* perm, int64_t Np, hipStream_t s) {
-  PTK_TRY(ensure(c, c->xs, (size_t)Np * 24));
-  PTK_HIP(c, gather3_f64(X, perm, Np, (double*)c->xs.ptr, s), "gather positions");
-  return PTK_OK;
-}
-
 InterpArgs base_args(const ptk_ctx* c) {
   InterpArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -972,13 +965,10 @@ int ptk_interpolate_learned(ptk_ctx* c, const double* X, int64_t Np, float* out,
     PTK_TRY(bin_sorted(c, Np, n_bins, &perm, s));
   }
   {
-    Timed t(c, s, PTK_T_PERMUTE);
-    PTK_TRY(gather_positions(c, X, perm, Np, s));
-  }
-  {
+    // the kernel reads the caller's positions through the permutation
     Timed t(c, s, PTK_T_LEARNED);
     PTK_HIP(c,
-            launch_learned_infer(lf, (const double*)c->xs.ptr, Np, perm, (const float*)c->lparams.ptr,
+            launch_learned_infer(lf, X, Np, perm, (const float*)c->lparams.ptr,
                                  (const uint16_t*)c->lw1b.ptr, (const uint16_t*)c->lw2b.ptr, out, (int*)c->flag.ptr,
                                  s),
             "learned interpolation");

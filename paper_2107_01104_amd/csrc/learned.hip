@@ -495,8 +495,9 @@ __global__ __launch_bounds__(NT) void k_update(float* params, float* m, float* v
 }
 
 // ---------------------------------------------------------------- inference
-// Particles in bin order, 64 per chunk; every workgroup keeps its layer
-// weights in registers and walks chunks blockIdx.x, + gridDim.x, ...
+// Particles in bin order (the k-th is the caller's orig[k]), 64 per chunk;
+// every workgroup keeps its layer weights in registers and walks a range of
+// chunks.
 __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X, int64_t n, const uint32_t* orig,
                                                  const float* params, const uint16_t* w1b, const uint16_t* w2b,
                                                  float* out, int* flag) {
@@ -532,7 +533,7 @@ __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X
     const bool active = ch * ROWS + pi < n;
     int c[3];
     double td[3];
-    const bool ok = locate_quad(X + 3 * p, k3, f.N, f.invd, c, td);
+    const bool ok = locate_quad(X + 3 * (int64_t)(orig ? orig[p] : (uint32_t)p), k3, f.N, f.invd, c, td);
     if (active && !ok) atomicOr(flag, 1);
     uint32_t fe[24];
     float u[3];
