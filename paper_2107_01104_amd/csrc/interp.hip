@@ -504,6 +504,12 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
   uint32_t pos_q[2] = {0u, 0u};
   int pos_n[2] = {0, 0};
   uint32_t pos_s[2] = {0u, 0u}, pos_e[2] = {0u, 0u};  // particle range of the buffered window
+  // one window ahead of the positions (kernels with one position buffer):
+  // the range of window w+2 and, per thread, the row of X and the destination
+  // index of its particle, so that a position read through the permutation
+  // waits for one load per window, not two in a row
+  uint32_t idx_i = 0u, idx_q = 0u, idx_s = 0u, idx_e = 0u;
+  int idx_n = 0;
 
   auto issue_planes = [&](int64_t wn, uint4 (&pre)[Gm::PRE][3], bool (&ok)[Gm::PRE]) {
     const int64_t zn = W * wn + I - 1;  // planes window wn adds: [zn, zn + W)
@@ -629,6 +635,27 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
     nv = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
     if (nv > 0) issue_pos(start, nv, xv, qv);
   };
+  // the range of window v (starting at `start`, the end of window v-1) and
+  // this thread's X row and destination index in it
+  auto issue_window_idx = [&](int64_t v, uint32_t start, uint32_t& iv, uint32_t& qv, int& nv, uint32_t& s_out,
+                              uint32_t& e_out) {
+    const uint32_t end = v < w_end ? a.offsets[tile * a.nw + v + 1] : start;
+    s_out = start;
+    e_out = end;
+    nv = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
+    if (nv > 0) {
+      const int pi = min(tid / 3, nv - 1);
+      const int64_t p = min((int64_t)start + pi, (int64_t)a.np - 1);
+      iv = a.x_by_orig ? a.orig[p] : (uint32_t)p;
+      // axis-1 threads fetch the gradient destination, the others the value one
+      const uint32_t* src = (tid % 3 == 1 && a.grad_orig) ? a.grad_orig : a.orig;
+      qv = src ? src[p] : (uint32_t)p;
+    }
+  };
+  // the coordinate of that row
+  auto issue_window_x = [&](uint32_t iv, int nv, double& xv) {
+    if (nv > 0) xv = a.X[3 * (int64_t)iv + tid % 3];
+  };
   // one window: records of w are in LDS, the ring holds w's planes; plane
   // buffer B (w - w_begin mod DEPTH) receives the planes of w+DEPTH, position
   // buffer P (w - w_begin mod 2) the positions of w+2
@@ -639,10 +666,18 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
     constexpr int P1 = (P + 1) % 2;
     constexpr int PW = POS2 ? P : 0;  // buffer holding w's range
     const uint32_t start = pos_s[PW], end = pos_e[PW];
-    if constexpr (!POS2)  // registers are short: positions one window ahead
-      issue_window_pos(w + 1, end, pos_x[0], pos_q[0], pos_n[0], pos_s[0], pos_e[0]);
-    else
+    if constexpr (!POS2) {
+      // registers are short: positions of w+1 from the rows found a window
+      // ago, then the rows of w+2
+      pos_s[0] = idx_s;
+      pos_e[0] = idx_e;
+      pos_n[0] = idx_n;
+      pos_q[0] = idx_q;
+      issue_window_x(idx_i, idx_n, pos_x[0]);
+      issue_window_idx(w + 2, idx_e, idx_i, idx_q, idx_n, idx_s, idx_e);
+    } else {
       issue_window_pos(w + 2, pos_e[P1], pos_x[P], pos_q[P], pos_n[P], pos_s[P], pos_e[P]);
+    }
     issue_planes(w + DEPTH, pre[B], pok[B]);
     __syncthreads();  // records of w and the ring are complete
     int n = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
@@ -695,13 +730,16 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
   // planes of w_begin+1 .. w_begin+DEPTH-1 in flight
   {
     double xv = 0.0;
-    uint32_t qv = 0;
+    uint32_t qv = 0, iv = 0;
     int nv = 0;
-    issue_window_pos(w_begin, a.offsets[tile * a.nw + w_begin], xv, qv, nv, pos_s[0], pos_e[0]);
+    issue_window_idx(w_begin, a.offsets[tile * a.nw + w_begin], iv, qv, nv, pos_s[0], pos_e[0]);
+    issue_window_x(iv, nv, xv);
     write_rec(w_begin, nv, xv, qv);
   }
   if constexpr (POS2)
     issue_window_pos(w_begin + 1, pos_e[0], pos_x[1], pos_q[1], pos_n[1], pos_s[1], pos_e[1]);
+  else
+    issue_window_idx(w_begin + 1, pos_e[0], idx_i, idx_q, idx_n, idx_s, idx_e);
   static_for<1, DEPTH>([&](auto K) { issue_planes(w_begin + decltype(K)::value, pre[decltype(K)::value], pok[decltype(K)::value]); });
   // windows in pairs so that every buffer index is a constant (single
   // windows when every buffer is the same)
