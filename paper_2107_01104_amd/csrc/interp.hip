@@ -486,28 +486,22 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
   };
 
   // ---- software pipeline over windows: while window w is computed, the
-  // positions of window w+1 and the planes window w+2 adds are in flight
-  // (issued in that order, so each wait only covers older loads).
-  // windows of plane prefetch: the planes of window v are loaded into buffer
+  // positions of window w+1, the particle rows of window w+2 and the planes
+  // window w+DEPTH adds are in flight (issued in that order, so each wait only
+  // covers older loads).  The planes of window v are loaded into buffer
   // v mod DEPTH, DEPTH windows ahead (one for the gradient kernels, which
-  // need the registers).  Positions and destination indices are loaded one
-  // window ahead, or two (into buffer v mod 2) where registers allow, so that
-  // a window with few particles does not wait for memory.
+  // need the registers).  Finding a window's rows (through the bin
+  // permutation where positions are read through it) one window before
+  // loading their coordinates keeps a window with few particles from waiting
+  // on two loads in a row.
   constexpr int DEPTH = GRAD ? 1 : 2;
-  // positions two windows ahead for the FP32 gradient kernel; one window
-  // ahead elsewhere (FP64 nodes and 16-bit gradients would spill; the value
-  // kernels measure faster with the registers left to the sums)
-  constexpr bool POS2 = GRAD && ST == ST_F32;
   uint4 pre[DEPTH][Gm::PRE][3];
   bool pok[DEPTH][Gm::PRE];
-  double pos_x[2] = {0.0, 0.0};
-  uint32_t pos_q[2] = {0u, 0u};
-  int pos_n[2] = {0, 0};
-  uint32_t pos_s[2] = {0u, 0u}, pos_e[2] = {0u, 0u};  // particle range of the buffered window
-  // one window ahead of the positions (kernels with one position buffer):
-  // the range of window w+2 and, per thread, the row of X and the destination
-  // index of its particle, so that a position read through the permutation
-  // waits for one load per window, not two in a row
+  // window w+1: its particle range, this thread's coordinate and destination
+  double pos_x = 0.0;
+  uint32_t pos_q = 0u, pos_s = 0u, pos_e = 0u;
+  int pos_n = 0;
+  // window w+2: its particle range, this thread's row of X and destination
   uint32_t idx_i = 0u, idx_q = 0u, idx_s = 0u, idx_e = 0u;
   int idx_n = 0;
 
@@ -624,17 +618,6 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
       }
     }
   };
-  // positions (up to CH particles) of window v, whose particles start at
-  // `start` (the end of window v-1), into a position buffer; only the end of
-  // its range is read from the offsets
-  auto issue_window_pos = [&](int64_t v, uint32_t start, double& xv, uint32_t& qv, int& nv, uint32_t& s_out,
-                              uint32_t& e_out) {
-    const uint32_t end = v < w_end ? a.offsets[tile * a.nw + v + 1] : start;
-    s_out = start;
-    e_out = end;
-    nv = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
-    if (nv > 0) issue_pos(start, nv, xv, qv);
-  };
   // the range of window v (starting at `start`, the end of window v-1) and
   // this thread's X row and destination index in it
   auto issue_window_idx = [&](int64_t v, uint32_t start, uint32_t& iv, uint32_t& qv, int& nv, uint32_t& s_out,
@@ -656,28 +639,20 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
   auto issue_window_x = [&](uint32_t iv, int nv, double& xv) {
     if (nv > 0) xv = a.X[3 * (int64_t)iv + tid % 3];
   };
-  // one window: records of w are in LDS, the ring holds w's planes; plane
-  // buffer B (w - w_begin mod DEPTH) receives the planes of w+DEPTH, position
-  // buffer P (w - w_begin mod 2) the positions of w+2
-  auto window = [&](int64_t w, auto B_, auto P_) {
+  // one window: records of w are in LDS, the ring holds w's planes, the
+  // position registers hold w's range; plane buffer B (w - w_begin mod DEPTH)
+  // receives the planes of w+DEPTH
+  auto window = [&](int64_t w, auto B_) {
     constexpr int B = decltype(B_)::value;
     constexpr int B1 = (B + 1) % DEPTH;
-    constexpr int P = decltype(P_)::value;
-    constexpr int P1 = (P + 1) % 2;
-    constexpr int PW = POS2 ? P : 0;  // buffer holding w's range
-    const uint32_t start = pos_s[PW], end = pos_e[PW];
-    if constexpr (!POS2) {
-      // registers are short: positions of w+1 from the rows found a window
-      // ago, then the rows of w+2
-      pos_s[0] = idx_s;
-      pos_e[0] = idx_e;
-      pos_n[0] = idx_n;
-      pos_q[0] = idx_q;
-      issue_window_x(idx_i, idx_n, pos_x[0]);
-      issue_window_idx(w + 2, idx_e, idx_i, idx_q, idx_n, idx_s, idx_e);
-    } else {
-      issue_window_pos(w + 2, pos_e[P1], pos_x[P], pos_q[P], pos_n[P], pos_s[P], pos_e[P]);
-    }
+    const uint32_t start = pos_s, end = pos_e;
+    // positions of w+1 from the rows found a window ago, then the rows of w+2
+    pos_s = idx_s;
+    pos_e = idx_e;
+    pos_n = idx_n;
+    pos_q = idx_q;
+    issue_window_x(idx_i, idx_n, pos_x);
+    issue_window_idx(w + 2, idx_e, idx_i, idx_q, idx_n, idx_s, idx_e);
     issue_planes(w + DEPTH, pre[B], pok[B]);
     __syncthreads();  // records of w and the ring are complete
     int n = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
@@ -697,8 +672,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
     // the ring holds at least the planes one window touches: w+1's new planes
     // replace planes no later window reads; then w+1's records
     store_planes(w + 1, pre[B1], pok[B1]);
-    constexpr int PR = POS2 ? P1 : 0;
-    if (w + 1 < w_end) write_rec(w + 1, pos_n[PR], pos_x[PR], pos_q[PR]);
+    if (w + 1 < w_end) write_rec(w + 1, pos_n, pos_x, pos_q);
   };
 
   {
@@ -726,32 +700,28 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
   fill(w_begin);
   __syncthreads();
 
-  // ---- prologue: records of the first window, positions of the second and
+  // ---- prologue: records of the first window, the rows of the second and
   // planes of w_begin+1 .. w_begin+DEPTH-1 in flight
   {
     double xv = 0.0;
     uint32_t qv = 0, iv = 0;
     int nv = 0;
-    issue_window_idx(w_begin, a.offsets[tile * a.nw + w_begin], iv, qv, nv, pos_s[0], pos_e[0]);
+    issue_window_idx(w_begin, a.offsets[tile * a.nw + w_begin], iv, qv, nv, pos_s, pos_e);
     issue_window_x(iv, nv, xv);
     write_rec(w_begin, nv, xv, qv);
   }
-  if constexpr (POS2)
-    issue_window_pos(w_begin + 1, pos_e[0], pos_x[1], pos_q[1], pos_n[1], pos_s[1], pos_e[1]);
-  else
-    issue_window_idx(w_begin + 1, pos_e[0], idx_i, idx_q, idx_n, idx_s, idx_e);
+  issue_window_idx(w_begin + 1, pos_e, idx_i, idx_q, idx_n, idx_s, idx_e);
   static_for<1, DEPTH>([&](auto K) { issue_planes(w_begin + decltype(K)::value, pre[decltype(K)::value], pok[decltype(K)::value]); });
-  // windows in pairs so that every buffer index is a constant (single
-  // windows when every buffer is the same)
+  // windows in pairs so that every plane buffer index is a constant (single
+  // windows when there is one buffer)
   static_assert(DEPTH == 1 || DEPTH == 2, "window pairs cover plane depths 1 and 2");
-  if constexpr (POS2 || DEPTH == 2) {
+  if constexpr (DEPTH == 2) {
     for (int64_t w = w_begin; w < w_end; w += 2) {
-      window(w, std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
-      if (w + 1 < w_end) window(w + 1, std::integral_constant<int, 1 % DEPTH>{}, std::integral_constant<int, 1>{});
+      window(w, std::integral_constant<int, 0>{});
+      if (w + 1 < w_end) window(w + 1, std::integral_constant<int, 1>{});
     }
   } else {
-    for (int64_t w = w_begin; w < w_end; ++w)
-      window(w, std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+    for (int64_t w = w_begin; w < w_end; ++w) window(w, std::integral_constant<int, 0>{});
   }
 }
 
