@@ -504,6 +504,8 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
   // window w+2: its particle range, this thread's row of X and destination
   uint32_t idx_i = 0u, idx_q = 0u, idx_s = 0u, idx_e = 0u;
   int idx_n = 0;
+  // the end of window w+3's range, read a window before it is needed
+  uint32_t end3 = 0u;
 
   auto issue_planes = [&](int64_t wn, uint4 (&pre)[Gm::PRE][3], bool (&ok)[Gm::PRE]) {
     const int64_t zn = W * wn + I - 1;  // planes window wn adds: [zn, zn + W)
@@ -618,11 +620,10 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
       }
     }
   };
-  // the range of window v (starting at `start`, the end of window v-1) and
-  // this thread's X row and destination index in it
-  auto issue_window_idx = [&](int64_t v, uint32_t start, uint32_t& iv, uint32_t& qv, int& nv, uint32_t& s_out,
+  // the range [start, end) of a window and this thread's X row and
+  // destination index in it
+  auto issue_window_idx = [&](uint32_t start, uint32_t end, uint32_t& iv, uint32_t& qv, int& nv, uint32_t& s_out,
                               uint32_t& e_out) {
-    const uint32_t end = v < w_end ? a.offsets[tile * a.nw + v + 1] : start;
     s_out = start;
     e_out = end;
     nv = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
@@ -652,7 +653,8 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
     pos_n = idx_n;
     pos_q = idx_q;
     issue_window_x(idx_i, idx_n, pos_x);
-    issue_window_idx(w + 2, idx_e, idx_i, idx_q, idx_n, idx_s, idx_e);
+    issue_window_idx(idx_e, w + 2 < w_end ? end3 : idx_e, idx_i, idx_q, idx_n, idx_s, idx_e);
+    if (w + 3 < w_end) end3 = a.offsets[tile * a.nw + w + 4];
     issue_planes(w + DEPTH, pre[B], pok[B]);
     __syncthreads();  // records of w and the ring are complete
     int n = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
@@ -706,11 +708,14 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_i
     double xv = 0.0;
     uint32_t qv = 0, iv = 0;
     int nv = 0;
-    issue_window_idx(w_begin, a.offsets[tile * a.nw + w_begin], iv, qv, nv, pos_s, pos_e);
+    const int64_t bin0 = tile * a.nw;
+    issue_window_idx(a.offsets[bin0 + w_begin], a.offsets[bin0 + w_begin + 1], iv, qv, nv, pos_s, pos_e);
     issue_window_x(iv, nv, xv);
     write_rec(w_begin, nv, xv, qv);
+    issue_window_idx(pos_e, w_begin + 1 < w_end ? a.offsets[bin0 + w_begin + 2] : pos_e, idx_i, idx_q, idx_n, idx_s,
+                     idx_e);
+    if (w_begin + 2 < w_end) end3 = a.offsets[bin0 + w_begin + 3];
   }
-  issue_window_idx(w_begin + 1, pos_e, idx_i, idx_q, idx_n, idx_s, idx_e);
   static_for<1, DEPTH>([&](auto K) { issue_planes(w_begin + decltype(K)::value, pre[decltype(K)::value], pok[decltype(K)::value]); });
   // windows in pairs so that every plane buffer index is a constant (single
   // windows when there is one buffer)
