@@ -82,6 +82,21 @@ def traffic_for(kind):
     return rec.get(kind)
 
 
+def cpu_references(u_host, X_dev, n_sample=20000):
+    """The CPU leg's reference values for the error statements of the forms:
+    the oracle (FP64) at the first n_sample workload particles, with the I=8
+    C2 spline (the wide kernel) and with the I=4 Lagrange kernel (the narrow
+    kernel the learned form corrects).  Host work, off the GPU path."""
+    import numpy as np
+    from oracle import interp
+    from oracle import kernels as K
+    sample = X_dev[:n_sample].cpu().numpy()
+    u = u_host.astype(np.float64) if u_host.shape[0] <= 256 else u_host
+    return {"sample": sample,
+            "wide": interp.interp_vec(u, sample, K.SPLINE, 8, 2),
+            "narrow": interp.interp_vec(u_host, sample, K.LAGRANGE, 4, 0)}
+
+
 def cpu_baseline(u_host, X_dev, budget_s=15.0):
     """Time the C oracle (value+gradient and value, as in one Heun step) on a sample.
 
@@ -254,10 +269,13 @@ def main():
                 "hbm_frac": round(hbm / HBM_PEAK_GBS, 4), "launches": launches}
     breakdown = {k: round(v[0] / K, 3) for k, v in timers.items()}
 
+    # CPU leg: the oracle on the host cores -- its timing on a bounded sample
+    # (cpu_baseline) and the reference values the forms' errors are stated
+    # against (cpu_references); nothing on the GPU path calls it
+    cpu = None if args.no_cpu_baseline else cpu_baseline(u_host, X0)
     forms = None
     if not args.no_forms:
-        forms = run_forms(ctx, ptk, u_host, X0, N, Np)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(u_host, X0)
+        forms = run_forms(ctx, ptk, u_host, X0, N, Np, cpu_references(u_host, X0))
 
     line = {
         "metric": "particle-interpolations/sec at I=8, 1024^3 grid; % HBM roofline; RMS err vs FP64",
@@ -277,16 +295,14 @@ def main():
     ctx.close()
 
 
-def run_forms(ctx, ptk, u_host, X0, N, Np):
+def run_forms(ctx, ptk, u_host, X0, N, Np, refs):
     """Interpolation-only timings (velocity) for FP64/FP32/BF16/FP16 storage and the learned
-    form, their errors against the FP64 oracle, and their speed against the FP64 path."""
+    form, their errors against the FP64 oracle values of the CPU leg (refs), and their speed
+    against the FP64 path."""
     import numpy as np
     import torch
-    from oracle import interp
-    from oracle import kernels as K
     dev = X0.device
-    sample = X0[:20000].cpu().numpy()
-    ref = interp.interp_vec(u_host.astype(np.float64) if N <= 256 else u_host, sample, K.SPLINE, 8, 2)
+    sample, ref = refs["sample"], refs["wide"]
     rms_ref = float(np.sqrt(np.mean(ref ** 2)))
     out = torch.empty((Np, 3), dtype=torch.float32, device=dev)
     res = {}
@@ -320,7 +336,7 @@ def run_forms(ctx, ptk, u_host, X0, N, Np):
                      "max_err_rel": float(np.max(np.abs(err)) / rms_ref)}
         log(f"form {name}: {res[name]}")
     del out64
-    res["learned"] = run_learned(ctx, ptk, u_dev, u_host, X0, Np, sample, ref, rms_ref, out)
+    res["learned"] = run_learned(ctx, ptk, u_dev, X0, Np, refs, rms_ref, out)
     log(f"form learned: {res['learned']}")
     # throughput against the plain FP64 I=8 path on the same GPU
     f64 = res["f64"]
@@ -333,7 +349,7 @@ def run_forms(ctx, ptk, u_host, X0, N, Np):
     return res
 
 
-def run_learned(ctx, ptk, u_dev, u_host, X0, Np, sample, ref, rms_ref, out):
+def run_learned(ctx, ptk, u_dev, X0, Np, refs, rms_ref, out):
     """Learned correction form: pairs on two 256^3 fields (k <= 80, seeds 100 and
     101, 5e6 uniform positions each), 8 epochs of Adam (batch 4096, lr 1e-3,
     output layer starting at zero), then inference on the benchmark field with
@@ -341,9 +357,8 @@ def run_learned(ctx, ptk, u_dev, u_host, X0, Np, sample, ref, rms_ref, out):
     sample as the storage forms."""
     import numpy as np
     import torch
-    from oracle import interp
-    from oracle import kernels as K
     from synthetic import fields, particles
+    sample, ref, narrow = refs["sample"], refs["wide"], refs["narrow"]
     dev = X0.device
     rng = np.random.default_rng(0)
     p0 = []
@@ -396,7 +411,6 @@ def run_learned(ctx, ptk, u_dev, u_host, X0, Np, sample, ref, rms_ref, out):
     kms = t["learned"][0] / max(t["learned"][1], 1)
     got, audit, fell = ctx.interpolate_learned(torch.from_numpy(sample).to(dev), audit_frac=1.0)
     err = got.cpu().numpy().astype(np.float64) - ref
-    narrow = interp.interp_vec(u_host, sample, K.LAGRANGE, 4, 0)
     res = {"train_pairs": int(n_pairs), "pairs_per_s": n_pairs / t_pairs, "train_s": round(t_train, 3),
            "train_pairs_per_s": len(curve) * 4096 / t_train, "steps": int(len(curve)),
            "loss_first": float(curve[0]), "loss_last": float(curve[-1]),
