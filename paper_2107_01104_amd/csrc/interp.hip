@@ -268,6 +268,10 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
   const int noff = l2 * RP + (l1 + jj) * NB;
   const int s0 = (z3 + h) % R;
   V acc[3] = {0, 0, 0}, ad2[3] = {0, 0, 0}, ad3[3] = {0, 0, 0};
+  // the unused fourth word of every 16-byte node read is folded into `sink`
+  // by an empty (schedulable) asm, so the reads stay 16 bytes wide without a
+  // wait after each one; one asm at the end keeps the chain alive
+  uint32_t sink = 0;
 #pragma unroll
   for (int m = 0; m < HALF; ++m) {
     const int slot = s0 + 2 * m < R ? s0 + 2 * m : s0 + 2 * m - R;
@@ -283,7 +287,7 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
         s[q] = fma(w2[i2], v[q], s[q]);
         if constexpr (GRAD) sd[q] = fma(dw2[i2], v[q], sd[q]);
       }
-      asm volatile("" ::"v"(keep));  // the unused word ends here: the read stays 16 bytes wide
+      asm("" : "+v"(sink) : "v"(keep));
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -294,6 +298,7 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
       }
     }
   }
+  asm volatile("" ::"v"(sink));
   // x1 weight, then the sum over the group's 16 lanes.  Values: r[q] = u_q,
   // r[3 + 3q + b] = d u_q / d x_b (before the 1/delta factor).
   V e[GRAD ? 12 : 3];
@@ -374,23 +379,27 @@ __device__ __forceinline__ void particle_sums32(const unsigned char* smem, const
   const int noff = l2 * RP + (l1 + jj) * NB;
   const int s0 = (z3 + 2 * q + h) % R;
   V acc[3] = {0, 0, 0};
+  uint32_t sink = 0;  // as in particle_sums: the reads stay 16 bytes wide, unwaited
 #pragma unroll
   for (int m = 0; m < NM; ++m) {
     const int slot = s0 + 4 * m < R ? s0 + 4 * m : s0 + 4 * m - R;
     const int base = slot * PL + noff;
     V sum[3] = {0, 0, 0};
+    // the plane's I rows are read before any is used: I reads in flight
+    V v[I][3];
+    uint32_t keep[I];
+#pragma unroll
+    for (int i2 = 0; i2 < I; ++i2) lds_get<ST>(smem, base + i2 * RP, v[i2], keep[i2]);
 #pragma unroll
     for (int i2 = 0; i2 < I; ++i2) {
-      V v[3];
-      uint32_t keep;
-      lds_get<ST>(smem, base + i2 * RP, v, keep);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) sum[c] = fma(w2[i2], v[c], sum[c]);
-      asm volatile("" ::"v"(keep));
+      for (int c = 0; c < 3; ++c) sum[c] = fma(w2[i2], v[i2][c], sum[c]);
+      asm("" : "+v"(sink) : "v"(keep[i2]));
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[c] = fma(w3[m], sum[c], acc[c]);
   }
+  asm volatile("" ::"v"(sink));
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     V v = rowsum(w1 * acc[c]);
