@@ -277,17 +277,24 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
     const int slot = s0 + 2 * m < R ? s0 + 2 * m : s0 + 2 * m - R;
     const int base = slot * PL + noff;
     V s[3] = {0, 0, 0}, sd[3] = {0, 0, 0};
+    // rows read together before use: four for values, two for gradients
+    // (four would pass the 128-VGPR budget of two workgroups per CU and spill)
+    constexpr int G = GRAD ? 2 : (I % 4 == 0 ? 4 : 2);
 #pragma unroll
-    for (int i2 = 0; i2 < I; ++i2) {
-      V v[3];
-      uint32_t keep;
-      lds_get<ST>(smem, base + i2 * RP, v, keep);
+    for (int g = 0; g < I; g += G) {
+      V v[G][3];
+      uint32_t keep[G];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        s[q] = fma(w2[i2], v[q], s[q]);
-        if constexpr (GRAD) sd[q] = fma(dw2[i2], v[q], sd[q]);
+      for (int k = 0; k < G; ++k) lds_get<ST>(smem, base + (g + k) * RP, v[k], keep[k]);
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          s[q] = fma(w2[g + k], v[k][q], s[q]);
+          if constexpr (GRAD) sd[q] = fma(dw2[g + k], v[k][q], sd[q]);
+        }
+        asm("" : "+v"(sink) : "v"(keep[k]));
       }
-      asm("" : "+v"(sink) : "v"(keep));
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -414,7 +421,9 @@ __device__ __forceinline__ void particle_sums32(const unsigned char* smem, const
 // instead of sweeping every plane.  Two workgroups per CU for FP32 and 16-bit
 // storage; FP64 nodes fill the LDS of one.
 template <int ST, int I, bool GRAD, bool SPARSE>
-__global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 1 : 2) void k_interp(InterpArgs a) {
+// the second bound is waves per SIMD: two 512-thread workgroups per CU are 4
+// (at most 128 VGPRs), one is 2
+__global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_interp(InterpArgs a) {
   using V = typename StoreT<ST>::acc;
   using Gm = Geom<ST, I>;
   constexpr int T = Gm::T;
