@@ -599,7 +599,9 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
         t1 = tf.x;
         t2 = tf.y;
         t3 = tf.z;
-        asm volatile("" ::"v"(tf.w));  // keep the record reads 16 bytes wide
+        // the unused word rides on t3 (arriving together), so the read stays
+        // 16 bytes wide and the next one is issued before either is waited on
+        asm("" : "+v"(t3) : "v"(tf.w));
       }
       const uint4 lc = *(const uint4*)(rp + 32);
       const int l1 = (int)(lc.x & 0xFFFFu), l2 = (int)(lc.x >> 16), z3 = (int)(lc.y & 0xFFFFu);
