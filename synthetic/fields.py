@@ -16,6 +16,16 @@ components fastest within a node), grid spacing delta = 2*pi/N, node j at j*delt
   transformed with an inverse real FFT and scaled so that the mean over grid
   and components of u_a^2 is 1.  Built with torch on the requested device
   (the FFT is input synthesis only).
+* ``spectrum_modes``: the same kind of random solenoidal modes as a half
+  spectrum ``spec[k2][k3][k1][a]`` (complex128, shape (N, N, N//2+1, 3),
+  directions 2 and 3 transposed as in a slab-decomposed solver's Fourier
+  array), unscaled, Hermitian on the k1 = 0 and k1 = N/2 planes: each mode
+  and its partner at (-k2, -k3) are set to (a + conj b)/2 and its conjugate,
+  self-conjugate modes to their real part.  Modes with an index N/2 are zero
+  unless ``nyquist`` (then random, made Hermitian the same way).
+* ``sparse_spectrum``: a few random modes with |k_d| <= kmax, as index lists
+  (k2 index, k3 index, k1) and amplitudes [n][3], with the conjugate partner
+  of every k1 = 0 mode listed too; for full-size grids.
 """
 from __future__ import annotations
 
@@ -146,3 +156,72 @@ def _chunked_ms(u):
     for i in range(0, u.shape[0], 64):
         acc += float(torch.sum(u[i:i + 64].to(torch.float64) ** 2))
     return acc / u.numel()
+
+
+def _hermitian_planes(spec: np.ndarray) -> np.ndarray:
+    N = spec.shape[0]
+    r = (-np.arange(N)) % N
+    for k1 in sorted({0, N // 2}):
+        P = spec[:, :, k1, :]
+        partner = np.conj(P[r][:, r])
+        spec[:, :, k1, :] = (P + partner) / 2.0
+    return spec
+
+
+def spectrum_modes(N: int, kc: float, seed: int, nyquist: bool = False) -> np.ndarray:
+    """Random solenoidal half spectrum spec[k2][k3][k1][a] (see module doc)."""
+    if N % 2:
+        raise ValueError("N must be even")
+    H = N // 2 + 1
+    rng = np.random.default_rng(seed)
+    kf = np.fft.fftfreq(N, d=1.0 / N)
+    K2 = kf[:, None, None]
+    K3 = kf[None, :, None]
+    K1 = np.arange(H, dtype=np.float64)[None, None, :]
+    kk = np.sqrt(K1 * K1 + K2 * K2 + K3 * K3)
+    kk_safe = np.where(kk > 0, kk, 1.0)
+    E = kk_safe ** (-5.0 / 3.0)
+    E = np.where(kk > kc, E * np.exp(-(kk - kc) / (0.1 * kc)), E)
+    amp = np.where(kk >= 1, np.sqrt(E / (4.0 * math.pi * kk_safe * kk_safe)), 0.0)
+    xi = (rng.standard_normal((N, N, H, 3)) + 1j * rng.standard_normal((N, N, H, 3))) / math.sqrt(2.0)
+    Ks = (K1, K2, K3)
+    kdot = sum(Ks[a] * xi[..., a] for a in range(3)) / kk_safe
+    spec = np.empty((N, N, H, 3), dtype=np.complex128)
+    for a in range(3):
+        spec[..., a] = (xi[..., a] - (Ks[a] / kk_safe) * kdot) * amp
+    idx = np.arange(N)
+    nyq = (idx[:, None, None] == N // 2) | (idx[None, :, None] == N // 2) | (np.arange(H)[None, None, :] == N // 2)
+    if nyquist:
+        spec[nyq] = (rng.standard_normal((int(nyq.sum()), 3))
+                     + 1j * rng.standard_normal((int(nyq.sum()), 3))) * float(np.mean(amp[amp > 0]))
+    else:
+        spec[nyq] = 0.0
+    return _hermitian_planes(spec)
+
+
+def sparse_spectrum(N: int, n_modes: int, kmax: int, seed: int):
+    """(k2 index, k3 index, k1, amp[n][3]) for n_modes random modes plus the
+    conjugate partners of the k1 = 0 ones (see module doc)."""
+    rng = np.random.default_rng(seed)
+    chosen = {}
+    while len(chosen) < n_modes:
+        k1 = int(rng.integers(0, kmax + 1))
+        k2 = int(rng.integers(-kmax, kmax + 1))
+        k3 = int(rng.integers(-kmax, kmax + 1))
+        key = (k2 % N, k3 % N, k1)
+        pkey = ((-k2) % N, (-k3) % N, k1)
+        if key in chosen or (k1 == 0 and pkey in chosen):
+            continue
+        a = (rng.standard_normal(3) + 1j * rng.standard_normal(3)) / math.sqrt(2.0)
+        if k1 == 0:
+            if key == pkey:
+                a = a.real + 0j
+            else:
+                chosen[pkey] = np.conj(a)
+        chosen[key] = a
+    keys = sorted(chosen)
+    k2i = np.array([k[0] for k in keys], dtype=np.int64)
+    k3i = np.array([k[1] for k in keys], dtype=np.int64)
+    k1 = np.array([k[2] for k in keys], dtype=np.int64)
+    amp = np.array([chosen[k] for k in keys], dtype=np.complex128)
+    return k2i, k3i, k1, amp
