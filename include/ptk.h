@@ -115,6 +115,45 @@ int ptk_set_field(ptk_ctx *ctx, const void *u, int64_t N, int in_dtype, int stor
  * float[3]. */
 int ptk_get_field_scale(const ptk_ctx *ctx, float *scale3);
 
+/* Set the field from the spectral state: the extra inverse transform that
+ * particle tracking needs in a pseudo-spectral solver (Sec. 4.2, "IFT for PT"
+ * in the breakdown of the overall performance).
+ * spec: device pointer to the half spectrum of a real field (Sec. 2.1), N x N x
+ *    (N/2+1) modes in the order [k2][k3][k1][a] -- directions 2 and 3
+ *    transposed against the grid's [x3][x2][x1], as in the slab layout of
+ *    Sec. 3.2 -- each complex number a (re, im) pair of `in_dtype` (PTK_F64 or
+ *    PTK_F32).  Wave numbers: k1 = index (0 .. N/2); k2, k3 = index up to N/2,
+ *    index - N above.  Not modified; may be freed once the call's work on
+ *    `stream` has completed.
+ * kind PTK_SPEC_VELOCITY: spec holds the velocity amplitudes u^(k).
+ * kind PTK_SPEC_VORTICITY: spec holds the vorticity w^(k); the Biot-Savart law
+ *    of Sec. 2.1 gives u^(k) = i k x w^(k) / |k|^2, with u^(0) = 0 and u^ = 0
+ *    on every mode with some index equal to N/2 (no signed wave number there).
+ * The grid field is the Fourier series u_a(x) = sum over all k of
+ *    u^_a(k) exp(i k.x) at the nodes x = delta (j1, j2, j3) (the modes with
+ *    k1 < 0 being the complex conjugates of the stored ones), computed by an
+ *    inverse real FFT in the precision of in_dtype (rocFFT), then stored as by
+ *    ptk_set_field (same storage types, scale and kernel rules).  The k1 = 0
+ *    and k1 = N/2 planes must be Hermitian, as those of a real field are
+ *    (u^(-k) = conj u^(k) within the plane); otherwise the result is
+ *    undefined.
+ * N: even, 8 <= N <= 2048.  The library keeps a transform buffer of
+ *    3 N^2 (N/2+1) complex numbers of in_dtype and the transform's work
+ *    buffer (grown, never shrunk, released by ptk_destroy).
+ * Errors: PTK_EINVAL (NULL pointer, odd or out-of-range N, bad kind or
+ *    dtype), PTK_EUNSUPPORTED (kernel), PTK_ENOMEM, PTK_EHIP (transform set-up
+ *    or launch); on an argument error the context is unchanged. */
+enum { PTK_SPEC_VELOCITY = 0, PTK_SPEC_VORTICITY = 1 };
+int ptk_set_field_spectral(ptk_ctx *ctx, const void *spec, int64_t N, int in_dtype, int kind,
+                           int storage_dtype, const ptk_kernel *k, void *stream);
+
+/* Copy of the stored field without its halo into u (device, N*N*N*3 elements
+ * of out_dtype, PTK_F64 or PTK_F32, layout u[x3][x2][x1][a]): the stored
+ * values converted exactly.  16-bit storage returns its values unscaled
+ * (multiply component a by ptk_get_field_scale's s_a for u_a).  Asynchronous
+ * on `stream`.  Errors: PTK_ENOFIELD, PTK_EINVAL. */
+int ptk_get_field(ptk_ctx *ctx, void *u, int out_dtype, void *stream);
+
 /* Steps 1-3 of the interpolation algorithm (Sec. 2.2) for every coordinate:
  * Xtilde = X mod 2*pi; cell c = floor(Xtilde/delta); offset t = Xtilde/delta - c
  * in [0,1).  Fixed binary64 sequence per coordinate x (no fused operations):
@@ -194,12 +233,14 @@ int ptk_get_binning(ptk_ctx *ctx, uint32_t *perm, uint32_t *offsets, void *strea
  *   PTK_T_UPDATE       position update (+ keys of the new positions)
  *   PTK_T_PERMUTE      gathers/scatters of particle state between orders
  *   PTK_T_LEARNED      learned-form inference kernel (features, L4 sum, network)
+ *   PTK_T_IFT          spectral set-up: spectrum reorder (and Biot-Savart) and
+ *                      the inverse FFT (the field pack is not included)
  * ptk_timing_enable(ctx, 1) starts (and clears) the accumulators, 0 stops.
  * ptk_timing_read waits for the recorded events, adds their durations to the
  * accumulators and copies them out: ms[PTK_T_COUNT] (milliseconds) and
  * launches[PTK_T_COUNT] (number of timed sequences); either may be NULL. */
 enum { PTK_T_INTERP = 0, PTK_T_INTERP_GRAD = 1, PTK_T_SORT = 2, PTK_T_KEYS = 3, PTK_T_UPDATE = 4,
-       PTK_T_PERMUTE = 5, PTK_T_LEARNED = 6, PTK_T_COUNT = 7 };
+       PTK_T_PERMUTE = 5, PTK_T_LEARNED = 6, PTK_T_IFT = 7, PTK_T_COUNT = 8 };
 int ptk_timing_enable(ptk_ctx *ctx, int enable);
 int ptk_timing_read(ptk_ctx *ctx, double *ms, int64_t *launches);
 

@@ -390,8 +390,10 @@ void ptk_destroy(ptk_ctx* c) {
                       &c->lm, &c->lv, &c->lw1b, &c->lw2b, &c->lw2bt, &c->lgpart, &c->llpart, &c->lwide,
                       &c->laudit_x, &c->laudit_u, &c->laudit_sums, &c->skeys, &c->skeys2, &c->offsets2,
                       &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->mo, &c->rb_in, &c->rb_out, &c->rb_inc,
-                      &c->rb_block};
+                      &c->rb_block, &c->spec, &c->fft_work};
     for (DevBuf* b : bufs) release(*b);
+    fft_release(c->fft);
+    c->fft = nullptr;
     for (TimedPair& p : c->pending) {
       (void)hipEventDestroy(p.start);
       (void)hipEventDestroy(p.stop);
@@ -403,11 +405,12 @@ void ptk_destroy(ptk_ctx* c) {
 
 const char* ptk_last_error(const ptk_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
 
-int ptk_set_field(ptk_ctx* c, const void* u, int64_t N, int in_dtype, int storage_dtype, const ptk_kernel* k,
-                  void* stream) {
-  if (!c) return PTK_EINVAL;
-  c->err.clear();
-  if (!u || !k) return fail(c, PTK_EINVAL, "NULL pointer");
+namespace {
+
+// Checks of the arguments ptk_set_field and ptk_set_field_spectral share; the
+// kernel tables come out.
+int check_field_args(ptk_ctx* c, int64_t N, int in_dtype, int storage_dtype, const ptk_kernel* k,
+                     KernelTables* tab, int* m_out) {
   if (N < 8 || N > 4096) return fail(c, PTK_EINVAL, "N must be in [8, 4096]");
   if (in_dtype != PTK_F64 && in_dtype != PTK_F32) return fail(c, PTK_EINVAL, "in_dtype must be F64 or F32");
   if (storage_dtype < PTK_F64 || storage_dtype > PTK_F16) return fail(c, PTK_EINVAL, "bad storage dtype");
@@ -416,13 +419,16 @@ int ptk_set_field(ptk_ctx* c, const void* u, int64_t N, int in_dtype, int storag
   if (k->I != 4 && k->I != 6 && k->I != 8) return fail(c, PTK_EUNSUPPORTED, "kernel size I must be 4, 6 or 8");
   const int m = k->family == PTK_LAGRANGE ? 0 : k->m;
   if (m < 0 || m > k->I / 2 - 1) return fail(c, PTK_EINVAL, "smoothness m must be in [0, I/2-1]");
-  KernelTables tab;
-  int tr = build_kernel_tables(k->family, k->I, m, &tab);
+  int tr = build_kernel_tables(k->family, k->I, m, tab);
   if (tr != 0) return fail(c, tr == -6 ? PTK_EUNSUPPORTED : PTK_EINVAL, "kernel table construction failed");
-  DeviceGuard g(c->device);
-  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
-  hipStream_t s = S(stream);
+  *m_out = m;
+  return PTK_OK;
+}
 
+// Stores the grid field u (layout l, FP64 or FP32) as the context's field:
+// the per-component scale for 16-bit storage, the coefficient tables, the pack.
+int store_field(ptk_ctx* c, const void* u, int in_f64, const SrcLayout& l, int64_t N, int storage_dtype,
+                const ptk_kernel* k, int m, const KernelTables& tab, hipStream_t s) {
   FieldGeom geo;
   geo.N = N;
   geo.P = N + k->I - 1;
@@ -438,7 +444,7 @@ int ptk_set_field(ptk_ctx* c, const void* u, int64_t N, int in_dtype, int storag
   if (storage_dtype == PTK_BF16 || storage_dtype == PTK_F16) {
     const int nblk = 1024;
     PTK_TRY(ensure(c, c->stage, (size_t)nblk * 3 * sizeof(double)));
-    PTK_HIP(c, launch_sumsq(u, in_dtype == PTK_F64, nodes, (double*)c->stage.ptr, nblk, s), "sum of squares");
+    PTK_HIP(c, launch_sumsq(u, in_f64, N, l, (double*)c->stage.ptr, nblk, s), "sum of squares");
     double* part = new (std::nothrow) double[nblk * 3];
     if (!part) return fail(c, PTK_ENOMEM, "host allocation failed");
     hipError_t e = hipMemcpyAsync(part, c->stage.ptr, sizeof(double) * nblk * 3, hipMemcpyDeviceToHost, s);
@@ -465,9 +471,7 @@ int ptk_set_field(ptk_ctx* c, const void* u, int64_t N, int in_dtype, int storag
   c->tables = tab;
   PTK_HIP(c, hipMemcpyAsync(c->coef.ptr, &c->tables, sizeof(KernelTables), hipMemcpyHostToDevice, s),
           "coefficient upload");
-  PTK_HIP(c,
-          launch_pack(u, in_dtype == PTK_F64, N, storage_dtype, k->I, c->field.ptr, geo.row_pitch,
-                      geo.plane_pitch, inv, s),
+  PTK_HIP(c, launch_pack(u, in_f64, l, N, storage_dtype, k->I, c->field.ptr, geo.row_pitch, geo.plane_pitch, inv, s),
           "field pack");
   c->geom = geo;
   c->family = k->family;
@@ -477,6 +481,66 @@ int ptk_set_field(ptk_ctx* c, const void* u, int64_t N, int in_dtype, int storag
   for (int q = 0; q < 3; ++q) c->scale[q] = scl[q];
   c->has_field = true;
   c->bin_valid = false;
+  return PTK_OK;
+}
+
+}  // namespace
+
+int ptk_set_field(ptk_ctx* c, const void* u, int64_t N, int in_dtype, int storage_dtype, const ptk_kernel* k,
+                  void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!u || !k) return fail(c, PTK_EINVAL, "NULL pointer");
+  KernelTables tab;
+  int m = 0;
+  PTK_TRY(check_field_args(c, N, in_dtype, storage_dtype, k, &tab, &m));
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  return store_field(c, u, in_dtype == PTK_F64, interleaved_layout(N), N, storage_dtype, k, m, tab, S(stream));
+}
+
+int ptk_set_field_spectral(ptk_ctx* c, const void* spec, int64_t N, int in_dtype, int kind, int storage_dtype,
+                           const ptk_kernel* k, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!spec || !k) return fail(c, PTK_EINVAL, "NULL pointer");
+  if (kind != PTK_SPEC_VELOCITY && kind != PTK_SPEC_VORTICITY) return fail(c, PTK_EINVAL, "bad spectrum kind");
+  if (N % 2 != 0) return fail(c, PTK_EINVAL, "N must be even for a half spectrum");
+  if (N > 2048) return fail(c, PTK_EINVAL, "N must be at most 2048 for a spectral field");
+  KernelTables tab;
+  int m = 0;
+  PTK_TRY(check_field_args(c, N, in_dtype, storage_dtype, k, &tab, &m));
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  const int f64 = in_dtype == PTK_F64;
+  const size_t rb = f64 ? 8 : 4;
+  const size_t modes = (size_t)N * (size_t)N * (size_t)(N / 2 + 1);
+  size_t work = 0;
+  const char* msg = nullptr;
+  if (fft_prepare(&c->fft, N, f64, &work, &msg) != 0) return fail(c, PTK_EHIP, msg);
+  PTK_TRY(ensure(c, c->spec, 3 * modes * 2 * rb));
+  if (work > 0) PTK_TRY(ensure(c, c->fft_work, work));
+  {
+    Timed t(c, s, PTK_T_IFT);
+    PTK_HIP(c, launch_spec_prep(spec, f64, N, kind == PTK_SPEC_VORTICITY, c->spec.ptr, s), "spectrum prep");
+    if (fft_run(c->fft, c->spec.ptr, c->fft_work.ptr, c->fft_work.cap, s, &msg) != 0) return fail(c, PTK_EHIP, msg);
+  }
+  return store_field(c, c->spec.ptr, f64, transform_layout(N), N, storage_dtype, k, m, tab, s);
+}
+
+int ptk_get_field(ptk_ctx* c, void* u, int out_dtype, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
+  if (!u) return fail(c, PTK_EINVAL, "NULL pointer");
+  if (out_dtype != PTK_F64 && out_dtype != PTK_F32) return fail(c, PTK_EINVAL, "out_dtype must be F64 or F32");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  PTK_HIP(c,
+          launch_unpack(c->field.ptr, c->geom.N, c->storage, c->I, c->geom.row_pitch, c->geom.plane_pitch, u,
+                        out_dtype == PTK_F64, S(stream)),
+          "field unpack");
   return PTK_OK;
 }
 

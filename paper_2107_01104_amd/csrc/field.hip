@@ -1,5 +1,8 @@
 // Field set-up: per-component sum of squares (for the BF16/FP16 scale) and the
-// copy of the caller's field u[x3][x2][x1][3] into the stored layout.
+// copy of a grid field into the stored layout, and the copy back out.  The
+// source is described by element strides (SrcLayout): the caller's
+// u[x3][x2][x1][3], or the three padded real planes an inverse transform
+// leaves.
 //
 // Stored layout: the periodic field padded by I/2-1 nodes below and I/2 nodes
 // above on every axis (so every stencil c + i, i = 1-I/2..I/2, of Eq.
@@ -11,22 +14,29 @@
 
 namespace ptk {
 
-__global__ __launch_bounds__(256) void k_sumsq(const void* __restrict__ u, int in_f64, int64_t nodes,
+// node (x1, x2, x3) of the source, component 0
+__device__ __forceinline__ int64_t src_node(const SrcLayout& l, int64_t x1, int64_t x2, int64_t x3) {
+  return x3 * l.ps + x2 * l.rs + x1 * l.ns;
+}
+
+__global__ __launch_bounds__(256) void k_sumsq(const void* __restrict__ u, int in_f64, int64_t N, SrcLayout l,
                                                double* __restrict__ partial) {
   __shared__ double sh[3][256];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  const int64_t nodes = N * N * N;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nodes; i += (int64_t)gridDim.x * 256) {
+    const int64_t o = src_node(l, i % N, (i / N) % N, i / (N * N));
     double a, b, c;
     if (in_f64) {
       const double* d = (const double*)u;
-      a = d[3 * i];
-      b = d[3 * i + 1];
-      c = d[3 * i + 2];
+      a = d[o];
+      b = d[o + l.cs];
+      c = d[o + 2 * l.cs];
     } else {
       const float* f = (const float*)u;
-      a = f[3 * i];
-      b = f[3 * i + 1];
-      c = f[3 * i + 2];
+      a = f[o];
+      b = f[o + l.cs];
+      c = f[o + 2 * l.cs];
     }
     s0 += a * a;
     s1 += b * b;
@@ -44,15 +54,15 @@ __global__ __launch_bounds__(256) void k_sumsq(const void* __restrict__ u, int i
   if (threadIdx.x < 3) partial[3 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-hipError_t launch_sumsq(const void* u, int in_f64, int64_t nodes, double* partial, int nblocks,
+hipError_t launch_sumsq(const void* u, int in_f64, int64_t N, const SrcLayout& l, double* partial, int nblocks,
                         hipStream_t s) {
-  k_sumsq<<<nblocks, 256, 0, s>>>(u, in_f64, nodes, partial);
+  k_sumsq<<<nblocks, 256, 0, s>>>(u, in_f64, N, l, partial);
   return hipGetLastError();
 }
 
 template <int STORAGE>
-__global__ __launch_bounds__(256) void k_pack(const void* __restrict__ u, int in_f64, int64_t N, int64_t P,
-                                              int halo_lo, unsigned char* __restrict__ field,
+__global__ __launch_bounds__(256) void k_pack(const void* __restrict__ u, int in_f64, SrcLayout l, int64_t N,
+                                              int64_t P, int halo_lo, unsigned char* __restrict__ field,
                                               int64_t row_pitch, int64_t plane_pitch, float inv0, float inv1,
                                               float inv2) {
   const int64_t total = P * P * P;
@@ -62,10 +72,10 @@ __global__ __launch_bounds__(256) void k_pack(const void* __restrict__ u, int in
     const int64_t sx = ((x - halo_lo) % N + N) % N;
     const int64_t sy = ((y - halo_lo) % N + N) % N;
     const int64_t sz = ((z - halo_lo) % N + N) % N;
-    const int64_t src = ((sz * N + sy) * N + sx) * 3;
+    const int64_t src = src_node(l, sx, sy, sz);
     double v[3];
     for (int q = 0; q < 3; ++q)
-      v[q] = in_f64 ? ((const double*)u)[src + q] : (double)((const float*)u)[src + q];
+      v[q] = in_f64 ? ((const double*)u)[src + q * l.cs] : (double)((const float*)u)[src + q * l.cs];
     unsigned char* dst = field + z * plane_pitch + y * row_pitch;
     if constexpr (STORAGE == 0) {
       double* d = (double*)(dst + x * 24);
@@ -92,7 +102,7 @@ __global__ __launch_bounds__(256) void k_pack(const void* __restrict__ u, int in
   }
 }
 
-hipError_t launch_pack(const void* u, int in_f64, int64_t N, int storage, int I, void* field,
+hipError_t launch_pack(const void* u, int in_f64, const SrcLayout& l, int64_t N, int storage, int I, void* field,
                        int64_t row_pitch, int64_t plane_pitch, const float* inv_scale, hipStream_t s) {
   const int64_t P = N + I - 1;
   const int halo_lo = I / 2 - 1;
@@ -102,12 +112,63 @@ hipError_t launch_pack(const void* u, int in_f64, int64_t N, int storage, int I,
   unsigned char* f = (unsigned char*)field;
   const float i0 = inv_scale[0], i1 = inv_scale[1], i2 = inv_scale[2];
   switch (storage) {
-    case 0: k_pack<0><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
-    case 1: k_pack<1><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
-    case 2: k_pack<2><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
-    case 3: k_pack<3><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
+    case 0: k_pack<0><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, l, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
+    case 1: k_pack<1><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, l, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
+    case 2: k_pack<2><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, l, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
+    case 3: k_pack<3><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, l, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// The stored field without its halo, as out[x3][x2][x1][3]: stored values
+// converted exactly (16-bit codes stay unscaled).
+template <int STORAGE, typename O>
+__global__ __launch_bounds__(256) void k_unpack(const unsigned char* __restrict__ field, int64_t N, int halo_lo,
+                                                int64_t row_pitch, int64_t plane_pitch, O* __restrict__ out) {
+  const int64_t nodes = N * N * N;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nodes; i += (int64_t)gridDim.x * 256) {
+    const int64_t x = i % N + halo_lo, y = (i / N) % N + halo_lo, z = i / (N * N) + halo_lo;
+    const unsigned char* src = field + z * plane_pitch + y * row_pitch;
+    for (int q = 0; q < 3; ++q) {
+      O v;
+      if constexpr (STORAGE == 0) {
+        v = (O)((const double*)(src + x * 24))[q];
+      } else if constexpr (STORAGE == 1) {
+        v = (O)((const float*)(src + x * 12))[q];
+      } else {
+        const uint16_t b = ((const uint16_t*)(src + x * 6))[q];
+        if constexpr (STORAGE == 2)
+          v = (O)bf16_to_f32(b);
+        else
+          v = (O)__half2float(__ushort_as_half((unsigned short)b));
+      }
+      out[3 * i + q] = v;
+    }
+  }
+}
+
+hipError_t launch_unpack(const void* field, int64_t N, int storage, int I, int64_t row_pitch, int64_t plane_pitch,
+                         void* out, int out_f64, hipStream_t s) {
+  const int64_t nodes = N * N * N;
+  int64_t blocks = (nodes + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  const unsigned char* f = (const unsigned char*)field;
+  const int h = I / 2 - 1;
+  const unsigned g = (unsigned)blocks;
+#define PTK_UNPACK(ST)                                                                              \
+  if (out_f64)                                                                                       \
+    k_unpack<ST, double><<<g, 256, 0, s>>>(f, N, h, row_pitch, plane_pitch, (double*)out);           \
+  else                                                                                               \
+    k_unpack<ST, float><<<g, 256, 0, s>>>(f, N, h, row_pitch, plane_pitch, (float*)out);
+  switch (storage) {
+    case 0: PTK_UNPACK(0) break;
+    case 1: PTK_UNPACK(1) break;
+    case 2: PTK_UNPACK(2) break;
+    case 3: PTK_UNPACK(3) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef PTK_UNPACK
   return hipGetLastError();
 }
 

@@ -51,10 +51,33 @@ hipError_t scatter_f32(const float* in, const uint32_t* idx, int64_t n, int widt
                        hipStream_t s);
 
 // field.hip
-hipError_t launch_sumsq(const void* u, int in_f64, int64_t nodes, double* partial, int nblocks,
+// A grid field in memory: component a of node (x1, x2, x3) is element
+// x3*ps + x2*rs + x1*ns + a*cs (elements of the input type).
+struct SrcLayout {
+  int64_t cs, ns, rs, ps;
+};
+inline SrcLayout interleaved_layout(int64_t N) { return SrcLayout{1, 3, 3 * N, 3 * N * N}; }
+// the three real planes an in-place inverse real transform leaves: x1 rows
+// padded to 2*(N/2+1) elements
+inline SrcLayout transform_layout(int64_t N) {
+  const int64_t r = 2 * (N / 2 + 1);
+  return SrcLayout{r * N * N, 1, r, r * N};
+}
+hipError_t launch_sumsq(const void* u, int in_f64, int64_t N, const SrcLayout& l, double* partial, int nblocks,
                         hipStream_t s);
-hipError_t launch_pack(const void* u, int in_f64, int64_t N, int storage, int I, void* field,
+hipError_t launch_pack(const void* u, int in_f64, const SrcLayout& l, int64_t N, int storage, int I, void* field,
                        int64_t row_pitch, int64_t plane_pitch, const float* inv_scale, hipStream_t s);
+hipError_t launch_unpack(const void* field, int64_t N, int storage, int I, int64_t row_pitch, int64_t plane_pitch,
+                         void* out, int out_f64, hipStream_t s);
+
+// spectral.hip: the spectrum in transform order, and the inverse real
+// transform (rocFFT) of three components in place
+hipError_t launch_spec_prep(const void* spec, int in_f64, int64_t N, int vorticity, void* out, hipStream_t s);
+struct FftState;
+// (re)creates the plan for (N, precision) if needed; *work_bytes = its work buffer
+int fft_prepare(FftState** st, int64_t N, int f64, size_t* work_bytes, const char** err);
+int fft_run(FftState* st, void* buf, void* work, size_t work_bytes, hipStream_t s, const char** err);
+void fft_release(FftState* st);
 
 // interp.hip
 struct InterpArgs {

@@ -48,11 +48,13 @@ struct FieldGeom {
 
 // Kernel timing (ptk_timing_enable / ptk_timing_read): event pairs recorded on
 // the call's stream around each instrumented launch sequence.
-constexpr int kTimerKinds = 7;
+constexpr int kTimerKinds = 8;
 struct TimedPair {
   hipEvent_t start, stop;
   int kind;
 };
+
+struct FftState;  // inverse-transform plan (spectral.hip)
 
 // One growable device allocation.
 struct DevBuf {
@@ -74,6 +76,9 @@ struct ptk_ctx {
   ptk::DevBuf field;
   ptk::DevBuf coef;         // device copy of the coefficient tables (KernelTables)
   ptk::KernelTables tables;
+  // spectral input: transform buffer, the transform's work buffer and plan
+  ptk::DevBuf spec, fft_work;
+  ptk::FftState* fft = nullptr;
   // binning of the last interpolate call
   int64_t bin_np = 0, bin_nbins = 0;
   uint32_t* bin_perm = nullptr;

@@ -23,10 +23,12 @@ LAGRANGE, SPLINE = 0, 1
 EULER, HEUN, AB2, AB3, AB4 = 1, 2, 3, 4, 5
 AB_ORDER = {AB2: 2, AB3: 3, AB4: 4}
 OK, EINVAL, ENOFIELD, ENOMEM, EHIP, EDOMAIN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-TIMERS = ["interp", "interp_grad", "sort", "keys", "update", "permute", "learned"]
+TIMERS = ["interp", "interp_grad", "sort", "keys", "update", "permute", "learned", "ift"]
+SPEC_VELOCITY, SPEC_VORTICITY = 0, 1
 LEARNED_NFEAT, LEARNED_FEAT_PITCH, LEARNED_NPARAMS = 195, 200, 41987
 
 EXPORTS = ["ptk_kernel_table", "ptk_create", "ptk_destroy", "ptk_last_error", "ptk_set_field", "ptk_get_field_scale",
+           "ptk_set_field_spectral", "ptk_get_field",
            "ptk_locate", "ptk_interpolate", "ptk_interpolate_gradient", "ptk_advance_particles",
            "ptk_binning_info", "ptk_get_binning", "ptk_timing_enable", "ptk_timing_read",
            "ptk_learned_make_pairs", "ptk_learned_set_params", "ptk_learned_get_params", "ptk_learned_loss_grad",
@@ -57,6 +59,8 @@ lib.ptk_last_error.argtypes = [_vp]
 lib.ptk_last_error.restype = ctypes.c_char_p
 lib.ptk_set_field.argtypes = [_vp, _vp, _i64, _int, _int, ctypes.POINTER(ptk_kernel), _vp]
 lib.ptk_get_field_scale.argtypes = [_vp, ctypes.POINTER(ctypes.c_float)]
+lib.ptk_set_field_spectral.argtypes = [_vp, _vp, _i64, _int, _int, _int, ctypes.POINTER(ptk_kernel), _vp]
+lib.ptk_get_field.argtypes = [_vp, _vp, _int, _vp]
 lib.ptk_locate.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
 lib.ptk_interpolate.argtypes = [_vp, _vp, _i64, _vp, _int, _vp]
 lib.ptk_interpolate_gradient.argtypes = [_vp, _vp, _i64, _vp, _vp, _int, _vp]
@@ -181,6 +185,34 @@ class Context:
         self._check(lib.ptk_set_field(self._h, _ptr(u), N, in_dt, int(storage), ctypes.byref(k),
                                       _stream(self.device)))
         self.storage, self.N = int(storage), N
+
+    def set_field_spectral(self, spec: torch.Tensor, family: int, I: int, m: int = 0, storage: int = F32,
+                           kind: int = SPEC_VELOCITY):
+        """Field from its half spectrum spec[k2][k3][k1][a] (complex128 or
+        complex64, shape (N, N, N//2+1, 3)): velocity amplitudes, or vorticity
+        with kind=SPEC_VORTICITY (include/ptk.h, ptk_set_field_spectral)."""
+        if spec.dtype not in (torch.complex128, torch.complex64):
+            raise TypeError("spectrum must be complex128 or complex64")
+        _dev_tensor(spec, spec.dtype, (3,), "spec")
+        N = spec.shape[0]
+        if spec.dim() != 4 or tuple(spec.shape) != (N, N, N // 2 + 1, 3):
+            raise ValueError("spectrum must have shape (N, N, N//2+1, 3)")
+        k = ptk_kernel(int(family), int(I), int(m))
+        in_dt = F64 if spec.dtype == torch.complex128 else F32
+        self._check(lib.ptk_set_field_spectral(self._h, _ptr(spec), N, in_dt, int(kind), int(storage),
+                                               ctypes.byref(k), _stream(self.device)))
+        self.storage, self.N = int(storage), N
+
+    def get_field(self, dtype=torch.float64):
+        """The stored field without halo, [N][N][N][3] (16-bit storage: unscaled)."""
+        if dtype not in _TORCH_OF.values():
+            raise TypeError("dtype must be float64 or float32")
+        code = F64 if dtype == torch.float64 else F32
+        if self.N is None:  # no field: the library reports it
+            self._check(lib.ptk_get_field(self._h, None, code, None))
+        out = torch.empty((self.N, self.N, self.N, 3), dtype=dtype, device=self.device)
+        self._check(lib.ptk_get_field(self._h, _ptr(out), code, _stream(self.device)))
+        return out
 
     def field_scale(self):
         s = (ctypes.c_float * 3)()
