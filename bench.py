@@ -188,6 +188,7 @@ def main():
     ap.add_argument("--grid", type=int, default=N_GRID)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-ift", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic record from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
@@ -276,6 +277,7 @@ def main():
     forms = None
     if not args.no_forms:
         forms = run_forms(ctx, ptk, u_host, X0, N, Np, cpu_references(u_host, X0))
+    ift = None if args.no_ift else run_ift(ptk, N, kc)
 
     line = {
         "metric": "particle-interpolations/sec at I=8, 1024^3 grid; % HBM roofline; RMS err vs FP64",
@@ -290,9 +292,53 @@ def main():
         "cpu_baseline": cpu,
         "ms_per_step_breakdown": breakdown,
         "forms": forms,
+        "ift": ift,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def run_ift(ptk, N, kc, calls=3):
+    """The field from the spectral state (ptk_set_field_spectral) at N^3 with
+    FP32 storage and the C2 spline I = 8: a vorticity spectrum in FP64 (the
+    solver's state, turned into velocity by Biot-Savart), a velocity spectrum
+    in FP64, and one in FP32.  Per call: the whole call on the stream (spectrum
+    reorder + inverse FFT + field pack), and the reorder + FFT part alone (the
+    library's ift timer).  The reorder kernel's algorithmic HBM bytes are one
+    read and one write of the 3 N^2 (N/2+1) complex amplitudes."""
+    import torch
+    from synthetic import fields
+    dev = torch.device("cuda", 0)
+    res = {"grid": N, "storage": "f32", "kernel": "spline I=8 m=2", "calls": calls}
+    stream = torch.cuda.current_stream(dev)
+    for label, cdt, kind in (("vorticity_f64", torch.complex128, ptk.SPEC_VORTICITY),
+                             ("velocity_f64", torch.complex128, ptk.SPEC_VELOCITY),
+                             ("velocity_f32", torch.complex64, ptk.SPEC_VELOCITY)):
+        spec = fields.spectrum_modes_torch(N, kc, seed=5, device=dev, dtype=cdt)
+        ctx = ptk.Context(0)
+        ctx.set_field_spectral(spec, ptk.SPLINE, 8, 2, storage=ptk.F32, kind=kind)  # plan, buffers
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(calls):
+            ctx.set_field_spectral(spec, ptk.SPLINE, 8, 2, storage=ptk.F32, kind=kind)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total = e0.elapsed_time(e1) / calls
+        t = ctx.timing_read()
+        ctx.timing(False)
+        ift_ms = t["ift"][0] / max(t["ift"][1], 1)
+        cb = 16 if cdt == torch.complex128 else 8
+        reorder_bytes = 2 * 3 * N * N * (N // 2 + 1) * cb
+        res[label] = {"ms_per_call": round(total, 3), "reorder_fft_ms": round(ift_ms, 3),
+                      "pack_ms": round(total - ift_ms, 3), "reorder_bytes": reorder_bytes,
+                      "fields_per_s": round(1e3 / total, 2)}
+        log(f"ift {label}: {total:.2f} ms per call ({ift_ms:.2f} reorder + FFT)")
+        ctx.close()
+        del spec
+        torch.cuda.empty_cache()
+    return res
 
 
 def run_forms(ctx, ptk, u_host, X0, N, Np, refs):

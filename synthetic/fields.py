@@ -23,6 +23,8 @@ components fastest within a node), grid spacing delta = 2*pi/N, node j at j*delt
   and its partner at (-k2, -k3) are set to (a + conj b)/2 and its conjugate,
   self-conjugate modes to their real part.  Modes with an index N/2 are zero
   unless ``nyquist`` (then random, made Hermitian the same way).
+* ``spectrum_modes_torch``: the same construction as ``spectrum_modes`` with
+  torch on the requested device (its own random stream), for full-size grids.
 * ``sparse_spectrum``: a few random modes with |k_d| <= kmax, as index lists
   (k2 index, k3 index, k1) and amplitudes [n][3], with the conjugate partner
   of every k1 = 0 mode listed too; for full-size grids.
@@ -225,3 +227,44 @@ def sparse_spectrum(N: int, n_modes: int, kmax: int, seed: int):
     k1 = np.array([k[2] for k in keys], dtype=np.int64)
     amp = np.array([chosen[k] for k in keys], dtype=np.complex128)
     return k2i, k3i, k1, amp
+
+
+def spectrum_modes_torch(N: int, kc: float, seed: int, device="cpu", dtype=None):
+    """Random solenoidal half spectrum spec[k2][k3][k1][a] as a torch complex
+    tensor on `device` (complex128 unless dtype=torch.complex64), Hermitian on
+    the k1 = 0 and N/2 planes, no modes with an index N/2 (see module doc)."""
+    import torch
+    if N % 2:
+        raise ValueError("N must be even")
+    cdt = torch.complex128 if dtype is None else dtype
+    rdt = torch.float64 if cdt == torch.complex128 else torch.float32
+    H = N // 2 + 1
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    kf = torch.fft.fftfreq(N, d=1.0 / N, device=device, dtype=rdt)
+    K2 = kf.view(N, 1, 1)
+    K3 = kf.view(1, N, 1)
+    K1 = torch.arange(H, device=device, dtype=rdt).view(1, 1, H)
+    kk = torch.sqrt(K1 * K1 + K2 * K2 + K3 * K3)
+    kk_safe = torch.where(kk > 0, kk, torch.ones_like(kk))
+    E = kk_safe ** (-5.0 / 3.0)
+    E = torch.where(kk > kc, E * torch.exp(-(kk - kc) / (0.1 * kc)), E)
+    keep = (kk >= 1) & (K1.abs() < N / 2) & (K2.abs() < N / 2) & (K3.abs() < N / 2)
+    amp = torch.where(keep, torch.sqrt(E / (4.0 * math.pi * kk_safe * kk_safe)), torch.zeros_like(E))
+    del E, kk, keep
+    spec = torch.empty((N, N, H, 3), dtype=cdt, device=device)
+    for a in range(3):
+        re = torch.randn((N, N, H), generator=gen, device=device, dtype=rdt)
+        im = torch.randn((N, N, H), generator=gen, device=device, dtype=rdt)
+        spec[..., a] = torch.complex(re, im) * (1.0 / math.sqrt(2.0))
+        del re, im
+    Ks = (K1, K2, K3)
+    kdot = (K1 * spec[..., 0] + K2 * spec[..., 1] + K3 * spec[..., 2]) / kk_safe
+    for a in range(3):
+        spec[..., a] = (spec[..., a] - (Ks[a] / kk_safe) * kdot) * amp
+    del kdot, amp
+    r = (-torch.arange(N, device=device)) % N
+    for k1 in sorted({0, N // 2}):
+        P = spec[:, :, k1, :].clone()
+        spec[:, :, k1, :] = (P + torch.conj(P[r][:, r])) / 2.0
+    return spec
