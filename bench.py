@@ -14,8 +14,12 @@ step; ``value`` counts both.
 
 Prints ONE JSON line.  Extra fields: ``roofline`` (dominant kernel, timed with
 HIP events on the library's stream), ``cpu_baseline`` (the oracle on the host
-cores, on a bounded sample) and ``forms`` (BF16/FP16 storage and FP32
-interpolation-only timings with their errors against the FP64 oracle).
+cores, on a bounded sample), ``modes`` (velocity and velocity + gradient:
+the kernel alone on bin-ordered particles, whole interpolate calls on
+caller-ordered particles, and inside the time step), ``forms`` (FP64 / FP32 /
+BF16 / FP16 storage and the learned form: interpolation-only timings with
+their errors against the FP64 oracle) and ``ift`` (the field from the
+spectral state, 1024^3).
 """
 from __future__ import annotations
 
@@ -116,7 +120,16 @@ def cpu_baseline(u_host, X_dev, budget_s=15.0):
     _, _, th = cbuild.triple_sum(u_host, X_host, K.SPLINE, 8, 2, gradient=True)
     cbuild.triple_sum(u_host, X_host, K.SPLINE, 8, 2, gradient=False)
     el = time.perf_counter() - t0
+    host = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                host = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": 2 * n / el, "unit": "particle-interpolations/s", "cores": int(th), "kind": "oracle",
+            "host_cpu": host, "host_threads_visible": os.cpu_count(),
             "sample": (f"first {n} of the 1e8 workload particles, each evaluated twice as in one Heun "
                        f"step (velocity+gradient, then velocity), I=8 C2 spline on the 1024^3 FP32 field "
                        f"values in FP64 arithmetic; plain C oracle with OpenMP over particles; "
@@ -273,6 +286,7 @@ def main():
     # CPU leg: the oracle on the host cores -- its timing on a bounded sample
     # (cpu_baseline) and the reference values the forms' errors are stated
     # against (cpu_references); nothing on the GPU path calls it
+    modes = run_modes(ctx, ptk, X0, Np, timers, K, total_ms)
     cpu = None if args.no_cpu_baseline else cpu_baseline(u_host, X0)
     forms = None
     if not args.no_forms:
@@ -291,11 +305,62 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ms_per_step_breakdown": breakdown,
+        "modes": modes,
         "forms": forms,
         "ift": ift,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def run_modes(ctx, ptk, X0, Np, timers, K, total_ms, calls=3):
+    """The three timing modes, velocity and velocity + gradient, FP32 storage:
+    K = the kernel alone on particles already in bin order (the library's
+    interp timers on a bin-ordered copy of X0, whose stable sort is the
+    identity), E = whole ptk_interpolate / ptk_interpolate_gradient calls on
+    the caller-ordered X0 (keys, sort, kernel reading positions through the
+    permutation, caller-order writes; HIP events on the stream), S = inside
+    ptk_advance_particles (Heun with gradient: per step one velocity+gradient
+    evaluation at X_n and one velocity evaluation at the re-binned predictor;
+    kernel times per step, and the whole step with re-binning and updates
+    amortised over its two evaluations)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    ctx.interpolate(X0)
+    perm = ctx.binning()[0].long()
+    Xb = X0[perm].contiguous()
+    del perm
+    out = torch.empty((Np, 3), dtype=torch.float32, device=dev)
+    res = {}
+    for label, grad in (("velocity", False), ("velocity_gradient", True)):
+        call = (lambda X: ctx.interpolate_gradient(X)) if grad else (lambda X: ctx.interpolate(X, out=out))
+        call(Xb)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        for _ in range(calls):
+            call(Xb)
+        t = ctx.timing_read()
+        ctx.timing(False)
+        key = "interp_grad" if grad else "interp"
+        k_ms = t[key][0] / max(t[key][1], 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(calls):
+            call(X0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        e_ms = e0.elapsed_time(e1) / calls
+        s_ms = timers[key][0] / K
+        res[label] = {"K_kernel_ms": round(k_ms, 3), "K_per_s": Np / (k_ms * 1e-3),
+                      "E_end_to_end_ms": round(e_ms, 3), "E_per_s": Np / (e_ms * 1e-3),
+                      "S_kernel_ms_per_step": round(s_ms, 3), "S_kernel_per_s": Np / (s_ms * 1e-3)}
+    res["S_step_per_evaluation_ms"] = round(total_ms / K / 2, 3)
+    res["S_step_per_s"] = 2.0 * Np * K / (total_ms * 1e-3)
+    del Xb, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_ift(ptk, N, kc, calls=3):
