@@ -280,7 +280,7 @@ int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* gr
   // order it also writes the results in): no gathered copy
   InterpArgs a = base_args(c);
   a.X = X;
-  a.x_by_orig = 1;
+  a.xrow = perm;
   a.np = Np;
   a.orig = perm;
   a.out = u_out;
@@ -668,9 +668,19 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     return vf64 ? scatter_f64((const double*)in, idx, Np, width, (double*)out, s)
                 : scatter_f32((const float*)in, idx, Np, width, (float*)out, s);
   };
+  // Positions: the bin-ordered particle i of the current step is row xrow[i]
+  // of xcur (row i while xrow is NULL); every update writes its result in the
+  // current bin order to xnext.  After a re-binning the next step reads xnext
+  // through the new permutation instead of gathering it: the permutation of
+  // one time step is close to the identity, so those reads stay nearly
+  // unit-stride.
+  double* xcur = xs;
+  double* xnext = xn;
+  const uint32_t* xrow = nullptr;
   auto update = [&](int kind, const UpdateVel& v) -> int {
     Timed t(c, s, PTK_T_UPDATE);
-    PTK_HIP(c, launch_update(kind, vf64, xs, v, dt, Np, xn, keys, (int)N, invd, bg, flag, s), "position update");
+    PTK_HIP(c, launch_update(kind, vf64, xcur, xrow, v, dt, Np, xnext, keys, (int)N, invd, bg, flag, s),
+            "position update");
     return PTK_OK;
   };
   auto vel = [](const void* a, const void* b) {
@@ -689,9 +699,11 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
                                     {55.0 / 24.0, -59.0 / 24.0, 37.0 / 24.0, -9.0 / 24.0}};
   PTK_TRY(ensure_rebin(c, Np, n_bins));
   // re-bin relative to the current (bin-ordered) state: new keys in `keys`;
-  // writes the permutation to vals_a and the new sorted keys / offsets to
-  // skeys2 / offsets2 (the current ones stay valid until swap_bins)
-  auto rebin = [&](uint32_t** pm) -> int {
+  // writes the permutation to `out` (vals_a after a step, vals_b for the Heun
+  // predictor, so that the step's own permutation, xrow, survives it) and the
+  // new sorted keys / offsets to skeys2 / offsets2 (the current ones stay
+  // valid until swap_bins)
+  auto rebin = [&](uint32_t* out, uint32_t** pm) -> int {
     Timed t(c, s, PTK_T_SORT);
     RebinScratch w;
     w.in_start = (uint32_t*)c->rb_in.ptr;
@@ -707,10 +719,9 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     w.scan_tmp = (uint32_t*)c->scan_tmp.ptr;
     PTK_HIP(c,
             rebin_incremental((const uint32_t*)c->skeys.ptr, (const uint32_t*)c->offsets.ptr, keys, Np, n_bins,
-                              bits_for(n_bins), w, (uint32_t*)c->vals_a.ptr, (uint32_t*)c->skeys2.ptr,
-                              (uint32_t*)c->offsets2.ptr, s),
+                              bits_for(n_bins), w, out, (uint32_t*)c->skeys2.ptr, (uint32_t*)c->offsets2.ptr, s),
             "re-bin");
-    *pm = (uint32_t*)c->vals_a.ptr;
+    *pm = out;
     return PTK_OK;
   };
   auto swap_bins = [&]() {
@@ -744,7 +755,8 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     {
       // the last step writes the gradient straight to the caller's order
       InterpArgs a = base_args(c);
-      a.X = xs;
+      a.X = xcur;
+      a.xrow = xrow;
       a.np = Np;
       a.out = k1;
       a.grad = grad_out ? (last ? grad_out : c->gint.ptr) : nullptr;
@@ -756,17 +768,18 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     if (scheme == PTK_EULER) {
       PTK_TRY(update(kEulerOrPredict, vel(k1, nullptr)));
     } else if (scheme == PTK_HEUN) {
-      // predictor, re-binned; u at the predictor is written back in xs order
+      // predictor (into xnext), re-binned; u at the predictor is written
+      // back in the step's bin order
       PTK_TRY(update(kEulerOrPredict, vel(k1, nullptr)));
       uint32_t* pp = nullptr;
-      PTK_TRY(rebin(&pp));
+      PTK_TRY(rebin((uint32_t*)c->vals_b.ptr, &pp));
       {
         // the kernel reads the predictor positions through pp, the order it
         // also writes u in: no gathered copy
         InterpArgs b = base_args(c);
         b.offsets = (const uint32_t*)c->offsets2.ptr;  // the predictor's bins
-        b.X = xn;
-        b.x_by_orig = 1;
+        b.X = xnext;
+        b.xrow = pp;
         b.np = Np;
         b.orig = pp;
         b.out = k2;
@@ -795,19 +808,21 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     }
     if (last) {
       Timed t(c, s, PTK_T_PERMUTE);
-      PTK_HIP(c, scatter_f64(xn, orig, Np, 3, X, s), "scatter positions");
+      PTK_HIP(c, scatter_f64(xnext, orig, Np, 3, X, s), "scatter positions");
       for (int j = 0; j < hl; ++j)
         PTK_HIP(c, scatter_v(h[j], orig, 3, (char*)rhs_hist + j * v3), "scatter history");
       break;
     }
-    // re-bin the new positions and carry the per-particle state along
-    PTK_TRY(rebin(&perm));
+    // re-bin the new positions and carry the per-particle state along (the
+    // positions stay where they are: the next step reads them through perm)
+    PTK_TRY(rebin((uint32_t*)c->vals_a.ptr, &perm));
     {
       Timed t(c, s, PTK_T_PERMUTE);
-      PTK_HIP(c, gather3_f64(xn, perm, Np, xs, s), "gather positions");
       PTK_HIP(c, gather_u32(orig, perm, Np, orig_b, s), "gather order");
       for (int j = 0; j < hl; ++j) PTK_HIP(c, gather_v(h[j], perm, hb[j]), "gather history");
     }
+    xrow = perm;
+    std::swap(xcur, xnext);
     swap_bins();
     uint32_t* to = orig;
     orig = orig_b;

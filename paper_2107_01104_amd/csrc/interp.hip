@@ -550,7 +550,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   auto issue_pos = [&](uint32_t c0, int n, double& xv, uint32_t& qv) {
     const int pi = min(tid / 3, max(n - 1, 0));
     const int64_t p = min((int64_t)c0 + pi, (int64_t)a.np - 1);
-    const int64_t xi = a.x_by_orig ? (int64_t)a.orig[p] : p;
+    const int64_t xi = a.xrow ? (int64_t)a.xrow[p] : p;
     xv = a.X[3 * xi + tid % 3];
     // axis-1 threads fetch the gradient destination, the others the value one
     const uint32_t* src = (tid % 3 == 1 && a.grad_orig) ? a.grad_orig : a.orig;
@@ -650,7 +650,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
     if (nv > 0) {
       const int pi = min(tid / 3, nv - 1);
       const int64_t p = min((int64_t)start + pi, (int64_t)a.np - 1);
-      iv = a.x_by_orig ? a.orig[p] : (uint32_t)p;
+      iv = a.xrow ? a.xrow[p] : (uint32_t)p;
       // axis-1 threads fetch the gradient destination, the others the value one
       const uint32_t* src = (tid % 3 == 1 && a.grad_orig) ? a.grad_orig : a.orig;
       qv = src ? src[p] : (uint32_t)p;

@@ -87,8 +87,8 @@ struct InterpArgs {
   double invd;
   int64_t ntx, n_tiles, nw;  // tile columns per axis, columns, x3 windows per column
   int64_t nseg, wps;         // x3 segments per column (one workgroup each), windows per segment
-  const double* X;          // positions in bin order, or indexed by orig (x_by_orig)
-  int x_by_orig;            // particle p's position is X[orig[p]] rather than X[p]
+  const double* X;          // positions: bin-ordered particle p's is row xrow[p] (row p if xrow is NULL)
+  const uint32_t* xrow;
   int64_t np;               // number of particles
   const uint32_t* offsets;  // [n_bins + 1]
   const uint32_t* orig;     // destination index of each bin-ordered particle, or NULL
@@ -110,8 +110,10 @@ struct UpdateVel {
   double b[4];
   int nk;
 };
-hipError_t launch_update(int kind, int vel_f64, const double* X, const UpdateVel& v, double dt, int64_t n,
-                         double* Xout, uint32_t* keys, int N, double invd, const BinGeom& g, int* flag,
+// X: particle i's position is row xrow[i] of X (row i if xrow is NULL); Xout
+// and keys are written in particle order
+hipError_t launch_update(int kind, int vel_f64, const double* X, const uint32_t* xrow, const UpdateVel& v, double dt,
+                         int64_t n, double* Xout, uint32_t* keys, int N, double invd, const BinGeom& g, int* flag,
                          hipStream_t s);
 
 // learned.hip

@@ -16,7 +16,10 @@ namespace ptk {
 // rows; the block stages its consecutive rows of each through LDS (16-byte
 // loads and stores where the block is full and the arrays are 16-byte
 // aligned), so every global access is a unit-stride wave access, then each
-// thread updates two particles.
+// thread updates two particles.  Positions may be read through a row index
+// (xrow): consecutive threads then read the coordinates of the rows in turn,
+// which stays nearly unit-stride while the index is close to the identity (a
+// re-binning after one time step).
 constexpr int kUpdThreads = 256;
 constexpr int kUpdParts = 512;
 
@@ -30,7 +33,8 @@ __device__ __forceinline__ void stage_in(void* dst, const void* src, int nbytes,
 }
 
 template <typename V>
-__global__ __launch_bounds__(kUpdThreads) void k_update(int kind, const double* __restrict__ X, UpdateVel v,
+__global__ __launch_bounds__(kUpdThreads) void k_update(int kind, const double* __restrict__ X,
+                                                        const uint32_t* __restrict__ xrow, UpdateVel v,
                                                         double dt, int64_t n, double* __restrict__ Xout,
                                                         uint32_t* __restrict__ keys, int N, double invd, BinGeom g,
                                                         int* __restrict__ flag, int aligned) {
@@ -41,7 +45,25 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(int kind, const double* 
   const int nb = (int)min((int64_t)kUpdParts, n - base);
   const int nk = kind == kEulerOrPredict ? 1 : kind == kHeunCorrect ? 2 : v.nk;
   const bool vec = aligned && nb == kUpdParts;
-  stage_in<double>(sx, X + 3 * base, 3 * nb * (int)sizeof(double), vec);
+  if (xrow) {
+    // each thread's two particles: both row indices, then all six
+    // coordinates, so the loads are in flight together
+    static_assert(kUpdParts == 2 * kUpdThreads, "two particles per thread");
+    const int p0 = threadIdx.x, p1 = threadIdx.x + kUpdThreads;
+    const int64_t r0 = p0 < nb ? (int64_t)xrow[base + p0] : 0;
+    const int64_t r1 = p1 < nb ? (int64_t)xrow[base + p1] : 0;
+    double c0[3], c1[3];
+    for (int d = 0; d < 3; ++d) {
+      c0[d] = p0 < nb ? X[3 * r0 + d] : 0.0;
+      c1[d] = p1 < nb ? X[3 * r1 + d] : 0.0;
+    }
+    for (int d = 0; d < 3; ++d) {
+      if (p0 < nb) sx[3 * p0 + d] = c0[d];
+      if (p1 < nb) sx[3 * p1 + d] = c1[d];
+    }
+  } else {
+    stage_in<double>(sx, X + 3 * base, 3 * nb * (int)sizeof(double), vec);
+  }
   for (int j = 0; j < nk; ++j)
     stage_in<V>(sk + j * 3 * kUpdParts, (const V*)v.k[j] + 3 * base, 3 * nb * (int)sizeof(V), vec);
   __syncthreads();
@@ -85,8 +107,8 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(int kind, const double* 
   }
 }
 
-hipError_t launch_update(int kind, int vel_f64, const double* X, const UpdateVel& v, double dt, int64_t n,
-                         double* Xout, uint32_t* keys, int N, double invd, const BinGeom& g, int* flag,
+hipError_t launch_update(int kind, int vel_f64, const double* X, const uint32_t* xrow, const UpdateVel& v, double dt,
+                         int64_t n, double* Xout, uint32_t* keys, int N, double invd, const BinGeom& g, int* flag,
                          hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int nk = kind == kEulerOrPredict ? 1 : kind == kHeunCorrect ? 2 : v.nk;
@@ -99,9 +121,11 @@ hipError_t launch_update(int kind, int vel_f64, const double* X, const UpdateVel
   const size_t vb = vel_f64 ? sizeof(double) : sizeof(float);
   const size_t lds = 3 * kUpdParts * sizeof(double) + (size_t)nk * 3 * kUpdParts * vb;
   if (vel_f64)
-    k_update<double><<<blocks, kUpdThreads, lds, s>>>(kind, X, v, dt, n, Xout, keys, N, invd, g, flag, aligned);
+    k_update<double><<<blocks, kUpdThreads, lds, s>>>(kind, X, xrow, v, dt, n, Xout, keys, N, invd, g, flag,
+                                                       aligned);
   else
-    k_update<float><<<blocks, kUpdThreads, lds, s>>>(kind, X, v, dt, n, Xout, keys, N, invd, g, flag, aligned);
+    k_update<float><<<blocks, kUpdThreads, lds, s>>>(kind, X, xrow, v, dt, n, Xout, keys, N, invd, g, flag,
+                                                      aligned);
   return hipGetLastError();
 }
 
