@@ -60,62 +60,64 @@ hipError_t launch_sumsq(const void* u, int in_f64, int64_t N, const SrcLayout& l
   return hipGetLastError();
 }
 
+// padded index k (0 <= k < N + I - 1) holds grid node (k - halo_lo) mod N
+__device__ __forceinline__ int wrap_node(int k, int halo_lo, int N) {
+  const int j = k - halo_lo;
+  return j < 0 ? j + N : (j >= N ? j - N : j);
+}
+
+// One padded plane z per blockIdx.y, its P*P nodes over blockIdx.x (32-bit
+// index arithmetic: P <= 4103, so P*P < 2^25)
 template <int STORAGE>
-__global__ __launch_bounds__(256) void k_pack(const void* __restrict__ u, int in_f64, SrcLayout l, int64_t N,
-                                              int64_t P, int halo_lo, unsigned char* __restrict__ field,
-                                              int64_t row_pitch, int64_t plane_pitch, float inv0, float inv1,
-                                              float inv2) {
-  const int64_t total = P * P * P;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-    const int64_t x = i % P, y = (i / P) % P, z = i / (P * P);
-    // padded index k holds grid node (k - halo_lo) mod N
-    const int64_t sx = ((x - halo_lo) % N + N) % N;
-    const int64_t sy = ((y - halo_lo) % N + N) % N;
-    const int64_t sz = ((z - halo_lo) % N + N) % N;
-    const int64_t src = src_node(l, sx, sy, sz);
-    double v[3];
-    for (int q = 0; q < 3; ++q)
-      v[q] = in_f64 ? ((const double*)u)[src + q * l.cs] : (double)((const float*)u)[src + q * l.cs];
-    unsigned char* dst = field + z * plane_pitch + y * row_pitch;
-    if constexpr (STORAGE == 0) {
-      double* d = (double*)(dst + x * 24);
-      d[0] = v[0];
-      d[1] = v[1];
-      d[2] = v[2];
-    } else if constexpr (STORAGE == 1) {
-      float* d = (float*)(dst + x * 12);
-      d[0] = (float)v[0];
-      d[1] = (float)v[1];
-      d[2] = (float)v[2];
-    } else {
-      // fl32(u32 * fl32(1/s_a)), then round to nearest even in 16 bits
-      const float inv[3] = {inv0, inv1, inv2};
-      uint16_t* d = (uint16_t*)(dst + x * 6);
-      for (int q = 0; q < 3; ++q) {
-        float sc = (float)v[q] * inv[q];
-        if constexpr (STORAGE == 2)
-          d[q] = f32_to_bf16_rne(sc);
-        else
-          d[q] = f32_to_f16_rne(sc);
-      }
+__global__ __launch_bounds__(256) void k_pack(const void* __restrict__ u, int in_f64, SrcLayout l, int N, int P,
+                                              int halo_lo, unsigned char* __restrict__ field, int64_t row_pitch,
+                                              int64_t plane_pitch, float inv0, float inv1, float inv2) {
+  const int z = blockIdx.y;
+  const uint32_t yx = blockIdx.x * 256u + threadIdx.x;
+  if (yx >= (uint32_t)(P * P)) return;
+  const int y = (int)(yx / (uint32_t)P), x = (int)yx - y * P;
+  const int64_t src = src_node(l, wrap_node(x, halo_lo, N), wrap_node(y, halo_lo, N), wrap_node(z, halo_lo, N));
+  double v[3];
+  for (int q = 0; q < 3; ++q)
+    v[q] = in_f64 ? ((const double*)u)[src + q * l.cs] : (double)((const float*)u)[src + q * l.cs];
+  unsigned char* dst = field + z * plane_pitch + y * row_pitch;
+  if constexpr (STORAGE == 0) {
+    double* d = (double*)(dst + x * 24);
+    d[0] = v[0];
+    d[1] = v[1];
+    d[2] = v[2];
+  } else if constexpr (STORAGE == 1) {
+    float* d = (float*)(dst + x * 12);
+    d[0] = (float)v[0];
+    d[1] = (float)v[1];
+    d[2] = (float)v[2];
+  } else {
+    // fl32(u32 * fl32(1/s_a)), then round to nearest even in 16 bits
+    const float inv[3] = {inv0, inv1, inv2};
+    uint16_t* d = (uint16_t*)(dst + x * 6);
+    for (int q = 0; q < 3; ++q) {
+      float sc = (float)v[q] * inv[q];
+      if constexpr (STORAGE == 2)
+        d[q] = f32_to_bf16_rne(sc);
+      else
+        d[q] = f32_to_f16_rne(sc);
     }
   }
 }
 
 hipError_t launch_pack(const void* u, int in_f64, const SrcLayout& l, int64_t N, int storage, int I, void* field,
                        int64_t row_pitch, int64_t plane_pitch, const float* inv_scale, hipStream_t s) {
-  const int64_t P = N + I - 1;
+  const int P = (int)(N + I - 1);
   const int halo_lo = I / 2 - 1;
-  int64_t total = P * P * P;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
+  const dim3 grid((unsigned)(((int64_t)P * P + 255) / 256), (unsigned)P);
   unsigned char* f = (unsigned char*)field;
   const float i0 = inv_scale[0], i1 = inv_scale[1], i2 = inv_scale[2];
+  const int n = (int)N;
   switch (storage) {
-    case 0: k_pack<0><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, l, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
-    case 1: k_pack<1><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, l, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
-    case 2: k_pack<2><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, l, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
-    case 3: k_pack<3><<<(unsigned)blocks, 256, 0, s>>>(u, in_f64, l, N, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
+    case 0: k_pack<0><<<grid, 256, 0, s>>>(u, in_f64, l, n, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
+    case 1: k_pack<1><<<grid, 256, 0, s>>>(u, in_f64, l, n, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
+    case 2: k_pack<2><<<grid, 256, 0, s>>>(u, in_f64, l, n, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
+    case 3: k_pack<3><<<grid, 256, 0, s>>>(u, in_f64, l, n, P, halo_lo, f, row_pitch, plane_pitch, i0, i1, i2); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -124,43 +126,43 @@ hipError_t launch_pack(const void* u, int in_f64, const SrcLayout& l, int64_t N,
 // The stored field without its halo, as out[x3][x2][x1][3]: stored values
 // converted exactly (16-bit codes stay unscaled).
 template <int STORAGE, typename O>
-__global__ __launch_bounds__(256) void k_unpack(const unsigned char* __restrict__ field, int64_t N, int halo_lo,
+__global__ __launch_bounds__(256) void k_unpack(const unsigned char* __restrict__ field, int N, int halo_lo,
                                                 int64_t row_pitch, int64_t plane_pitch, O* __restrict__ out) {
-  const int64_t nodes = N * N * N;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nodes; i += (int64_t)gridDim.x * 256) {
-    const int64_t x = i % N + halo_lo, y = (i / N) % N + halo_lo, z = i / (N * N) + halo_lo;
-    const unsigned char* src = field + z * plane_pitch + y * row_pitch;
-    for (int q = 0; q < 3; ++q) {
-      O v;
-      if constexpr (STORAGE == 0) {
-        v = (O)((const double*)(src + x * 24))[q];
-      } else if constexpr (STORAGE == 1) {
-        v = (O)((const float*)(src + x * 12))[q];
-      } else {
-        const uint16_t b = ((const uint16_t*)(src + x * 6))[q];
-        if constexpr (STORAGE == 2)
-          v = (O)bf16_to_f32(b);
-        else
-          v = (O)__half2float(__ushort_as_half((unsigned short)b));
-      }
-      out[3 * i + q] = v;
+  const int z = blockIdx.y;
+  const uint32_t yx = blockIdx.x * 256u + threadIdx.x;
+  if (yx >= (uint32_t)(N * N)) return;
+  const int y = (int)(yx / (uint32_t)N), x = (int)yx - y * N;
+  const unsigned char* src = field + (int64_t)(z + halo_lo) * plane_pitch + (int64_t)(y + halo_lo) * row_pitch;
+  const int xs = x + halo_lo;
+  const int64_t i = (int64_t)z * N * N + yx;
+  for (int q = 0; q < 3; ++q) {
+    O v;
+    if constexpr (STORAGE == 0) {
+      v = (O)((const double*)(src + xs * 24))[q];
+    } else if constexpr (STORAGE == 1) {
+      v = (O)((const float*)(src + xs * 12))[q];
+    } else {
+      const uint16_t b = ((const uint16_t*)(src + xs * 6))[q];
+      if constexpr (STORAGE == 2)
+        v = (O)bf16_to_f32(b);
+      else
+        v = (O)__half2float(__ushort_as_half((unsigned short)b));
     }
+    out[3 * i + q] = v;
   }
 }
 
 hipError_t launch_unpack(const void* field, int64_t N, int storage, int I, int64_t row_pitch, int64_t plane_pitch,
                          void* out, int out_f64, hipStream_t s) {
-  const int64_t nodes = N * N * N;
-  int64_t blocks = (nodes + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
+  const int n = (int)N;
+  const dim3 g((unsigned)(((int64_t)n * n + 255) / 256), (unsigned)n);
   const unsigned char* f = (const unsigned char*)field;
   const int h = I / 2 - 1;
-  const unsigned g = (unsigned)blocks;
 #define PTK_UNPACK(ST)                                                                              \
   if (out_f64)                                                                                       \
-    k_unpack<ST, double><<<g, 256, 0, s>>>(f, N, h, row_pitch, plane_pitch, (double*)out);           \
+    k_unpack<ST, double><<<g, 256, 0, s>>>(f, n, h, row_pitch, plane_pitch, (double*)out);           \
   else                                                                                               \
-    k_unpack<ST, float><<<g, 256, 0, s>>>(f, N, h, row_pitch, plane_pitch, (float*)out);
+    k_unpack<ST, float><<<g, 256, 0, s>>>(f, n, h, row_pitch, plane_pitch, (float*)out);
   switch (storage) {
     case 0: PTK_UNPACK(0) break;
     case 1: PTK_UNPACK(1) break;
