@@ -24,14 +24,19 @@
 
 namespace ptk {
 
+// One k3 plane per blockIdx.y, its N (N/2+1) modes over blockIdx.x (32-bit
+// index arithmetic within the plane: N <= 2048)
 template <typename R>
-__global__ __launch_bounds__(256) void k_spec_prep(const R* __restrict__ in, int64_t N, int vorticity,
+__global__ __launch_bounds__(256) void k_spec_prep(const R* __restrict__ in, int N, int vorticity,
                                                    R* __restrict__ out) {
-  const int64_t H = N / 2 + 1;
-  const int64_t modes = N * N * H;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < modes; i += (int64_t)gridDim.x * 256) {
-    const int64_t k1 = i % H, k2 = (i / H) % N, k3 = i / (H * N);
-    const int64_t src = ((k2 * N + k3) * H + k1) * 3;
+  const int H = N / 2 + 1;
+  const int64_t modes = (int64_t)N * N * H;
+  const int k3 = blockIdx.y;
+  const uint32_t r = blockIdx.x * 256u + threadIdx.x;
+  if (r < (uint32_t)(N * H)) {
+    const int k2 = (int)(r / (uint32_t)H), k1 = (int)r - k2 * H;
+    const int64_t i = (int64_t)k3 * N * H + r;  // the mode's index in [k3][k2][k1] order
+    const int64_t src = (((int64_t)k2 * N + k3) * H + k1) * 3;
     R re[3], im[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -41,7 +46,7 @@ __global__ __launch_bounds__(256) void k_spec_prep(const R* __restrict__ in, int
     if (vorticity) {
       // signed wave numbers (index - N above N/2); the Nyquist index N/2 has
       // no sign, and a derivative there has no real representation: zero
-      const int64_t n2 = N / 2;
+      const int n2 = N / 2;
       const bool nyq = k1 == n2 || k2 == n2 || k3 == n2;
       const R q1 = (R)k1, q2 = (R)(k2 <= n2 ? k2 : k2 - N), q3 = (R)(k3 <= n2 ? k3 : k3 - N);
       const R kk = q1 * q1 + q2 * q2 + q3 * q3;
@@ -64,13 +69,12 @@ __global__ __launch_bounds__(256) void k_spec_prep(const R* __restrict__ in, int
 }
 
 hipError_t launch_spec_prep(const void* spec, int in_f64, int64_t N, int vorticity, void* out, hipStream_t s) {
-  const int64_t modes = N * N * (N / 2 + 1);
-  int64_t blocks = (modes + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
+  const int n = (int)N;
+  const dim3 grid((unsigned)(((int64_t)n * (n / 2 + 1) + 255) / 256), (unsigned)n);
   if (in_f64)
-    k_spec_prep<double><<<(unsigned)blocks, 256, 0, s>>>((const double*)spec, N, vorticity, (double*)out);
+    k_spec_prep<double><<<grid, 256, 0, s>>>((const double*)spec, n, vorticity, (double*)out);
   else
-    k_spec_prep<float><<<(unsigned)blocks, 256, 0, s>>>((const float*)spec, N, vorticity, (float*)out);
+    k_spec_prep<float><<<grid, 256, 0, s>>>((const float*)spec, n, vorticity, (float*)out);
   return hipGetLastError();
 }
 
