@@ -202,6 +202,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-ift", action="store_true")
+    ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic record from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
@@ -286,7 +287,7 @@ def main():
     # CPU leg: the oracle on the host cores -- its timing on a bounded sample
     # (cpu_baseline) and the reference values the forms' errors are stated
     # against (cpu_references); nothing on the GPU path calls it
-    modes = run_modes(ctx, ptk, X0, Np, timers, K, total_ms)
+    modes = None if args.no_modes else run_modes(ctx, ptk, X0, Np, timers, K, total_ms)
     cpu = None if args.no_cpu_baseline else cpu_baseline(u_host, X0)
     forms = None
     if not args.no_forms:
