@@ -207,6 +207,42 @@ int ptk_interpolate_gradient(ptk_ctx *ctx, const double *X, int64_t Np, void *u_
 int ptk_advance_particles(ptk_ctx *ctx, double *X, int64_t Np, void *rhs_hist, int *hist_len,
                           int scheme, double dt, int nsteps, void *grad_out, void *stream);
 
+/* Particles kept in the library between advance calls, for a field that
+ * changes between steps: in the paper's loop each step of the fluid solver is
+ * followed by a tracking step on the new velocity (the extra inverse transform
+ * of Sec. 4.2, here ptk_set_field_spectral), and the particle state (positions
+ * and the Adams-Bashforth history, the *state* and *rhs* arrays of Sec. 3.3.1)
+ * persists across steps.  ptk_particles_load sorts the caller's particles into
+ * bin order once; ptk_particles_advance steps them on the current field with
+ * the same schemes, arithmetic and results as ptk_advance_particles, without
+ * its per-call sort, gather and final scatter; ptk_particles_store writes them
+ * back in the caller's order.  Fields may be set between the calls (same N;
+ * with a history loaded, a storage type of the same velocity precision).
+ * The loaded state lives in the context's advance buffers: a call of
+ * ptk_advance_particles or a new load replaces it.  ptk_interpolate and the
+ * learned-form calls leave it alone.
+ *
+ * ptk_particles_load: X device [Np][3] binary64 (any real values; wrapped like
+ *    ptk_locate); hist_depth 0 (no history: Euler, Heun) or the
+ *    Adams-Bashforth order 2..4 the history is for; rhs_hist device
+ *    [hist_depth][Np][3] of the current storage's velocity type, caller order,
+ *    its first hist_len (0..hist_depth) entries valid (may be NULL when
+ *    hist_len = 0).  X and rhs_hist are not kept: they may be reused once the
+ *    call's work on the stream has completed.  Non-finite positions give
+ *    PTK_EDOMAIN (the state is then not loaded).
+ * ptk_particles_advance: scheme as in ptk_advance_particles (an
+ *    Adams-Bashforth scheme must match hist_depth; Euler and Heun leave a
+ *    loaded history alone); grad_out as there (caller order, the last step's).
+ *    PTK_EINVAL without a loaded state, with a field of another N, or with a
+ *    storage type whose velocity precision differs from the loaded history's.
+ * ptk_particles_store: X device [Np][3] (positions, caller order); with a
+ *    history loaded, rhs_hist [hist_depth][Np][3] and *hist_len receive it.
+ *    The state stays loaded. */
+int ptk_particles_load(ptk_ctx *ctx, const double *X, int64_t Np, const void *rhs_hist, int hist_len,
+                       int hist_depth, void *stream);
+int ptk_particles_advance(ptk_ctx *ctx, int scheme, double dt, int nsteps, void *grad_out, void *stream);
+int ptk_particles_store(ptk_ctx *ctx, double *X, void *rhs_hist, int *hist_len, void *stream);
+
 /* Binning of the last ptk_interpolate / ptk_interpolate_gradient call:
  * number of particles, number of bins, tile edge T and window depth W (cells).
  * Bins are tile columns of T x T cells in (x1, x2), each cut along x3 into

@@ -187,9 +187,10 @@ int ensure_binning(ptk_ctx* c, int64_t Np, int64_t n_bins) {
 // scratch of the incremental re-binning (in addition to ensure_binning's)
 int ensure_rebin(ptk_ctx* c, int64_t Np, int64_t n_bins) {
   const size_t n4 = (size_t)Np * 4, b4 = (size_t)(n_bins + 1) * 4;
-  DevBuf* per_particle[] = {&c->skeys, &c->skeys2, &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->mo};
+  DevBuf* per_particle[] = {&c->skeys, &c->skeys2, &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->mo,
+                            &c->aperm, &c->aperm_p};
   for (DevBuf* b : per_particle) PTK_TRY(ensure(c, *b, n4));
-  DevBuf* per_bin[] = {&c->offsets2, &c->rb_in, &c->rb_out, &c->rb_inc};
+  DevBuf* per_bin[] = {&c->aoff, &c->offsets2, &c->rb_in, &c->rb_out, &c->rb_inc};
   for (DevBuf* b : per_bin) PTK_TRY(ensure(c, *b, b4));
   PTK_TRY(ensure(c, c->rb_block, rebin_block_words(Np) * 4));
   return PTK_OK;
@@ -198,14 +199,14 @@ int ensure_rebin(ptk_ctx* c, int64_t Np, int64_t n_bins) {
 // keys -> stable sort -> offsets.  keys of the particles must be in keys_a.
 // *skeys (optional) receives the sorted keys' location.
 int bin_sorted(ptk_ctx* c, int64_t Np, int64_t n_bins, uint32_t** perm, hipStream_t s,
-               uint32_t** skeys = nullptr) {
+               uint32_t** skeys = nullptr, uint32_t* off_out = nullptr) {
   uint32_t* sk = nullptr;
   PTK_HIP(c,
           radix_sort_keys((uint32_t*)c->keys_a.ptr, (uint32_t*)c->keys_b.ptr, (uint32_t*)c->vals_a.ptr,
                           (uint32_t*)c->vals_b.ptr, Np, nullptr, false, bits_for(n_bins), (uint32_t*)c->hist.ptr,
                           (uint32_t*)c->scan_tmp.ptr, &sk, perm, s),
           "radix sort");
-  PTK_HIP(c, launch_offsets(sk, Np, n_bins, (uint32_t*)c->offsets.ptr, s), "bin offsets");
+  PTK_HIP(c, launch_offsets(sk, Np, n_bins, off_out ? off_out : (uint32_t*)c->offsets.ptr, s), "bin offsets");
   if (skeys) *skeys = sk;
   return PTK_OK;
 }
@@ -390,7 +391,7 @@ void ptk_destroy(ptk_ctx* c) {
                       &c->lm, &c->lv, &c->lw1b, &c->lw2b, &c->lw2bt, &c->lgpart, &c->llpart, &c->lwide,
                       &c->laudit_x, &c->laudit_u, &c->laudit_sums, &c->skeys, &c->skeys2, &c->offsets2,
                       &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->mo, &c->rb_in, &c->rb_out, &c->rb_inc,
-                      &c->rb_block, &c->spec, &c->fft_work};
+                      &c->rb_block, &c->spec, &c->fft_work, &c->aoff, &c->aperm, &c->aperm_p};
     for (DevBuf* b : bufs) release(*b);
     fft_release(c->fft);
     c->fft = nullptr;
@@ -604,26 +605,97 @@ int ptk_get_binning(ptk_ctx* c, uint32_t* perm, uint32_t* offsets, void* stream)
   return PTK_OK;
 }
 
-int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int* hist_len, int scheme,
-                          double dt, int nsteps, void* grad_out, void* stream) {
-  if (!c) return PTK_EINVAL;
-  c->err.clear();
-  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
-  if (scheme < PTK_EULER || scheme > PTK_AB4) return fail(c, PTK_EINVAL, "bad scheme");
-  // Adams-Bashforth order and history depth
-  const int K = scheme == PTK_AB2 ? 2 : scheme == PTK_AB3 ? 3 : scheme == PTK_AB4 ? 4 : 0;
-  if (Np < 0 || Np > (int64_t)0xFFFFFFFF) return fail(c, PTK_EINVAL, "Np out of range [0, 2^32)");
-  if (nsteps < 0) return fail(c, PTK_EINVAL, "nsteps must be >= 0");
-  if (!std::isfinite(dt)) return fail(c, PTK_EINVAL, "dt must be finite");
-  if (K) {
-    if (!rhs_hist || !hist_len) return fail(c, PTK_EINVAL, "Adams-Bashforth needs rhs_hist and hist_len");
-    if (*hist_len < 0 || *hist_len > K) return fail(c, PTK_EINVAL, "hist_len must be in [0, order]");
+namespace {
+
+// Adams-Bashforth order of a scheme (0: not a multistep scheme)
+int ab_order(int scheme) { return scheme == PTK_AB2 ? 2 : scheme == PTK_AB3 ? 3 : scheme == PTK_AB4 ? 4 : 0; }
+
+// Adams-Bashforth weights of u_{n-j} by order (order 1 is Euler)
+const double kABW[5][4] = {{0, 0, 0, 0},
+                           {1.0, 0, 0, 0},
+                           {1.5, -0.5, 0, 0},
+                           {23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0, 0},
+                           {55.0 / 24.0, -59.0 / 24.0, 37.0 / 24.0, -9.0 / 24.0}};
+
+// Sorts the caller's particles into bin order and makes them the loaded
+// state: positions gathered into xs, caller index into orig, the hl valid
+// history entries of rhs_hist ([K][Np][3], caller order) gathered, the bins'
+// sorted keys and offsets in skeys / aoff.  Argument checks are the caller's.
+int adv_load(ptk_ctx* c, const double* X, int64_t Np, const void* rhs_hist, int hl, int K, hipStream_t s) {
+  auto& st = c->adv;
+  st.valid = false;
+  const int64_t N = c->geom.N;
+  const BinGeom bg = bin_geom(c);
+  const int64_t n_bins = n_bins_of(bg);
+  const int vb = vel_bytes(c);
+  const bool vf64 = vb == 8;
+  const size_t v3 = (size_t)Np * 3 * vb;
+  PTK_TRY(ensure_binning(c, Np, n_bins));
+  PTK_TRY(ensure_rebin(c, Np, n_bins));
+  PTK_TRY(ensure(c, c->xs, (size_t)Np * 24));
+  PTK_TRY(ensure(c, c->xn, (size_t)Np * 24));
+  PTK_TRY(ensure(c, c->orig, (size_t)Np * 4));
+  PTK_TRY(ensure(c, c->orig_b, (size_t)Np * 4));
+  PTK_TRY(ensure(c, c->k1, v3));
+  for (int j = 0; j < K; ++j) {
+    PTK_TRY(ensure(c, c->abh[j], v3));
+    PTK_TRY(ensure(c, c->abh_b[j], v3));
   }
-  if (Np > 0 && !X) return fail(c, PTK_EINVAL, "NULL positions");
-  if (Np == 0 || nsteps == 0) return PTK_OK;
-  DeviceGuard g(c->device);
-  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
-  hipStream_t s = S(stream);
+  c->bin_valid = false;  // the sort below reuses the interpolate calls' sort buffers
+  uint32_t* keys = (uint32_t*)c->keys_a.ptr;
+  int* flag = (int*)c->flag.ptr;
+  PTK_HIP(c, hipMemsetAsync(flag, 0, sizeof(int), s), "flag clear");
+  if (Np > 0) {
+    {
+      Timed t(c, s, PTK_T_KEYS);
+      PTK_HIP(c, launch_keys(X, Np, (int)N, invd_of(N), bg, keys, flag, s), "keys");
+    }
+    uint32_t* perm = nullptr;
+    {
+      Timed t(c, s, PTK_T_SORT);
+      uint32_t* sk = nullptr;
+      PTK_TRY(bin_sorted(c, Np, n_bins, &perm, s, &sk, (uint32_t*)c->aoff.ptr));
+      PTK_HIP(c, hipMemcpyAsync(c->skeys.ptr, sk, (size_t)Np * 4, hipMemcpyDeviceToDevice, s), "sorted keys");
+    }
+    Timed t(c, s, PTK_T_PERMUTE);
+    PTK_HIP(c, gather3_f64(X, perm, Np, (double*)c->xs.ptr, s), "gather positions");
+    PTK_HIP(c, hipMemcpyAsync(c->orig.ptr, perm, (size_t)Np * 4, hipMemcpyDeviceToDevice, s), "copy order");
+    for (int j = 0; j < hl; ++j) {
+      const char* in = (const char*)rhs_hist + j * v3;
+      PTK_HIP(c,
+              vf64 ? gather3_f64((const double*)in, perm, Np, (double*)c->abh[j].ptr, s)
+                   : gather3_f32((const float*)in, perm, Np, (float*)c->abh[j].ptr, s),
+              "gather history");
+    }
+  }
+  st.Np = Np;
+  st.N = N;
+  st.vb = vb;
+  st.K = K;
+  st.hl = K ? hl : 0;
+  st.xcur = (double*)c->xs.ptr;
+  st.xnext = (double*)c->xn.ptr;
+  st.xrow = nullptr;
+  st.orig = (uint32_t*)c->orig.ptr;
+  st.orig_b = (uint32_t*)c->orig_b.ptr;
+  st.k1 = c->k1.ptr;
+  for (int j = 0; j < 4; ++j) {
+    st.h[j] = j < K ? c->abh[j].ptr : nullptr;
+    st.hb[j] = j < K ? c->abh_b[j].ptr : nullptr;
+  }
+  st.valid = true;
+  return PTK_OK;
+}
+
+// nsteps steps of the loaded state on the current field.  With final_X (the
+// one-shot form) the last step writes the positions, and the history to
+// final_hist, straight to the caller's order and skips its re-binning, which
+// leaves no loaded state; otherwise every step re-binns and the state stays
+// loaded.  grad_out: the last step's velocity gradient, caller order.
+int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hipStream_t s, double* final_X,
+              void* final_hist) {
+  auto& st = c->adv;
+  const int64_t Np = st.Np;
   const int64_t N = c->geom.N;
   const BinGeom bg = bin_geom(c);
   const int64_t n_bins = n_bins_of(bg);
@@ -631,35 +703,19 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
   const int vb = vel_bytes(c);
   const bool vf64 = vb == 8;
   const size_t v3 = (size_t)Np * 3 * vb;
-
-  PTK_TRY(ensure_binning(c, Np, n_bins));
-  PTK_TRY(ensure(c, c->xs, (size_t)Np * 24));
-  PTK_TRY(ensure(c, c->xn, (size_t)Np * 24));
-  PTK_TRY(ensure(c, c->orig, (size_t)Np * 4));
-  PTK_TRY(ensure(c, c->orig_b, (size_t)Np * 4));
-  PTK_TRY(ensure(c, c->k1, v3));
-  if (scheme == PTK_HEUN) PTK_TRY(ensure(c, c->k2, v3));
-  for (int j = 0; j < K; ++j) {
-    PTK_TRY(ensure(c, c->abh[j], v3));
-    PTK_TRY(ensure(c, c->abh_b[j], v3));
+  const int K = ab_order(scheme);
+  if (st.K == 0) {
+    // no history: the velocity buffer may change width with the storage type
+    PTK_TRY(ensure(c, c->k1, v3));
+    st.k1 = c->k1.ptr;
   }
+  if (scheme == PTK_HEUN) PTK_TRY(ensure(c, c->k2, v3));
   if (grad_out) PTK_TRY(ensure(c, c->gint, (size_t)Np * 9 * vb));
-  c->bin_valid = false;
 
-  double* xs = (double*)c->xs.ptr;
-  double* xn = (double*)c->xn.ptr;
-  uint32_t* orig = (uint32_t*)c->orig.ptr;
-  uint32_t* orig_b = (uint32_t*)c->orig_b.ptr;
   uint32_t* keys = (uint32_t*)c->keys_a.ptr;
   int* flag = (int*)c->flag.ptr;
-  void* k1 = c->k1.ptr;
   void* k2 = c->k2.ptr;
-  void *h[4] = {nullptr, nullptr, nullptr, nullptr}, *hb[4] = {nullptr, nullptr, nullptr, nullptr};
-  for (int j = 0; j < K; ++j) {
-    h[j] = c->abh[j].ptr;
-    hb[j] = c->abh_b[j].ptr;
-  }
-  int hl = K ? *hist_len : 0;
+  int hl = st.hl;
   auto gather_v = [&](const void* in, const uint32_t* pm, void* out) -> hipError_t {
     return vf64 ? gather3_f64((const double*)in, pm, Np, (double*)out, s)
                 : gather3_f32((const float*)in, pm, Np, (float*)out, s);
@@ -668,18 +724,14 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     return vf64 ? scatter_f64((const double*)in, idx, Np, width, (double*)out, s)
                 : scatter_f32((const float*)in, idx, Np, width, (float*)out, s);
   };
-  // Positions: the bin-ordered particle i of the current step is row xrow[i]
-  // of xcur (row i while xrow is NULL); every update writes its result in the
-  // current bin order to xnext.  After a re-binning the next step reads xnext
-  // through the new permutation instead of gathering it: the permutation of
-  // one time step is close to the identity, so those reads stay nearly
-  // unit-stride.
-  double* xcur = xs;
-  double* xnext = xn;
-  const uint32_t* xrow = nullptr;
+  // Positions: particle i of the current bin order is row xrow[i] of xcur
+  // (row i while xrow is NULL); every update writes its result in the current
+  // bin order to xnext.  After a re-binning the next step reads xnext through
+  // the new permutation instead of gathering it: the permutation of one time
+  // step is close to the identity, so those reads stay nearly unit-stride.
   auto update = [&](int kind, const UpdateVel& v) -> int {
     Timed t(c, s, PTK_T_UPDATE);
-    PTK_HIP(c, launch_update(kind, vf64, xcur, xrow, v, dt, Np, xnext, keys, (int)N, invd, bg, flag, s),
+    PTK_HIP(c, launch_update(kind, vf64, st.xcur, st.xrow, v, dt, Np, st.xnext, keys, (int)N, invd, bg, flag, s),
             "position update");
     return PTK_OK;
   };
@@ -691,19 +743,12 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     v.nk = b ? 2 : 1;
     return v;
   };
-  // Adams-Bashforth weights of u_{n-j} by order (order 1 is Euler)
-  static const double kABW[5][4] = {{0, 0, 0, 0},
-                                    {1.0, 0, 0, 0},
-                                    {1.5, -0.5, 0, 0},
-                                    {23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0, 0},
-                                    {55.0 / 24.0, -59.0 / 24.0, 37.0 / 24.0, -9.0 / 24.0}};
-  PTK_TRY(ensure_rebin(c, Np, n_bins));
   // re-bin relative to the current (bin-ordered) state: new keys in `keys`;
-  // writes the permutation to `out` (vals_a after a step, vals_b for the Heun
+  // writes the permutation to `out` (aperm after a step, aperm_p for the Heun
   // predictor, so that the step's own permutation, xrow, survives it) and the
-  // new sorted keys / offsets to skeys2 / offsets2 (the current ones stay
-  // valid until swap_bins)
-  auto rebin = [&](uint32_t* out, uint32_t** pm) -> int {
+  // new sorted keys / offsets to skeys2 / offsets2 (the current ones, skeys /
+  // aoff, stay valid until swap_bins)
+  auto rebin = [&](uint32_t* out) -> int {
     Timed t(c, s, PTK_T_SORT);
     RebinScratch w;
     w.in_start = (uint32_t*)c->rb_in.ptr;
@@ -718,49 +763,31 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
     w.hist = (uint32_t*)c->hist.ptr;
     w.scan_tmp = (uint32_t*)c->scan_tmp.ptr;
     PTK_HIP(c,
-            rebin_incremental((const uint32_t*)c->skeys.ptr, (const uint32_t*)c->offsets.ptr, keys, Np, n_bins,
+            rebin_incremental((const uint32_t*)c->skeys.ptr, (const uint32_t*)c->aoff.ptr, keys, Np, n_bins,
                               bits_for(n_bins), w, out, (uint32_t*)c->skeys2.ptr, (uint32_t*)c->offsets2.ptr, s),
             "re-bin");
-    *pm = out;
     return PTK_OK;
   };
   auto swap_bins = [&]() {
     std::swap(c->skeys, c->skeys2);
-    std::swap(c->offsets, c->offsets2);
+    std::swap(c->aoff, c->offsets2);
   };
 
   PTK_HIP(c, hipMemsetAsync(flag, 0, sizeof(int), s), "flag clear");
-  // initial binning of the caller's positions; the state is then kept in bin order
-  {
-    Timed t(c, s, PTK_T_KEYS);
-    PTK_HIP(c, launch_keys(X, Np, (int)N, invd, bg, keys, flag, s), "keys");
-  }
-  uint32_t* perm = nullptr;
-  {
-    Timed t(c, s, PTK_T_SORT);
-    uint32_t* sk = nullptr;
-    PTK_TRY(bin_sorted(c, Np, n_bins, &perm, s, &sk));
-    PTK_HIP(c, hipMemcpyAsync(c->skeys.ptr, sk, (size_t)Np * 4, hipMemcpyDeviceToDevice, s), "sorted keys");
-  }
-  {
-    Timed t(c, s, PTK_T_PERMUTE);
-    PTK_HIP(c, gather3_f64(X, perm, Np, xs, s), "gather positions");
-    PTK_HIP(c, hipMemcpyAsync(orig, perm, (size_t)Np * 4, hipMemcpyDeviceToDevice, s), "copy order");
-    for (int j = 0; j < hl; ++j)
-      PTK_HIP(c, gather_v((const char*)rhs_hist + j * v3, perm, h[j]), "gather history");
-  }
   for (int step = 0; step < nsteps; ++step) {
     const bool last = step == nsteps - 1;
+    void* k1 = st.k1;
     // u(X_n), and its gradient, at the bin-ordered positions
     {
       // the last step writes the gradient straight to the caller's order
       InterpArgs a = base_args(c);
-      a.X = xcur;
-      a.xrow = xrow;
+      a.offsets = (const uint32_t*)c->aoff.ptr;
+      a.X = st.xcur;
+      a.xrow = st.xrow;
       a.np = Np;
       a.out = k1;
       a.grad = grad_out ? (last ? grad_out : c->gint.ptr) : nullptr;
-      a.grad_orig = grad_out && last ? orig : nullptr;
+      a.grad_orig = grad_out && last ? st.orig : nullptr;
       a.out_f64 = vf64;
       Timed t(c, s, grad_out ? PTK_T_INTERP_GRAD : PTK_T_INTERP);
       PTK_HIP(c, launch_interp(c->storage, c->I, a, s), "interpolate");
@@ -771,14 +798,14 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
       // predictor (into xnext), re-binned; u at the predictor is written
       // back in the step's bin order
       PTK_TRY(update(kEulerOrPredict, vel(k1, nullptr)));
-      uint32_t* pp = nullptr;
-      PTK_TRY(rebin((uint32_t*)c->vals_b.ptr, &pp));
+      uint32_t* pp = (uint32_t*)c->aperm_p.ptr;
+      PTK_TRY(rebin(pp));
       {
         // the kernel reads the predictor positions through pp, the order it
         // also writes u in: no gathered copy
         InterpArgs b = base_args(c);
         b.offsets = (const uint32_t*)c->offsets2.ptr;  // the predictor's bins
-        b.X = xnext;
+        b.X = st.xnext;
         b.xrow = pp;
         b.np = Np;
         b.orig = pp;
@@ -794,43 +821,151 @@ int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int
       UpdateVel v;
       std::memset(&v, 0, sizeof(v));
       v.k[0] = k1;
-      for (int j = 1; j < q; ++j) v.k[j] = h[j - 1];
+      for (int j = 1; j < q; ++j) v.k[j] = st.h[j - 1];
       for (int j = 0; j < q; ++j) v.b[j] = kABW[q][j];
       v.nk = q;
       PTK_TRY(update(q == 1 ? kEulerOrPredict : kAB, v));
       // history rotation: u_{n-j-1} <- u_{n-j}, u_n <- k1; the dropped buffer
       // takes the next step's velocity
-      void* t = h[K - 1];
-      for (int j = K - 1; j > 0; --j) h[j] = h[j - 1];
-      h[0] = k1;
-      k1 = t;
+      void* t = st.h[K - 1];
+      for (int j = K - 1; j > 0; --j) st.h[j] = st.h[j - 1];
+      st.h[0] = k1;
+      st.k1 = t;
       hl = hl < K ? hl + 1 : K;
     }
-    if (last) {
+    if (last && final_X) {
       Timed t(c, s, PTK_T_PERMUTE);
-      PTK_HIP(c, scatter_f64(xnext, orig, Np, 3, X, s), "scatter positions");
+      PTK_HIP(c, scatter_f64(st.xnext, st.orig, Np, 3, final_X, s), "scatter positions");
       for (int j = 0; j < hl; ++j)
-        PTK_HIP(c, scatter_v(h[j], orig, 3, (char*)rhs_hist + j * v3), "scatter history");
+        PTK_HIP(c, scatter_v(st.h[j], st.orig, 3, (char*)final_hist + j * v3), "scatter history");
+      st.valid = false;
       break;
     }
     // re-bin the new positions and carry the per-particle state along (the
     // positions stay where they are: the next step reads them through perm)
-    PTK_TRY(rebin((uint32_t*)c->vals_a.ptr, &perm));
+    uint32_t* perm = (uint32_t*)c->aperm.ptr;
+    PTK_TRY(rebin(perm));
     {
       Timed t(c, s, PTK_T_PERMUTE);
-      PTK_HIP(c, gather_u32(orig, perm, Np, orig_b, s), "gather order");
-      for (int j = 0; j < hl; ++j) PTK_HIP(c, gather_v(h[j], perm, hb[j]), "gather history");
+      PTK_HIP(c, gather_u32(st.orig, perm, Np, st.orig_b, s), "gather order");
+      for (int j = 0; j < hl; ++j) PTK_HIP(c, gather_v(st.h[j], perm, st.hb[j]), "gather history");
     }
-    xrow = perm;
-    std::swap(xcur, xnext);
+    st.xrow = perm;
+    std::swap(st.xcur, st.xnext);
     swap_bins();
-    uint32_t* to = orig;
-    orig = orig_b;
-    orig_b = to;
-    for (int j = 0; j < hl; ++j) std::swap(h[j], hb[j]);
+    std::swap(st.orig, st.orig_b);
+    for (int j = 0; j < hl; ++j) std::swap(st.h[j], st.hb[j]);
   }
-  if (K) *hist_len = hl;
+  st.hl = hl;
   return check_flag(c, s);
+}
+
+// the loaded positions (and history) in the caller's order
+int adv_store(ptk_ctx* c, double* X, void* rhs_hist, hipStream_t s) {
+  auto& st = c->adv;
+  const int64_t Np = st.Np;
+  if (Np == 0) return PTK_OK;
+  const bool vf64 = st.vb == 8;
+  const size_t v3 = (size_t)Np * 3 * st.vb;
+  Timed t(c, s, PTK_T_PERMUTE);
+  const double* x = st.xcur;
+  if (st.xrow) {
+    PTK_HIP(c, gather3_f64(st.xcur, st.xrow, Np, st.xnext, s), "gather positions");
+    x = st.xnext;
+  }
+  PTK_HIP(c, scatter_f64(x, st.orig, Np, 3, X, s), "scatter positions");
+  for (int j = 0; j < st.hl; ++j) {
+    char* out = (char*)rhs_hist + j * v3;
+    PTK_HIP(c,
+            vf64 ? scatter_f64((const double*)st.h[j], st.orig, Np, 3, (double*)out, s)
+                 : scatter_f32((const float*)st.h[j], st.orig, Np, 3, (float*)out, s),
+            "scatter history");
+  }
+  return PTK_OK;
+}
+
+}  // namespace
+
+int ptk_advance_particles(ptk_ctx* c, double* X, int64_t Np, void* rhs_hist, int* hist_len, int scheme,
+                          double dt, int nsteps, void* grad_out, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
+  if (scheme < PTK_EULER || scheme > PTK_AB4) return fail(c, PTK_EINVAL, "bad scheme");
+  // Adams-Bashforth order and history depth
+  const int K = ab_order(scheme);
+  if (Np < 0 || Np > (int64_t)0xFFFFFFFF) return fail(c, PTK_EINVAL, "Np out of range [0, 2^32)");
+  if (nsteps < 0) return fail(c, PTK_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(c, PTK_EINVAL, "dt must be finite");
+  if (K) {
+    if (!rhs_hist || !hist_len) return fail(c, PTK_EINVAL, "Adams-Bashforth needs rhs_hist and hist_len");
+    if (*hist_len < 0 || *hist_len > K) return fail(c, PTK_EINVAL, "hist_len must be in [0, order]");
+  }
+  if (Np > 0 && !X) return fail(c, PTK_EINVAL, "NULL positions");
+  if (Np == 0 || nsteps == 0) return PTK_OK;
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  // the one-shot form runs on the buffers of the loaded state
+  c->adv.valid = false;
+  PTK_TRY(adv_load(c, X, Np, rhs_hist, K ? *hist_len : 0, K, s));
+  const int r = adv_steps(c, scheme, dt, nsteps, grad_out, s, X, rhs_hist);
+  if (K && r == PTK_OK) *hist_len = c->adv.hl;
+  c->adv.valid = false;
+  return r;
+}
+
+int ptk_particles_load(ptk_ctx* c, const double* X, int64_t Np, const void* rhs_hist, int hist_len, int hist_depth,
+                       void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
+  if (Np < 0 || Np > (int64_t)0xFFFFFFFF) return fail(c, PTK_EINVAL, "Np out of range [0, 2^32)");
+  if (Np > 0 && !X) return fail(c, PTK_EINVAL, "NULL positions");
+  if (hist_depth < 0 || hist_depth > 4 || hist_depth == 1)
+    return fail(c, PTK_EINVAL, "hist_depth must be 0 or an Adams-Bashforth order 2..4");
+  if (hist_len < 0 || hist_len > hist_depth) return fail(c, PTK_EINVAL, "hist_len must be in [0, hist_depth]");
+  if (hist_len > 0 && Np > 0 && !rhs_hist) return fail(c, PTK_EINVAL, "NULL history");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  PTK_TRY(adv_load(c, X, Np, rhs_hist, hist_len, hist_depth, s));
+  const int r = check_flag(c, s);
+  if (r != PTK_OK) c->adv.valid = false;
+  return r;
+}
+
+int ptk_particles_advance(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!c->adv.valid) return fail(c, PTK_EINVAL, "no particles loaded");
+  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
+  if (scheme < PTK_EULER || scheme > PTK_AB4) return fail(c, PTK_EINVAL, "bad scheme");
+  if (nsteps < 0) return fail(c, PTK_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt)) return fail(c, PTK_EINVAL, "dt must be finite");
+  if (c->geom.N != c->adv.N) return fail(c, PTK_EINVAL, "the field's grid differs from the loaded particles' bins");
+  const int K = ab_order(scheme);
+  if (K && K != c->adv.K) return fail(c, PTK_EINVAL, "Adams-Bashforth order differs from the loaded history depth");
+  if (c->adv.K && vel_bytes(c) != c->adv.vb)
+    return fail(c, PTK_EINVAL, "the storage type changes the loaded history's precision");
+  if (c->adv.Np == 0 || nsteps == 0) return PTK_OK;
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  return adv_steps(c, scheme, dt, nsteps, grad_out, S(stream), nullptr, nullptr);
+}
+
+int ptk_particles_store(ptk_ctx* c, double* X, void* rhs_hist, int* hist_len, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!c->adv.valid) return fail(c, PTK_EINVAL, "no particles loaded");
+  if (c->adv.Np > 0 && !X) return fail(c, PTK_EINVAL, "NULL positions");
+  if (c->adv.K && (!hist_len || (c->adv.hl > 0 && !rhs_hist)))
+    return fail(c, PTK_EINVAL, "the loaded history needs rhs_hist and hist_len");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  PTK_TRY(adv_store(c, X, rhs_hist, S(stream)));
+  if (hist_len) *hist_len = c->adv.K ? c->adv.hl : 0;
+  return PTK_OK;
 }
 
 int ptk_timing_enable(ptk_ctx* c, int enable) {

@@ -88,8 +88,28 @@ struct ptk_ctx {
   ptk::DevBuf xs, xn, orig, orig_b, k1, k2, gint, stage;
   ptk::DevBuf abh[4], abh_b[4];  // Adams-Bashforth history in bin order, and its permuted copy
   // incremental re-binning inside advance: sorted keys and offsets of the
-  // current order and of the next, mover lists, per-bin counters
-  ptk::DevBuf skeys, skeys2, offsets2, mk_a, mk_b, mv_a, mv_b, mo, rb_in, rb_out, rb_inc, rb_block;
+  // current order (skeys, aoff) and of the next (skeys2, offsets2), mover
+  // lists, per-bin counters, and the permutations of the last re-binning
+  // (aperm) and of the Heun predictor's (aperm_p)
+  ptk::DevBuf skeys, skeys2, aoff, offsets2, mk_a, mk_b, mv_a, mv_b, mo, rb_in, rb_out, rb_inc, rb_block;
+  ptk::DevBuf aperm, aperm_p;
+  // the particle state between advance calls (ptk_particles_load .. _store):
+  // which buffers hold what, in the current bin order
+  struct {
+    bool valid = false;
+    int64_t Np = 0, N = 0;
+    int vb = 0;   // bytes per velocity component of the history
+    int K = 0;    // history depth (Adams-Bashforth order) it was loaded for
+    int hl = 0;   // valid history entries
+    double* xcur = nullptr;    // positions: particle i's is row xrow[i] (row i if xrow is NULL)
+    double* xnext = nullptr;   // the other position buffer
+    uint32_t* xrow = nullptr;
+    uint32_t* orig = nullptr;  // caller index of particle i
+    uint32_t* orig_b = nullptr;
+    void* k1 = nullptr;        // buffer for the next u(X_n)
+    void* h[4] = {nullptr, nullptr, nullptr, nullptr};   // u_{n-1-j}
+    void* hb[4] = {nullptr, nullptr, nullptr, nullptr};  // their re-binned copies
+  } adv;
   // learned form: FP32 master parameters, Adam moments, BF16 layer copies,
   // per-workgroup gradient and loss partials, audit scratch
   ptk::DevBuf lparams, lm, lv, lw1b, lw2b, lw2bt, lgpart, llpart, lwide, laudit_x, laudit_u, laudit_sums;

@@ -28,7 +28,8 @@ SPEC_VELOCITY, SPEC_VORTICITY = 0, 1
 LEARNED_NFEAT, LEARNED_FEAT_PITCH, LEARNED_NPARAMS = 195, 200, 41987
 
 EXPORTS = ["ptk_kernel_table", "ptk_create", "ptk_destroy", "ptk_last_error", "ptk_set_field", "ptk_get_field_scale",
-           "ptk_set_field_spectral", "ptk_get_field",
+           "ptk_set_field_spectral", "ptk_get_field", "ptk_particles_load", "ptk_particles_advance",
+           "ptk_particles_store",
            "ptk_locate", "ptk_interpolate", "ptk_interpolate_gradient", "ptk_advance_particles",
            "ptk_binning_info", "ptk_get_binning", "ptk_timing_enable", "ptk_timing_read",
            "ptk_learned_make_pairs", "ptk_learned_set_params", "ptk_learned_get_params", "ptk_learned_loss_grad",
@@ -65,6 +66,9 @@ lib.ptk_locate.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
 lib.ptk_interpolate.argtypes = [_vp, _vp, _i64, _vp, _int, _vp]
 lib.ptk_interpolate_gradient.argtypes = [_vp, _vp, _i64, _vp, _vp, _int, _vp]
 lib.ptk_advance_particles.argtypes = [_vp, _vp, _i64, _vp, ctypes.POINTER(_int), _int, _dbl, _int, _vp, _vp]
+lib.ptk_particles_load.argtypes = [_vp, _vp, _i64, _vp, _int, _int, _vp]
+lib.ptk_particles_advance.argtypes = [_vp, _int, _dbl, _int, _vp, _vp]
+lib.ptk_particles_store.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_int), _vp]
 lib.ptk_binning_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int),
                                  ctypes.POINTER(_int)]
 lib.ptk_get_binning.argtypes = [_vp, _vp, _vp, _vp]
@@ -266,6 +270,37 @@ class Context:
                                               ctypes.byref(hl) if hist is not None else None,
                                               int(scheme), float(dt), int(nsteps), _ptr(grad_out),
                                               _stream(self.device)))
+        return hl.value
+
+    # ---- particles kept in the library between advance calls
+    def particles_load(self, X: torch.Tensor, hist=None, hist_len: int = 0, hist_depth: int = 0):
+        """Load X ([Np][3] float64) and optionally an Adams-Bashforth history
+        ([hist_depth][Np][3], hist_len valid entries) as the resident state."""
+        _dev_tensor(X, torch.float64, (3,), "X")
+        n = X.numel() // 3
+        if hist is not None:
+            _dev_tensor(hist, self.vel_dtype(), (3,), "rhs_hist")
+            if tuple(hist.shape) != (int(hist_depth), n, 3):
+                raise ValueError(f"rhs_hist must have shape ({hist_depth}, Np, 3)")
+        self._check(lib.ptk_particles_load(self._h, _ptr(X), n, _ptr(hist), int(hist_len), int(hist_depth),
+                                           _stream(self.device)))
+
+    def particles_advance(self, scheme: int, dt: float, nsteps: int, grad_out=None):
+        """Step the resident particles on the current field."""
+        if grad_out is not None:
+            _dev_tensor(grad_out, self.vel_dtype(), (3, 3), "grad_out")
+        self._check(lib.ptk_particles_advance(self._h, int(scheme), float(dt), int(nsteps), _ptr(grad_out),
+                                              _stream(self.device)))
+
+    def particles_store(self, X: torch.Tensor, hist=None):
+        """Write the resident positions (and history) in caller order; returns
+        the history length."""
+        _dev_tensor(X, torch.float64, (3,), "X")
+        if hist is not None:
+            _dev_tensor(hist, self.vel_dtype(), (3,), "rhs_hist")
+        hl = ctypes.c_int(0)
+        self._check(lib.ptk_particles_store(self._h, _ptr(X), _ptr(hist), ctypes.byref(hl),
+                                            _stream(self.device)))
         return hl.value
 
     def binning(self):

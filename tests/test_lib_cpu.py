@@ -73,4 +73,7 @@ def test_null_and_bad_arguments_without_device(ptk):
     assert ptk.lib.ptk_advance_particles(None, None, 0, None, None, 2, 1e-3, 1, None, None) == ptk.EINVAL
     assert ptk.lib.ptk_set_field_spectral(None, None, 32, 0, 0, 0, None, None) == ptk.EINVAL
     assert ptk.lib.ptk_get_field(None, None, 0, None) == ptk.EINVAL
+    assert ptk.lib.ptk_particles_load(None, None, 0, None, 0, 0, None) == ptk.EINVAL
+    assert ptk.lib.ptk_particles_advance(None, 2, 1e-3, 1, None, None) == ptk.EINVAL
+    assert ptk.lib.ptk_particles_store(None, None, None, None, None) == ptk.EINVAL
     ptk.lib.ptk_destroy(None)
