@@ -292,7 +292,7 @@ def main():
     forms = None
     if not args.no_forms:
         forms = run_forms(ctx, ptk, u_host, X0, N, Np, cpu_references(u_host, X0))
-    ift = None if args.no_ift else run_ift(ptk, N, kc)
+    ift = None if args.no_ift else run_ift(ptk, N, kc, X0, Np)
 
     line = {
         "metric": "particle-interpolations/sec at I=8, 1024^3 grid; % HBM roofline; RMS err vs FP64",
@@ -364,14 +364,20 @@ def run_modes(ctx, ptk, X0, Np, timers, K, total_ms, calls=3):
     return res
 
 
-def run_ift(ptk, N, kc, calls=3):
+def run_ift(ptk, N, kc, X0, Np, calls=3):
     """The field from the spectral state (ptk_set_field_spectral) at N^3 with
     FP32 storage and the C2 spline I = 8: a vorticity spectrum in FP64 (the
     solver's state, turned into velocity by Biot-Savart), a velocity spectrum
     in FP64, and one in FP32.  Per call: the whole call on the stream (spectrum
     reorder + inverse FFT + field pack), and the reorder + FFT part alone (the
     library's ift timer).  The reorder kernel's algorithmic HBM bytes are one
-    read and one write of the 3 N^2 (N/2+1) complex amplitudes."""
+    read and one write of the 3 N^2 (N/2+1) complex amplitudes.
+
+    ``coupled``: the paper's loop of a field that changes every step, per step
+    the field from the FP64 vorticity spectrum and one Heun step with gradient
+    of all particles on it: with the particles resident in the library
+    (ptk_particles_*), and with a one-shot ptk_advance_particles call per step
+    (which sorts, gathers and scatters the particles each time)."""
     import torch
     from synthetic import fields
     dev = torch.device("cuda", 0)
@@ -401,10 +407,54 @@ def run_ift(ptk, N, kc, calls=3):
                       "pack_ms": round(total - ift_ms, 3), "reorder_bytes": reorder_bytes,
                       "fields_per_s": round(1e3 / total, 2)}
         log(f"ift {label}: {total:.2f} ms per call ({ift_ms:.2f} reorder + FFT)")
+        if label == "vorticity_f64":
+            res["coupled"] = run_coupled(ptk, ctx, spec, X0, Np, calls)
         ctx.close()
         del spec
         torch.cuda.empty_cache()
     return res
+
+
+def run_coupled(ptk, ctx, spec, X0, Np, steps):
+    import torch
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    grad = torch.empty((Np, 3, 3), dtype=torch.float32, device=dev)
+    X = X0.clone()
+
+    def field():
+        ctx.set_field_spectral(spec, ptk.SPLINE, 8, 2, storage=ptk.F32, kind=ptk.SPEC_VORTICITY)
+
+    def timed(body):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        body()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    ctx.particles_load(X)
+    ctx.particles_advance(ptk.HEUN, DT, 1, grad_out=grad)  # warm
+
+    def resident():
+        for _ in range(steps):
+            field()
+            ctx.particles_advance(ptk.HEUN, DT, 1, grad_out=grad)
+    ms_res = timed(resident)
+    ctx.particles_store(X)
+
+    def one_shot():
+        for _ in range(steps):
+            field()
+            ctx.advance(X, ptk.HEUN, DT, 1, grad_out=grad)
+    ms_one = timed(one_shot)
+    del grad, X
+    out = {"steps": steps, "resident_ms_per_step": round(ms_res / steps, 3),
+           "one_shot_ms_per_step": round(ms_one / steps, 3),
+           "resident_interp_per_s": 2.0 * Np * steps / (ms_res * 1e-3)}
+    log(f"coupled: {out}")
+    return out
 
 
 def run_forms(ctx, ptk, u_host, X0, N, Np, refs):
