@@ -138,8 +138,9 @@ int ptk_get_field_scale(const ptk_ctx *ctx, float *scale3);
  *    (u^(-k) = conj u^(k) within the plane); otherwise the result is
  *    undefined.
  * N: even, 8 <= N <= 2048.  The library keeps a transform buffer of
- *    3 N^2 (N/2+1) complex numbers of in_dtype and the transform's work
- *    buffer (grown, never shrunk, released by ptk_destroy).
+ *    3 N^2 (N/2+1) complex numbers of in_dtype, one of 3 N^3 real numbers for
+ *    its result and the transform's work buffer (grown, never shrunk,
+ *    released by ptk_destroy).
  * Errors: PTK_EINVAL (NULL pointer, odd or out-of-range N, bad kind or
  *    dtype), PTK_EUNSUPPORTED (kernel), PTK_ENOMEM, PTK_EHIP (transform set-up
  *    or launch); on an argument error the context is unchanged. */

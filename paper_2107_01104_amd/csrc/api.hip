@@ -391,7 +391,7 @@ void ptk_destroy(ptk_ctx* c) {
                       &c->lm, &c->lv, &c->lw1b, &c->lw2b, &c->lw2bt, &c->lgpart, &c->llpart, &c->lwide,
                       &c->laudit_x, &c->laudit_u, &c->laudit_sums, &c->skeys, &c->skeys2, &c->offsets2,
                       &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->mo, &c->rb_in, &c->rb_out, &c->rb_inc,
-                      &c->rb_block, &c->spec, &c->fft_work, &c->aoff, &c->aperm, &c->aperm_p};
+                      &c->rb_block, &c->spec, &c->fft_out, &c->fft_work, &c->aoff, &c->aperm, &c->aperm_p};
     for (DevBuf* b : bufs) release(*b);
     fft_release(c->fft);
     c->fft = nullptr;
@@ -521,13 +521,15 @@ int ptk_set_field_spectral(ptk_ctx* c, const void* spec, int64_t N, int in_dtype
   const char* msg = nullptr;
   if (fft_prepare(&c->fft, N, f64, &work, &msg) != 0) return fail(c, PTK_EHIP, msg);
   PTK_TRY(ensure(c, c->spec, 3 * modes * 2 * rb));
+  PTK_TRY(ensure(c, c->fft_out, 3 * (size_t)N * (size_t)N * (size_t)N * rb));
   if (work > 0) PTK_TRY(ensure(c, c->fft_work, work));
   {
     Timed t(c, s, PTK_T_IFT);
     PTK_HIP(c, launch_spec_prep(spec, f64, N, kind == PTK_SPEC_VORTICITY, c->spec.ptr, s), "spectrum prep");
-    if (fft_run(c->fft, c->spec.ptr, c->fft_work.ptr, c->fft_work.cap, s, &msg) != 0) return fail(c, PTK_EHIP, msg);
+    if (fft_run(c->fft, c->spec.ptr, c->fft_out.ptr, c->fft_work.ptr, c->fft_work.cap, s, &msg) != 0)
+      return fail(c, PTK_EHIP, msg);
   }
-  return store_field(c, c->spec.ptr, f64, transform_layout(N), N, storage_dtype, k, m, tab, s);
+  return store_field(c, c->fft_out.ptr, f64, transform_layout(N), N, storage_dtype, k, m, tab, s);
 }
 
 int ptk_get_field(ptk_ctx* c, void* u, int out_dtype, void* stream) {

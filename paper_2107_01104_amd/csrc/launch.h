@@ -57,12 +57,8 @@ struct SrcLayout {
   int64_t cs, ns, rs, ps;
 };
 inline SrcLayout interleaved_layout(int64_t N) { return SrcLayout{1, 3, 3 * N, 3 * N * N}; }
-// the three real planes an in-place inverse real transform leaves: x1 rows
-// padded to 2*(N/2+1) elements
-inline SrcLayout transform_layout(int64_t N) {
-  const int64_t r = 2 * (N / 2 + 1);
-  return SrcLayout{r * N * N, 1, r, r * N};
-}
+// the three real planes [a][x3][x2][x1] the inverse real transform writes
+inline SrcLayout transform_layout(int64_t N) { return SrcLayout{N * N * N, 1, N, N * N}; }
 hipError_t launch_sumsq(const void* u, int in_f64, int64_t N, const SrcLayout& l, double* partial, int nblocks,
                         hipStream_t s);
 hipError_t launch_pack(const void* u, int in_f64, const SrcLayout& l, int64_t N, int storage, int I, void* field,
@@ -71,12 +67,12 @@ hipError_t launch_unpack(const void* field, int64_t N, int storage, int I, int64
                          void* out, int out_f64, hipStream_t s);
 
 // spectral.hip: the spectrum in transform order, and the inverse real
-// transform (rocFFT) of three components in place
+// transform (rocFFT) of three components into a separate real buffer
 hipError_t launch_spec_prep(const void* spec, int in_f64, int64_t N, int vorticity, void* out, hipStream_t s);
 struct FftState;
 // (re)creates the plan for (N, precision) if needed; *work_bytes = its work buffer
 int fft_prepare(FftState** st, int64_t N, int f64, size_t* work_bytes, const char** err);
-int fft_run(FftState* st, void* buf, void* work, size_t work_bytes, hipStream_t s, const char** err);
+int fft_run(FftState* st, void* buf, void* out, void* work, size_t work_bytes, hipStream_t s, const char** err);
 void fft_release(FftState* st);
 
 // interp.hip

