@@ -75,8 +75,7 @@ typedef float f32x4a __attribute__((ext_vector_type(4), aligned(4)));
 // Steps 1-3 of Sec. 2.2 for the particle of this lane's group of 4: lane k
 // (k < 3) locates coordinate k, and the group shares cells and offsets.
 // Returns whether this lane's coordinate is inside the domain (lane 3: true).
-__device__ __forceinline__ bool locate_quad(const double* Xp, int k3, int N, double invd, int* c, double* td) {
-  const double x = Xp[k3 < 3 ? k3 : 2];
+__device__ __forceinline__ bool locate_quad_x(double x, int k3, int N, double invd, int* c, double* td) {
   const bool ok = k3 == 3 || in_domain(x);
   int cc;
   double tt;
@@ -89,6 +88,11 @@ __device__ __forceinline__ bool locate_quad(const double* Xp, int k3, int N, dou
   PTK_Q(0) PTK_Q(1) PTK_Q(2)
 #undef PTK_Q
   return ok;
+}
+
+// the same from the particle's row of X: thread k3 loads coordinate min(k3, 2)
+__device__ __forceinline__ bool locate_quad(const double* Xp, int k3, int N, double invd, int* c, double* td) {
+  return locate_quad_x(Xp[k3 < 3 ? k3 : 2], k3, N, invd, c, td);
 }
 
 // One quarter of a particle's 4 x 4 x 4 stencil (the x3 plane k3): its 48
@@ -497,7 +501,9 @@ __global__ __launch_bounds__(NT) void k_update(float* params, float* m, float* v
 // ---------------------------------------------------------------- inference
 // Particles in bin order (the k-th is the caller's orig[k]), 64 per chunk;
 // every workgroup keeps its layer weights in registers and walks a range of
-// chunks.
+// chunks.  The row index and coordinate of the next chunk's particles are
+// loaded while the current chunk runs, so a chunk waits for its stencil
+// loads only, not for the index -> position -> stencil chain.
 __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X, int64_t n, const uint32_t* orig,
                                                  const float* params, const uint16_t* w1b, const uint16_t* w2b,
                                                  float* out, int* flag) {
@@ -507,6 +513,7 @@ __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X
   __shared__ __attribute__((aligned(16))) float sW3[NO * NH];
   __shared__ float sU[ROWS * NO];
   __shared__ float sB3[NO];
+  __shared__ uint32_t sOrig[ROWS];  // the chunk's rows of X (caller indices)
   uint16_t* sX = (uint16_t*)lds;
   float* sH2 = (float*)lds;
   uint16_t* sH1 = (uint16_t*)(lds + RX);
@@ -527,13 +534,29 @@ __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X
   const int64_t bid = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   const int64_t per_block = (nchunks + gridDim.x - 1) / gridDim.x;
   const int64_t ch_end = min(nchunks, (bid + 1) * per_block);
-  for (int64_t ch = bid * per_block; ch < ch_end; ++ch) {
+  const int64_t ch0 = bid * per_block;
+  const int kx = (t & 3) < 3 ? (t & 3) : 2;  // the coordinate this thread loads
+  // row of X of this thread's particle in chunk ch (clamped to the last particle)
+  auto xrow = [&](int64_t ch) -> uint32_t {
+    const int64_t p = min(ch * ROWS + (t >> 2), n - 1);
+    return orig ? orig[p] : (uint32_t)p;
+  };
+  uint32_t oi_c = 0, oi_n = 0;
+  double x_c = 0.0;
+  if (ch0 < ch_end) {
+    oi_c = xrow(ch0);
+    x_c = X[3 * (int64_t)oi_c + kx];
+    oi_n = xrow(min(ch0 + 1, ch_end - 1));
+  }
+  for (int64_t ch = ch0; ch < ch_end; ++ch) {
     const int pi = t >> 2, k3 = t & 3;
-    const int64_t p = min(ch * ROWS + pi, n - 1);
     const bool active = ch * ROWS + pi < n;
+    // the next chunk's coordinate and the row index of the one after it
+    const double x_n = X[3 * (int64_t)oi_n + kx];
+    const uint32_t oi_nn = xrow(min(ch + 2, ch_end - 1));
     int c[3];
     double td[3];
-    const bool ok = locate_quad(X + 3 * (int64_t)(orig ? orig[p] : (uint32_t)p), k3, f.N, f.invd, c, td);
+    const bool ok = locate_quad_x(x_c, k3, f.N, f.invd, c, td);
     if (active && !ok) atomicOr(flag, 1);
     uint32_t fe[24];
     float u[3];
@@ -549,6 +572,7 @@ __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X
       sU[pi * NO] = u[0];
       sU[pi * NO + 1] = u[1];
       sU[pi * NO + 2] = u[2];
+      sOrig[pi] = oi_c;
     } else if (k3 == 1) {
 #pragma unroll
       for (int k = NF; k < PX; ++k) row[k] = 0;
@@ -559,9 +583,12 @@ __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X
       const int r = t / 3, a = t % 3;
       const int64_t q = ch * ROWS + r;
       const float y = output_layer(sH2, sW3, sB3, t);
-      if (q < n) out[3 * (int64_t)(orig ? orig[q] : (uint32_t)q) + a] = sU[r * NO + a] + y;
+      if (q < n) out[3 * (int64_t)sOrig[r] + a] = sU[r * NO + a] + y;
     }
-    __syncthreads();  // h2 and sU are read before the next chunk overwrites them
+    __syncthreads();  // h2, sU and sOrig are read before the next chunk overwrites them
+    oi_c = oi_n;
+    x_c = x_n;
+    oi_n = oi_nn;
   }
 }
 
