@@ -692,7 +692,7 @@ int adv_load(ptk_ctx* c, const double* X, int64_t Np, const void* rhs_hist, int 
 // nsteps steps of the loaded state on the current field.  With final_X (the
 // one-shot form) the last step writes the positions, and the history to
 // final_hist, straight to the caller's order and skips its re-binning, which
-// leaves no loaded state; otherwise every step re-binns and the state stays
+// leaves no loaded state; otherwise every step re-bins and the state stays
 // loaded.  grad_out: the last step's velocity gradient, caller order.
 int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hipStream_t s, double* final_X,
               void* final_hist) {
