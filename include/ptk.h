@@ -9,7 +9,11 @@
  * enumerated steps and Eq. "triple_sum"), its gradient through derivative
  * kernels, and the tracer ODE dX/dt = u(X) (Eq. "tracers") advanced with
  * Euler, Heun or Adams-Bashforth of order 2 to 4 using a per-particle rhs
- * history (Sec. 2.2; Sec. 3.3.1 "Particle data structure").
+ * history (Sec. 2.2; Sec. 3.3.1 "Particle data structure").  Beside it: the
+ * field set from the solver's spectral state (velocity, or vorticity through
+ * the Biot-Savart law of Sec. 2.1; the extra inverse transform of Sec. 4.2),
+ * particles kept in the library across steps of a changing field, reduced
+ * precision field storage, and a learned correction form.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
