@@ -21,9 +21,9 @@
  * j*delta.  Field layout u[x3][x2][x1][a]: x1 fastest, the 3 components
  * fastest within a node (Sec. 2.2 "array of vectorial field values", with the
  * paper's x3-slab convention, Sec. 3.2).  Positions X[p][3] = (x1, x2, x3) in
- * binary64 with |x| < 2^50 (they are wrapped modulo 2*pi; beyond 2^50 the
- * binary64 wrap is no longer exact enough and such positions, like NaN and
- * infinities, are reported as PTK_EDOMAIN).  Gradients
+ * binary64 with |x| < 2^50 (they are reduced modulo 2*pi wherever the field
+ * is evaluated; beyond 2^50 the binary64 reduction is no longer exact enough
+ * and such positions, like NaN and infinities, are reported as PTK_EDOMAIN).  Gradients
  * grad[p][a][b] = d u_a / d x_b.
  *
  * Pointers named as device pointers must be device memory of the context's
@@ -69,7 +69,11 @@ enum {
   PTK_ENOMEM = -3,        /* device allocation failed (or the test byte cap) */
   PTK_EHIP = -4,          /* a HIP runtime call failed */
   PTK_EDOMAIN = -5,       /* a position was NaN, infinite or |x| >= 2^50 */
-  PTK_EUNSUPPORTED = -6   /* valid but unsupported request (e.g. odd I) */
+  PTK_EUNSUPPORTED = -6,  /* valid but unsupported request (e.g. odd I) */
+  PTK_EINTERNAL = -7      /* an internal consistency check failed (a scratch
+                             buffer smaller than a launch needs, or a particle
+                             outside the tile its bin names); nothing was
+                             written out of bounds */
 };
 
 /* Interpolation kernel: family, points per direction I (even; 4, 6 or 8 here)
@@ -186,14 +190,16 @@ int ptk_interpolate_gradient(ptk_ctx *ctx, const double *X, int64_t Np, void *u_
 
 /* Advance tracers dX/dt = u(X) (Eq. "tracers") by nsteps steps of dt in the
  * frozen field.
- * X: device [Np][3] binary64, in/out; positions are returned wrapped to
- *    [0, 2*pi).
- * scheme PTK_EULER: X <- W(X + dt u(X)).
- * scheme PTK_HEUN:  k1 = u(X); Xs = W(X + dt k1); k2 = u(Xs);
- *                   X <- W(X + (0.5 dt)(k1 + k2)).
+ * X: device [Np][3] binary64, in/out.  The state is the position itself,
+ *    not wrapped: the reduction modulo 2*pi is step 1 of each interpolation
+ *    (Sec. 2.2), so a returned trajectory keeps its crossings of the periodic
+ *    faces (|x| must stay below 2^50).
+ * scheme PTK_EULER: X <- X + dt u(X).
+ * scheme PTK_HEUN:  k1 = u(X); Xs = X + dt k1; k2 = u(Xs);
+ *                   X <- X + (0.5 dt)(k1 + k2).
  * schemes PTK_AB2, PTK_AB3, PTK_AB4 (Adams-Bashforth of order k = 2, 3, 4,
  *    the paper's multi-step integration, Sec. 2.2):
- *      X <- W(X + dt (b_0 u_n + b_1 u_{n-1} + ... + b_{k-1} u_{n-k+1})),
+ *      X <- X + dt (b_0 u_n + b_1 u_{n-1} + ... + b_{k-1} u_{n-k+1}),
  *    b = (3/2, -1/2), (23/12, -16/12, 5/12), (55/24, -59/24, 37/24, -9/24),
  *    summed in that order; while fewer than k-1 past velocities are stored the
  *    step uses the highest order they allow (Euler first).  rhs_hist: device
@@ -201,7 +207,7 @@ int ptk_interpolate_gradient(ptk_ctx *ctx, const double *X, int64_t Np, void *u_
  *    for F64 storage, else FP32), in the order of X; *hist_len (host, 0..k)
  *    says how many entries are valid and is updated, so a run can resume.
  *    rhs_hist/hist_len may be NULL for Euler and Heun.
- * W is the wrap of ptk_locate; every update is separately rounded binary64.
+ * Every update is separately rounded binary64.
  * grad_out: device [Np][3][3] (binary64 for F64 storage, else FP32) or NULL;
  *    if given, every step also evaluates the gradient at its start position,
  *    and on return grad_out holds the one of the last step.
@@ -227,8 +233,8 @@ int ptk_advance_particles(ptk_ctx *ctx, double *X, int64_t Np, void *rhs_hist, i
  * ptk_advance_particles or a new load replaces it.  ptk_interpolate and the
  * learned-form calls leave it alone.
  *
- * ptk_particles_load: X device [Np][3] binary64 (any real values; wrapped like
- *    ptk_locate); hist_depth 0 (no history: Euler, Heun) or the
+ * ptk_particles_load: X device [Np][3] binary64 (any real values with
+ *    |x| < 2^50, kept as they are; the cells come from ptk_locate's reduction); hist_depth 0 (no history: Euler, Heun) or the
  *    Adams-Bashforth order 2..4 the history is for; rhs_hist device
  *    [hist_depth][Np][3] of the current storage's velocity type, caller order,
  *    its first hist_len (0..hist_depth) entries valid (may be NULL when
@@ -355,6 +361,13 @@ int ptk_learned_train(ptk_ctx *ctx, const uint16_t *feat, const float *target, i
  * (it reads the audit back). */
 int ptk_interpolate_learned(ptk_ctx *ctx, const double *X, int64_t Np, float *out, double audit_frac,
                             double tol_rel_rms, double *audit_rms, int *fell_back, void *stream);
+
+/* Host-only self-test of the library's internal checks (the scratch capacity
+ * guard that every launch sequence passes before it writes scratch, the byte
+ * cap of PTK_TEST_MAX_BYTES, the decoding of the device status word).  Needs
+ * no device and no context; returns PTK_OK when every check behaves as
+ * documented, PTK_EINTERNAL otherwise. */
+int ptk_selftest(void);
 
 #ifdef __cplusplus
 }

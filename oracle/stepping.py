@@ -6,10 +6,12 @@ multi-step Adams-Bashforth integration with an rhs history kept per particle
 
 Readings (the paper gives neither the order nor the start-up):
 
-* The field is frozen (no fluid solver runs beside the particles).
-* Euler:  X <- W(X + dt*u(X)).
-* Heun:   k1 = u(X); Xs = W(X + dt*k1); k2 = u(Xs); X <- W(X + (dt/2)*(k1 + k2)).
-* AB2:    X <- W(X + dt*(3/2*u_n - 1/2*u_{n-1})) with an Euler first step; the
+* The field is frozen (no fluid solver runs beside the particles); the
+  two-field Heun step (``heun_two_fields``) takes each stage's velocity from
+  the field of that stage's time.
+* Euler:  X <- X + dt*u(X).
+* Heun:   k1 = u(X); Xs = X + dt*k1; k2 = u(Xs); X <- X + (dt/2)*(k1 + k2).
+* AB2:    X <- X + dt*(3/2*u_n - 1/2*u_{n-1}) with an Euler first step; the
   history holds [u_n, u_{n-1}] and its length (0, 1 or 2) so a run can resume.
 * AB3, AB4 (the paper's "multi-step" read as orders up to 4): the textbook
   Adams-Bashforth weights (from integrating the interpolant of the last k
@@ -18,7 +20,10 @@ Readings (the paper gives neither the order nor the start-up):
   While the history is shorter, the step uses the highest order it allows
   (Euler, then AB2, AB3).  The history holds the last k velocities, most
   recent first, and its length (0..k).
-* W is the periodic wrap of ``geometry.wrap``: the state is stored wrapped.
+* The state X is the particle's position itself, not wrapped: the reduction
+  modulo 2*pi is step 1 of the interpolation (Sec. 2.2), applied where the
+  field is evaluated, so a trajectory keeps its crossings of the periodic
+  faces (the displacement statistics the method is for need them).
 * Every operation is a separately rounded binary64 operation in the order
   written (``dt/2`` is formed once as 0.5*dt).
 * When a gradient is requested it is evaluated at each step's start position
@@ -29,8 +34,6 @@ from __future__ import annotations
 
 import numpy as np
 
-from .geometry import wrap
-
 EULER, HEUN, AB2, AB3, AB4 = 1, 2, 3, 4, 5
 
 # Adams-Bashforth weights b_j of u_{n-j}, by order
@@ -40,20 +43,20 @@ AB_ORDER = {AB2: 2, AB3: 3, AB4: 4}
 
 
 def euler_update(X, dt, u):
-    return wrap(np.add(X, np.multiply(dt, u)))
+    return np.add(X, np.multiply(dt, u))
 
 
 def heun_predict(X, dt, k1):
-    return wrap(np.add(X, np.multiply(dt, k1)))
+    return np.add(X, np.multiply(dt, k1))
 
 
 def heun_correct(X, dt, k1, k2):
-    return wrap(np.add(X, np.multiply(0.5 * dt, np.add(k1, k2))))
+    return np.add(X, np.multiply(0.5 * dt, np.add(k1, k2)))
 
 
 def ab2_update(X, dt, u_n, u_prev):
     inc = np.subtract(np.multiply(1.5, u_n), np.multiply(0.5, u_prev))
-    return wrap(np.add(X, np.multiply(dt, inc)))
+    return np.add(X, np.multiply(dt, inc))
 
 
 def ab_update(X, dt, us, order: int):
@@ -62,7 +65,7 @@ def ab_update(X, dt, us, order: int):
     inc = np.multiply(b[0], us[0])
     for j in range(1, order):
         inc = np.add(inc, np.multiply(b[j], us[j]))
-    return wrap(np.add(X, np.multiply(dt, inc)))
+    return np.add(X, np.multiply(dt, inc))
 
 
 def advance(X, velocity, scheme: int, dt: float, nsteps: int, hist=None, hist_len: int = 0,
@@ -109,3 +112,25 @@ def advance(X, velocity, scheme: int, dt: float, nsteps: int, hist=None, hist_le
         else:
             raise ValueError("unknown scheme")
     return X, hist, hist_len, grad_last
+
+
+def heun_two_fields(X, vel_now, vel_next, dt: float, gradient_now=None):
+    """One Heun step in a field that changes during the step (Eq. "tracers"
+    with u = u(x, t)): the first stage takes the velocity of the field at the
+    step's start time, the second that of the field at its end time,
+
+        k1 = u(X, t_n);  Xs = X + dt*k1;  k2 = u(Xs, t_n + dt);
+        X <- X + (dt/2)*(k1 + k2).
+
+    ``vel_now(X)`` and ``vel_next(X)`` evaluate the two fields;
+    ``gradient_now(X) -> (u, grad)`` (optional) replaces vel_now for the first
+    stage and its gradient is returned.  Returns (X, grad or None)."""
+    X = np.array(X, dtype=np.float64)
+    grad = None
+    if gradient_now is not None:
+        k1, grad = gradient_now(X)
+    else:
+        k1 = vel_now(X)
+    Xs = heun_predict(X, dt, k1)
+    k2 = vel_next(Xs)
+    return heun_correct(X, dt, k1, k2), grad

@@ -60,6 +60,37 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_host_sanitized(driver: str, out_dir: str) -> str:
+    """Build of the library's sources with AddressSanitizer and
+    UndefinedBehaviorSanitizer on the host code only (the device code is built
+    as usual, without them), linked with the C++ `driver` into an executable;
+    returns its path.  The driver is meant to run without a GPU."""
+    os.makedirs(out_dir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+    flags = ["-O1", "-g", "-std=c++17", "-fPIC", "-ffp-contract=off", f"-I{INCLUDE}", f"-I{CSRC}"]
+
+    def one(src_path: str) -> str:
+        obj = os.path.join(out_dir, os.path.basename(src_path) + ".o")
+        cmd = [HIPCC, "-x", "hip", *DEVICE, *san, *flags, "-c", src_path, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    srcs = [os.path.join(CSRC, f) for f in SOURCES] + [driver]
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(one, srcs))
+    exe = os.path.join(out_dir, "host_driver")
+    clang = os.path.join(os.path.dirname(HIPCC), "..", "llvm", "bin", "clang++")
+    cmd = [clang, "-fsanitize=address,undefined", "-o", exe, *objs, "-L/opt/rocm/lib", "-lamdhip64", "-lrocfft",
+           "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return exe
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

@@ -52,32 +52,61 @@ int hip_fail(ptk_ctx* c, hipError_t e, const char* what) {
     if (r_ != PTK_OK) return r_; \
   } while (0)
 
-// Make `b` hold at least `bytes`.  Growing waits for the device first, so no
-// enqueued kernel still uses the old allocation when it is freed.
+// Make `b` hold at least `bytes`.  The new block is allocated beside the old
+// one first, so a failed growth leaves the old block (and its contents)
+// intact; only when both do not fit is the old block released before a second
+// attempt, and a failure then leaves `b` empty (callers whose state lives in
+// the buffer, the stored field, withdraw that state before growing it).
+// Releasing waits for the device, so no enqueued kernel still uses the old
+// allocation when it is freed.
+bool within_cap(const ptk_ctx* c, size_t extra) {
+  return !c->byte_cap || c->bytes_in_use + extra <= c->byte_cap;
+}
+
+void* try_malloc(size_t bytes) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void drop(ptk_ctx* c, DevBuf& b) {
+  if (!b.ptr) return;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(b.ptr);
+  c->bytes_in_use -= b.cap;
+  b.ptr = nullptr;
+  b.cap = 0;
+}
+
 int ensure(ptk_ctx* c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return PTK_OK;
   size_t want = bytes + bytes / 8;
   want = (want + 255) & ~(size_t)255;
-  if (c->byte_cap && c->bytes_in_use - b.cap + want > c->byte_cap)
-    return fail(c, PTK_ENOMEM, "device scratch would exceed PTK_TEST_MAX_BYTES");
-  if (b.ptr) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(b.ptr);
-    c->bytes_in_use -= b.cap;
-    b.ptr = nullptr;
-    b.cap = 0;
+  void* p = within_cap(c, want) ? try_malloc(want) : nullptr;
+  if (!p && b.ptr) {
+    drop(c, b);
+    p = within_cap(c, want) ? try_malloc(want) : nullptr;
   }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, want);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(c, PTK_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
-  }
+  if (!p)
+    return fail(c, PTK_ENOMEM,
+                within_cap(c, want) ? "hipMalloc of " + std::to_string(want) + " bytes failed"
+                                    : std::string("device scratch would exceed PTK_TEST_MAX_BYTES"));
+  drop(c, b);
   b.ptr = p;
   b.cap = want;
   c->bytes_in_use += want;
   return PTK_OK;
+}
+
+// Host-side guard of a launch that writes `bytes` into scratch buffer `b`: an
+// undersized buffer is reported as an error instead of being overrun.
+int need(ptk_ctx* c, const DevBuf& b, size_t bytes, const char* what) {
+  if (b.ptr && b.cap >= bytes) return PTK_OK;
+  return fail(c, PTK_EINTERNAL, std::string("scratch buffer too small for ") + what);
 }
 
 void release(DevBuf& b) {
@@ -160,13 +189,19 @@ inline double invd_of(int64_t N) { return (double)N / kL; }
 
 int vel_bytes(const ptk_ctx* c) { return c->storage == PTK_F64 ? 8 : 4; }
 
+int flag_error(ptk_ctx* c, int h) {
+  if (h & kFlagDomain) return fail(c, PTK_EDOMAIN, "a particle position is NaN, infinite or has |x| >= 2^50");
+  if (h & kFlagBinning)
+    return fail(c, PTK_EINTERNAL, "a particle's cell lies outside the tile column or window of its bin");
+  return PTK_OK;
+}
+
 int check_flag(ptk_ctx* c, hipStream_t s) {
   if (!c->check) return PTK_OK;
   int h = 0;
   PTK_HIP(c, hipMemcpyAsync(&h, c->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s), "flag read");
   PTK_HIP(c, hipStreamSynchronize(s), "stream synchronize");
-  if (h) return fail(c, PTK_EDOMAIN, "a particle position is NaN, infinite or has |x| >= 2^50");
-  return PTK_OK;
+  return flag_error(c, h);
 }
 
 // scratch for binning Np particles over n_bins bins
@@ -193,6 +228,34 @@ int ensure_rebin(ptk_ctx* c, int64_t Np, int64_t n_bins) {
   DevBuf* per_bin[] = {&c->aoff, &c->offsets2, &c->rb_in, &c->rb_out, &c->rb_inc};
   for (DevBuf* b : per_bin) PTK_TRY(ensure(c, *b, b4));
   PTK_TRY(ensure(c, c->rb_block, rebin_block_words(Np) * 4));
+  return PTK_OK;
+}
+
+// Host-side checks that the scratch a launch sequence writes is as large as
+// the launches assume (the ensure calls grow it; these catch a growth that a
+// code path forgot, as an error code instead of an out-of-bounds write).
+int check_binning_caps(ptk_ctx* c, int64_t Np, int64_t n_bins) {
+  const size_t n4 = (size_t)Np * 4;
+  PTK_TRY(need(c, c->keys_a, n4, "bin keys"));
+  PTK_TRY(need(c, c->keys_b, n4, "bin keys"));
+  PTK_TRY(need(c, c->vals_a, n4, "sort values"));
+  PTK_TRY(need(c, c->vals_b, n4, "sort values"));
+  const size_t hw = sort_hist_words(Np);
+  PTK_TRY(need(c, c->hist, hw * 4, "sort histograms"));
+  const int64_t scan_max = (int64_t)hw > n_bins + 1 ? (int64_t)hw : n_bins + 1;
+  PTK_TRY(need(c, c->scan_tmp, scan_tmp_words(scan_max) * 4, "scan partials"));
+  PTK_TRY(need(c, c->offsets, (size_t)(n_bins + 1) * 4, "bin offsets"));
+  return PTK_OK;
+}
+
+int check_rebin_caps(ptk_ctx* c, int64_t Np, int64_t n_bins) {
+  const size_t n4 = (size_t)Np * 4, b4 = (size_t)(n_bins + 1) * 4;
+  const DevBuf* per_particle[] = {&c->skeys, &c->skeys2, &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->mo,
+                                  &c->aperm, &c->aperm_p};
+  for (const DevBuf* b : per_particle) PTK_TRY(need(c, *b, n4, "re-binning lists"));
+  const DevBuf* per_bin[] = {&c->aoff, &c->offsets2, &c->rb_in, &c->rb_out, &c->rb_inc};
+  for (const DevBuf* b : per_bin) PTK_TRY(need(c, *b, b4, "re-binning offsets"));
+  PTK_TRY(need(c, c->rb_block, rebin_block_words(Np) * 4, "re-binning block offsets"));
   return PTK_OK;
 }
 
@@ -232,6 +295,7 @@ InterpArgs base_args(const ptk_ctx* c) {
   a.nseg = (a.nw + a.wps - 1) / a.wps;
   a.offsets = (const uint32_t*)c->offsets.ptr;
   a.coef = c->coef.ptr;
+  a.flag = (int*)c->flag.ptr;
   a.scale[0] = c->scale[0];
   a.scale[1] = c->scale[1];
   a.scale[2] = c->scale[2];
@@ -264,6 +328,7 @@ int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* gr
     return PTK_OK;
   }
   PTK_TRY(ensure_binning(c, Np, n_bins));
+  PTK_TRY(check_binning_caps(c, Np, n_bins));
   PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
   {
     Timed t(c, s, PTK_T_KEYS);
@@ -330,6 +395,8 @@ int ensure_partials(ptk_ctx* c, int64_t batch) {
   const int64_t parts = batch / 64;
   PTK_TRY(ensure(c, c->lgpart, (size_t)parts * kLearnedNParams * 4));
   PTK_TRY(ensure(c, c->llpart, (size_t)parts * 4));
+  PTK_TRY(need(c, c->lgpart, (size_t)parts * kLearnedNParams * 4, "gradient partials"));
+  PTK_TRY(need(c, c->llpart, (size_t)parts * 4, "loss partials"));
   return PTK_OK;
 }
 
@@ -445,6 +512,7 @@ int store_field(ptk_ctx* c, const void* u, int in_f64, const SrcLayout& l, int64
   if (storage_dtype == PTK_BF16 || storage_dtype == PTK_F16) {
     const int nblk = 1024;
     PTK_TRY(ensure(c, c->stage, (size_t)nblk * 3 * sizeof(double)));
+    PTK_TRY(need(c, c->stage, (size_t)nblk * 3 * sizeof(double), "sum-of-squares partials"));
     PTK_HIP(c, launch_sumsq(u, in_f64, N, l, (double*)c->stage.ptr, nblk, s), "sum of squares");
     double* part = new (std::nothrow) double[nblk * 3];
     if (!part) return fail(c, PTK_ENOMEM, "host allocation failed");
@@ -467,8 +535,15 @@ int store_field(ptk_ctx* c, const void* u, int in_f64, const SrcLayout& l, int64
     }
     delete[] part;
   }
+  // the stored field is withdrawn while its buffer is replaced and filled: a
+  // failure below leaves the context without a field (PTK_ENOFIELD), never
+  // with a released or half-written one
+  c->has_field = false;
+  c->bin_valid = false;
   PTK_TRY(ensure(c, c->field, field_bytes));
   PTK_TRY(ensure(c, c->coef, sizeof(KernelTables)));
+  PTK_TRY(need(c, c->field, field_bytes, "stored field"));
+  PTK_TRY(need(c, c->coef, sizeof(KernelTables), "coefficient tables"));
   c->tables = tab;
   PTK_HIP(c, hipMemcpyAsync(c->coef.ptr, &c->tables, sizeof(KernelTables), hipMemcpyHostToDevice, s),
           "coefficient upload");
@@ -523,6 +598,9 @@ int ptk_set_field_spectral(ptk_ctx* c, const void* spec, int64_t N, int in_dtype
   PTK_TRY(ensure(c, c->spec, 3 * modes * 2 * rb));
   PTK_TRY(ensure(c, c->fft_out, 3 * (size_t)N * (size_t)N * (size_t)N * rb));
   if (work > 0) PTK_TRY(ensure(c, c->fft_work, work));
+  PTK_TRY(need(c, c->spec, 3 * modes * 2 * rb, "transform input"));
+  PTK_TRY(need(c, c->fft_out, 3 * (size_t)N * (size_t)N * (size_t)N * rb, "transform output"));
+  if (work > 0) PTK_TRY(need(c, c->fft_work, work, "transform work"));
   {
     Timed t(c, s, PTK_T_IFT);
     PTK_HIP(c, launch_spec_prep(spec, f64, N, kind == PTK_SPEC_VORTICITY, c->spec.ptr, s), "spectrum prep");
@@ -643,6 +721,17 @@ int adv_load(ptk_ctx* c, const double* X, int64_t Np, const void* rhs_hist, int 
     PTK_TRY(ensure(c, c->abh[j], v3));
     PTK_TRY(ensure(c, c->abh_b[j], v3));
   }
+  PTK_TRY(check_binning_caps(c, Np, n_bins));
+  PTK_TRY(check_rebin_caps(c, Np, n_bins));
+  PTK_TRY(need(c, c->xs, (size_t)Np * 24, "positions"));
+  PTK_TRY(need(c, c->xn, (size_t)Np * 24, "positions"));
+  PTK_TRY(need(c, c->orig, (size_t)Np * 4, "caller index"));
+  PTK_TRY(need(c, c->orig_b, (size_t)Np * 4, "caller index"));
+  PTK_TRY(need(c, c->k1, v3, "velocities"));
+  for (int j = 0; j < K; ++j) {
+    PTK_TRY(need(c, c->abh[j], v3, "history"));
+    PTK_TRY(need(c, c->abh_b[j], v3, "history"));
+  }
   c->bin_valid = false;  // the sort below reuses the interpolate calls' sort buffers
   uint32_t* keys = (uint32_t*)c->keys_a.ptr;
   int* flag = (int*)c->flag.ptr;
@@ -713,6 +802,23 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
   }
   if (scheme == PTK_HEUN) PTK_TRY(ensure(c, c->k2, v3));
   if (grad_out) PTK_TRY(ensure(c, c->gint, (size_t)Np * 9 * vb));
+  // every buffer the steps below write, by its capacity (the state's
+  // pointers rotate among these buffers)
+  PTK_TRY(check_binning_caps(c, Np, n_bins));
+  PTK_TRY(check_rebin_caps(c, Np, n_bins));
+  {
+    const DevBuf* pos[] = {&c->xs, &c->xn};
+    for (const DevBuf* b : pos) PTK_TRY(need(c, *b, (size_t)Np * 24, "positions"));
+    const DevBuf* idx[] = {&c->orig, &c->orig_b};
+    for (const DevBuf* b : idx) PTK_TRY(need(c, *b, (size_t)Np * 4, "caller index"));
+    PTK_TRY(need(c, c->k1, v3, "velocities"));
+    for (int j = 0; j < st.K; ++j) {
+      PTK_TRY(need(c, c->abh[j], v3, "history"));
+      PTK_TRY(need(c, c->abh_b[j], v3, "history"));
+    }
+    if (scheme == PTK_HEUN) PTK_TRY(need(c, c->k2, v3, "predictor velocities"));
+    if (grad_out) PTK_TRY(need(c, c->gint, (size_t)Np * 9 * vb, "gradients"));
+  }
 
   uint32_t* keys = (uint32_t*)c->keys_a.ptr;
   int* flag = (int*)c->flag.ptr;
@@ -1008,6 +1114,7 @@ int ptk_learned_make_pairs(ptk_ctx* c, const double* X, int64_t Np, uint16_t* fe
   hipStream_t s = S(stream);
   if (target) {
     PTK_TRY(ensure(c, c->lwide, (size_t)Np * 12));
+    PTK_TRY(need(c, c->lwide, (size_t)Np * 12, "wide-kernel values"));
     PTK_TRY(interp_common(c, X, Np, c->lwide.ptr, nullptr, PTK_F32, stream));
   }
   PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
@@ -1194,7 +1301,7 @@ int ptk_interpolate_learned(ptk_ctx* c, const double* X, int64_t Np, float* out,
     int h = 0;
     PTK_HIP(c, hipMemcpyAsync(&h, c->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s), "flag read");
     PTK_HIP(c, hipStreamSynchronize(s), "stream synchronize");
-    if (h) return fail(c, PTK_EDOMAIN, "a particle position is NaN, infinite or has |x| >= 2^50");
+    PTK_TRY(flag_error(c, h));
   }
   // audit with the wide kernel at particles 0, k, 2k, ...
   int64_t k = (int64_t)std::llround(1.0 / audit_frac);
@@ -1203,6 +1310,9 @@ int ptk_interpolate_learned(ptk_ctx* c, const double* X, int64_t Np, float* out,
   PTK_TRY(ensure(c, c->laudit_x, (size_t)na * 24));
   PTK_TRY(ensure(c, c->laudit_u, (size_t)na * 12));
   PTK_TRY(ensure(c, c->laudit_sums, 16));
+  PTK_TRY(need(c, c->laudit_x, (size_t)na * 24, "audit positions"));
+  PTK_TRY(need(c, c->laudit_u, (size_t)na * 12, "audit values"));
+  PTK_TRY(need(c, c->laudit_sums, 16, "audit sums"));
   PTK_HIP(c, launch_stride_gather(X, k, na, (double*)c->laudit_x.ptr, s), "audit positions");
   PTK_TRY(interp_common(c, (const double*)c->laudit_x.ptr, na, c->laudit_u.ptr, nullptr, PTK_F32, stream));
   PTK_HIP(c, launch_audit(out, k, na, (const float*)c->laudit_u.ptr, (double*)c->laudit_sums.ptr, s), "audit");
@@ -1216,6 +1326,51 @@ int ptk_interpolate_learned(ptk_ctx* c, const double* X, int64_t Np, float* out,
     *fell_back = 1;
   }
   return PTK_OK;
+}
+
+int ptk_selftest(void) {
+  // A context that never touches a device: its buffers hold no allocation
+  // (growth is refused by the byte cap before hipMalloc is reached) or a
+  // placeholder address that nothing dereferences.
+  ptk_ctx c;
+  char placeholder[64];
+  int bad = 0;
+  auto expect = [&](bool ok) { bad += ok ? 0 : 1; };
+  // capacity guard: too small, absent, exact, larger
+  DevBuf b;
+  b.ptr = placeholder;
+  b.cap = 1024;
+  expect(need(&c, b, 1025, "self-test") == PTK_EINTERNAL && !c.err.empty());
+  expect(need(&c, b, 1024, "self-test") == PTK_OK);
+  expect(need(&c, b, 16, "self-test") == PTK_OK);
+  DevBuf none;
+  expect(need(&c, none, 1, "self-test") == PTK_EINTERNAL);
+  // growth refused by the byte cap leaves an empty buffer empty and reports
+  // PTK_ENOMEM without any runtime call
+  c.byte_cap = 4096;
+  c.bytes_in_use = 0;
+  DevBuf grow;
+  expect(ensure(&c, grow, 1 << 20) == PTK_ENOMEM && grow.ptr == nullptr && grow.cap == 0);
+  expect(c.bytes_in_use == 0);
+  // status bits of the device flag word
+  expect(flag_error(&c, 0) == PTK_OK);
+  expect(flag_error(&c, kFlagDomain) == PTK_EDOMAIN);
+  expect(flag_error(&c, kFlagBinning) == PTK_EINTERNAL);
+  expect(flag_error(&c, kFlagDomain | kFlagBinning) == PTK_EDOMAIN);
+  // binning and advance buffer checks on a context whose buffers are short
+  DevBuf* bufs[] = {&c.keys_a, &c.keys_b, &c.vals_a, &c.vals_b, &c.hist, &c.scan_tmp, &c.offsets};
+  for (DevBuf* d : bufs) {
+    d->ptr = placeholder;
+    d->cap = (size_t)1 << 30;
+  }
+  expect(check_binning_caps(&c, 1000, 5000) == PTK_OK);
+  c.offsets.cap = 4 * 5000;  // one word short of n_bins + 1
+  expect(check_binning_caps(&c, 1000, 5000) == PTK_EINTERNAL);
+  c.offsets.cap = 4 * 5001;
+  c.keys_b.cap = 3999;
+  expect(check_binning_caps(&c, 1000, 5000) == PTK_EINTERNAL);
+  for (DevBuf* d : bufs) *d = DevBuf();  // nothing for the destructor-free context to release
+  return bad == 0 ? PTK_OK : PTK_EINTERNAL;
 }
 
 }  // extern "C"

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_keys(const double* __restrict__ X, int6
   if (i >= n) return;
   double x1 = X[3 * i], x2 = X[3 * i + 1], x3 = X[3 * i + 2];
   if (!in_domain3(x1, x2, x3)) {
-    flag[0] = 1;
+    atomicOr(flag, kFlagDomain);
     keys[i] = 0;
     return;
   }
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_locate(const double* __restrict__ X, in
   if (i >= n3) return;
   double x = X[i];
   if (!in_domain(x)) {
-    flag[0] = 1;
+    atomicOr(flag, kFlagDomain);
     cell[i] = 0;
     if (off) off[i] = 0.0;
     return;

@@ -563,13 +563,24 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
       int c;
       double td;
       locate(xv, N, invd, &c, &td);
+      // the cell must lie in the bin's tile column and window (binning and
+      // kernel locate alike); a particle outside them is reported, and its
+      // record clamped so that every LDS read stays inside the ring
       int lc;
-      if (ax == 0)
-        lc = min(max(c - (int)x0, 0), T - 1);
-      else if (ax == 1)
-        lc = min(max(c - (int)y0, 0), T - 1);
-      else
+      bool inside;
+      if (ax == 0) {
+        lc = c - (int)x0;
+        inside = lc >= 0 && lc < T;
+        lc = min(max(lc, 0), T - 1);
+      } else if (ax == 1) {
+        lc = c - (int)y0;
+        inside = lc >= 0 && lc < T;
+        lc = min(max(lc, 0), T - 1);
+      } else {
+        inside = (int64_t)c >= W * wr && (int64_t)c < W * wr + W;
         lc = (int)min(max((int64_t)c, W * wr), W * wr + W - 1);
+      }
+      if (!inside) atomicOr(a.flag, kFlagBinning);
       unsigned char* rp = recs + pi * RECB;
       if constexpr (sizeof(V) == 8)
         ((double*)rp)[ax] = td;

@@ -8,6 +8,11 @@
 
 namespace ptk {
 
+// Bits of the device status word the kernels raise (atomicOr) and the host
+// reads at the end of a call.
+constexpr int kFlagDomain = 1;   // a position was NaN, infinite or |x| >= 2^50
+constexpr int kFlagBinning = 2;  // a particle's cell lies outside its bin's tile column or window
+
 // Bin geometry: tile columns of T x T cells in (x1, x2), ntx = ceil(N/T) per
 // axis, each cut along x3 into nw = ceil(N/W) windows of W cell layers.
 struct BinGeom {
@@ -94,6 +99,7 @@ struct InterpArgs {
   int out_f64;
   const void* coef;         // device KernelTables
   float scale[3];
+  int* flag;                // device status word (kFlag* bits)
 };
 hipError_t launch_interp(int storage, int I, const InterpArgs& a, hipStream_t s);
 

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(NT) void k_pairs(LearnedField f, const double* X, i
   int c[3];
   double td[3];
   const bool ok = locate_quad(X + 3 * p, k3, f.N, f.invd, c, td);
-  if (active && !ok) atomicOr(flag, 1);
+  if (active && !ok) atomicOr(flag, kFlagDomain);
   uint32_t fe[24];
   float u[3];
   stencil_plane(f, c, td, k3, fe, u);
@@ -557,7 +557,7 @@ __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X
     int c[3];
     double td[3];
     const bool ok = locate_quad_x(x_c, k3, f.N, f.invd, c, td);
-    if (active && !ok) atomicOr(flag, 1);
+    if (active && !ok) atomicOr(flag, kFlagDomain);
     uint32_t fe[24];
     float u[3];
     stencil_plane(f, c, td, k3, fe, u);

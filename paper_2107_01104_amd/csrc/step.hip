@@ -1,6 +1,9 @@
-// Position updates of the tracer ODE dX/dt = u(X) (Eq. "tracers") with the
-// periodic wrap, fused with the bin key of the new position so that the next
-// re-binning needs no separate key pass.  Velocities come in as FP64 or FP32
+// Position updates of the tracer ODE dX/dt = u(X) (Eq. "tracers"), fused with
+// the bin key of the new position so that the next re-binning needs no
+// separate key pass.  The state is the position itself, not wrapped: the
+// reduction modulo 2*pi is step 1 of every interpolation (Sec. 2.2), here only
+// inside the key's cell location, so trajectories keep their crossings of
+// the periodic faces.  Velocities come in as FP64 or FP32
 // and are widened to FP64; every operation is a separately rounded binary64
 // operation in the order written (the file is built with -ffp-contract=off).
 //   kEulerOrPredict: X + dt*k0              (Euler step, Heun predictor)
@@ -93,9 +96,10 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(int kind, const double* 
         xn = 0.0;
       }
       double t;
-      sx[e] = locate(xn, N, invd, &c[d], &t);  // only this thread touches its three entries
+      (void)locate(xn, N, invd, &c[d], &t);
+      sx[e] = xn;  // only this thread touches its three entries
     }
-    if (!ok) flag[0] = 1;
+    if (!ok) atomicOr(flag, kFlagDomain);
     keys[base + p] = bin_key(c[0], c[1], c[2], g);
   }
   __syncthreads();

@@ -22,7 +22,7 @@ F64, F32, BF16, F16 = 0, 1, 2, 3
 LAGRANGE, SPLINE = 0, 1
 EULER, HEUN, AB2, AB3, AB4 = 1, 2, 3, 4, 5
 AB_ORDER = {AB2: 2, AB3: 3, AB4: 4}
-OK, EINVAL, ENOFIELD, ENOMEM, EHIP, EDOMAIN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOFIELD, ENOMEM, EHIP, EDOMAIN, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 TIMERS = ["interp", "interp_grad", "sort", "keys", "update", "permute", "learned", "ift"]
 SPEC_VELOCITY, SPEC_VORTICITY = 0, 1
 LEARNED_NFEAT, LEARNED_FEAT_PITCH, LEARNED_NPARAMS = 195, 200, 41987
@@ -33,7 +33,7 @@ EXPORTS = ["ptk_kernel_table", "ptk_create", "ptk_destroy", "ptk_last_error", "p
            "ptk_locate", "ptk_interpolate", "ptk_interpolate_gradient", "ptk_advance_particles",
            "ptk_binning_info", "ptk_get_binning", "ptk_timing_enable", "ptk_timing_read",
            "ptk_learned_make_pairs", "ptk_learned_set_params", "ptk_learned_get_params", "ptk_learned_loss_grad",
-           "ptk_learned_train", "ptk_interpolate_learned"]
+           "ptk_learned_train", "ptk_interpolate_learned", "ptk_selftest"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2107_01104_amd/build.py (or "
@@ -81,6 +81,7 @@ lib.ptk_learned_loss_grad.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp]
 lib.ptk_learned_train.argtypes = [_vp, _vp, _vp, _i64, ctypes.POINTER(ptk_train_config), _vp, _vp]
 lib.ptk_interpolate_learned.argtypes = [_vp, _vp, _i64, _vp, _dbl, _dbl, ctypes.POINTER(_dbl),
                                         ctypes.POINTER(_int), _vp]
+lib.ptk_selftest.argtypes = []
 for _name in EXPORTS:
     if _name not in ("ptk_destroy", "ptk_last_error"):
         getattr(lib, _name).restype = _int
@@ -106,6 +107,7 @@ ptk_learned_get_params = lib.ptk_learned_get_params
 ptk_learned_loss_grad = lib.ptk_learned_loss_grad
 ptk_learned_train = lib.ptk_learned_train
 ptk_interpolate_learned = lib.ptk_interpolate_learned
+ptk_selftest = lib.ptk_selftest
 
 
 def kernel_table(family: int, I: int, m: int = 0):
@@ -371,7 +373,7 @@ class Context:
                                           _stream(self.device)))
         return curve[:steps]
 
-    def interpolate_learned(self, X: torch.Tensor, audit_frac: float = 1e-3, tol_rel_rms: float = float("inf"),
+    def interpolate_learned(self, X: torch.Tensor, audit_frac: float = 1e-3, tol_rel_rms: float = 1e-4,
                             out=None):
         """(out float32 [Np, 3], audit_rms, fell_back)."""
         _dev_tensor(X, torch.float64, (3,), "X")

@@ -5,9 +5,10 @@ with dt = 2e-3 and re-binning every step.
 The oracle computes a seeded sample of particles one by one: values and
 gradients, and the first two steps (Euler start-up, then AB2) of the sample's
 trajectories on the same stored FP32 values.  The 100-step run is checked by
-properties that hold at any size: positions stay in [0, 2 pi), the history
-depth is 2, and 100 steps equal 40 + 60 steps resumed from the returned state
-bit for bit.  Bars as in test_gpu_parity (FP32 sums within 64 * 2^-24 * A).
+properties that hold at any size: the history depth is 2, 100 steps equal
+40 + 60 steps resumed from the returned state bit for bit, and every particle
+moved by at most 100 dt max|u| (positions are not wrapped).  Bars as in
+test_gpu_parity (FP32 sums: relative RMS 1e-6 and relative max 1e-5).
 """
 import sys
 
@@ -19,6 +20,8 @@ from oracle import geometry, interp, stepping
 from oracle import kernels as K
 from synthetic import fields, particles
 
+from bars import check_f32
+
 pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda", 0)
@@ -26,21 +29,11 @@ L = geometry.L
 N, NP, NS = 256, 10_000_000, 2048
 DT = 2e-3
 FAM, I, M = K.SPLINE, 6, 1
-F32_BOUND = 64 * 2.0 ** -24
 
 
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def within(gpu, ref, absum):
-    return bool(np.all(np.abs(gpu - ref) <= F32_BOUND * absum))
-
-
-def circ(a, b):
-    d = np.abs(a - b) % L
-    return np.minimum(d, L - d)
 
 
 @pytest.fixture(scope="module")
@@ -72,10 +65,11 @@ def test_values_and_gradients_sampled(ptk, setup):
     uv, g = ctx.interpolate_gradient(X, out_dtype=torch.float32)
     val = ctx.interpolate(X)
     ru, rg = interp.interp_vec(uh, Xs, FAM, I, M, gradient=True)
-    au, ag = interp.interp_vec(uh, Xs, FAM, I, M, gradient=True, absolute=True)
-    assert within(uv[idx_d].cpu().numpy().astype(np.float64), ru, au)
-    assert within(g[idx_d].cpu().numpy().astype(np.float64), rg, ag)
-    assert within(val[idx_d].cpu().numpy().astype(np.float64), ru, au)
+    ev = check_f32(uv[idx_d].cpu().numpy(), ru, what="value")
+    eg = check_f32(g[idx_d].cpu().numpy(), rg, what="gradient")
+    e1 = check_f32(val[idx_d].cpu().numpy(), ru, what="value kernel")
+    say(f"  rel rms / max: value {ev[0]:.2e} / {ev[1]:.2e}, gradient {eg[0]:.2e} / {eg[1]:.2e}, "
+        f"value kernel {e1[0]:.2e} / {e1[1]:.2e}")
 
 
 def test_ab2_first_steps_sampled(ptk, setup):
@@ -96,18 +90,16 @@ def test_ab2_first_steps_sampled(ptk, setup):
     vel = lambda Y: interp.interp_vec(uh, Y, FAM, I, M)
     Xo, ho, hlo, _ = stepping.advance(Xs, vel, stepping.AB2, DT, 2)
     assert hlo == 2
-    X1o = stepping.advance(Xs, vel, stepping.AB2, DT, 1)[0]
-    a0 = interp.interp_vec(uh, Xs, FAM, I, M, absolute=True).max(axis=1)
-    a1 = interp.interp_vec(uh, X1o, FAM, I, M, absolute=True).max(axis=1)
-    # step 1: dt * e0; step 2: dt * (1.5 e1 + 0.5 e0)
-    tol = DT * F32_BOUND * (1.5 * a0 + 1.5 * a1) * 1.1 + 8 * np.spacing(L)
-    d = circ(X2, Xo).max(axis=1)
-    say(f"  max position difference {d.max():.3e} (tolerance min {tol.min():.3e})")
+    # each velocity is within the value bar, 1e-5 rms(u):
+    # step 1 moves by dt e0, step 2 by dt (1.5 e1 + 0.5 e0)
+    urms = float(np.sqrt(np.mean(ho ** 2)))
+    tol = DT * 1e-5 * urms * 3.0 * 1.1 + 8 * np.spacing(L)
+    d = np.abs(X2 - Xo).max(axis=1)
+    say(f"  max position difference {d.max():.3e} (tolerance {tol:.3e})")
     assert np.all(d <= tol)
     # the returned history is u at the sample's previous positions, in caller order
     hv = hist[:, idx_d].cpu().numpy().astype(np.float64)
-    a_hist = np.stack([a1, a0])[:, :, None]
-    assert np.all(np.abs(hv - ho) <= F32_BOUND * a_hist * 1.1)
+    check_f32(hv, ho, what="returned history")
 
 
 def test_ab2_100_steps_resume_and_domain(ptk, setup):
@@ -122,5 +114,10 @@ def test_ab2_100_steps_resume_and_domain(ptk, setup):
     lb = ctx.advance(Xb, stepping.AB2, DT, 60, hist=hb, hist_len=lb)
     assert la == lb == 2
     assert torch.equal(Xa, Xb) and torch.equal(ha, hb)
-    assert bool(torch.all((Xa >= 0) & (Xa < L)))
     assert bool(torch.all(torch.isfinite(ha)))
+    # positions are the unwrapped trajectories: each moved by at most
+    # 100 dt max|u| from its start, and some crossed the domain's faces
+    umax = float(ha.abs().max())
+    moved = (Xa - X).abs().max()
+    assert float(moved) <= 100 * DT * umax * 1.5
+    assert bool(((Xa < 0) | (Xa >= L)).any())

@@ -169,7 +169,8 @@ def test_inference_and_audit(ptk, setup):
     p = params_init(7, scale=0.3)
     ctx.learned_set_params(p)
     X = np.concatenate([edge_positions(32), particles.uniform_particles(4000, seed=24).numpy()])
-    out, audit, fell = ctx.interpolate_learned(torch.from_numpy(X).to(DEV), audit_frac=0.05)
+    out, audit, fell = ctx.interpolate_learned(torch.from_numpy(X).to(DEV), audit_frac=0.05,
+                                               tol_rel_rms=float("inf"))
     out = out.cpu().numpy().astype(np.float64)
     assert not fell
     narrow = interp.interp_vec(u, X, K.LAGRANGE, 4, 0)
@@ -252,13 +253,22 @@ def test_learning_gain(ptk):
     ctx.learned_set_params(p0)
     curve = ctx.learned_train(feat, tg, epochs=8, batch=4096, lr=1e-3).cpu().numpy()
     Xe = particles.uniform_particles(4000, seed=102).numpy()
-    out, _, _ = ctx.interpolate_learned(torch.from_numpy(Xe).to(DEV), audit_frac=1.0)
+    out, _, fell = ctx.interpolate_learned(torch.from_numpy(Xe).to(DEV), audit_frac=1.0,
+                                           tol_rel_rms=float("inf"))
+    assert not fell
     wide = interp.interp_vec(u, Xe, K.SPLINE, 8, 2)
     narrow = interp.interp_vec(u, Xe, K.LAGRANGE, 4, 0)
     gap = float(np.sqrt(np.mean((narrow - wide) ** 2)))
     res = float(np.sqrt(np.mean((out.cpu().numpy() - wide) ** 2)))
+    # the oracle's reference point: the best affine map from the same 195
+    # features to the same target, fitted by least squares on oracle pairs
+    # (features and targets of the oracle on the stored field) and evaluated
+    # on held-out ones
+    Xf = particles.uniform_particles(60000, seed=103).numpy()
+    floor = LN.linear_floor(LN.features(u, Xf), LN.targets(u, Xf, K.SPLINE, 8, 2), 50000)
     say(f"  loss {curve[0]:.3e} -> {curve[-1]:.3e}; rms(u_L4 - u_wide) {gap:.3e}, "
-        f"rms(learned - u_wide) {res:.3e}, gain {gap / res:.2f}")
+        f"rms(learned - u_wide) {res:.3e}, gain {gap / res:.2f}; affine least-squares floor {floor:.3e} "
+        f"(learned / floor {res / floor:.2f})")
     assert curve[-1] < curve[0]
     assert res < 0.8 * gap
     ctx.close()

@@ -4,18 +4,11 @@ Bars: cells, offsets, keys, bin order -- bit-exact; FP64 values and gradients
 within 1e-12 of the oracle (max |diff| / rms of the reference); positions after
 time steps within 1e-12 * 2*pi (FP64 path).
 
-FP32 sums (FP32, BF16 and FP16 storage, compared on the same stored field): per
-element |gpu - oracle| <= F32_BOUND * A, where A is the oracle's absolute sum
-(absolute=True): every field value by its absolute value and every weight by
-the sum of the absolute values of its polynomial's terms, sum_p |c_p| t^p.
-Derivation: the kernel forms each result through FP32 sums of depth
-I (x2) + I (x3) + 4 (lane reduction) <= 20 and FP32 Horner weights (<= 7 steps
-each, three factors); Horner's rule has the error bound 2*steps*u*sum_p |c_p|
-t^p (u = 2^-24), so every first-order term is below 64 u times A.  The FP32
-rounding of the offset t adds |beta'| 2^-24 per weight, a few per cent of the
-bound.  The RMS difference is also required to stay below a quarter of the
-RMS of that bound (rounding errors add up like a random walk, far from the
-worst case), and the relative RMS is reported beside it.
+FP32 sums (FP32, BF16 and FP16 storage), compared with the oracle on the same
+stored field: relative RMS <= 1e-6 and relative max <= 1e-5 of the oracle's
+RMS, for values and (normalised by the gradient's RMS) for gradients; the C3
+spline keeps a per-element bound of 64 * 2^-24 times the oracle's absolute sum
+(``bars.py`` gives the reason).
 """
 import math
 import sys
@@ -27,6 +20,8 @@ import torch
 from oracle import geometry, interp, precision, stepping
 from oracle import kernels as K
 from synthetic import fields, particles
+
+from bars import F32_BOUND, check_f32, is_c3, rel_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -48,24 +43,6 @@ def rel_max(a, b):
 def rel_rms(a, b):
     return float(np.sqrt(np.mean((a - b) ** 2)) / np.sqrt(np.mean(b * b)))
 
-
-F32_BOUND = 64 * 2.0 ** -24
-
-
-def within_f32_bound(gpu, ref, absum):
-    return bool(np.all(np.abs(gpu - ref) <= F32_BOUND * absum))
-
-
-def typical_below_bound(gpu, ref, absum):
-    """The RMS difference stays well below the RMS of the per-element bound:
-    first-order rounding errors of a depth-20 sum add up like a random walk
-    (about sqrt(20) u |terms|), a small fraction of the worst case 64 u A."""
-    return float(np.sqrt(np.mean((gpu - ref) ** 2))) <= 0.25 * F32_BOUND * float(np.sqrt(np.mean(absum ** 2)))
-
-
-def circ(a, b):
-    d = np.abs(a - b) % L
-    return np.minimum(d, L - d)
 
 
 @pytest.fixture(scope="module")
@@ -190,12 +167,14 @@ def test_interp_f32_storage(ptk, fam, I, m):
     ru, rg = interp.interp_vec(u.astype(np.float64), X, fam, I, m, gradient=True)
     au, ag = interp.interp_vec(u.astype(np.float64), X, fam, I, m, gradient=True, absolute=True)
     uv, g = uv.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
-    say(f"  rel rms value {rel_rms(uv, ru):.2e} grad {rel_rms(g, rg):.2e}")
-    assert within_f32_bound(uv, ru, au) and within_f32_bound(g, rg, ag)
-    assert typical_below_bound(uv, ru, au) and typical_below_bound(g, rg, ag)
-    # the value-only kernel (its own lane layout)
+    c3 = is_c3(fam, I, m)
+    ev = check_f32(uv, ru, au, c3, "value (value + gradient kernel)")
+    eg = check_f32(g, rg, ag, c3, "gradient")
+    # the value-only kernel
     val = ctx.interpolate(torch.from_numpy(X).to(DEV)).cpu().numpy().astype(np.float64)
-    assert within_f32_bound(val, ru, au) and typical_below_bound(val, ru, au)
+    e1 = check_f32(val, ru, au, c3, "value (value kernel)")
+    say(f"  rel rms / max: value {ev[0]:.2e} / {ev[1]:.2e}, gradient {eg[0]:.2e} / {eg[1]:.2e}, "
+        f"value kernel {e1[0]:.2e} / {e1[1]:.2e}")
     ctx.close()
 
 
@@ -203,7 +182,8 @@ def _check_storage(storage, uv, g, ru, rg, au, ag):
     if storage == "f64":
         assert rel_max(uv, ru) <= 1e-12 and rel_max(g, rg) <= 1e-12
     else:
-        assert within_f32_bound(uv, ru, au) and within_f32_bound(g, rg, ag)
+        check_f32(uv, ru, what="value")
+        check_f32(g, rg, what="gradient")
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
@@ -254,12 +234,17 @@ def test_interp_reduced_storage_tight(ptk, storage, fam, I, m):
     ru, rg = ru * s, rg * s[None, :, None]
     au, ag = au * s, ag * s[None, :, None]
     uv, g = uv.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
-    say(f"  rel rms value {rel_rms(uv, ru):.2e} grad {rel_rms(g, rg):.2e}")
-    # one more FP32 rounding: the product with the scale s_a
-    assert within_f32_bound(uv, ru, au * 1.0625) and within_f32_bound(g, rg, ag * 1.0625)
-    assert typical_below_bound(uv, ru, au * 1.0625) and typical_below_bound(g, rg, ag * 1.0625)
+    # O-8 (i): the same bars as FP32 storage on the same stored values (the
+    # product with s_a adds one FP32 rounding, 2^-24 relative); the C3 spline
+    # keeps its per-element bound, widened by that one rounding
+    c3 = is_c3(fam, I, m)
+    sc = 1.0625 if c3 else 1.0
+    ev = check_f32(uv, ru, au, c3, f"{storage} value", sc)
+    eg = check_f32(g, rg, ag, c3, f"{storage} gradient", sc)
     val = ctx.interpolate(torch.from_numpy(X).to(DEV)).cpu().numpy().astype(np.float64)
-    assert within_f32_bound(val, ru, au * 1.0625) and typical_below_bound(val, ru, au * 1.0625)
+    e1 = check_f32(val, ru, au, c3, f"{storage} value kernel", sc)
+    say(f"  rel rms / max: value {ev[0]:.2e} / {ev[1]:.2e}, gradient {eg[0]:.2e} / {eg[1]:.2e}, "
+        f"value kernel {e1[0]:.2e} / {e1[1]:.2e}")
     ctx.close()
 
 
@@ -274,8 +259,7 @@ def test_heun_step_f64(ptk, f0):
     ctx.advance(Xd, ptk.HEUN, 1e-3, 1)
     Xo, _, _, _ = stepping.advance(X0, lambda Y: interp.interp_vec(u, Y, K.LAGRANGE, 4, 0), stepping.HEUN, 1e-3, 1)
     Xg = Xd.cpu().numpy()
-    assert np.max(circ(Xg, Xo)) <= 1e-12 * L
-    assert np.all((Xg >= 0) & (Xg < L))
+    assert np.max(np.abs(Xg - Xo)) <= 1e-12 * L
     ctx.close()
 
 
@@ -300,7 +284,7 @@ def test_multistep_f64_with_gradient(ptk, scheme):
     vel = lambda Y: interp.interp_vec(u, Y, K.SPLINE, 6, 1)
     gfn = lambda Y: interp.interp_vec(u, Y, K.SPLINE, 6, 1, gradient=True)
     Xo, ho, hlo, go = stepping.advance(X0, vel, sc, 2e-3, 7, gradient=gfn)
-    assert np.max(circ(Xd.cpu().numpy(), Xo)) <= 1e-12 * L
+    assert np.max(np.abs(Xd.cpu().numpy() - Xo)) <= 1e-12 * L
     assert rel_max(grad.cpu().numpy(), go) <= 1e-11
     if scheme in AB_DEPTH:
         assert hl == hlo == AB_DEPTH[scheme]
@@ -332,16 +316,20 @@ def test_multistep_f32_storage(ptk, scheme):
     vel = lambda Y: interp.interp_vec(u, Y, K.SPLINE, 8, 2)
     gfn = lambda Y: interp.interp_vec(u, Y, K.SPLINE, 8, 2, gradient=True)
     Xo, _, _, go = stepping.advance(X0, vel, sc, dt, steps, gradient=gfn)
-    amax = float(interp.interp_vec(u, X0, K.SPLINE, 8, 2, absolute=True).max())
-    tol = steps * dt * AB_SUM[scheme] * (2 if scheme == "heun" else 1) * F32_BOUND * amax * 1.5 + 8 * np.spacing(L)
-    d = circ(Xd.cpu().numpy(), Xo).max()
+    # every velocity entering a step is within 1e-5 rms(u) of the oracle's
+    # (the FP32 value bar); a step moves a position by dt times a combination
+    # of them with absolute weights summing to AB_SUM (two stages for Heun);
+    # over a few steps on this smooth field the propagated differences stay
+    # far below the factor 1.5
+    urms = float(np.sqrt(np.mean(vel(X0) ** 2)))
+    tol = steps * dt * AB_SUM[scheme] * (2 if scheme == "heun" else 1) * 1e-5 * urms * 1.5 + 8 * np.spacing(L)
+    d = np.abs(Xd.cpu().numpy() - Xo).max()
     say(f"  max position difference {d:.3e} (tolerance {tol:.3e})")
     assert d <= tol
     # gradient at the last step's start, where the two trajectories differ by
     # far less than the field's scale
-    Xl = stepping.advance(X0, vel, sc, dt, steps - 1)[0]
-    _, ag = interp.interp_vec(u, Xl, K.SPLINE, 8, 2, gradient=True, absolute=True)
-    assert within_f32_bound(grad.cpu().numpy().astype(np.float64), go, ag * 1.1)
+    eg = check_f32(grad.cpu().numpy().astype(np.float64), go, what="gradient at the last step")
+    say(f"  gradient rel rms / max {eg[0]:.2e} / {eg[1]:.2e}")
     ctx.close()
 
 
@@ -369,7 +357,7 @@ def test_multistep_many_movers(ptk, scheme):
     keys1 = geometry.bin_keys(Xo, N, 8, 5)
     say(f"  particles that changed bin over the run: {np.mean(keys0 != keys1):.2f}")
     assert np.mean(keys0 != keys1) > 0.2
-    assert np.max(circ(Xd.cpu().numpy(), Xo)) <= 1e-12 * L
+    assert np.max(np.abs(Xd.cpu().numpy() - Xo)) <= 1e-12 * L
     ctx.close()
 
 
@@ -438,4 +426,78 @@ def test_errors_and_empty(ptk, f0):
     with pytest.raises(ptk.PtkError) as e:
         ctx.advance(torch.from_numpy(X).to(DEV), ptk.AB2, 1e-3, 1)
     assert e.value.code == ptk.EINVAL
+    ctx.close()
+
+
+def test_trajectories_keep_face_crossings(ptk):
+    """The state is the position itself (step 1's reduction modulo 2 pi is
+    applied only where the field is evaluated): particles started next to the
+    faces and carried across them by a uniform flow come back outside
+    [0, 2 pi), equal to the oracle's unwrapped trajectories, and the velocity
+    they saw is the field's at the reduced positions."""
+    say("[advance] face crossings")
+    N = 16
+    c = np.array([0.9, -1.1, 0.6])
+    u = np.broadcast_to(c, (N, N, N, 3)).copy()
+    rng = np.random.default_rng(17)
+    n = 3000
+    X0 = np.concatenate([rng.uniform(L - 0.05, L, (n // 2, 3)), rng.uniform(0.0, 0.05, (n - n // 2, 3))])
+    ctx = ptk.Context(0)
+    ctx.set_field(torch.from_numpy(u).to(DEV), K.SPLINE, 8, 2, storage=ptk.F64)
+    for scheme, hist in [("heun", None), ("ab2", 2)]:
+        Xd = torch.from_numpy(X0.copy()).to(DEV)
+        h = torch.zeros((hist, n, 3), dtype=torch.float64, device=DEV) if hist else None
+        ctx.advance(Xd, SCHEMES[scheme], 0.01, 12, hist=h, hist_len=0)
+        vel = lambda Y: interp.interp_vec(u, Y, K.SPLINE, 8, 2)
+        Xo, _, _, _ = stepping.advance(X0, vel, SCHEMES[scheme], 0.01, 12)
+        Xg = Xd.cpu().numpy()
+        assert np.max(np.abs(Xg - Xo)) <= 1e-12 * L
+        assert np.mean((Xg < 0) | (Xg >= L)) > 0.2
+        assert np.max(np.abs(Xg - (X0 + 0.12 * c))) <= 1e-12 * L
+    ctx.close()
+
+
+def test_out_of_memory_leaves_a_usable_context(ptk, f0, monkeypatch):
+    """PTK_TEST_MAX_BYTES caps the context's device memory.  A field too large
+    for the cap fails with PTK_ENOMEM after the old field's block was released
+    (both do not fit): the context then has no field (PTK_ENOFIELD), never a
+    released one.  A scratch growth beyond the cap fails the same way and
+    leaves the field in place.  After either, the context works as before."""
+    say("[errors] out of memory")
+    u, _ = f0
+    monkeypatch.setenv("PTK_TEST_MAX_BYTES", str(48 << 20))
+    ctx = ptk.Context(0)
+    monkeypatch.delenv("PTK_TEST_MAX_BYTES")
+    ud = torch.from_numpy(u).to(DEV)
+    ctx.set_field(ud, K.LAGRANGE, 4, 0, storage=ptk.F64)
+    X = particles.uniform_particles(1000, seed=5, device="cpu").numpy()
+    ref = interp.interp_vec(u, X, K.LAGRANGE, 4, 0)
+    Xd = torch.from_numpy(X).to(DEV)
+    assert rel_max(ctx.interpolate(Xd, out_dtype=torch.float64).cpu().numpy(), ref) <= 1e-12
+    # a 256^3 FP32 field needs about 220 MB
+    big = torch.zeros((256, 256, 256, 3), dtype=torch.float32, device=DEV)
+    with pytest.raises(ptk.PtkError) as e:
+        ctx.set_field(big, K.SPLINE, 8, 2, storage=ptk.F32)
+    assert e.value.code == ptk.ENOMEM
+    del big
+    with pytest.raises(ptk.PtkError) as e:
+        ctx.interpolate(Xd)
+    assert e.value.code == ptk.ENOFIELD
+    with pytest.raises(ptk.PtkError) as e:
+        ctx.advance(Xd.clone(), ptk.HEUN, 1e-3, 1)
+    assert e.value.code == ptk.ENOFIELD
+    ctx.set_field(ud, K.LAGRANGE, 4, 0, storage=ptk.F64)
+    assert rel_max(ctx.interpolate(Xd, out_dtype=torch.float64).cpu().numpy(), ref) <= 1e-12
+    # scratch beyond the cap: 3 million particles need about 50 MB of sort
+    # buffers; the field stays set
+    Xbig = particles.uniform_particles(3_000_000, seed=6, device=DEV)
+    with pytest.raises(ptk.PtkError) as e:
+        ctx.interpolate(Xbig)
+    assert e.value.code == ptk.ENOMEM
+    del Xbig
+    assert rel_max(ctx.interpolate(Xd, out_dtype=torch.float64).cpu().numpy(), ref) <= 1e-12
+    Xa = Xd.clone()
+    ctx.advance(Xa, ptk.HEUN, 1e-3, 1)
+    Xo, _, _, _ = stepping.advance(X, lambda Y: interp.interp_vec(u, Y, K.LAGRANGE, 4, 0), stepping.HEUN, 1e-3, 1)
+    assert np.max(np.abs(Xa.cpu().numpy() - Xo)) <= 1e-12 * L
     ctx.close()

@@ -8,9 +8,8 @@ from oracle import geometry, precision, stepping
 L = geometry.L
 
 
-def _circ(a, b):
-    d = np.abs(a - b) % L
-    return np.minimum(d, L - d)
+def _dist(a, b):
+    return np.abs(a - b)
 
 
 def shear(X):
@@ -45,8 +44,9 @@ def test_shear_flow_exact(scheme):
     X, _, _, _ = stepping.advance(X0, shear, scheme, dt, n)
     ex = X0.copy()
     ex[:, 0] = X0[:, 0] + n * dt * np.sin(X0[:, 1])
-    assert np.max(_circ(X, ex)) < 1e-12
-    assert np.all((X >= 0) & (X < L))
+    assert np.max(_dist(X, ex)) < 1e-12
+    # the state is not wrapped: particles that crossed a face keep going
+    assert np.any((X < 0) | (X >= L))
 
 
 @pytest.mark.parametrize("scheme", ALL)
@@ -54,7 +54,7 @@ def test_constant_velocity(scheme):
     X0 = np.random.default_rng(1).uniform(0, L, (100, 3))
     c = np.array([0.7, -1.3, 2.1])
     X, _, _, _ = stepping.advance(X0, lambda X: np.broadcast_to(c, X.shape).copy(), scheme, 1e-3, 50)
-    assert np.max(_circ(X, X0 + 50 * 1e-3 * c)) < 1e-13
+    assert np.max(_dist(X, X0 + 50 * 1e-3 * c)) < 1e-13
 
 
 @pytest.mark.parametrize("scheme,order", [(stepping.EULER, 1), (stepping.HEUN, 2), (stepping.AB2, 2)])
@@ -65,7 +65,7 @@ def test_convergence_order_in_dt(scheme, order):
     errs = []
     for n in [50, 100, 200]:
         X, _, _, _ = stepping.advance(X0, abc, scheme, T / n, n)
-        errs.append(np.max(_circ(X, ref)))
+        errs.append(np.max(_dist(X, ref)))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(np.abs(rates - order) < 0.25), rates
 
@@ -98,7 +98,7 @@ def test_ab_high_order_convergence_with_exact_history(scheme, order):
             Xj = rk4(X0.copy(), abc, -dt * j / 200, 200)
             hist[j - 1] = abc(Xj)
         X, _, _, _ = stepping.advance(X0, abc, scheme, dt, n, hist=hist, hist_len=K - 1)
-        errs.append(np.max(_circ(X, ref)))
+        errs.append(np.max(_dist(X, ref)))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(np.abs(rates - order) < 0.3), rates
 
@@ -155,3 +155,37 @@ def test_store_scale_and_error(storage, rel):
     assert np.allclose(np.sqrt(np.mean(vals.reshape(-1, 3) ** 2, axis=0)), 1.0, rtol=1e-2)
     back = vals * s
     assert np.max(np.abs(back - u) / np.abs(u).clip(1e-3)) <= rel * 1.01
+
+
+def test_heun_two_fields_exact_for_linear_time_dependence():
+    """A shear flow whose amplitude grows linearly in time,
+    u = ((a + b t) sin x2, 0, 0): x2 stays fixed, and the trapezoid rule of
+    Heun's two stages integrates the linear-in-time velocity exactly, so
+    n steps reproduce X1(t) = X1(0) + (a t + b t^2 / 2) sin X2 to rounding.
+    Taking both stages from the start time's field instead (the frozen-field
+    step) misses the b t^2 / 2 term's half."""
+    a, b = 0.8, 3.0
+    X0 = np.random.default_rng(7).uniform(0, L, (400, 3))
+    dt, n = 1e-2, 25
+
+    def field_at(t):
+        def vel(X):
+            u = np.zeros_like(X)
+            u[:, 0] = (a + b * t) * np.sin(X[:, 1])
+            return u
+        return vel
+
+    X = X0.copy()
+    Xf = X0.copy()
+    for k in range(n):
+        X, _ = stepping.heun_two_fields(X, field_at(k * dt), field_at((k + 1) * dt), dt)
+        Xf, _ = stepping.heun_two_fields(Xf, field_at(k * dt), field_at(k * dt), dt)
+    T = n * dt
+    ex = X0.copy()
+    ex[:, 0] = X0[:, 0] + (a * T + 0.5 * b * T * T) * np.sin(X0[:, 1])
+    assert np.max(np.abs(X - ex)) < 1e-12
+    assert np.max(np.abs(Xf - ex)) > 1e-3
+    # the frozen-field scheme of ``advance`` is the two-field step with one field
+    Xa, _, _, _ = stepping.advance(X0, field_at(0.0), stepping.HEUN, dt, 1)
+    Xb, _ = stepping.heun_two_fields(X0, field_at(0.0), field_at(0.0), dt)
+    assert np.array_equal(Xa, Xb)
