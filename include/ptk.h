@@ -70,6 +70,8 @@ enum {
   PTK_EHIP = -4,          /* a HIP runtime call failed */
   PTK_EDOMAIN = -5,       /* a position was NaN, infinite or |x| >= 2^50 */
   PTK_EUNSUPPORTED = -6,  /* valid but unsupported request (e.g. odd I) */
+  PTK_EIO = -8,           /* a state file could not be written or read, or is
+                             not a state file of this version */
   PTK_EINTERNAL = -7      /* an internal consistency check failed (a scratch
                              buffer smaller than a launch needs, or a particle
                              outside the tile its bin names); nothing was
@@ -95,6 +97,15 @@ typedef struct {
  * last column is 0).  Host buffers of I*I doubles each; der may be NULL.
  * Host-only, needs no device or context. */
 int ptk_kernel_table(const ptk_kernel *k, double *val, double *der);
+
+/* The same polynomials in powers of (t - 1/2), the form the kernels evaluate
+ * (by Horner's rule at t - 1/2, which on [0, 1) loses far less to
+ * cancellation than powers of t): val[j*I + p] is the coefficient of
+ * (t - 1/2)^p of beta for node offset j - (I/2 - 1), der[j*I + p] that of
+ * d beta/dt; each exact rational rounded once (to nearest even) to binary64
+ * (val, der) and to binary32 (val32, der32).  Host buffers of I*I elements;
+ * der, val32 and der32 may be NULL.  Host-only. */
+int ptk_kernel_table_centred(const ptk_kernel *k, double *val, double *der, float *val32, float *der32);
 
 /* Create a context on HIP device `device`.  *out receives the handle. */
 int ptk_create(ptk_ctx **out, int device);
@@ -152,9 +163,24 @@ int ptk_get_field_scale(const ptk_ctx *ctx, float *scale3);
  * Errors: PTK_EINVAL (NULL pointer, odd or out-of-range N, bad kind or
  *    dtype), PTK_EUNSUPPORTED (kernel), PTK_ENOMEM, PTK_EHIP (transform set-up
  *    or launch); on an argument error the context is unchanged. */
-enum { PTK_SPEC_VELOCITY = 0, PTK_SPEC_VORTICITY = 1 };
+enum { PTK_SPEC_VELOCITY = 0, PTK_SPEC_VORTICITY = 1, PTK_GRID = 2 };
 int ptk_set_field_spectral(ptk_ctx *ctx, const void *spec, int64_t N, int in_dtype, int kind,
                            int storage_dtype, const ptk_kernel *k, void *stream);
+
+/* The field of the end of the next time step, for a tracer step in a field
+ * that changes during the step (Eq. "tracers" with u = u(x, t); in the paper's
+ * loop the solver advances, the extra inverse transform of Sec. 4.2 gives the
+ * new grid velocity, and the particles step from the old time to the new).
+ * src: device pointer, in the form `form`:
+ *   PTK_GRID: grid values u[x3][x2][x1][a] as for ptk_set_field;
+ *   PTK_SPEC_VELOCITY / PTK_SPEC_VORTICITY: a half spectrum as for
+ *   ptk_set_field_spectral (N even, N <= 2048).
+ * N must equal the current field's; the field is stored with the current
+ * field's kernel and storage type (its own per-component scale for 16-bit
+ * storage) beside the current field, which it does not replace.  A new
+ * current field (ptk_set_field, ptk_set_field_spectral) discards it.
+ * Errors: PTK_ENOFIELD (no current field), PTK_EINVAL, PTK_ENOMEM, PTK_EHIP. */
+int ptk_set_field_next(ptk_ctx *ctx, const void *src, int64_t N, int in_dtype, int form, void *stream);
 
 /* Copy of the stored field without its halo into u (device, N*N*N*3 elements
  * of out_dtype, PTK_F64 or PTK_F32, layout u[x3][x2][x1][a]): the stored
@@ -253,6 +279,67 @@ int ptk_particles_load(ptk_ctx *ctx, const double *X, int64_t Np, const void *rh
                        int hist_depth, void *stream);
 int ptk_particles_advance(ptk_ctx *ctx, int scheme, double dt, int nsteps, void *grad_out, void *stream);
 int ptk_particles_store(ptk_ctx *ctx, double *X, void *rhs_hist, int *hist_len, void *stream);
+
+/* Orientation of axisymmetric ellipsoids, a second particle type (Sec. 2.2
+ * names ellipsoids among the particle types; the equation is Jeffery's,
+ * 1922): the loaded particles carry unit axes p that turn with the local
+ * velocity gradient A[a][b] = du_a/dx_b interpolated at the particle,
+ *   dp/dt = W p + shape (S p - (p . S p) p),  S = (A + A^T)/2, W = (A - A^T)/2,
+ * shape = (r^2 - 1)/(r^2 + 1) for the axis ratio r (0 spheres, 1 thin rods,
+ * -1 flat discs).  Once set, ptk_particles_advance and
+ * ptk_particles_step_next_field advance the axes with the positions' scheme:
+ * every stage evaluates the gradient at its own position (Heun's second stage
+ * then uses the value + gradient kernel), the axis rhs is FP64, an
+ * Adams-Bashforth axis history is kept like the velocity history (its own
+ * [k][Np][3] FP64 buffer), and p is normalized to unit length at the end of
+ * each step.
+ * ptk_particles_set_orientation: p device [Np][3] FP64 in the caller's order
+ *    (unit vectors); p_hist device [k][Np][3] FP64 with the first hist_len
+ *    entries valid, where hist_len must equal the loaded position history's
+ *    length (0 without one).  Needs loaded particles; a new load drops the axes.
+ * ptk_particles_get_orientation: the axes (and their history) in the caller's
+ *    order.
+ * Errors: PTK_EINVAL (nothing loaded, no axes set, shape outside [-1, 1],
+ *    NULL pointers, history length). */
+int ptk_particles_set_orientation(ptk_ctx *ctx, const double *p, const double *p_hist, int hist_len, double shape,
+                                  void *stream);
+int ptk_particles_get_orientation(ptk_ctx *ctx, double *p, double *p_hist, void *stream);
+
+/* In-order particle state files: checkpoint / restart and output for
+ * post-processing (Sec. 3.4: the particles are written in the original order
+ * given as input, so that outputs are consistent from one to the next whatever
+ * order the library keeps them in).
+ * ptk_particles_save writes the loaded state to `path` (host file, replaced):
+ * a 64-byte header -- "PTKSTATE", uint32 version 1, uint32 flags (bit 0: axes
+ * follow), int64 Np, int32 history depth k, int32 valid history entries h,
+ * int32 bytes per history component (8 or 4), int32 grid N, float64 axis
+ * shape, 16 reserved bytes, little-endian -- then, in the caller's order,
+ * positions [Np][3] float64, the history [h][Np][3], and with axes the axes
+ * [Np][3] float64 and their history [h][Np][3] float64.  Waits for the
+ * stream; goes through the device (a staging copy of the state) and one
+ * 32 MiB pinned host buffer.
+ * ptk_particles_restore makes a file's state the loaded state, as
+ * ptk_particles_load (and ptk_particles_set_orientation) would from those
+ * arrays; needs a field with the file's N (and, with a history, a storage
+ * type of its velocity precision).  A run restored from a file continues bit
+ * for bit as the run that saved it.
+ * Errors: PTK_EIO (file cannot be opened, written or read; bad header),
+ * PTK_EINVAL, PTK_ENOFIELD, PTK_ENOMEM, PTK_EHIP, PTK_EDOMAIN. */
+int ptk_particles_save(ptk_ctx *ctx, const char *path, void *stream);
+int ptk_particles_restore(ptk_ctx *ctx, const char *path, void *stream);
+
+/* One Heun step of the loaded particles from t to t + dt whose stages see the
+ * fields of their own times: the current field (time t) and the next field
+ * (time t + dt, ptk_set_field_next):
+ *   k1 = u(X, t); Xs = X + dt k1; k2 = u(Xs, t + dt); X <- X + (0.5 dt)(k1 + k2).
+ * Same arithmetic, re-binning and state handling as ptk_particles_advance with
+ * PTK_HEUN (a loaded Adams-Bashforth history is left alone); grad_out as there
+ * (at X, on the current field).  Afterwards the next field is the current one
+ * (its buffer swapped in; no copy) and no next field is set.  The Heun stages
+ * fall exactly on the two times, so no interpolation in time is needed.
+ * Errors: PTK_EINVAL (nothing loaded, other N), PTK_ENOFIELD (no current or
+ * next field). */
+int ptk_particles_step_next_field(ptk_ctx *ctx, double dt, void *grad_out, void *stream);
 
 /* Binning of the last ptk_interpolate / ptk_interpolate_gradient call:
  * number of particles, number of bins, tile edge T and window depth W (cells).

@@ -68,49 +68,113 @@ def ab_update(X, dt, us, order: int):
     return np.add(X, np.multiply(dt, inc))
 
 
+def jeffery_rhs(A, p, shape: float):
+    """Jeffery's equation for the unit axis p of an axisymmetric ellipsoid in
+    a velocity gradient A[..][a][b] = du_a/dx_b (Jeffery 1922; the paper names
+    ellipsoids among TurTLE's particle types, Sec. 2.2, without the equation):
+
+        dp/dt = W p + shape (S p - (p . S p) p),
+
+    S = (A + A^T)/2 the strain rate, W = (A - A^T)/2 the rotation rate,
+    shape = (r^2 - 1)/(r^2 + 1) for the axis ratio r (0 for spheres, 1 for
+    thin rods, -1 for flat discs)."""
+    A = np.asarray(A, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    S = 0.5 * (A + np.swapaxes(A, -1, -2))
+    W = 0.5 * (A - np.swapaxes(A, -1, -2))
+    Sp = np.einsum("...ab,...b->...a", S, p)
+    Wp = np.einsum("...ab,...b->...a", W, p)
+    pSp = np.sum(p * Sp, axis=-1, keepdims=True)
+    return Wp + shape * (Sp - pSp * p)
+
+
+def normalize(p):
+    """p / |p| per row (the unit length Jeffery's equation conserves)."""
+    p = np.asarray(p, dtype=np.float64)
+    return p / np.sqrt(np.sum(p * p, axis=-1, keepdims=True))
+
+
 def advance(X, velocity, scheme: int, dt: float, nsteps: int, hist=None, hist_len: int = 0,
-            gradient=None):
+            gradient=None, orientation=None):
     """Advance positions X[Np][3] by nsteps.
 
     ``velocity(X) -> u[Np][3]``; ``gradient(X) -> (u, grad)`` if given.
-    Returns (X, hist, hist_len, grad_last).
+    ``orientation = (p, shape[, p_hist])``: also advance unit axes p[Np][3]
+    by Jeffery's equation with the same scheme (reading: every stage of the
+    position scheme evaluates the gradient at its own position and the axis
+    rhs with it, the axis history holds the rhs as the position history holds
+    the velocity, and p is normalized once at the end of each step); needs
+    ``gradient``.  Returns (X, hist, hist_len, grad_last), plus (p, p_hist)
+    when an orientation is given.
     """
     X = np.array(X, dtype=np.float64)
     grad_last = None
     if hist is None:
         hist = np.zeros((AB_ORDER.get(scheme, 2),) + X.shape)
     hist = np.array(hist, dtype=np.float64)
+    P = None
+    if orientation is not None:
+        if gradient is None:
+            raise ValueError("the orientation needs the gradient")
+        P = np.array(orientation[0], dtype=np.float64)
+        shape = float(orientation[1])
+        ph = np.array(orientation[2], dtype=np.float64) if len(orientation) > 2 and orientation[2] is not None \
+            else np.zeros_like(hist)
     for _ in range(nsteps):
         if gradient is not None:
             u0, grad_last = gradient(X)
         else:
             u0 = velocity(X)
+        r0 = jeffery_rhs(grad_last, P, shape) if P is not None else None
         if scheme == EULER:
             X = euler_update(X, dt, u0)
+            if P is not None:
+                P = normalize(euler_update(P, dt, r0))
         elif scheme == HEUN:
             Xs = heun_predict(X, dt, u0)
-            k2 = velocity(Xs)
+            if P is not None:
+                Ps = heun_predict(P, dt, r0)
+                k2, g2 = gradient(Xs)
+                r2 = jeffery_rhs(g2, Ps, shape)
+                P = normalize(heun_correct(P, dt, r0, r2))
+            else:
+                k2 = velocity(Xs)
             X = heun_correct(X, dt, u0, k2)
         elif scheme == AB2:
             if hist_len == 0:
                 Xn = euler_update(X, dt, u0)
+                Pn = euler_update(P, dt, r0) if P is not None else None
             else:
                 Xn = ab2_update(X, dt, u0, hist[0])
+                Pn = ab2_update(P, dt, r0, ph[0]) if P is not None else None
             hist[1] = hist[0]
             hist[0] = u0
+            if P is not None:
+                ph[1] = ph[0]
+                ph[0] = r0
+                P = normalize(Pn)
             hist_len = min(hist_len + 1, 2)
             X = Xn
         elif scheme in (AB3, AB4):
             K = AB_ORDER[scheme]
             q = min(K, hist_len + 1)
             Xn = ab_update(X, dt, [u0] + [hist[j] for j in range(q - 1)], q)
+            if P is not None:
+                Pn = ab_update(P, dt, [r0] + [ph[j] for j in range(q - 1)], q)
             for j in range(K - 1, 0, -1):
                 hist[j] = hist[j - 1]
+                if P is not None:
+                    ph[j] = ph[j - 1]
             hist[0] = u0
+            if P is not None:
+                ph[0] = r0
+                P = normalize(Pn)
             hist_len = min(hist_len + 1, K)
             X = Xn
         else:
             raise ValueError("unknown scheme")
+    if P is not None:
+        return X, hist, hist_len, grad_last, P, ph
     return X, hist, hist_len, grad_last
 
 

@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -274,11 +275,11 @@ int bin_sorted(ptk_ctx* c, int64_t Np, int64_t n_bins, uint32_t** perm, hipStrea
   return PTK_OK;
 }
 
-InterpArgs base_args(const ptk_ctx* c) {
+InterpArgs base_args(const ptk_ctx* c, bool next_field = false) {
   InterpArgs a;
   std::memset(&a, 0, sizeof(a));
   const BinGeom g = bin_geom(c);
-  a.field = c->field.ptr;
+  a.field = next_field ? c->field_next.ptr : c->field.ptr;
   a.row_pitch = c->geom.row_pitch;
   a.plane_pitch = c->geom.plane_pitch;
   a.P = c->geom.P;
@@ -296,55 +297,63 @@ InterpArgs base_args(const ptk_ctx* c) {
   a.offsets = (const uint32_t*)c->offsets.ptr;
   a.coef = c->coef.ptr;
   a.flag = (int*)c->flag.ptr;
-  a.scale[0] = c->scale[0];
-  a.scale[1] = c->scale[1];
-  a.scale[2] = c->scale[2];
+  for (int q = 0; q < 3; ++q) a.scale[q] = next_field ? c->scale_next[q] : c->scale[q];
   return a;
 }
 
-int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* grad, int out_dtype,
-                  void* stream) {
-  if (!c) return PTK_EINVAL;
-  c->err.clear();
+// Device scratch of one interpolate call: sort keys and values (double
+// buffered), radix histograms, scan partials, bin offsets.
+struct InterpScratch {
+  uint32_t *keys_a, *keys_b, *vals_a, *vals_b, *hist, *scan_tmp, *offsets;
+};
+
+int check_interp_args(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* grad, int out_dtype) {
   if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
   if (Np < 0 || Np > (int64_t)0xFFFFFFFF) return fail(c, PTK_EINVAL, "Np out of range [0, 2^32)");
   if (out_dtype != PTK_F64 && out_dtype != PTK_F32) return fail(c, PTK_EINVAL, "out_dtype must be F64 or F32");
   if (Np > 0 && (!X || (!u_out && !grad))) return fail(c, PTK_EINVAL, "NULL pointer");
-  DeviceGuard g(c->device);
-  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
-  hipStream_t s = S(stream);
+  return PTK_OK;
+}
+
+// keys -> stable sort -> offsets -> interpolation kernel, on the given
+// scratch; records the binning when `record` (the scratch then stays the
+// context's until the next call).  Arguments are checked by the caller and
+// the device is current.
+int interp_core(ptk_ctx* c, const InterpScratch& w, const double* X, int64_t Np, void* u_out, void* grad,
+                int out_dtype, hipStream_t s, bool record) {
   const int64_t N = c->geom.N;
   const BinGeom bg = bin_geom(c);
   const int64_t n_bins = n_bins_of(bg);
   c->bin_valid = false;
   if (Np == 0) {
-    c->bin_np = 0;
-    c->bin_nbins = n_bins;
-    PTK_TRY(ensure(c, c->offsets, (size_t)(n_bins + 1) * 4));
-    PTK_HIP(c, launch_offsets((const uint32_t*)c->keys_a.ptr, 0, n_bins, (uint32_t*)c->offsets.ptr, s),
-            "bin offsets");
-    c->bin_perm = nullptr;
-    c->bin_valid = true;
+    PTK_HIP(c, launch_offsets(w.keys_a, 0, n_bins, w.offsets, s), "bin offsets");
+    if (record) {
+      c->bin_np = 0;
+      c->bin_nbins = n_bins;
+      c->bin_perm = nullptr;
+      c->bin_valid = true;
+    }
     return PTK_OK;
   }
-  PTK_TRY(ensure_binning(c, Np, n_bins));
-  PTK_TRY(check_binning_caps(c, Np, n_bins));
-  PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
+  PTK_HIP(c, launch_fill_i32((int*)c->flag.ptr, 1, 0, s), "flag clear");
   {
     Timed t(c, s, PTK_T_KEYS);
-    PTK_HIP(c,
-            launch_keys(X, Np, (int)N, invd_of(N), bg, (uint32_t*)c->keys_a.ptr,
-                        (int*)c->flag.ptr, s),
-            "keys");
+    PTK_HIP(c, launch_keys(X, Np, (int)N, invd_of(N), bg, w.keys_a, (int*)c->flag.ptr, s), "keys");
   }
   uint32_t* perm = nullptr;
   {
     Timed t(c, s, PTK_T_SORT);
-    PTK_TRY(bin_sorted(c, Np, n_bins, &perm, s));
+    uint32_t* sk = nullptr;
+    PTK_HIP(c,
+            radix_sort_keys(w.keys_a, w.keys_b, w.vals_a, w.vals_b, Np, nullptr, false, bits_for(n_bins), w.hist,
+                            w.scan_tmp, &sk, &perm, s),
+            "radix sort");
+    PTK_HIP(c, launch_offsets(sk, Np, n_bins, w.offsets, s), "bin offsets");
   }
   // the kernel reads the caller's positions through the bin permutation (the
   // order it also writes the results in): no gathered copy
   InterpArgs a = base_args(c);
+  a.offsets = w.offsets;
   a.X = X;
   a.xrow = perm;
   a.np = Np;
@@ -356,13 +365,36 @@ int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* gr
     Timed t(c, s, grad ? PTK_T_INTERP_GRAD : PTK_T_INTERP);
     PTK_HIP(c, launch_interp(c->storage, c->I, a, s), "interpolate");
   }
-  c->bin_perm = perm;
-  c->bin_np = Np;
-  c->bin_nbins = n_bins;
-  c->bin_valid = true;
+  if (record) {
+    c->bin_perm = perm;
+    c->bin_np = Np;
+    c->bin_nbins = n_bins;
+    c->bin_valid = true;
+  }
   return check_flag(c, s);
 }
 
+int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* grad, int out_dtype,
+                  void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  PTK_TRY(check_interp_args(c, X, Np, u_out, grad, out_dtype));
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  const int64_t n_bins = n_bins_of(bin_geom(c));
+  c->bin_valid = false;
+  if (Np == 0) {
+    PTK_TRY(ensure(c, c->offsets, (size_t)(n_bins + 1) * 4));
+  } else {
+    PTK_TRY(ensure_binning(c, Np, n_bins));
+    PTK_TRY(check_binning_caps(c, Np, n_bins));
+  }
+  PTK_TRY(need(c, c->offsets, (size_t)(n_bins + 1) * 4, "bin offsets"));
+  InterpScratch w{(uint32_t*)c->keys_a.ptr, (uint32_t*)c->keys_b.ptr, (uint32_t*)c->vals_a.ptr,
+                  (uint32_t*)c->vals_b.ptr,  (uint32_t*)c->hist.ptr,   (uint32_t*)c->scan_tmp.ptr,
+                  (uint32_t*)c->offsets.ptr};
+  return interp_core(c, w, X, Np, u_out, grad, out_dtype, S(stream), true);
+}
 
 // ---- learned form helpers
 int learned_field(ptk_ctx* c, LearnedField* lf) {
@@ -422,6 +454,26 @@ int ptk_kernel_table(const ptk_kernel* k, double* val, double* der) {
   return PTK_OK;
 }
 
+int ptk_kernel_table_centred(const ptk_kernel* k, double* val, double* der, float* val32, float* der32) {
+  if (!k || !val) return PTK_EINVAL;
+  if (k->family != PTK_LAGRANGE && k->family != PTK_SPLINE) return PTK_EINVAL;
+  if (k->I % 2 != 0) return PTK_EUNSUPPORTED;
+  if (k->I != 4 && k->I != 6 && k->I != 8) return PTK_EUNSUPPORTED;
+  const int m = k->family == PTK_LAGRANGE ? 0 : k->m;
+  if (m < 0 || m > k->I / 2 - 1) return PTK_EINVAL;
+  KernelTables tab;
+  int r = build_kernel_tables(k->family, k->I, m, &tab);
+  if (r != 0) return r == -6 ? PTK_EUNSUPPORTED : PTK_EINVAL;
+  for (int j = 0; j < k->I; ++j)
+    for (int p = 0; p < k->I; ++p) {
+      val[j * k->I + p] = tab.cval64[j][p];
+      if (der) der[j * k->I + p] = tab.cder64[j][p];
+      if (val32) val32[j * k->I + p] = tab.cval32[j][p];
+      if (der32) der32[j * k->I + p] = tab.cder32[j][p];
+    }
+  return PTK_OK;
+}
+
 int ptk_create(ptk_ctx** out, int device) {
   if (!out) return PTK_EINVAL;
   *out = nullptr;
@@ -451,14 +503,17 @@ void ptk_destroy(ptk_ctx* c) {
   {
     DeviceGuard g(c->device);
     (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&c->field, &c->coef, &c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->offsets,
+    DevBuf* bufs[] = {&c->field, &c->field_next, &c->coef, &c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->offsets,
                       &c->hist, &c->scan_tmp, &c->flag, &c->xs, &c->xn, &c->orig, &c->orig_b, &c->k1,
                       &c->k2, &c->abh[0], &c->abh[1], &c->abh[2], &c->abh[3], &c->abh_b[0], &c->abh_b[1],
                       &c->abh_b[2], &c->abh_b[3], &c->gint, &c->stage, &c->lparams,
                       &c->lm, &c->lv, &c->lw1b, &c->lw2b, &c->lw2bt, &c->lgpart, &c->llpart, &c->lwide,
                       &c->laudit_x, &c->laudit_u, &c->laudit_sums, &c->skeys, &c->skeys2, &c->offsets2,
                       &c->mk_a, &c->mk_b, &c->mv_a, &c->mv_b, &c->mo, &c->rb_in, &c->rb_out, &c->rb_inc,
-                      &c->rb_block, &c->spec, &c->fft_out, &c->fft_work, &c->aoff, &c->aperm, &c->aperm_p};
+                      &c->rb_block, &c->spec, &c->fft_out, &c->fft_work, &c->aoff, &c->aperm, &c->aperm_p,
+                      &c->ori_p, &c->ori_pn, &c->ori_r1, &c->ori_r2, &c->ori_ps, &c->ori_h[0], &c->ori_h[1],
+                      &c->ori_h[2], &c->ori_h[3], &c->ori_hb[0], &c->ori_hb[1], &c->ori_hb[2], &c->ori_hb[3],
+                      &c->gint2, &c->io};
     for (DevBuf* b : bufs) release(*b);
     fft_release(c->fft);
     c->fft = nullptr;
@@ -496,7 +551,7 @@ int check_field_args(ptk_ctx* c, int64_t N, int in_dtype, int storage_dtype, con
 // Stores the grid field u (layout l, FP64 or FP32) as the context's field:
 // the per-component scale for 16-bit storage, the coefficient tables, the pack.
 int store_field(ptk_ctx* c, const void* u, int in_f64, const SrcLayout& l, int64_t N, int storage_dtype,
-                const ptk_kernel* k, int m, const KernelTables& tab, hipStream_t s) {
+                const ptk_kernel* k, int m, const KernelTables& tab, hipStream_t s, bool next_field = false) {
   FieldGeom geo;
   geo.N = N;
   geo.P = N + k->I - 1;
@@ -535,10 +590,25 @@ int store_field(ptk_ctx* c, const void* u, int in_f64, const SrcLayout& l, int64
     }
     delete[] part;
   }
+  if (next_field) {
+    // the next time's field: same kernel, tables and storage as the current
+    c->has_next = false;
+    PTK_TRY(ensure(c, c->field_next, field_bytes));
+    PTK_TRY(need(c, c->field_next, field_bytes, "stored next field"));
+    PTK_HIP(c,
+            launch_pack(u, in_f64, l, N, storage_dtype, k->I, c->field_next.ptr, geo.row_pitch, geo.plane_pitch, inv,
+                        s),
+            "field pack");
+    c->geom_next = geo;
+    for (int q = 0; q < 3; ++q) c->scale_next[q] = scl[q];
+    c->has_next = true;
+    return PTK_OK;
+  }
   // the stored field is withdrawn while its buffer is replaced and filled: a
   // failure below leaves the context without a field (PTK_ENOFIELD), never
   // with a released or half-written one
   c->has_field = false;
+  c->has_next = false;  // a new current field retires the next one
   c->bin_valid = false;
   PTK_TRY(ensure(c, c->field, field_bytes));
   PTK_TRY(ensure(c, c->coef, sizeof(KernelTables)));
@@ -557,6 +627,31 @@ int store_field(ptk_ctx* c, const void* u, int in_f64, const SrcLayout& l, int64
   for (int q = 0; q < 3; ++q) c->scale[q] = scl[q];
   c->has_field = true;
   c->bin_valid = false;
+  return PTK_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// The grid field of a half spectrum (velocity, or vorticity through the
+// Biot-Savart law) into c->fft_out: the three real planes [a][x3][x2][x1].
+int spectrum_to_grid(ptk_ctx* c, const void* spec, int64_t N, int f64, int kind, hipStream_t s) {
+  const size_t rb = f64 ? 8 : 4;
+  const size_t modes = (size_t)N * (size_t)N * (size_t)(N / 2 + 1);
+  size_t work = 0;
+  const char* msg = nullptr;
+  if (fft_prepare(&c->fft, N, f64, &work, &msg) != 0) return fail(c, PTK_EHIP, msg);
+  PTK_TRY(ensure(c, c->spec, 3 * modes * 2 * rb));
+  PTK_TRY(ensure(c, c->fft_out, 3 * (size_t)N * (size_t)N * (size_t)N * rb));
+  if (work > 0) PTK_TRY(ensure(c, c->fft_work, work));
+  PTK_TRY(need(c, c->spec, 3 * modes * 2 * rb, "transform input"));
+  PTK_TRY(need(c, c->fft_out, 3 * (size_t)N * (size_t)N * (size_t)N * rb, "transform output"));
+  if (work > 0) PTK_TRY(need(c, c->fft_work, work, "transform work"));
+  Timed t(c, s, PTK_T_IFT);
+  PTK_HIP(c, launch_spec_prep(spec, f64, N, kind == PTK_SPEC_VORTICITY, c->spec.ptr, s), "spectrum prep");
+  if (fft_run(c->fft, c->spec.ptr, c->fft_out.ptr, c->fft_work.ptr, c->fft_work.cap, s, &msg) != 0)
+    return fail(c, PTK_EHIP, msg);
   return PTK_OK;
 }
 
@@ -590,24 +685,30 @@ int ptk_set_field_spectral(ptk_ctx* c, const void* spec, int64_t N, int in_dtype
   if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
   hipStream_t s = S(stream);
   const int f64 = in_dtype == PTK_F64;
-  const size_t rb = f64 ? 8 : 4;
-  const size_t modes = (size_t)N * (size_t)N * (size_t)(N / 2 + 1);
-  size_t work = 0;
-  const char* msg = nullptr;
-  if (fft_prepare(&c->fft, N, f64, &work, &msg) != 0) return fail(c, PTK_EHIP, msg);
-  PTK_TRY(ensure(c, c->spec, 3 * modes * 2 * rb));
-  PTK_TRY(ensure(c, c->fft_out, 3 * (size_t)N * (size_t)N * (size_t)N * rb));
-  if (work > 0) PTK_TRY(ensure(c, c->fft_work, work));
-  PTK_TRY(need(c, c->spec, 3 * modes * 2 * rb, "transform input"));
-  PTK_TRY(need(c, c->fft_out, 3 * (size_t)N * (size_t)N * (size_t)N * rb, "transform output"));
-  if (work > 0) PTK_TRY(need(c, c->fft_work, work, "transform work"));
-  {
-    Timed t(c, s, PTK_T_IFT);
-    PTK_HIP(c, launch_spec_prep(spec, f64, N, kind == PTK_SPEC_VORTICITY, c->spec.ptr, s), "spectrum prep");
-    if (fft_run(c->fft, c->spec.ptr, c->fft_out.ptr, c->fft_work.ptr, c->fft_work.cap, s, &msg) != 0)
-      return fail(c, PTK_EHIP, msg);
-  }
+  PTK_TRY(spectrum_to_grid(c, spec, N, f64, kind, s));
   return store_field(c, c->fft_out.ptr, f64, transform_layout(N), N, storage_dtype, k, m, tab, s);
+}
+
+int ptk_set_field_next(ptk_ctx* c, const void* src, int64_t N, int in_dtype, int form, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!src) return fail(c, PTK_EINVAL, "NULL pointer");
+  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no current field: set one with ptk_set_field first");
+  if (form != PTK_GRID && form != PTK_SPEC_VELOCITY && form != PTK_SPEC_VORTICITY)
+    return fail(c, PTK_EINVAL, "form must be PTK_GRID, PTK_SPEC_VELOCITY or PTK_SPEC_VORTICITY");
+  if (in_dtype != PTK_F64 && in_dtype != PTK_F32) return fail(c, PTK_EINVAL, "in_dtype must be F64 or F32");
+  if (N != c->geom.N) return fail(c, PTK_EINVAL, "the next field must have the current field's N");
+  if (form != PTK_GRID && (N % 2 != 0 || N > 2048))
+    return fail(c, PTK_EINVAL, "a spectral field needs an even N of at most 2048");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  const ptk_kernel k{c->family, c->I, c->m};
+  const int f64 = in_dtype == PTK_F64;
+  if (form == PTK_GRID)
+    return store_field(c, src, f64, interleaved_layout(N), N, c->storage, &k, c->m, c->tables, s, true);
+  PTK_TRY(spectrum_to_grid(c, src, N, f64, form, s));
+  return store_field(c, c->fft_out.ptr, f64, transform_layout(N), N, c->storage, &k, c->m, c->tables, s, true);
 }
 
 int ptk_get_field(ptk_ctx* c, void* u, int out_dtype, void* stream) {
@@ -759,6 +860,7 @@ int adv_load(ptk_ctx* c, const double* X, int64_t Np, const void* rhs_hist, int 
               "gather history");
     }
   }
+  st.ori = false;
   st.Np = Np;
   st.N = N;
   st.vb = vb;
@@ -784,7 +886,7 @@ int adv_load(ptk_ctx* c, const double* X, int64_t Np, const void* rhs_hist, int 
 // leaves no loaded state; otherwise every step re-bins and the state stays
 // loaded.  grad_out: the last step's velocity gradient, caller order.
 int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hipStream_t s, double* final_X,
-              void* final_hist) {
+              void* final_hist, bool stage2_next = false) {
   auto& st = c->adv;
   const int64_t Np = st.Np;
   const int64_t N = c->geom.N;
@@ -801,7 +903,20 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
     st.k1 = c->k1.ptr;
   }
   if (scheme == PTK_HEUN) PTK_TRY(ensure(c, c->k2, v3));
-  if (grad_out) PTK_TRY(ensure(c, c->gint, (size_t)Np * 9 * vb));
+  const bool ori = st.ori;
+  const size_t g9 = (size_t)Np * 9 * vb, p3 = (size_t)Np * 24;
+  if (grad_out || ori) PTK_TRY(ensure(c, c->gint, g9));
+  if (ori) {
+    // the stage rhs and the predictor's axes and gradient (the axes and their
+    // history were allocated when the orientation was set)
+    PTK_TRY(ensure(c, c->ori_r1, p3));
+    PTK_TRY(ensure(c, c->ori_r2, p3));
+    PTK_TRY(ensure(c, c->ori_ps, p3));
+    if (scheme == PTK_HEUN) PTK_TRY(ensure(c, c->gint2, g9));
+    if (st.K == 0) st.r1 = (double*)c->ori_r1.ptr;
+    st.r2 = (double*)c->ori_r2.ptr;
+    st.ps = (double*)c->ori_ps.ptr;
+  }
   // every buffer the steps below write, by its capacity (the state's
   // pointers rotate among these buffers)
   PTK_TRY(check_binning_caps(c, Np, n_bins));
@@ -817,7 +932,16 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
       PTK_TRY(need(c, c->abh_b[j], v3, "history"));
     }
     if (scheme == PTK_HEUN) PTK_TRY(need(c, c->k2, v3, "predictor velocities"));
-    if (grad_out) PTK_TRY(need(c, c->gint, (size_t)Np * 9 * vb, "gradients"));
+    if (grad_out || ori) PTK_TRY(need(c, c->gint, g9, "gradients"));
+    if (ori) {
+      const DevBuf* o3[] = {&c->ori_p, &c->ori_pn, &c->ori_r1, &c->ori_r2, &c->ori_ps};
+      for (const DevBuf* b : o3) PTK_TRY(need(c, *b, p3, "orientations"));
+      for (int j = 0; j < st.K; ++j) {
+        PTK_TRY(need(c, c->ori_h[j], p3, "orientation history"));
+        PTK_TRY(need(c, c->ori_hb[j], p3, "orientation history"));
+      }
+      if (scheme == PTK_HEUN) PTK_TRY(need(c, c->gint2, g9, "predictor gradients"));
+    }
   }
 
   uint32_t* keys = (uint32_t*)c->keys_a.ptr;
@@ -894,35 +1018,61 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
       a.xrow = st.xrow;
       a.np = Np;
       a.out = k1;
-      a.grad = grad_out ? (last ? grad_out : c->gint.ptr) : nullptr;
-      a.grad_orig = grad_out && last ? st.orig : nullptr;
+      // the axes' rhs needs the gradient in bin order; without axes the last
+      // step writes it straight to the caller's order
+      a.grad = ori ? c->gint.ptr : grad_out ? (last ? grad_out : c->gint.ptr) : nullptr;
+      a.grad_orig = !ori && grad_out && last ? st.orig : nullptr;
       a.out_f64 = vf64;
-      Timed t(c, s, grad_out ? PTK_T_INTERP_GRAD : PTK_T_INTERP);
-      PTK_HIP(c, launch_interp(c->storage, c->I, a, s), "interpolate");
+      {
+        Timed t(c, s, a.grad ? PTK_T_INTERP_GRAD : PTK_T_INTERP);
+        PTK_HIP(c, launch_interp(c->storage, c->I, a, s), "interpolate");
+      }
+      if (ori) {
+        Timed t(c, s, PTK_T_UPDATE);
+        if (grad_out && last) PTK_HIP(c, scatter_v(c->gint.ptr, st.orig, 9, grad_out), "scatter gradient");
+        PTK_HIP(c, launch_jeffery_rhs(vf64, c->gint.ptr, st.p, st.shape, Np, st.r1, s), "axis rhs");
+      }
     }
+    // the axes' update with the stage rhs in v (unit length at the step's end)
+    auto orient = [&](int kind, const UpdateVel& v, double* out, int unit) -> int {
+      Timed t(c, s, PTK_T_UPDATE);
+      PTK_HIP(c, launch_orient_update(kind, st.p, v, dt, Np, unit, out, s), "axis update");
+      return PTK_OK;
+    };
     if (scheme == PTK_EULER) {
       PTK_TRY(update(kEulerOrPredict, vel(k1, nullptr)));
+      if (ori) PTK_TRY(orient(kEulerOrPredict, vel(st.r1, nullptr), st.pn, 1));
     } else if (scheme == PTK_HEUN) {
       // predictor (into xnext), re-binned; u at the predictor is written
       // back in the step's bin order
       PTK_TRY(update(kEulerOrPredict, vel(k1, nullptr)));
+      if (ori) PTK_TRY(orient(kEulerOrPredict, vel(st.r1, nullptr), st.ps, 0));
       uint32_t* pp = (uint32_t*)c->aperm_p.ptr;
       PTK_TRY(rebin(pp));
       {
         // the kernel reads the predictor positions through pp, the order it
-        // also writes u in: no gathered copy
-        InterpArgs b = base_args(c);
+        // also writes u in: no gathered copy.  With stage2_next the second
+        // stage sees the field of the step's end time.
+        InterpArgs b = base_args(c, stage2_next);
         b.offsets = (const uint32_t*)c->offsets2.ptr;  // the predictor's bins
         b.X = st.xnext;
         b.xrow = pp;
         b.np = Np;
         b.orig = pp;
         b.out = k2;
+        b.grad = ori ? c->gint2.ptr : nullptr;  // the axes' second stage needs the gradient there
         b.out_f64 = vf64;
-        Timed t(c, s, PTK_T_INTERP);
+        Timed t(c, s, ori ? PTK_T_INTERP_GRAD : PTK_T_INTERP);
         PTK_HIP(c, launch_interp(c->storage, c->I, b, s), "interpolate predictor");
       }
       PTK_TRY(update(kHeunCorrect, vel(k1, k2)));
+      if (ori) {
+        {
+          Timed t(c, s, PTK_T_UPDATE);
+          PTK_HIP(c, launch_jeffery_rhs(vf64, c->gint2.ptr, st.ps, st.shape, Np, st.r2, s), "axis rhs");
+        }
+        PTK_TRY(orient(kHeunCorrect, vel(st.r1, st.r2), st.pn, 1));
+      }
     } else {
       // order min(K, hl + 1): u_n = k1 and the hl stored velocities
       const int q = hl + 1 < K ? hl + 1 : K;
@@ -933,6 +1083,16 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
       for (int j = 0; j < q; ++j) v.b[j] = kABW[q][j];
       v.nk = q;
       PTK_TRY(update(q == 1 ? kEulerOrPredict : kAB, v));
+      if (ori) {
+        UpdateVel vp = v;
+        vp.k[0] = st.r1;
+        for (int j = 1; j < q; ++j) vp.k[j] = st.ph[j - 1];
+        PTK_TRY(orient(q == 1 ? kEulerOrPredict : kAB, vp, st.pn, 1));
+        double* tp = st.ph[K - 1];
+        for (int j = K - 1; j > 0; --j) st.ph[j] = st.ph[j - 1];
+        st.ph[0] = st.r1;
+        st.r1 = tp;
+      }
       // history rotation: u_{n-j-1} <- u_{n-j}, u_n <- k1; the dropped buffer
       // takes the next step's velocity
       void* t = st.h[K - 1];
@@ -957,6 +1117,12 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
       Timed t(c, s, PTK_T_PERMUTE);
       PTK_HIP(c, gather_u32(st.orig, perm, Np, st.orig_b, s), "gather order");
       for (int j = 0; j < hl; ++j) PTK_HIP(c, gather_v(st.h[j], perm, st.hb[j]), "gather history");
+      if (ori) {
+        // the new axes into the new bin order (the old axes' buffer takes them)
+        PTK_HIP(c, gather3_f64(st.pn, perm, Np, st.p, s), "gather axes");
+        for (int j = 0; j < hl; ++j) PTK_HIP(c, gather3_f64(st.ph[j], perm, Np, st.phb[j], s), "gather axis history");
+        for (int j = 0; j < hl; ++j) std::swap(st.ph[j], st.phb[j]);
+      }
     }
     st.xrow = perm;
     std::swap(st.xcur, st.xnext);
@@ -1060,6 +1226,229 @@ int ptk_particles_advance(ptk_ctx* c, int scheme, double dt, int nsteps, void* g
   DeviceGuard g(c->device);
   if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
   return adv_steps(c, scheme, dt, nsteps, grad_out, S(stream), nullptr, nullptr);
+}
+
+int ptk_particles_set_orientation(ptk_ctx* c, const double* p, const double* p_hist, int hist_len, double shape,
+                                  void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  auto& st = c->adv;
+  if (!st.valid) return fail(c, PTK_EINVAL, "no particles loaded");
+  if (!(shape >= -1.0 && shape <= 1.0)) return fail(c, PTK_EINVAL, "shape must be in [-1, 1]");
+  if (st.Np > 0 && !p) return fail(c, PTK_EINVAL, "NULL axes");
+  if (hist_len != (st.K ? st.hl : 0))
+    return fail(c, PTK_EINVAL, "hist_len must equal the loaded position history's length");
+  if (hist_len > 0 && st.Np > 0 && !p_hist) return fail(c, PTK_EINVAL, "NULL axis history");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  const int64_t Np = st.Np;
+  const size_t p3 = (size_t)Np * 24;
+  st.ori = false;
+  PTK_TRY(ensure(c, c->ori_p, p3));
+  PTK_TRY(ensure(c, c->ori_pn, p3));
+  PTK_TRY(ensure(c, c->ori_r1, p3));
+  for (int j = 0; j < st.K; ++j) {
+    PTK_TRY(ensure(c, c->ori_h[j], p3));
+    PTK_TRY(ensure(c, c->ori_hb[j], p3));
+  }
+  PTK_TRY(need(c, c->ori_p, p3, "axes"));
+  st.p = (double*)c->ori_p.ptr;
+  st.pn = (double*)c->ori_pn.ptr;
+  st.r1 = (double*)c->ori_r1.ptr;
+  for (int j = 0; j < 4; ++j) {
+    st.ph[j] = j < st.K ? (double*)c->ori_h[j].ptr : nullptr;
+    st.phb[j] = j < st.K ? (double*)c->ori_hb[j].ptr : nullptr;
+  }
+  if (Np > 0) {
+    // into the current bin order: particle i is the caller's orig[i]
+    PTK_HIP(c, gather3_f64(p, st.orig, Np, st.p, s), "gather axes");
+    for (int j = 0; j < hist_len; ++j)
+      PTK_HIP(c, gather3_f64(p_hist + (size_t)j * Np * 3, st.orig, Np, st.ph[j], s), "gather axis history");
+  }
+  st.shape = shape;
+  st.ori = true;
+  return PTK_OK;
+}
+
+int ptk_particles_get_orientation(ptk_ctx* c, double* p, double* p_hist, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  auto& st = c->adv;
+  if (!st.valid) return fail(c, PTK_EINVAL, "no particles loaded");
+  if (!st.ori) return fail(c, PTK_EINVAL, "the loaded particles carry no axes");
+  const int hl = st.K ? st.hl : 0;
+  if (st.Np > 0 && (!p || (hl > 0 && !p_hist))) return fail(c, PTK_EINVAL, "NULL pointer");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  const int64_t Np = st.Np;
+  if (Np == 0) return PTK_OK;
+  PTK_HIP(c, scatter_f64(st.p, st.orig, Np, 3, p, s), "scatter axes");
+  for (int j = 0; j < hl; ++j)
+    PTK_HIP(c, scatter_f64(st.ph[j], st.orig, Np, 3, p_hist + (size_t)j * Np * 3, s), "scatter axis history");
+  return PTK_OK;
+}
+
+namespace {
+
+// ---- particle state files (in the caller's order, Sec. 3.4)
+struct StateHeader {
+  char magic[8];       // "PTKSTATE"
+  uint32_t version;    // 1
+  uint32_t flags;      // bit 0: axes (and their history) follow
+  int64_t np;
+  int32_t depth;       // Adams-Bashforth history depth k (0 without history)
+  int32_t hist_len;    // valid history entries
+  int32_t vel_bytes;   // 8 (FP64 storage) or 4
+  int32_t grid;        // N of the field the state was saved with
+  double shape;        // axes' shape factor
+  uint64_t reserved[2];
+};
+static_assert(sizeof(StateHeader) == 64, "state header is 64 bytes");
+constexpr size_t kIoChunk = (size_t)32 << 20;
+
+// Device <-> file copies through one pinned host buffer of kIoChunk bytes.
+struct PinnedChunk {
+  void* p = nullptr;
+  ~PinnedChunk() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+int write_device(ptk_ctx* c, FILE* f, const void* dev, size_t bytes, PinnedChunk& h, hipStream_t s) {
+  for (size_t off = 0; off < bytes; off += kIoChunk) {
+    const size_t n = bytes - off < kIoChunk ? bytes - off : kIoChunk;
+    PTK_HIP(c, hipMemcpyAsync(h.p, (const char*)dev + off, n, hipMemcpyDeviceToHost, s), "state copy to host");
+    PTK_HIP(c, hipStreamSynchronize(s), "stream synchronize");
+    if (fwrite(h.p, 1, n, f) != n) return fail(c, PTK_EIO, "short write of the state file");
+  }
+  return PTK_OK;
+}
+
+int read_device(ptk_ctx* c, FILE* f, void* dev, size_t bytes, PinnedChunk& h, hipStream_t s) {
+  for (size_t off = 0; off < bytes; off += kIoChunk) {
+    const size_t n = bytes - off < kIoChunk ? bytes - off : kIoChunk;
+    if (fread(h.p, 1, n, f) != n) return fail(c, PTK_EIO, "the state file is shorter than its header says");
+    PTK_HIP(c, hipMemcpyAsync((char*)dev + off, h.p, n, hipMemcpyHostToDevice, s), "state copy to device");
+    PTK_HIP(c, hipStreamSynchronize(s), "stream synchronize");
+  }
+  return PTK_OK;
+}
+
+struct FileCloser {
+  FILE* f;
+  ~FileCloser() {
+    if (f) fclose(f);
+  }
+};
+
+}  // namespace
+
+int ptk_particles_save(ptk_ctx* c, const char* path, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  auto& st = c->adv;
+  if (!path) return fail(c, PTK_EINVAL, "NULL path");
+  if (!st.valid) return fail(c, PTK_EINVAL, "no particles loaded");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  const int64_t Np = st.Np;
+  const int hl = st.K ? st.hl : 0;
+  const size_t x3 = (size_t)Np * 24, v3 = (size_t)Np * 3 * st.vb;
+  // the state in the caller's order, staged on the device (positions, then
+  // each history entry, then the axes and theirs)
+  const size_t total = x3 + (size_t)hl * v3 + (st.ori ? x3 + (size_t)hl * x3 : 0);
+  PTK_TRY(ensure(c, c->io, total > 0 ? total : 256));
+  PTK_TRY(need(c, c->io, total, "state staging"));
+  char* dst = (char*)c->io.ptr;
+  if (Np > 0) {
+    PTK_TRY(adv_store(c, (double*)dst, dst + x3, s));
+    if (st.ori)
+      PTK_TRY(ptk_particles_get_orientation(c, (double*)(dst + x3 + (size_t)hl * v3),
+                                            (double*)(dst + x3 + (size_t)hl * v3 + x3), stream));
+  }
+  StateHeader hd;
+  std::memset(&hd, 0, sizeof(hd));
+  std::memcpy(hd.magic, "PTKSTATE", 8);
+  hd.version = 1;
+  hd.flags = st.ori ? 1u : 0u;
+  hd.np = Np;
+  hd.depth = st.K;
+  hd.hist_len = hl;
+  hd.vel_bytes = st.vb;
+  hd.grid = (int32_t)st.N;
+  hd.shape = st.ori ? st.shape : 0.0;
+  FileCloser fc{fopen(path, "wb")};
+  if (!fc.f) return fail(c, PTK_EIO, std::string("cannot open ") + path + " for writing");
+  if (fwrite(&hd, sizeof(hd), 1, fc.f) != 1) return fail(c, PTK_EIO, "short write of the state header");
+  PinnedChunk h;
+  PTK_HIP(c, hipHostMalloc(&h.p, kIoChunk, hipHostMallocDefault), "pinned host buffer");
+  PTK_TRY(write_device(c, fc.f, dst, total, h, s));
+  if (fflush(fc.f) != 0) return fail(c, PTK_EIO, "flush of the state file failed");
+  return PTK_OK;
+}
+
+int ptk_particles_restore(ptk_ctx* c, const char* path, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!path) return fail(c, PTK_EINVAL, "NULL path");
+  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
+  FileCloser fc{fopen(path, "rb")};
+  if (!fc.f) return fail(c, PTK_EIO, std::string("cannot open ") + path);
+  StateHeader hd;
+  if (fread(&hd, sizeof(hd), 1, fc.f) != 1 || std::memcmp(hd.magic, "PTKSTATE", 8) != 0 || hd.version != 1)
+    return fail(c, PTK_EIO, "not a particle state file of this version");
+  if (hd.np < 0 || hd.np > (int64_t)0xFFFFFFFF || !(hd.depth == 0 || (hd.depth >= 2 && hd.depth <= 4)) ||
+      hd.hist_len < 0 || hd.hist_len > hd.depth || (hd.vel_bytes != 4 && hd.vel_bytes != 8) ||
+      (hd.flags & ~1u) != 0 || !(hd.shape >= -1.0 && hd.shape <= 1.0))
+    return fail(c, PTK_EIO, "corrupt particle state header");
+  if (hd.grid != (int32_t)c->geom.N) return fail(c, PTK_EINVAL, "the state was saved on a grid of another N");
+  if (hd.depth > 0 && hd.vel_bytes != vel_bytes(c))
+    return fail(c, PTK_EINVAL, "the state's history has another velocity precision than the field's storage");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  const int64_t Np = hd.np;
+  const int hl = hd.hist_len;
+  const bool axes = hd.flags & 1u;
+  const size_t x3 = (size_t)Np * 24, v3 = (size_t)Np * 3 * hd.vel_bytes;
+  const size_t total = x3 + (size_t)hl * v3 + (axes ? x3 + (size_t)hl * x3 : 0);
+  PTK_TRY(ensure(c, c->io, total > 0 ? total : 256));
+  PTK_TRY(need(c, c->io, total, "state staging"));
+  char* src = (char*)c->io.ptr;
+  PinnedChunk h;
+  PTK_HIP(c, hipHostMalloc(&h.p, kIoChunk, hipHostMallocDefault), "pinned host buffer");
+  PTK_TRY(read_device(c, fc.f, src, total, h, s));
+  c->adv.valid = false;
+  PTK_TRY(adv_load(c, (const double*)src, Np, src + x3, hl, hd.depth, s));
+  PTK_TRY(check_flag(c, s));
+  if (axes)
+    PTK_TRY(ptk_particles_set_orientation(c, (const double*)(src + x3 + (size_t)hl * v3),
+                                          (const double*)(src + x3 + (size_t)hl * v3 + x3), hl, hd.shape, stream));
+  return PTK_OK;
+}
+
+int ptk_particles_step_next_field(ptk_ctx* c, double dt, void* grad_out, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (!c->adv.valid) return fail(c, PTK_EINVAL, "no particles loaded");
+  if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
+  if (!c->has_next) return fail(c, PTK_ENOFIELD, "no next field: set it with ptk_set_field_next");
+  if (!std::isfinite(dt)) return fail(c, PTK_EINVAL, "dt must be finite");
+  if (c->geom.N != c->adv.N) return fail(c, PTK_EINVAL, "the field's grid differs from the loaded particles' bins");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  if (c->adv.Np > 0) PTK_TRY(adv_steps(c, PTK_HEUN, dt, 1, grad_out, S(stream), nullptr, nullptr, true));
+  // the end time's field is now the current one; the old current buffer is
+  // kept for the next call of ptk_set_field_next
+  std::swap(c->field, c->field_next);
+  std::swap(c->geom, c->geom_next);
+  std::swap(c->scale, c->scale_next);
+  c->has_next = false;
+  c->bin_valid = false;
+  return PTK_OK;
 }
 
 int ptk_particles_store(ptk_ctx* c, double* X, void* rhs_hist, int* hist_len, void* stream) {

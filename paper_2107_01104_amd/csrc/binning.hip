@@ -554,6 +554,18 @@ hipError_t rebin_incremental(const uint32_t* okeys, const uint32_t* ooff, const 
   return hipGetLastError();
 }
 
+// a fill of n ints (a kernel, so that a captured graph records no memset node)
+__global__ __launch_bounds__(256) void k_fill_i32(int* __restrict__ p, int64_t n, int value) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+hipError_t launch_fill_i32(int* p, int64_t n, int value, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_fill_i32<<<blocks_for(n, 256), 256, 0, s>>>(p, n, value);
+  return hipGetLastError();
+}
+
 hipError_t launch_offsets(const uint32_t* skeys, int64_t n, int64_t n_bins, uint32_t* offsets,
                           hipStream_t s) {
   k_offsets<<<blocks_for(n + 1, 256), 256, 0, s>>>(skeys, n, n_bins, offsets);

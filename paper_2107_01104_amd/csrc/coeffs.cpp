@@ -15,6 +15,7 @@
 // The conditions form a (2n+2)x(2n+2) linear system on the monomial
 // coefficients of p; it is solved for all I right-hand sides at once by
 // fraction-exact Gauss-Jordan elimination over __int128 rationals.
+#include <cmath>
 #include <cstdint>
 #include <cstdlib>
 #include <vector>
@@ -162,20 +163,71 @@ bool solve(std::vector<std::vector<Q>>& A, std::vector<std::vector<Q>>& B) {
   return !g_overflow;
 }
 
-// Correctly rounded conversion of an exact rational: one IEEE division of
-// exactly representable operands.
-bool to_double(Q q, double* out) {
-  const i128 lim = (i128)1 << 53;
-  if (iabs(q.num) >= lim || q.den >= lim) return false;
-  *out = (double)(int64_t)q.num / (double)(int64_t)q.den;
+// Correctly rounded (to nearest, ties to even) conversion of an exact
+// rational to a binary floating-point number with `bits` significand bits:
+// the quotient is scaled by a power of two into [2^(bits-1), 2^bits) and
+// rounded in integer arithmetic from its remainder.  The magnitudes of kernel
+// coefficients keep every intermediate far inside __int128 and the result
+// far inside the normal range.
+bool to_binary(Q q, int bits, double* out) {
+  if (q.num == 0) {
+    *out = 0.0;
+    return true;
+  }
+  const bool neg = q.num < 0;
+  const i128 a = iabs(q.num), d = q.den;
+  const int top = 124;  // keep a * 2^k and d * 2^k below 2^125
+  int nb = 0, db = 0;
+  for (i128 t = a; t; t >>= 1) ++nb;
+  for (i128 t = d; t; t >>= 1) ++db;
+  // e: the quotient a/d lies in [2^(nb-db-1), 2^(nb-db+1)); scale by 2^(-e)
+  // so that it lies in [2^(bits-1), 2^(bits+1))
+  int e = nb - db - bits;
+  i128 num = a, den = d;
+  if (e < 0) {
+    if (nb - e > top) return false;
+    num <<= -e;
+  } else {
+    if (db + e > top) return false;
+    den <<= e;
+  }
+  i128 quo = num / den, rem = num % den;
+  if (quo >= ((i128)1 << bits)) {  // one bit too many: halve, folding the dropped bit into the remainder
+    const i128 lowbit = quo & 1;
+    quo >>= 1;
+    rem = lowbit * den + rem;
+    den <<= 1;
+    ++e;
+  }
+  const i128 twice = 2 * rem;
+  if (twice > den || (twice == den && (quo & 1))) ++quo;  // a carry to 2^bits stays exact
+  double v = (double)(int64_t)quo;
+  v = ldexp(v, e);
+  *out = neg ? -v : v;
   return true;
 }
 
+bool to_double(Q q, double* out) { return to_binary(q, 53, out); }
+
 bool to_float(Q q, float* out) {
-  const i128 lim = (i128)1 << 24;
-  if (iabs(q.num) >= lim || q.den >= lim) return false;
-  *out = (float)(int32_t)q.num / (float)(int32_t)q.den;
+  double v;
+  if (!to_binary(q, 24, &v)) return false;
+  *out = (float)v;  // exact: v already has at most 24 significand bits
   return true;
+}
+
+// The same polynomial in powers of (t - 1/2): coefficient q is
+// sum_{p >= q} c_p C(p, q) (1/2)^(p - q).
+Poly centred(const Poly& c) {
+  const int n = (int)c.size();
+  Poly d(n, make(0));
+  for (int q = 0; q < n; ++q)
+    for (int p = q; p < n; ++p) {
+      i128 binom = 1;
+      for (int r = 0; r < q; ++r) binom = binom * (p - r) / (r + 1);
+      d[q] = d[q] + c[p] * make(binom, (i128)1 << (p - q));
+    }
+  return d;
 }
 
 }  // namespace
@@ -240,18 +292,27 @@ int build_kernel_tables(int family, int I, int m, KernelTables* out) {
       out->der64[c][p] = 0.0;
       out->val32[c][p] = 0.f;
       out->der32[c][p] = 0.f;
+      out->cval64[c][p] = 0.0;
+      out->cder64[c][p] = 0.0;
+      out->cval32[c][p] = 0.f;
+      out->cder32[c][p] = 0.f;
     }
   for (int c = 0; c < I; ++c) {
+    Poly mono(I), cen;
+    for (int p = 0; p < I; ++p) mono[p] = B[p][c];
+    cen = centred(mono);
     for (int p = 0; p < I; ++p) {
-      Q v = B[p][c];
+      const Q v = mono[p], w = cen[p];
       if (!to_double(v, &out->val64[c][p]) || !to_float(v, &out->val32[c][p])) return -1;
+      if (!to_double(w, &out->cval64[c][p]) || !to_float(w, &out->cval32[c][p])) return -1;
       if (p >= 1) {
-        Q d = v * make(p);
+        const Q d = v * make(p), e = w * make(p);
         if (!to_double(d, &out->der64[c][p - 1]) || !to_float(d, &out->der32[c][p - 1])) return -1;
+        if (!to_double(e, &out->cder64[c][p - 1]) || !to_float(e, &out->cder32[c][p - 1])) return -1;
       }
     }
   }
-  return 0;
+  return g_overflow ? -1 : 0;
 }
 
 }  // namespace ptk

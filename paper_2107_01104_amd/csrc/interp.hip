@@ -23,7 +23,8 @@
 // half-wave read planes whose offsets make the 16-byte reads conflict-free.
 //
 // Weights: every lane evaluates its own node of beta (and beta') by Horner from
-// its row of the coefficient table; the group shares them with DPP
+// its row of the coefficient table, in powers of t - 1/2 (the centred form
+// keeps FP32 cancellation small); the group shares them with DPP
 // row_newbcast.  (Folding the broadcast into the FMAs as their DPP operand
 // issues fewer instructions but measures slower.)  Sums are FP64 for FP64
 // storage and FP32 otherwise.
@@ -125,6 +126,33 @@ __device__ __forceinline__ V rowsum(V v) {
   return v;
 }
 
+// Reduce-scatter of a particle's three value partials over the 16 lanes of a
+// row (lane l16 = j + 8h): after it, lane (h, j) holds the row's total of
+// value 2h + (j >> 2) (value 3 is the zero padding), summed over all 16 lanes.
+// Five DPP additions instead of three full row sums (twelve).
+template <typename V>
+__device__ __forceinline__ V rowsum_scatter3(const V* e, int j, int h) {
+  const V z = (V)0;
+  // lanes l and l^8 (row_ror:8): the h = 0 half keeps values 0, 1, the h = 1
+  // half keeps 2 and the padding
+  const V k0 = h ? e[2] : e[0], k1 = h ? z : e[1];
+  const V s0 = h ? e[0] : e[2], s1 = h ? e[1] : z;
+  const V f0 = k0 + dpp<0x128>(s0);
+  const V f1 = k1 + dpp<0x128>(s1);
+  // lanes j and 7 - j of a half (row_half_mirror): j < 4 keeps f0, j >= 4 f1
+  const bool hi = (j & 4) != 0;
+  V g = (hi ? f1 : f0) + dpp<0x141>(hi ? f0 : f1);
+  g += dpp<0xB1>(g);  // quad_perm [1,0,3,2]
+  g += dpp<0x4E>(g);  // quad_perm [2,3,0,1]
+  return g;
+}
+
+// The value of lane l ^ 16 within each 32-lane group (ds_swizzle, bit mode:
+// and-mask 0x1F, xor-mask 0x10): the other row of a 32-lane particle group.
+__device__ __forceinline__ float swap_rows(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
+}
+
 // ---- node access
 // copy node q of a 48-byte chunk (12 words) into LDS at byte offset `off`
 template <int ST>
@@ -185,6 +213,33 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
+// Row of I coefficients of the lane's node from the workgroup's LDS copy of
+// the table, read when a round needs it instead of being held in registers
+// for the whole launch (the registers go to LDS reads in flight).  The row
+// address passes through an empty asm statement each time, so the compiler
+// cannot hoist the reads out of the particle loop.
+template <int I, typename V>
+__device__ __forceinline__ void coef_row(const V* row, V* c) {
+  asm volatile("" : "+v"(row));
+  if constexpr (sizeof(V) == 4) {
+#pragma unroll
+    for (int p = 0; p < I; p += 4) {
+      const float4 f = *(const float4*)(row + p);
+      c[p] = f.x;
+      if (p + 1 < I) c[p + 1] = f.y;
+      if (p + 2 < I) c[p + 2] = f.z;
+      if (p + 3 < I) c[p + 3] = f.w;
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < I; p += 2) {
+      const double2 f = *(const double2*)(row + p);
+      c[p] = f.x;
+      c[p + 1] = f.y;
+    }
+  }
+}
+
 template <int NC, typename V>
 __device__ __forceinline__ V horner(const V* c, V t) {
   V acc = c[NC - 1];
@@ -228,12 +283,36 @@ __device__ __forceinline__ void store_unit(unsigned char* smem, int64_t zp, int 
   }
 }
 
+// Reference value U(z) of padded plane zp for a tile whose halo starts at
+// (x0, y0): the plane's node nearest the tile's centre (clamped into the
+// padded field; a plane beyond it is never stored).
+__device__ __forceinline__ float3 plane_ref(const InterpArgs& a, int64_t x0, int64_t y0, int64_t zp, int tx) {
+  const int64_t X = min(x0 + tx / 2, a.P - 1), Y = min(y0 + tx / 2, a.P - 1), Z = min(zp, a.P - 1);
+  const float* p = (const float*)((const unsigned char*)a.field + Z * a.plane_pitch + Y * a.row_pitch + X * 12);
+  return make_float3(p[0], p[1], p[2]);
+}
+
+// store_unit for FP32 nodes held relative to the plane's reference: every
+// component minus U(z) (one FP32 rounding of the difference)
+template <int ST, int I>
+__device__ __forceinline__ void store_unit_shifted(unsigned char* smem, int64_t zp, int u, const uint4* c, float3 U) {
+  static_assert(ST == ST_F32, "plane references are used with FP32 nodes");
+  const float uu[3] = {U.x, U.y, U.z};
+  uint4 d[3];
+  const uint32_t* w = (const uint32_t*)c;
+  uint32_t* o = (uint32_t*)d;
+#pragma unroll
+  for (int e = 0; e < 12; ++e) o[e] = __float_as_uint(__uint_as_float(w[e]) - uu[e % 3]);
+  store_unit<ST, I>(smem, zp, u, d);
+}
+
 // One particle: 16 lanes (this lane owns x1 offset j and the planes whose ring
 // slot has parity h).
 // Leaves in r the 3 values (and 9 gradient entries) summed over the group.
 template <int ST, int I, bool GRAD, typename V>
-__device__ __forceinline__ void particle_sums(const unsigned char* smem, const V* cv, const V* cd, int j, int jj,
-                                              int h, V t1, V t2, V t3, int l1, int l2, int z3, V* r) {
+__device__ __forceinline__ void particle_sums(const unsigned char* smem, const float4* uref, const V* cvrow,
+                                              const V* cdrow, int j, int jj, int h, V t1, V t2, V t3, int l1, int l2,
+                                              int z3, V* r) {
   using Gm = Geom<ST, I>;
   constexpr int NB = Gm::NB, RP = Gm::RP, PL = Gm::PL, R = Gm::R;
   constexpr int HALF = I / 2;
@@ -242,6 +321,9 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
   // number of plane pitches
   // weights: lanes 0-7 evaluate beta_j(t2), lanes 8-15 beta_j(t3); all lanes beta_j(t1)
   const V tsel = h ? t3 : t2;
+  V cvl[GRAD ? I : 1];
+  if constexpr (GRAD) coef_row<I>(cvrow, cvl);
+  const V* cv = GRAD ? cvl : cvrow;
   const V wsel = horner<I>(cv, tsel);
   V w1 = horner<I>(cv, t1);
   if (j >= I) w1 = (V)0;
@@ -254,6 +336,8 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
 #undef PTK_B3
   V d1 = (V)0, dw2[I], dw3[HALF];
   if constexpr (GRAD) {
+    V cd[I];
+    coef_row<I>(cdrow, cd);
     const V dsel = horner<I - 1>(cd, tsel);
     d1 = horner<I - 1>(cd, t1);
     if (j >= I) d1 = (V)0;
@@ -272,6 +356,16 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
   // by an empty (schedulable) asm, so the reads stay 16 bytes wide without a
   // wait after each one; one asm at the end keeps the chain alive
   uint32_t sink = 0;
+  // FP32 gradients: the ring holds every plane z relative to a reference
+  // value U(z) of that plane (see plane_ref); the x2 sums of a plane then get
+  // U(z) - U(z_c) added back, z_c the particle's own plane, and the value
+  // U(z_c) at the end.  Exact arithmetic is unchanged (the weights sum to 1,
+  // their derivatives to 0, along every axis), while the FP32 roundings of the
+  // large sums scale with the variation of u within a plane of the tile
+  // instead of with u.
+  constexpr bool SHIFT = GRAD && ST == ST_F32;
+  float4 uc = make_float4(0.f, 0.f, 0.f, 0.f);
+  if constexpr (SHIFT) uc = uref[(z3 + I / 2 - 1) % R];
 #pragma unroll
   for (int m = 0; m < HALF; ++m) {
     const int slot = s0 + 2 * m < R ? s0 + 2 * m : s0 + 2 * m - R;
@@ -296,6 +390,12 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
         asm("" : "+v"(sink) : "v"(keep[k]));
       }
     }
+    if constexpr (SHIFT) {
+      const float4 um = uref[slot];
+      s[0] += um.x - uc.x;
+      s[1] += um.y - uc.y;
+      s[2] += um.z - uc.z;
+    }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       acc[q] = fma(w3[m], s[q], acc[q]);
@@ -319,9 +419,8 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
     }
   }
   if constexpr (!GRAD) {
-    // every lane gets the 3 totals
-#pragma unroll
-    for (int q = 0; q < 3; ++q) r[q] = rowsum(e[q]);
+    // lane (h, j) gets the total of value 2h + (j >> 2)
+    r[0] = rowsum_scatter3(e, j, h);
   } else {
     // reduce-scatter: lanes l and l^8 split the 12 values 6/6, then lanes j and
     // 7-j of each half split their 6 values 3/3, then each quad sums its 3.
@@ -344,6 +443,14 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
       g += dpp<0x4E>(g);
       r[k] = g;
     }
+    // lanes 0-3 hold the values: add back the particle plane's reference
+    if constexpr (SHIFT) {
+      if (h == 0 && b2 == 0) {
+        r[0] += uc.x;
+        r[1] += uc.y;
+        r[2] += uc.z;
+      }
+    }
   }
 }
 
@@ -355,7 +462,7 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const V
 // Each row evaluates its own x2/x3 weights; the rows' partial sums meet with
 // a row broadcast.  Leaves the 3 totals in r on the odd rows.
 template <int ST, int I, typename V>
-__device__ __forceinline__ void particle_sums32(const unsigned char* smem, const V* cv, int j, int jj, int h,
+__device__ __forceinline__ void particle_sums32(const unsigned char* smem, const V* cvrow, int j, int jj, int h,
                                                 V t1, V t2, V t3, int l1, int l2, int z3, V* r) {
   using Gm = Geom<ST, I>;
   constexpr int NB = Gm::NB, RP = Gm::RP, PL = Gm::PL, R = Gm::R;
@@ -363,6 +470,7 @@ __device__ __forceinline__ void particle_sums32(const unsigned char* smem, const
   static_assert(I % 4 == 0, "32-lane groups need I divisible by 4");
   const int q = (threadIdx.x >> 4) & 1;
   const V tsel = h ? t3 : t2;
+  const V* cv = cvrow;
   const V wsel = horner<I>(cv, tsel);
   V w1 = horner<I>(cv, t1);
   if (j >= I) w1 = (V)0;
@@ -407,13 +515,13 @@ __device__ __forceinline__ void particle_sums32(const unsigned char* smem, const
     for (int c = 0; c < 3; ++c) acc[c] = fma(w3[m], sum[c], acc[c]);
   }
   asm volatile("" ::"v"(sink));
+  // each row reduce-scatters its three partials (lane (h, j) of the row: value
+  // 2h + (j >> 2)), then the two rows of the group add their totals
+  V e[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    V v = rowsum(w1 * acc[c]);
-    // odd rows add the even row's total: row_bcast:15 into rows 1 and 3
-    v += __builtin_bit_cast(V, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
-    r[c] = v;
-  }
+  for (int c = 0; c < 3; ++c) e[c] = w1 * acc[c];
+  const V g = rowsum_scatter3(e, j, h);
+  r[0] = g + swap_rows(g);
 }
 
 // SPARSE: for launches with few particles per window -- visit only the
@@ -439,6 +547,10 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   constexpr int RECB = 48;
   __shared__ __attribute__((aligned(16))) unsigned char smem[Gm::LDS];
   __shared__ __attribute__((aligned(16))) unsigned char recs[CH * RECB];
+  // FP32 gradient kernels hold the ring's planes relative to a reference
+  // value per plane: U(z) of the plane in ring slot s (see particle_sums)
+  constexpr bool PSHIFT = GRAD && ST == ST_F32;
+  __shared__ float4 uref[PSHIFT ? Gm::R : 1];
 
   // ---- block -> (tile column, x3 segment); consecutive blocks go round-robin
   // to the 8 XCDs, so XCD x is given a contiguous range of an ordering of the
@@ -477,17 +589,30 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   const int h = l16 >> 3;             // plane half
   const int jj = j < I ? j : I - 1;
   const int grp = tid / GL;
-  const KernelTables* tab = (const KernelTables*)a.coef;
-  V cv[I], cd[I];
-#pragma unroll
-  for (int p = 0; p < I; ++p) {
-    if constexpr (sizeof(V) == 8) {
-      cv[p] = tab->val64[jj][p];
-      cd[p] = tab->der64[jj][p];
-    } else {
-      cv[p] = tab->val32[jj][p];
-      cd[p] = tab->der32[jj][p];
+  // the kernel's coefficient rows (in powers of t - 1/2) in LDS: [2][I][I]
+  // values then derivatives; written here, read after the first barrier
+  __shared__ __attribute__((aligned(16))) V ctab[2 * I * I];
+  {
+    const KernelTables* tab = (const KernelTables*)a.coef;
+    for (int e = tid; e < 2 * I * I; e += Gm::THREADS) {
+      const int d = e / (I * I), rr = (e / I) % I, p = e % I;
+      if constexpr (sizeof(V) == 8)
+        ctab[e] = d ? tab->cder64[rr][p] : tab->cval64[rr][p];
+      else
+        ctab[e] = d ? tab->cder32[rr][p] : tab->cval32[rr][p];
     }
+  }
+  const V* cvrow = ctab + jj * I;
+  const V* cdrow = ctab + I * I + jj * I;
+  // value kernels hold their row in registers for the whole launch (a read
+  // per round would sit at the head of every round's dependency chain); the
+  // gradient kernels, which need their registers for the sums, read both
+  // rows from LDS at the start of each round
+  V cvr[GRAD ? 1 : I];
+  if constexpr (!GRAD) {
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < I; ++p) cvr[p] = cvrow[p];
   }
   const int N = a.N;
   const double invd = a.invd;
@@ -499,7 +624,15 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
     for (int u = tid; u < UNITS; u += NT) {
       uint4 c[3];
       const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
-      if (load_unit<ST, I>(a, x0, y0, z_lo + pl, uu, c)) store_unit<ST, I>(smem, z_lo + pl, uu, c);
+      if constexpr (PSHIFT) {
+        const float3 U = plane_ref(a, x0, y0, z_lo + pl, Gm::TX);
+        if (load_unit<ST, I>(a, x0, y0, z_lo + pl, uu, c)) {
+          store_unit_shifted<ST, I>(smem, z_lo + pl, uu, c, U);
+          if (uu == 0) uref[(z_lo + pl) % Gm::R] = make_float4(U.x, U.y, U.z, 0.f);
+        }
+      } else {
+        if (load_unit<ST, I>(a, x0, y0, z_lo + pl, uu, c)) store_unit<ST, I>(smem, z_lo + pl, uu, c);
+      }
     }
   };
 
@@ -535,6 +668,9 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
       ok[k] = load_unit<ST, I>(a, x0, y0, zn + pl, uu, pre[k]) && uraw < W * Gm::UNITS_PER_PLANE && wn < w_end;
     }
   };
+  // (the planes' references are read here, when the planes are stored: a
+  // broadcast read of one node per plane, which keeps no registers busy
+  // during the window's compute)
   auto store_planes = [&](int64_t wn, const uint4 (&pre)[Gm::PRE][3], const bool (&ok)[Gm::PRE]) {
     const int64_t zn = W * wn + I - 1;
 #pragma unroll
@@ -542,7 +678,13 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
       const int u = tid + k * NT;
       if (ok[k]) {
         const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
-        store_unit<ST, I>(smem, zn + pl, uu, pre[k]);
+        if constexpr (PSHIFT) {
+          const float3 U = plane_ref(a, x0, y0, zn + pl, Gm::TX);
+          store_unit_shifted<ST, I>(smem, zn + pl, uu, pre[k], U);
+          if (uu == 0) uref[(zn + pl) % Gm::R] = make_float4(U.x, U.y, U.z, 0.f);
+        } else {
+          store_unit<ST, I>(smem, zn + pl, uu, pre[k]);
+        }
       }
     }
   };
@@ -581,11 +723,14 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
         lc = (int)min(max((int64_t)c, W * wr), W * wr + W - 1);
       }
       if (!inside) atomicOr(a.flag, kFlagBinning);
+      // the weights are polynomials in t - 1/2 (exact in binary64 for t >= 1/4
+      // by Sterbenz's lemma and for every t that is a multiple of 2^-53;
+      // below that it rounds by less than 2^-54)
       unsigned char* rp = recs + pi * RECB;
       if constexpr (sizeof(V) == 8)
-        ((double*)rp)[ax] = td;
+        ((double*)rp)[ax] = td - 0.5;
       else
-        ((float*)rp)[ax] = (float)td;
+        ((float*)rp)[ax] = (float)(td - 0.5);
       ((uint16_t*)(rp + 32))[ax] = (uint16_t)lc;
       if (ax == 0) *(uint32_t*)(rp + 40) = qv;
       if (ax == 1) *(uint32_t*)(rp + 44) = qv;
@@ -618,13 +763,17 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
       const int l1 = (int)(lc.x & 0xFFFFu), l2 = (int)(lc.x >> 16), z3 = (int)(lc.y & 0xFFFFu);
       V r[3];
       if constexpr (GL == 32)
-        particle_sums32<ST, I>(smem, cv, j, jj, h, t1, t2, t3, l1, l2, z3, r);
+        particle_sums32<ST, I>(smem, cvr, j, jj, h, t1, t2, t3, l1, l2, z3, r);
       else
-        particle_sums<ST, I, GRAD>(smem, cv, cd, j, jj, h, t1, t2, t3, l1, l2, z3, r);
-      // which of its three totals this lane writes, and which value that is
-      // (32-lane groups: the totals are on the odd row)
-      const int sub = GRAD ? (l16 & 3) : (GL == 32 && ((tid >> 4) & 1) == 0) ? 3 : l16;
-      const int ev = GRAD ? 6 * (l16 >> 3) + 3 * ((l16 >> 2) & 1) + (l16 & 3) : l16;
+        particle_sums<ST, I, GRAD>(smem, uref, GRAD ? cvrow : cvr, cdrow, j, jj, h, t1, t2, t3, l1, l2, z3, r);
+      // which of its totals this lane writes, and which value that is: the
+      // gradient kernels hold three (value 6h + 3((j >> 2) & 1) + k in r[k],
+      // lane j & 3 writes k = j & 3); the value kernels one (value 2h +
+      // (j >> 2) in r[0], written by lane j & 3 = 0, on the first row of a
+      // 32-lane group)
+      const int sub = GRAD ? (l16 & 3)
+                           : ((j & 3) == 0 && 2 * h + (j >> 2) < 3 && (GL == 16 || ((tid >> 4) & 1) == 0)) ? 0 : 3;
+      const int ev = GRAD ? 6 * (l16 >> 3) + 3 * ((l16 >> 2) & 1) + (l16 & 3) : 2 * h + (j >> 2);
       V val = r[0];
       val = sub == 1 ? r[1] : val;
       val = sub == 2 ? r[2] : val;

@@ -45,6 +45,7 @@ size_t rebin_block_words(int64_t n);
 hipError_t rebin_incremental(const uint32_t* okeys, const uint32_t* ooff, const uint32_t* nkeys, int64_t n,
                              int64_t n_bins, int key_bits, const RebinScratch& w, uint32_t* perm, uint32_t* skeys,
                              uint32_t* noff, hipStream_t s);
+hipError_t launch_fill_i32(int* p, int64_t n, int value, hipStream_t s);
 hipError_t launch_offsets(const uint32_t* skeys, int64_t n, int64_t n_bins, uint32_t* offsets,
                           hipStream_t s);
 hipError_t gather3_f64(const double* in, const uint32_t* perm, int64_t n, double* out, hipStream_t s);
@@ -117,6 +118,15 @@ struct UpdateVel {
 hipError_t launch_update(int kind, int vel_f64, const double* X, const uint32_t* xrow, const UpdateVel& v, double dt,
                          int64_t n, double* Xout, uint32_t* keys, int N, double invd, const BinGeom& g, int* flag,
                          hipStream_t s);
+
+// orientation of axisymmetric ellipsoids (Jeffery's equation): r = rhs(G, p)
+// in FP64 from the gradient G [n][3][3] (FP64 or FP32); the update of p with
+// the rhs in v (FP64 [n][3] each) as launch_update does for positions, then
+// normalized to unit length when `unit`
+hipError_t launch_jeffery_rhs(int grad_f64, const void* G, const double* p, double shape, int64_t n, double* r,
+                              hipStream_t s);
+hipError_t launch_orient_update(int kind, const double* p, const UpdateVel& v, double dt, int64_t n, int unit,
+                                double* out, hipStream_t s);
 
 // learned.hip
 struct LearnedField {

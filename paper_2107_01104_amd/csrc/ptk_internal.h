@@ -24,13 +24,21 @@ constexpr int kLearnedPitch = 200;
 constexpr int kLearnedNParams = 41987;
 
 // Coefficients of beta_j (val) and d beta_j / dt (der) for node index
-// c = 0..I-1 (offset c - (I/2 - 1)), ascending powers of t.
+// c = 0..I-1 (offset c - (I/2 - 1)): ascending powers of t, and (cval, cder)
+// ascending powers of (t - 1/2).  The kernels evaluate the centred form: on
+// [0, 1) its terms are smaller (|t - 1/2| <= 1/2), so Horner's rule in FP32
+// loses far less to cancellation (for the I = 8 C2 spline's derivative the
+// sum of the terms' magnitudes drops from about 42 to 4).
 struct KernelTables {
   int I = 0;
   double val64[kMaxI][kMaxI];
   double der64[kMaxI][kMaxI];
   float val32[kMaxI][kMaxI];
   float der32[kMaxI][kMaxI];
+  double cval64[kMaxI][kMaxI];
+  double cder64[kMaxI][kMaxI];
+  float cval32[kMaxI][kMaxI];
+  float cder32[kMaxI][kMaxI];
 };
 
 int build_kernel_tables(int family, int I, int m, KernelTables* out);
@@ -74,6 +82,12 @@ struct ptk_ctx {
   float scale[3] = {1.f, 1.f, 1.f};
   ptk::FieldGeom geom;
   ptk::DevBuf field;
+  // the field of the end of the next time step (same grid, kernel and
+  // storage), for a Heun step whose stages see the fields of their own times
+  bool has_next = false;
+  ptk::FieldGeom geom_next;
+  ptk::DevBuf field_next;
+  float scale_next[3] = {1.f, 1.f, 1.f};
   ptk::DevBuf coef;         // device copy of the coefficient tables (KernelTables)
   ptk::KernelTables tables;
   // spectral input: transform buffer, the transform's work buffer and plan
@@ -109,7 +123,21 @@ struct ptk_ctx {
     void* k1 = nullptr;        // buffer for the next u(X_n)
     void* h[4] = {nullptr, nullptr, nullptr, nullptr};   // u_{n-1-j}
     void* hb[4] = {nullptr, nullptr, nullptr, nullptr};  // their re-binned copies
+    // orientation of axisymmetric ellipsoids (Jeffery's equation), FP64, in
+    // the current bin order: the unit axes, the next step's axes, the rhs of
+    // the step's stages, the predictor's axes, and the rhs history
+    bool ori = false;
+    double shape = 0.0;
+    double* p = nullptr;
+    double* pn = nullptr;
+    double* r1 = nullptr;
+    double* r2 = nullptr;
+    double* ps = nullptr;
+    double* ph[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* phb[4] = {nullptr, nullptr, nullptr, nullptr};
   } adv;
+  ptk::DevBuf ori_p, ori_pn, ori_r1, ori_r2, ori_ps, ori_h[4], ori_hb[4], gint2;
+  ptk::DevBuf io;  // the particle state in the caller's order, for state files
   // learned form: FP32 master parameters, Adam moments, BF16 layer copies,
   // per-workgroup gradient and loss partials, audit scratch
   ptk::DevBuf lparams, lm, lv, lw1b, lw2b, lw2bt, lgpart, llpart, lwide, laudit_x, laudit_u, laudit_sums;

@@ -133,4 +133,86 @@ hipError_t launch_update(int kind, int vel_f64, const double* X, const uint32_t*
   return hipGetLastError();
 }
 
+// ---- Orientation of axisymmetric ellipsoids (Jeffery's equation):
+//   dp/dt = W p + shape (S p - (p . S p) p),  S = (A + A^T)/2, W = (A - A^T)/2,
+// A[a][b] = du_a/dx_b the interpolated gradient (FP64 or FP32, widened).
+// Every operation is a separately rounded binary64 operation.
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_jeffery_rhs(const V* __restrict__ G, const double* __restrict__ p,
+                                                     double shape, int64_t n, double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double A[3][3], q[3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) A[a][b] = (double)G[9 * i + 3 * a + b];
+  for (int a = 0; a < 3; ++a) q[a] = p[3 * i + a];
+  double Sp[3], Wp[3];
+  for (int a = 0; a < 3; ++a) {
+    double s = 0.0, w = 0.0;
+    for (int b = 0; b < 3; ++b) {
+      const double sab = 0.5 * (A[a][b] + A[b][a]);
+      const double wab = 0.5 * (A[a][b] - A[b][a]);
+      s = s + sab * q[b];
+      w = w + wab * q[b];
+    }
+    Sp[a] = s;
+    Wp[a] = w;
+  }
+  const double pSp = (q[0] * Sp[0] + q[1] * Sp[1]) + q[2] * Sp[2];
+  for (int a = 0; a < 3; ++a) r[3 * i + a] = Wp[a] + shape * (Sp[a] - pSp * q[a]);
+}
+
+// p_out = p + dt (b0 r0 + b1 r1 + ...), or p + (0.5 dt)(r0 + r1) for the Heun
+// corrector, then (with `unit`) divided by its length.
+__global__ __launch_bounds__(256) void k_orient_update(int kind, const double* __restrict__ p, UpdateVel v,
+                                                       double dt, int64_t n, int unit, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int nk = kind == kEulerOrPredict ? 1 : kind == kHeunCorrect ? 2 : v.nk;
+  double q[3];
+  for (int d = 0; d < 3; ++d) {
+    const int64_t e = 3 * i + d;
+    const double a = ((const double*)v.k[0])[e];
+    double x;
+    if (kind == kEulerOrPredict) {
+      x = p[e] + dt * a;
+    } else if (kind == kHeunCorrect) {
+      x = p[e] + (0.5 * dt) * (a + ((const double*)v.k[1])[e]);
+    } else {
+      double inc = v.b[0] * a;
+      for (int j = 1; j < nk; ++j) inc = inc + v.b[j] * ((const double*)v.k[j])[e];
+      x = p[e] + dt * inc;
+    }
+    q[d] = x;
+  }
+  if (unit) {
+    const double len = sqrt((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]);
+    for (int d = 0; d < 3; ++d) q[d] = q[d] / len;
+  }
+  for (int d = 0; d < 3; ++d) out[3 * i + d] = q[d];
+}
+
+hipError_t launch_jeffery_rhs(int grad_f64, const void* G, const double* p, double shape, int64_t n, double* r,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (grad_f64)
+    k_jeffery_rhs<double><<<blocks, 256, 0, s>>>((const double*)G, p, shape, n, r);
+  else
+    k_jeffery_rhs<float><<<blocks, 256, 0, s>>>((const float*)G, p, shape, n, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_orient_update(int kind, const double* p, const UpdateVel& v, double dt, int64_t n, int unit,
+                                double* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int nk = kind == kEulerOrPredict ? 1 : kind == kHeunCorrect ? 2 : v.nk;
+  if (nk < 1 || nk > 4) return hipErrorInvalidValue;
+  for (int j = 0; j < nk; ++j)
+    if (!v.k[j]) return hipErrorInvalidValue;
+  k_orient_update<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(kind, p, v, dt, n, unit, out);
+  return hipGetLastError();
+}
+
 }  // namespace ptk

@@ -22,14 +22,16 @@ F64, F32, BF16, F16 = 0, 1, 2, 3
 LAGRANGE, SPLINE = 0, 1
 EULER, HEUN, AB2, AB3, AB4 = 1, 2, 3, 4, 5
 AB_ORDER = {AB2: 2, AB3: 3, AB4: 4}
-OK, EINVAL, ENOFIELD, ENOMEM, EHIP, EDOMAIN, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOFIELD, ENOMEM, EHIP, EDOMAIN, EUNSUPPORTED, EINTERNAL, EIO = 0, -1, -2, -3, -4, -5, -6, -7, -8
 TIMERS = ["interp", "interp_grad", "sort", "keys", "update", "permute", "learned", "ift"]
-SPEC_VELOCITY, SPEC_VORTICITY = 0, 1
+SPEC_VELOCITY, SPEC_VORTICITY, GRID = 0, 1, 2
 LEARNED_NFEAT, LEARNED_FEAT_PITCH, LEARNED_NPARAMS = 195, 200, 41987
 
-EXPORTS = ["ptk_kernel_table", "ptk_create", "ptk_destroy", "ptk_last_error", "ptk_set_field", "ptk_get_field_scale",
-           "ptk_set_field_spectral", "ptk_get_field", "ptk_particles_load", "ptk_particles_advance",
-           "ptk_particles_store",
+EXPORTS = ["ptk_kernel_table", "ptk_kernel_table_centred", "ptk_create", "ptk_destroy", "ptk_last_error", "ptk_set_field", "ptk_get_field_scale",
+           "ptk_set_field_spectral", "ptk_set_field_next", "ptk_get_field", "ptk_particles_load",
+           "ptk_particles_advance", "ptk_particles_store", "ptk_particles_step_next_field",
+           "ptk_particles_set_orientation", "ptk_particles_get_orientation", "ptk_particles_save",
+           "ptk_particles_restore",
            "ptk_locate", "ptk_interpolate", "ptk_interpolate_gradient", "ptk_advance_particles",
            "ptk_binning_info", "ptk_get_binning", "ptk_timing_enable", "ptk_timing_read",
            "ptk_learned_make_pairs", "ptk_learned_set_params", "ptk_learned_get_params", "ptk_learned_loss_grad",
@@ -53,6 +55,7 @@ class ptk_train_config(ctypes.Structure):
 
 _vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
 lib.ptk_kernel_table.argtypes = [ctypes.POINTER(ptk_kernel), _vp, _vp]
+lib.ptk_kernel_table_centred.argtypes = [ctypes.POINTER(ptk_kernel), _vp, _vp, _vp, _vp]
 lib.ptk_create.argtypes = [ctypes.POINTER(_vp), _int]
 lib.ptk_destroy.argtypes = [_vp]
 lib.ptk_destroy.restype = None
@@ -62,6 +65,12 @@ lib.ptk_set_field.argtypes = [_vp, _vp, _i64, _int, _int, ctypes.POINTER(ptk_ker
 lib.ptk_get_field_scale.argtypes = [_vp, ctypes.POINTER(ctypes.c_float)]
 lib.ptk_set_field_spectral.argtypes = [_vp, _vp, _i64, _int, _int, _int, ctypes.POINTER(ptk_kernel), _vp]
 lib.ptk_get_field.argtypes = [_vp, _vp, _int, _vp]
+lib.ptk_set_field_next.argtypes = [_vp, _vp, _i64, _int, _int, _vp]
+lib.ptk_particles_step_next_field.argtypes = [_vp, _dbl, _vp, _vp]
+lib.ptk_particles_set_orientation.argtypes = [_vp, _vp, _vp, _int, _dbl, _vp]
+lib.ptk_particles_get_orientation.argtypes = [_vp, _vp, _vp, _vp]
+lib.ptk_particles_save.argtypes = [_vp, ctypes.c_char_p, _vp]
+lib.ptk_particles_restore.argtypes = [_vp, ctypes.c_char_p, _vp]
 lib.ptk_locate.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
 lib.ptk_interpolate.argtypes = [_vp, _vp, _i64, _vp, _int, _vp]
 lib.ptk_interpolate_gradient.argtypes = [_vp, _vp, _i64, _vp, _vp, _int, _vp]
@@ -88,6 +97,7 @@ for _name in EXPORTS:
 
 # the C entry points under their own names
 ptk_kernel_table = lib.ptk_kernel_table
+ptk_kernel_table_centred = lib.ptk_kernel_table_centred
 ptk_create = lib.ptk_create
 ptk_destroy = lib.ptk_destroy
 ptk_last_error = lib.ptk_last_error
@@ -120,6 +130,20 @@ def kernel_table(family: int, I: int, m: int = 0):
     if rc != OK:
         raise PtkError(rc, "ptk_kernel_table failed")
     return val, der
+
+
+def kernel_table_centred(family: int, I: int, m: int = 0):
+    """(val, der, val32, der32) coefficient tables [I][I] in powers of
+    (t - 1/2), binary64 and binary32 (host only)."""
+    import numpy as np
+    val, der = np.zeros((I, I)), np.zeros((I, I))
+    v32, d32 = np.zeros((I, I), dtype=np.float32), np.zeros((I, I), dtype=np.float32)
+    k = ptk_kernel(int(family), int(I), int(m))
+    rc = lib.ptk_kernel_table_centred(ctypes.byref(k), val.ctypes.data_as(_vp), der.ctypes.data_as(_vp),
+                                      v32.ctypes.data_as(_vp), d32.ctypes.data_as(_vp))
+    if rc != OK:
+        raise PtkError(rc, "ptk_kernel_table_centred failed")
+    return val, der, v32, d32
 
 
 class PtkError(RuntimeError):
@@ -208,6 +232,36 @@ class Context:
         self._check(lib.ptk_set_field_spectral(self._h, _ptr(spec), N, in_dt, int(kind), int(storage),
                                                ctypes.byref(k), _stream(self.device)))
         self.storage, self.N = int(storage), N
+
+    def set_field_next(self, src: torch.Tensor):
+        """The field of the end of the next step (include/ptk.h,
+        ptk_set_field_next): grid values [N][N][N][3] (float64/float32) or a
+        half spectrum [N][N][N//2+1][3] (complex128/complex64) of velocity;
+        pass kind=SPEC_VORTICITY through set_field_next_spectral for a
+        vorticity spectrum."""
+        return self._set_next(src, None)
+
+    def set_field_next_spectral(self, spec: torch.Tensor, kind: int = SPEC_VELOCITY):
+        return self._set_next(spec, int(kind))
+
+    def _set_next(self, src, kind):
+        if kind is None:
+            if src.dtype not in (torch.float64, torch.float32):
+                raise TypeError("grid field must be float64 or float32")
+            form, in_dt = GRID, (F64 if src.dtype == torch.float64 else F32)
+        else:
+            if src.dtype not in (torch.complex128, torch.complex64):
+                raise TypeError("spectrum must be complex128 or complex64")
+            form, in_dt = kind, (F64 if src.dtype == torch.complex128 else F32)
+        _dev_tensor(src, src.dtype, (3,), "src")
+        self._check(lib.ptk_set_field_next(self._h, _ptr(src), src.shape[0], in_dt, form, _stream(self.device)))
+
+    def particles_step_next_field(self, dt: float, grad_out=None):
+        """One Heun step of the resident particles: first stage on the current
+        field, second on the next; the next field then becomes current."""
+        if grad_out is not None:
+            _dev_tensor(grad_out, self.vel_dtype(), (3, 3), "grad_out")
+        self._check(lib.ptk_particles_step_next_field(self._h, float(dt), _ptr(grad_out), _stream(self.device)))
 
     def get_field(self, dtype=torch.float64):
         """The stored field without halo, [N][N][N][3] (16-bit storage: unscaled)."""
@@ -304,6 +358,31 @@ class Context:
         self._check(lib.ptk_particles_store(self._h, _ptr(X), _ptr(hist), ctypes.byref(hl),
                                             _stream(self.device)))
         return hl.value
+
+    def particles_set_orientation(self, p: torch.Tensor, shape: float, hist=None, hist_len: int = 0):
+        """Unit axes p ([Np][3] float64, caller order) of the loaded particles,
+        turned by Jeffery's equation with the given shape factor in later
+        steps; an Adams-Bashforth axis history ([k][Np][3] float64) with as
+        many valid entries as the position history."""
+        _dev_tensor(p, torch.float64, (3,), "p")
+        if hist is not None:
+            _dev_tensor(hist, torch.float64, (3,), "p_hist")
+        self._check(lib.ptk_particles_set_orientation(self._h, _ptr(p), _ptr(hist), int(hist_len), float(shape),
+                                                      _stream(self.device)))
+
+    def particles_get_orientation(self, p: torch.Tensor, hist=None):
+        _dev_tensor(p, torch.float64, (3,), "p")
+        if hist is not None:
+            _dev_tensor(hist, torch.float64, (3,), "p_hist")
+        self._check(lib.ptk_particles_get_orientation(self._h, _ptr(p), _ptr(hist), _stream(self.device)))
+
+    def particles_save(self, path: str):
+        """Write the loaded state to a file in the caller's order."""
+        self._check(lib.ptk_particles_save(self._h, os.fsencode(path), _stream(self.device)))
+
+    def particles_restore(self, path: str):
+        """Make a state file's particles the loaded state."""
+        self._check(lib.ptk_particles_restore(self._h, os.fsencode(path), _stream(self.device)))
 
     def binning(self):
         """(perm, offsets, tile, window) of the last interpolate call."""

@@ -77,3 +77,49 @@ def test_null_and_bad_arguments_without_device(ptk):
     assert ptk.lib.ptk_particles_advance(None, 2, 1e-3, 1, None, None) == ptk.EINVAL
     assert ptk.lib.ptk_particles_store(None, None, None, None, None) == ptk.EINVAL
     ptk.lib.ptk_destroy(None)
+
+
+def _f32_rne(fr):
+    """Binary32 nearest to the exact rational fr (ties to even), by comparing
+    exact distances to the float32 neighbours of a candidate."""
+    from fractions import Fraction
+    c = np.float32(float(fr))
+    best = None
+    for cand in (np.nextafter(c, np.float32(-np.inf)), c, np.nextafter(c, np.float32(np.inf))):
+        d = abs(Fraction(float(cand)) - fr)
+        key = (d, int(np.array(cand, dtype=np.float32).view(np.uint32)) & 1)
+        if best is None or key < best[0]:
+            best = (key, cand)
+    return best[1]
+
+
+@pytest.mark.parametrize("fam,I,m", [(K.LAGRANGE, 4, 0), (K.LAGRANGE, 8, 0), (K.SPLINE, 4, 1),
+                                     (K.SPLINE, 6, 1), (K.SPLINE, 8, 2), (K.SPLINE, 8, 3)])
+def test_centred_tables_are_the_taylor_coefficients_at_one_half(ptk, fam, I, m):
+    """The library's tables in powers of (t - 1/2) are the oracle polynomials'
+    Taylor coefficients at t = 1/2, p^(q)(1/2) / q! (computed here exactly
+    from the oracle's rational kernels), each correctly rounded to binary64
+    and binary32; the derivative tables likewise for d beta/dt."""
+    from fractions import Fraction
+    from math import factorial
+    val, der, v32, d32 = ptk.kernel_table_centred(fam, I, m)
+    polys = K.kernel(fam, I, m)
+    half = Fraction(1, 2)
+    for j, p in enumerate(polys):
+        for q in range(I):
+            c = K.poly_eval(K.poly_deriv(list(p), q), half) / factorial(q) if q < len(p) else Fraction(0)
+            assert val[j, q] == float(c), (j, q)
+            assert v32[j, q] == _f32_rne(c), (j, q)
+            # d/dt of sum_q c_q (t - 1/2)^q has coefficient (q + 1) c_{q+1}
+            cd = (q + 1) * (K.poly_eval(K.poly_deriv(list(p), q + 1), half) / factorial(q + 1)) \
+                if q + 1 < len(p) else Fraction(0)
+            assert der[j, q] == float(cd), (j, q)
+            assert d32[j, q] == _f32_rne(cd), (j, q)
+    # the centred form evaluates to the same weights: at t = 1/4 (Horner in
+    # binary64) against the exact rationals of the golden table's reading
+    t = 0.25
+    for j, p in enumerate(polys):
+        acc = 0.0
+        for q in range(I - 1, -1, -1):
+            acc = acc * (t - 0.5) + val[j, q]
+        assert abs(acc - float(K.poly_eval(list(p), Fraction(1, 4)))) <= 1e-15

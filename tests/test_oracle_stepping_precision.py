@@ -4,6 +4,7 @@ import pytest
 import torch
 
 from oracle import geometry, precision, stepping
+from oracle.stepping import advance, jeffery_rhs, normalize, EULER, HEUN, AB2
 
 L = geometry.L
 
@@ -189,3 +190,74 @@ def test_heun_two_fields_exact_for_linear_time_dependence():
     Xa, _, _, _ = stepping.advance(X0, field_at(0.0), stepping.HEUN, dt, 1)
     Xb, _ = stepping.heun_two_fields(X0, field_at(0.0), field_at(0.0), dt)
     assert np.array_equal(Xa, Xb)
+
+
+# ---- Jeffery's equation (orientation of axisymmetric ellipsoids)
+
+def _const_grad(A):
+    def g(X):
+        return np.zeros_like(X), np.broadcast_to(A, (X.shape[0], 3, 3)).copy()
+    return g
+
+
+def test_jeffery_pure_rotation_is_a_rigid_rotation():
+    """A antisymmetric (a solid-body rotation, A p = w x p): S = 0 and W = A,
+    so dp/dt = w x p rotates p rigidly by the angle |w| t about w whatever the
+    shape; Heun converges to that rotation at second order."""
+    from scipy.spatial.transform import Rotation
+    wv = np.array([0.3, -0.7, 1.1])
+    # A such that A p = wv x p: A_ab = -eps_abc wv_c
+    A = np.array([[0.0, -wv[2], wv[1]], [wv[2], 0.0, -wv[0]], [-wv[1], wv[0], 0.0]])
+    rng = np.random.default_rng(3)
+    p0 = normalize(rng.standard_normal((50, 3)))
+    X0 = np.zeros((50, 3))
+    T = 1.0
+    ex = Rotation.from_rotvec(wv * T).apply(p0)
+    errs = []
+    for n in (40, 80, 160):
+        out = advance(X0, None, HEUN, T / n, n, gradient=_const_grad(A), orientation=(p0, 0.7))
+        errs.append(np.max(np.abs(out[4] - ex)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - 2) < 0.2), rates
+    assert errs[-1] < 3e-5
+
+
+def test_jeffery_rods_in_steady_strain_follow_the_closed_form():
+    """shape = 1 (thin rods) in a constant symmetric gradient S: dp/dt =
+    S p - (p.S p) p has the solution p(t) = e^{St} p0 / |e^{St} p0|; Heun, AB2
+    and AB4 (started from the exact history) converge to it at their order."""
+    from scipy.linalg import expm
+    B = np.array([[0.4, 0.2, -0.1], [0.2, -0.3, 0.25], [-0.1, 0.25, -0.1]])
+    rng = np.random.default_rng(4)
+    p0 = normalize(rng.standard_normal((30, 3)))
+    X0 = np.zeros((30, 3))
+    T = 1.0
+    ex = normalize(p0 @ expm(B * T).T)
+    for scheme, order in ((HEUN, 2), (AB2, 2), (EULER, 1)):
+        errs = []
+        for n in (50, 100, 200):
+            out = advance(X0, None, scheme, T / n, n, gradient=_const_grad(B), orientation=(p0, 1.0))
+            errs.append(np.max(np.abs(out[4] - ex)))
+        rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+        assert np.all(np.abs(rates - order) < 0.3), (scheme, rates)
+    # the unit length is kept and the rods turn towards the largest strain axis
+    out = advance(X0, None, HEUN, 0.01, 2000, gradient=_const_grad(B), orientation=(p0, 1.0))
+    w, v = np.linalg.eigh(B)
+    assert np.allclose(np.sum(out[4] ** 2, axis=1), 1.0, atol=1e-14)
+    assert np.min(np.abs(out[4] @ v[:, -1])) > 0.999
+
+
+def test_jeffery_rhs_special_cases():
+    """Spheres (shape 0) only rotate with the fluid, W p; the rhs is
+    orthogonal to p for every shape (the length is conserved); discs (shape
+    -1) and rods (1) differ by the sign of the strain term."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((100, 3, 3))
+    p = normalize(rng.standard_normal((100, 3)))
+    W = 0.5 * (A - np.swapaxes(A, 1, 2))
+    assert np.allclose(jeffery_rhs(A, p, 0.0), np.einsum("pab,pb->pa", W, p), atol=1e-15)
+    for shape in (-1.0, 0.3, 1.0):
+        r = jeffery_rhs(A, p, shape)
+        assert np.max(np.abs(np.sum(r * p, axis=1))) < 1e-14
+    strain = jeffery_rhs(A, p, 1.0) - jeffery_rhs(A, p, 0.0)
+    assert np.allclose(jeffery_rhs(A, p, -1.0), jeffery_rhs(A, p, 0.0) - strain, atol=1e-15)
