@@ -214,6 +214,23 @@ int ptk_interpolate(ptk_ctx *ctx, const double *X, int64_t Np, void *out, int ou
 int ptk_interpolate_gradient(ptk_ctx *ctx, const double *X, int64_t Np, void *u_out, void *grad,
                              int out_dtype, void *stream);
 
+/* Interpolation for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same computation, kernels and results as ptk_interpolate, with every
+ * scratch buffer (sort keys and values, histograms, scan partials, bin
+ * offsets) carved out of a fixed 32 MiB array in the library's own code object
+ * instead of the context's growable scratch.  The call allocates and frees
+ * nothing; the caller passes X and out as for ptk_interpolate (the field must
+ * have been set before).  Limit: the scratch of Np particles on the field's
+ * bins must fit the array (about 16 bytes per particle plus 4 per bin: some
+ * 1.6 million particles on a 1024^3 grid); larger calls return PTK_EINVAL
+ * with the size they need.  Every GPU holds one copy of the array until the
+ * process ends, shared by all contexts and calls on that GPU: calls that may
+ * overlap in time on one GPU (other streams, other host threads) race and
+ * must be ordered by the caller.  ptk_get_binning reports no binning after
+ * this call. */
+int ptk_interpolate_noalloc(ptk_ctx *ctx, const double *X, int64_t Np, void *out, int out_dtype, void *stream);
+
 /* Advance tracers dX/dt = u(X) (Eq. "tracers") by nsteps steps of dt in the
  * frozen field.
  * X: device [Np][3] binary64, in/out.  The state is the position itself,

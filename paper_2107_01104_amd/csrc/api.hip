@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <string>
 
 #include "launch.h"
@@ -396,6 +397,58 @@ int interp_common(ptk_ctx* c, const double* X, int64_t Np, void* u_out, void* gr
   return interp_core(c, w, X, Np, u_out, grad, out_dtype, S(stream), true);
 }
 
+// ---- the no-allocation entry point's scratch: one array per GPU, in the
+// library's code object (the loader places a copy on every device the
+// library runs on; it lives until the process ends).  Host code uses only the
+// device address hipGetSymbolAddress reports for the current device, never
+// the array's name.
+constexpr size_t kNoAllocBytes = (size_t)32 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device `device`, looked up
+// once per device (at ptk_create); NULL on failure.
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    g_scratch_ptr[device] = p;
+    g_scratch_done[device] = true;
+  }
+  return g_scratch_ptr[device];
+}
+
+// Carve an interpolate call's scratch out of `base` (kNoAllocBytes); false
+// if it does not fit.
+bool carve_noalloc(unsigned char* base, int64_t Np, int64_t n_bins, InterpScratch* w, size_t* need_bytes) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return (uint32_t*)p;
+  };
+  const size_t n4 = (size_t)(Np > 0 ? Np : 1) * 4;
+  w->keys_a = take(n4);
+  w->keys_b = take(n4);
+  w->vals_a = take(n4);
+  w->vals_b = take(n4);
+  const size_t hw = sort_hist_words(Np);
+  w->hist = take(hw * 4);
+  const int64_t scan_max = (int64_t)hw > n_bins + 1 ? (int64_t)hw : n_bins + 1;
+  w->scan_tmp = take(scan_tmp_words(scan_max) * 4);
+  w->offsets = take((size_t)(n_bins + 1) * 4);
+  *need_bytes = off;
+  return off <= kNoAllocBytes;
+}
+
 // ---- learned form helpers
 int learned_field(ptk_ctx* c, LearnedField* lf) {
   if (!c->has_field) return fail(c, PTK_ENOFIELD, "no field set");
@@ -494,6 +547,7 @@ int ptk_create(ptk_ctx** out, int device) {
     delete c;
     return r;
   }
+  c->noalloc = noalloc_scratch(device);
   *out = c;
   return PTK_OK;
 }
@@ -758,6 +812,24 @@ int ptk_interpolate_gradient(ptk_ctx* c, const double* X, int64_t Np, void* u_ou
                              void* stream) {
   if (c && Np > 0 && !grad) return fail(c, PTK_EINVAL, "NULL gradient output");
   return interp_common(c, X, Np, u_out, grad, out_dtype, stream);
+}
+
+int ptk_interpolate_noalloc(ptk_ctx* c, const double* X, int64_t Np, void* out, int out_dtype, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  if (Np > 0 && !out) return fail(c, PTK_EINVAL, "NULL output");
+  PTK_TRY(check_interp_args(c, X, Np, out, nullptr, out_dtype));
+  if (!c->noalloc) return fail(c, PTK_EHIP, "the device address of the library's scratch array is unknown");
+  const int64_t n_bins = n_bins_of(bin_geom(c));
+  InterpScratch w;
+  size_t need_bytes = 0;
+  if (!carve_noalloc((unsigned char*)c->noalloc, Np, n_bins, &w, &need_bytes))
+    return fail(c, PTK_EINVAL,
+                "the call needs " + std::to_string(need_bytes) + " bytes of scratch, more than the " +
+                    std::to_string(kNoAllocBytes) + " of the no-allocation array");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  return interp_core(c, w, X, Np, out, nullptr, out_dtype, S(stream), false);
 }
 
 int ptk_binning_info(const ptk_ctx* c, int64_t* np, int64_t* n_bins, int* tile, int* window) {

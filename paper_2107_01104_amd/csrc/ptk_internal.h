@@ -143,6 +143,7 @@ struct ptk_ctx {
   ptk::DevBuf lparams, lm, lv, lw1b, lw2b, lw2bt, lgpart, llpart, lwide, laudit_x, laudit_u, laudit_sums;
   bool learned_ready = false;
   int64_t learned_step = 0;
+  void* noalloc = nullptr;   // device address of the no-allocation scratch array on this device
   size_t bytes_in_use = 0;
   size_t byte_cap = 0;      // 0 = unlimited (test hook PTK_TEST_MAX_BYTES)
   bool check = true;        // PTK_NO_CHECK clears it

@@ -35,7 +35,7 @@ EXPORTS = ["ptk_kernel_table", "ptk_kernel_table_centred", "ptk_create", "ptk_de
            "ptk_locate", "ptk_interpolate", "ptk_interpolate_gradient", "ptk_advance_particles",
            "ptk_binning_info", "ptk_get_binning", "ptk_timing_enable", "ptk_timing_read",
            "ptk_learned_make_pairs", "ptk_learned_set_params", "ptk_learned_get_params", "ptk_learned_loss_grad",
-           "ptk_learned_train", "ptk_interpolate_learned", "ptk_selftest"]
+           "ptk_learned_train", "ptk_interpolate_learned", "ptk_selftest", "ptk_interpolate_noalloc"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2107_01104_amd/build.py (or "
@@ -74,6 +74,7 @@ lib.ptk_particles_restore.argtypes = [_vp, ctypes.c_char_p, _vp]
 lib.ptk_locate.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
 lib.ptk_interpolate.argtypes = [_vp, _vp, _i64, _vp, _int, _vp]
 lib.ptk_interpolate_gradient.argtypes = [_vp, _vp, _i64, _vp, _vp, _int, _vp]
+lib.ptk_interpolate_noalloc.argtypes = [_vp, _vp, _i64, _vp, _int, _vp]
 lib.ptk_advance_particles.argtypes = [_vp, _vp, _i64, _vp, ctypes.POINTER(_int), _int, _dbl, _int, _vp, _vp]
 lib.ptk_particles_load.argtypes = [_vp, _vp, _i64, _vp, _int, _int, _vp]
 lib.ptk_particles_advance.argtypes = [_vp, _int, _dbl, _int, _vp, _vp]
@@ -106,6 +107,7 @@ ptk_get_field_scale = lib.ptk_get_field_scale
 ptk_locate = lib.ptk_locate
 ptk_interpolate = lib.ptk_interpolate
 ptk_interpolate_gradient = lib.ptk_interpolate_gradient
+ptk_interpolate_noalloc = lib.ptk_interpolate_noalloc
 ptk_advance_particles = lib.ptk_advance_particles
 ptk_binning_info = lib.ptk_binning_info
 ptk_get_binning = lib.ptk_get_binning
@@ -297,6 +299,20 @@ class Context:
             out = torch.empty((n, 3), dtype=out_dtype, device=X.device)
         code = F64 if out.dtype == torch.float64 else F32
         self._check(lib.ptk_interpolate(self._h, _ptr(X), n, _ptr(out), code, _stream(self.device)))
+        return out
+
+    def interpolate_noalloc(self, X: torch.Tensor, out: torch.Tensor):
+        """ptk_interpolate_noalloc: the library allocates nothing; out is the
+        caller's [Np][3] float32 or float64 tensor."""
+        _dev_tensor(X, torch.float64, (3,), "X")
+        n = X.numel() // 3
+        if out.dtype not in (torch.float32, torch.float64):
+            raise TypeError("out must be float32 or float64")
+        _dev_tensor(out, out.dtype, (3,), "out")
+        if out.numel() // 3 != n:
+            raise ValueError("out must have Np rows")
+        code = F64 if out.dtype == torch.float64 else F32
+        self._check(lib.ptk_interpolate_noalloc(self._h, _ptr(X), n, _ptr(out), code, _stream(self.device)))
         return out
 
     def interpolate_gradient(self, X: torch.Tensor, out_dtype=torch.float32, with_value: bool = True):
