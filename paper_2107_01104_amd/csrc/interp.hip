@@ -38,11 +38,14 @@ namespace ptk {
 
 enum { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_F16 = 3 };
 
+// 16-bit storage: the nodes are widened to FP32 (exactly) when they are staged
+// into the LDS ring, so the sums read the same 16-byte nodes as FP32 storage
+// and spend no instruction on conversions; HBM moves the 6-byte nodes.
 template <int ST>
 struct StoreT {
   using acc = float;
   static constexpr int T = kTileF32;   // tile edge in cells
-  static constexpr int NB = 8;         // LDS bytes per node
+  static constexpr int NB = 16;        // LDS bytes per node
   static constexpr int GB = 6;         // global (stored) bytes per node
   static constexpr int THREADS = 512;
 };
@@ -167,7 +170,17 @@ __device__ __forceinline__ void lds_put(unsigned char* smem, int off, const uint
     const uint32_t h0 = (w[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
     const uint32_t h1 = (w[(k + 1) >> 1] >> (((k + 1) & 1) * 16)) & 0xFFFFu;
     const uint32_t h2 = (w[(k + 2) >> 1] >> (((k + 2) & 1) * 16)) & 0xFFFFu;
-    *(uint2*)(smem + off) = make_uint2(h0 | (h1 << 16), h2);
+    float f0, f1, f2;
+    if constexpr (ST == ST_BF16) {
+      f0 = __uint_as_float(h0 << 16);
+      f1 = __uint_as_float(h1 << 16);
+      f2 = __uint_as_float(h2 << 16);
+    } else {
+      f0 = __half2float(__ushort_as_half((unsigned short)h0));
+      f1 = __half2float(__ushort_as_half((unsigned short)h1));
+      f2 = __half2float(__ushort_as_half((unsigned short)h2));
+    }
+    *(float4*)(smem + off) = make_float4(f0, f1, f2, 0.f);
   }
 }
 
@@ -189,18 +202,13 @@ __device__ __forceinline__ void lds_get(const unsigned char* smem, int off, V* v
     v[1] = a.y;
     v[2] = b.x;
     keep = (uint32_t)__double_as_longlong(b.y);
-  } else if constexpr (ST == ST_BF16) {
-    const uint2 u = *(const uint2*)(smem + off);
-    v[0] = __uint_as_float(u.x << 16);
-    v[1] = __uint_as_float(u.x & 0xFFFF0000u);
-    v[2] = __uint_as_float(u.y << 16);
-    keep = 0;
   } else {
-    const uint2 u = *(const uint2*)(smem + off);
-    v[0] = __half2float(__ushort_as_half((unsigned short)(u.x & 0xFFFFu)));
-    v[1] = __half2float(__ushort_as_half((unsigned short)(u.x >> 16)));
-    v[2] = __half2float(__ushort_as_half((unsigned short)(u.y & 0xFFFFu)));
-    keep = 0;
+    // 16-bit storage, widened at staging
+    const float4 f = *(const float4*)(smem + off);
+    v[0] = f.x;
+    v[1] = f.y;
+    v[2] = f.z;
+    keep = __float_as_uint(f.w);
   }
 }
 
@@ -321,6 +329,8 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const f
   // number of plane pitches
   // weights: lanes 0-7 evaluate beta_j(t2), lanes 8-15 beta_j(t3); all lanes beta_j(t1)
   const V tsel = h ? t3 : t2;
+  // the gradient kernels read their coefficient rows from LDS here (their
+  // registers are needed for the sums); the value kernels pass register rows
   V cvl[GRAD ? I : 1];
   if constexpr (GRAD) coef_row<I>(cvrow, cvl);
   const V* cv = GRAD ? cvl : cvrow;
@@ -645,7 +655,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   // permutation where positions are read through it) one window before
   // loading their coordinates keeps a window with few particles from waiting
   // on two loads in a row.
-  constexpr int DEPTH = GRAD ? 1 : 2;
+  constexpr int DEPTH = (GRAD || ST == ST_BF16 || ST == ST_F16) ? 1 : 2;
   uint4 pre[DEPTH][Gm::PRE][3];
   bool pok[DEPTH][Gm::PRE];
   // window w+1: its particle range, this thread's coordinate and destination
