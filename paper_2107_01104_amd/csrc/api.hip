@@ -293,6 +293,7 @@ InterpArgs base_args(const ptk_ctx* c, bool next_field = false) {
   int64_t nseg = (1024 + a.n_tiles - 1) / a.n_tiles;
   if (nseg > a.nw) nseg = a.nw;
   if (nseg < 1) nseg = 1;
+  if (nseg < (a.nw + kMaxWps - 1) / kMaxWps) nseg = (a.nw + kMaxWps - 1) / kMaxWps;
   a.wps = (a.nw + nseg - 1) / nseg;
   a.nseg = (a.nw + a.wps - 1) / a.wps;
   a.offsets = (const uint32_t*)c->offsets.ptr;

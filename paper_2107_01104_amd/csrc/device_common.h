@@ -24,10 +24,19 @@ __device__ __forceinline__ bool in_domain(double x) { return fabs(x) < 0x1p50; }
 __device__ __forceinline__ double locate(double x, int N, double invd, int* c, double* t) {
   const double L = 6.283185307179586;
   if (!in_domain(x)) x = 0.0;
-  double q = floor(x / L);
-  double y = x - L * q;
-  if (y < 0.0) y = y + L;
-  if (y >= L) y = 0.0;
+  double y;
+  if (x >= 0.0 && x < L) {
+    // the sequence below gives q = 0 here (x / L rounds below 1 for every
+    // x < L: x <= L - 2^-50, so x / L <= 1 - 1.59 * 2^-53, which rounds to
+    // 1 - 2^-52) and so y = x - 0 = x + 0: skip the division (x + 0.0 turns
+    // -0 into +0 as the subtraction does)
+    y = x + 0.0;
+  } else {
+    const double q = floor(x / L);
+    y = x - L * q;
+    if (y < 0.0) y = y + L;
+    if (y >= L) y = 0.0;
+  }
   double s = y * invd;
   double cf = floor(s);
   int ci = (int)cf;

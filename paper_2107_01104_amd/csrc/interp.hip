@@ -89,12 +89,27 @@ template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
+// 64-bit moves: one v_mov_b64_dpp for row_newbcast (the only control DPP
+// has for 64-bit operands; the compiler splits the others into two 32-bit
+// moves).  A 64-bit broadcast issues as fast as a 32-bit one.
+// (the builtin's result is given a 64-bit type explicitly: inside a
+// template the front end types the generic builtin's call as int)
+template <int CTRL>
+__device__ __forceinline__ long dpp64(long v) {
+  const long r = __builtin_amdgcn_update_dpp(0L, v, CTRL, 0xF, 0xF, true);
+  return r;
+}
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
-  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+  return __builtin_bit_cast(double, dpp64<CTRL>(__builtin_bit_cast(long, v)));
+}
+// a pair of FP32 values moved by one 64-bit DPP move
+__device__ __forceinline__ long pack2(float lo, float hi) {
+  return (long)(((unsigned long)__float_as_uint(hi) << 32) | __float_as_uint(lo));
+}
+__device__ __forceinline__ void unpack2(long p, float& lo, float& hi) {
+  lo = __uint_as_float((uint32_t)(unsigned long)p);
+  hi = __uint_as_float((uint32_t)((unsigned long)p >> 32));
 }
 // value of lane L of this row
 template <int L, typename V>
@@ -109,14 +124,14 @@ __device__ __forceinline__ float bcast2(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(a, __builtin_bit_cast(int, v), 0x150 + L1, 0xF, 0xC, false));
 }
 template <int L0, int L1>
+__device__ __forceinline__ long bcast2_64(long b) {
+  const long a = __builtin_amdgcn_update_dpp(0L, b, 0x150 + L0, 0xF, 0xF, true);
+  const long r = __builtin_amdgcn_update_dpp(a, b, 0x150 + L1, 0xF, 0xC, false);
+  return r;
+}
+template <int L0, int L1>
 __device__ __forceinline__ double bcast2(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = (int)(b & 0xFFFFFFFFll), hi = (int)(b >> 32);
-  const int alo = __builtin_amdgcn_mov_dpp(lo, 0x150 + L0, 0xF, 0xF, true);
-  const int ahi = __builtin_amdgcn_mov_dpp(hi, 0x150 + L0, 0xF, 0xF, true);
-  const int rlo = __builtin_amdgcn_update_dpp(alo, lo, 0x150 + L1, 0xF, 0xC, false);
-  const int rhi = __builtin_amdgcn_update_dpp(ahi, hi, 0x150 + L1, 0xF, 0xC, false);
-  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)rhi << 32) | (unsigned)rlo));
+  return __builtin_bit_cast(double, bcast2_64<L0, L1>(__builtin_bit_cast(long, v)));
 }
 
 // sum over the 16 lanes of the row (every lane gets the total)
@@ -212,6 +227,23 @@ __device__ __forceinline__ void lds_get(const unsigned char* smem, int off, V* v
   }
 }
 
+// An empty asm that reads a prefetched register, placed where every path
+// needs the load complete anyway: then no load into the register is still
+// pending on any path when the next prefetch reuses it (the compiler would
+// otherwise wait there for every outstanding load, the ones just issued
+// included).
+__device__ __forceinline__ void settle(uint32_t v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void settle(double v) {
+  settle((uint32_t)__double_as_longlong(v));
+  settle((uint32_t)((unsigned long long)__double_as_longlong(v) >> 32));
+}
+__device__ __forceinline__ void settle(const uint4& v) {
+  settle(v.x);
+  settle(v.y);
+  settle(v.z);
+  settle(v.w);
+}
+
 // f(integral_constant<int, K>) for K = B .. E-1
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -223,12 +255,15 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 // Row of I coefficients of the lane's node from the workgroup's LDS copy of
 // the table, read when a round needs it instead of being held in registers
-// for the whole launch (the registers go to LDS reads in flight).  The row
-// address passes through an empty asm statement each time, so the compiler
-// cannot hoist the reads out of the particle loop.
+// for the whole launch (the registers go to LDS reads in flight).  The row's
+// offset passes through an empty asm statement each time, so the compiler
+// cannot hoist the reads out of the particle loop; the pointer itself stays
+// visibly an LDS pointer (laundering it would turn the reads into flat loads,
+// whose waits also wait for every global load in flight).
 template <int I, typename V>
-__device__ __forceinline__ void coef_row(const V* row, V* c) {
-  asm volatile("" : "+v"(row));
+__device__ __forceinline__ void coef_row(const V* tab, int off, V* c) {
+  asm volatile("" : "+v"(off));
+  const V* row = tab + off;
   if constexpr (sizeof(V) == 4) {
 #pragma unroll
     for (int p = 0; p < I; p += 4) {
@@ -318,8 +353,8 @@ __device__ __forceinline__ void store_unit_shifted(unsigned char* smem, int64_t 
 // slot has parity h).
 // Leaves in r the 3 values (and 9 gradient entries) summed over the group.
 template <int ST, int I, bool GRAD, typename V>
-__device__ __forceinline__ void particle_sums(const unsigned char* smem, const float4* uref, const V* cvrow,
-                                              const V* cdrow, int j, int jj, int h, V t1, V t2, V t3, int l1, int l2,
+__device__ __forceinline__ void particle_sums(const unsigned char* smem, const float4* uref, const V* ctab,
+                                              const V* cvreg, int j, int jj, int h, V t1, V t2, V t3, int l1, int l2,
                                               int z3, V* r) {
   using Gm = Geom<ST, I>;
   constexpr int NB = Gm::NB, RP = Gm::RP, PL = Gm::PL, R = Gm::R;
@@ -332,31 +367,47 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const f
   // the gradient kernels read their coefficient rows from LDS here (their
   // registers are needed for the sums); the value kernels pass register rows
   V cvl[GRAD ? I : 1];
-  if constexpr (GRAD) coef_row<I>(cvrow, cvl);
-  const V* cv = GRAD ? cvl : cvrow;
+  if constexpr (GRAD) coef_row<I>(ctab, jj * I, cvl);
+  const V* cv = GRAD ? cvl : cvreg;
   const V wsel = horner<I>(cv, tsel);
   V w1 = horner<I>(cv, t1);
   if (j >= I) w1 = (V)0;
   V w2[I], w3[HALF];
-#define PTK_B2(k) if constexpr ((k) < I) w2[k] = bcast<k>(wsel);
-  PTK_B2(0) PTK_B2(1) PTK_B2(2) PTK_B2(3) PTK_B2(4) PTK_B2(5) PTK_B2(6) PTK_B2(7)
-#undef PTK_B2
-#define PTK_B3(m) if constexpr ((m) < HALF) w3[m] = bcast2<8 + 2 * (m), 9 + 2 * (m)>(wsel);
-  PTK_B3(0) PTK_B3(1) PTK_B3(2) PTK_B3(3)
-#undef PTK_B3
   V d1 = (V)0, dw2[I], dw3[HALF];
-  if constexpr (GRAD) {
+  if constexpr (GRAD && sizeof(V) == 4) {
+    // FP32 gradients: each lane's (beta, beta') pair travels in one 64-bit move
     V cd[I];
-    coef_row<I>(cdrow, cd);
+    coef_row<I>(ctab, I * I + jj * I, cd);
     const V dsel = horner<I - 1>(cd, tsel);
     d1 = horner<I - 1>(cd, t1);
     if (j >= I) d1 = (V)0;
+    const long pr = pack2(wsel, dsel);
+#define PTK_P2(k) if constexpr ((k) < I) unpack2(dpp64<0x150 + (k)>(pr), w2[k], dw2[k]);
+    PTK_P2(0) PTK_P2(1) PTK_P2(2) PTK_P2(3) PTK_P2(4) PTK_P2(5) PTK_P2(6) PTK_P2(7)
+#undef PTK_P2
+#define PTK_P3(m) if constexpr ((m) < HALF) unpack2(bcast2_64<8 + 2 * (m), 9 + 2 * (m)>(pr), w3[m], dw3[m]);
+    PTK_P3(0) PTK_P3(1) PTK_P3(2) PTK_P3(3)
+#undef PTK_P3
+  } else {
+#define PTK_B2(k) if constexpr ((k) < I) w2[k] = bcast<k>(wsel);
+    PTK_B2(0) PTK_B2(1) PTK_B2(2) PTK_B2(3) PTK_B2(4) PTK_B2(5) PTK_B2(6) PTK_B2(7)
+#undef PTK_B2
+#define PTK_B3(m) if constexpr ((m) < HALF) w3[m] = bcast2<8 + 2 * (m), 9 + 2 * (m)>(wsel);
+    PTK_B3(0) PTK_B3(1) PTK_B3(2) PTK_B3(3)
+#undef PTK_B3
+    if constexpr (GRAD) {
+      V cd[I];
+      coef_row<I>(ctab, I * I + jj * I, cd);
+      const V dsel = horner<I - 1>(cd, tsel);
+      d1 = horner<I - 1>(cd, t1);
+      if (j >= I) d1 = (V)0;
 #define PTK_D2(k) if constexpr ((k) < I) dw2[k] = bcast<k>(dsel);
-    PTK_D2(0) PTK_D2(1) PTK_D2(2) PTK_D2(3) PTK_D2(4) PTK_D2(5) PTK_D2(6) PTK_D2(7)
+      PTK_D2(0) PTK_D2(1) PTK_D2(2) PTK_D2(3) PTK_D2(4) PTK_D2(5) PTK_D2(6) PTK_D2(7)
 #undef PTK_D2
 #define PTK_D3(m) if constexpr ((m) < HALF) dw3[m] = bcast2<8 + 2 * (m), 9 + 2 * (m)>(dsel);
-    PTK_D3(0) PTK_D3(1) PTK_D3(2) PTK_D3(3)
+      PTK_D3(0) PTK_D3(1) PTK_D3(2) PTK_D3(3)
 #undef PTK_D3
+    }
   }
   // contraction: x2 over all rows per plane, x3 over this lane's planes
   const int noff = l2 * RP + (l1 + jj) * NB;
@@ -381,6 +432,14 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const f
     const int slot = s0 + 2 * m < R ? s0 + 2 * m : s0 + 2 * m - R;
     const int base = slot * PL + noff;
     V s[3] = {0, 0, 0}, sd[3] = {0, 0, 0};
+    if constexpr (SHIFT) {
+      // the plane's U(z) - U(z_c) starts the x2 sum (the x2 derivative sum
+      // needs none: the derivative weights sum to 0)
+      const float4 um = uref[slot];
+      s[0] = um.x - uc.x;
+      s[1] = um.y - uc.y;
+      s[2] = um.z - uc.z;
+    }
     // rows read together before use: four for values, two for gradients
     // (four would pass the 128-VGPR budget of two workgroups per CU and spill)
     constexpr int G = GRAD ? 2 : (I % 4 == 0 ? 4 : 2);
@@ -399,12 +458,6 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const f
         }
         asm("" : "+v"(sink) : "v"(keep[k]));
       }
-    }
-    if constexpr (SHIFT) {
-      const float4 um = uref[slot];
-      s[0] += um.x - uc.x;
-      s[1] += um.y - uc.y;
-      s[2] += um.z - uc.z;
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -561,6 +614,12 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   // value per plane: U(z) of the plane in ring slot s (see particle_sums)
   constexpr bool PSHIFT = GRAD && ST == ST_F32;
   __shared__ float4 uref[PSHIFT ? Gm::R : 1];
+  // the references of the planes the next window adds, posted before the
+  // barrier that precedes their store
+  __shared__ float4 unext[PSHIFT ? W : 1];
+  // the bin offsets of this segment's windows, [w_begin, w_end]: read once, so
+  // no window waits on a global load to find its range
+  __shared__ uint32_t woff[kMaxWps + 1];
 
   // ---- block -> (tile column, x3 segment); consecutive blocks go round-robin
   // to the 8 XCDs, so XCD x is given a contiguous range of an ordering of the
@@ -589,6 +648,10 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   const int64_t w_begin = (int64_t)seg * a.wps;
   const int64_t w_end = min(a.nw, w_begin + a.wps);
   if (w_begin >= w_end) return;
+  {
+    const int64_t bin0 = tile * a.nw + w_begin;
+    for (int e = threadIdx.x; e <= (int)(w_end - w_begin); e += Gm::THREADS) woff[e] = a.offsets[bin0 + e];
+  }
   const int tx = (int)(tile % a.ntx), ty = (int)(tile / a.ntx);
   const int64_t x0 = (int64_t)tx * T, y0 = (int64_t)ty * T;
   const int tid = threadIdx.x;
@@ -613,14 +676,13 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
     }
   }
   const V* cvrow = ctab + jj * I;
-  const V* cdrow = ctab + I * I + jj * I;
   // value kernels hold their row in registers for the whole launch (a read
   // per round would sit at the head of every round's dependency chain); the
   // gradient kernels, which need their registers for the sums, read both
   // rows from LDS at the start of each round
   V cvr[GRAD ? 1 : I];
+  __syncthreads();  // ctab and woff are complete
   if constexpr (!GRAD) {
-    __syncthreads();
 #pragma unroll
     for (int p = 0; p < I; ++p) cvr[p] = cvrow[p];
   }
@@ -678,20 +740,55 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
       ok[k] = load_unit<ST, I>(a, x0, y0, zn + pl, uu, pre[k]) && uraw < W * Gm::UNITS_PER_PLANE && wn < w_end;
     }
   };
-  // (the planes' references are read here, when the planes are stored: a
-  // broadcast read of one node per plane, which keeps no registers busy
-  // during the window's compute)
+  // FP32 gradient kernels: the reference node of every plane (plane_ref's
+  // node, clamped into the padded field) lies in one unit of the plane, the
+  // same unit index for every plane of the column; the thread that holds it
+  // in its prefetch registers posts its value before the barrier that
+  // precedes store_planes, so no thread waits on a global load to shift its
+  // nodes.
+  int ref_unit = 0, ref_q = 0;
+  if constexpr (PSHIFT) {
+    const int rx = (int)min((int64_t)(Gm::TX / 2), a.P - 1 - x0), ry = (int)min((int64_t)(Gm::TX / 2), a.P - 1 - y0);
+    ref_unit = ry * Gm::RG + rx / Gm::G;
+    ref_q = rx % Gm::G;
+  }
+  auto post_refs = [&](const uint4 (&pre)[Gm::PRE][3], const bool (&ok)[Gm::PRE]) {
+    if constexpr (PSHIFT) {
+#pragma unroll
+      for (int k = 0; k < Gm::PRE; ++k) {
+        const int u = tid + k * NT;
+        if (ok[k] && u % Gm::UNITS_PER_PLANE == ref_unit) {
+          // node ref_q of the chunk, picked by selects (a run-time index into
+          // the registers would move them to scratch memory)
+          const uint32_t wd[12] = {pre[k][0].x, pre[k][0].y, pre[k][0].z, pre[k][0].w, pre[k][1].x, pre[k][1].y,
+                                   pre[k][1].z, pre[k][1].w, pre[k][2].x, pre[k][2].y, pre[k][2].z, pre[k][2].w};
+          uint32_t n0 = wd[0], n1 = wd[1], n2 = wd[2];
+#pragma unroll
+          for (int q = 1; q < Gm::G; ++q) {
+            n0 = ref_q == q ? wd[3 * q] : n0;
+            n1 = ref_q == q ? wd[3 * q + 1] : n1;
+            n2 = ref_q == q ? wd[3 * q + 2] : n2;
+          }
+          unext[u / Gm::UNITS_PER_PLANE] = make_float4(__uint_as_float(n0), __uint_as_float(n1), __uint_as_float(n2), 0.f);
+        }
+      }
+    }
+  };
   auto store_planes = [&](int64_t wn, const uint4 (&pre)[Gm::PRE][3], const bool (&ok)[Gm::PRE]) {
     const int64_t zn = W * wn + I - 1;
+#pragma unroll
+    for (int k = 0; k < Gm::PRE; ++k)
+      for (int c = 0; c < 3; ++c) settle(pre[k][c]);
 #pragma unroll
     for (int k = 0; k < Gm::PRE; ++k) {
       const int u = tid + k * NT;
       if (ok[k]) {
         const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
         if constexpr (PSHIFT) {
-          const float3 U = plane_ref(a, x0, y0, zn + pl, Gm::TX);
+          const float4 U4 = unext[pl];
+          const float3 U = make_float3(U4.x, U4.y, U4.z);
           store_unit_shifted<ST, I>(smem, zn + pl, uu, pre[k], U);
-          if (uu == 0) uref[(zn + pl) % Gm::R] = make_float4(U.x, U.y, U.z, 0.f);
+          if (uu == 0) uref[(zn + pl) % Gm::R] = U4;
         } else {
           store_unit<ST, I>(smem, zn + pl, uu, pre[k]);
         }
@@ -710,6 +807,8 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   };
   // steps 1-3 of Sec. 2.2 once per coordinate: one thread per (particle, axis)
   auto write_rec = [&](int64_t wr, int n, double xv, uint32_t qv) {
+    settle(xv);
+    settle(qv);
     if (tid < 3 * n) {
       const int pi = tid / 3, ax = tid % 3;
       int c;
@@ -775,7 +874,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
       if constexpr (GL == 32)
         particle_sums32<ST, I>(smem, cvr, j, jj, h, t1, t2, t3, l1, l2, z3, r);
       else
-        particle_sums<ST, I, GRAD>(smem, uref, GRAD ? cvrow : cvr, cdrow, j, jj, h, t1, t2, t3, l1, l2, z3, r);
+        particle_sums<ST, I, GRAD>(smem, uref, ctab, cvr, j, jj, h, t1, t2, t3, l1, l2, z3, r);
       // which of its totals this lane writes, and which value that is: the
       // gradient kernels hold three (value 6h + 3((j >> 2) & 1) + k in r[k],
       // lane j & 3 writes k = j & 3); the value kernels one (value 2h +
@@ -817,19 +916,18 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
     s_out = start;
     e_out = end;
     nv = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
-    if (nv > 0) {
-      const int pi = min(tid / 3, nv - 1);
-      const int64_t p = min((int64_t)start + pi, (int64_t)a.np - 1);
-      iv = a.xrow ? a.xrow[p] : (uint32_t)p;
-      // axis-1 threads fetch the gradient destination, the others the value one
-      const uint32_t* src = (tid % 3 == 1 && a.grad_orig) ? a.grad_orig : a.orig;
-      qv = src ? src[p] : (uint32_t)p;
-    }
+    // unconditional (clamped to a particle of the launch: the segment has
+    // one), so every path has the same loads in flight and no wait for them
+    // lands early
+    const int pi = min(tid / 3, max(nv - 1, 0));
+    const int64_t p = min((int64_t)start + pi, (int64_t)a.np - 1);
+    iv = a.xrow ? a.xrow[p] : (uint32_t)p;
+    // axis-1 threads fetch the gradient destination, the others the value one
+    const uint32_t* src = (tid % 3 == 1 && a.grad_orig) ? a.grad_orig : a.orig;
+    qv = src ? src[p] : (uint32_t)p;
   };
-  // the coordinate of that row
-  auto issue_window_x = [&](uint32_t iv, int nv, double& xv) {
-    if (nv > 0) xv = a.X[3 * (int64_t)iv + tid % 3];
-  };
+  // the coordinate of that row (iv is always a row of X)
+  auto issue_window_x = [&](uint32_t iv, double& xv) { xv = a.X[3 * (int64_t)iv + tid % 3]; };
   // one window: records of w are in LDS, the ring holds w's planes, the
   // position registers hold w's range; plane buffer B (w - w_begin mod DEPTH)
   // receives the planes of w+DEPTH
@@ -838,13 +936,16 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
     constexpr int B1 = (B + 1) % DEPTH;
     const uint32_t start = pos_s, end = pos_e;
     // positions of w+1 from the rows found a window ago, then the rows of w+2
+    // (the rows' loads are waited for before any new load is issued)
+    settle(idx_i);
+    settle(idx_q);
     pos_s = idx_s;
     pos_e = idx_e;
     pos_n = idx_n;
     pos_q = idx_q;
-    issue_window_x(idx_i, idx_n, pos_x);
+    issue_window_x(idx_i, pos_x);
     issue_window_idx(idx_e, w + 2 < w_end ? end3 : idx_e, idx_i, idx_q, idx_n, idx_s, idx_e);
-    if (w + 3 < w_end) end3 = a.offsets[tile * a.nw + w + 4];
+    if (w + 3 < w_end) end3 = woff[w + 4 - w_begin];
     issue_planes(w + DEPTH, pre[B], pok[B]);
     __syncthreads();  // records of w and the ring are complete
     int n = (int)min((int64_t)CH, (int64_t)end - (int64_t)start);
@@ -860,6 +961,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
       __syncthreads();
       compute_chunk(m);
     }
+    post_refs(pre[B1], pok[B1]);
     __syncthreads();  // every read of this window's ring slots and records is done
     // the ring holds at least the planes one window touches: w+1's new planes
     // replace planes no later window reads; then w+1's records
@@ -868,11 +970,10 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   };
 
   {
-    const int64_t bin0 = tile * a.nw;
-    if (a.offsets[bin0 + w_begin] == a.offsets[bin0 + w_end]) return;  // no particle in this segment
+    if (woff[0] == woff[w_end - w_begin]) return;  // no particle in this segment
     if constexpr (SPARSE) {
       for (int64_t w = w_begin; w < w_end; ++w) {
-        const uint32_t start = a.offsets[bin0 + w], end = a.offsets[bin0 + w + 1];
+        const uint32_t start = woff[w - w_begin], end = woff[w + 1 - w_begin];
         if (start == end) continue;
         fill(w);
         for (uint32_t c0 = start; c0 < end; c0 += CH) {
@@ -898,13 +999,11 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
     double xv = 0.0;
     uint32_t qv = 0, iv = 0;
     int nv = 0;
-    const int64_t bin0 = tile * a.nw;
-    issue_window_idx(a.offsets[bin0 + w_begin], a.offsets[bin0 + w_begin + 1], iv, qv, nv, pos_s, pos_e);
-    issue_window_x(iv, nv, xv);
+    issue_window_idx(woff[0], woff[1], iv, qv, nv, pos_s, pos_e);
+    issue_window_x(iv, xv);
     write_rec(w_begin, nv, xv, qv);
-    issue_window_idx(pos_e, w_begin + 1 < w_end ? a.offsets[bin0 + w_begin + 2] : pos_e, idx_i, idx_q, idx_n, idx_s,
-                     idx_e);
-    if (w_begin + 2 < w_end) end3 = a.offsets[bin0 + w_begin + 3];
+    issue_window_idx(pos_e, w_begin + 1 < w_end ? woff[2] : pos_e, idx_i, idx_q, idx_n, idx_s, idx_e);
+    if (w_begin + 2 < w_end) end3 = woff[3];
   }
   static_for<1, DEPTH>([&](auto K) { issue_planes(w_begin + decltype(K)::value, pre[decltype(K)::value], pok[decltype(K)::value]); });
   // windows in pairs so that every plane buffer index is a constant (single
@@ -913,7 +1012,15 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   if constexpr (DEPTH == 2) {
     for (int64_t w = w_begin; w < w_end; w += 2) {
       window(w, std::integral_constant<int, 0>{});
-      if (w + 1 < w_end) window(w + 1, std::integral_constant<int, 1>{});
+      if (w + 1 < w_end) {
+        window(w + 1, std::integral_constant<int, 1>{});
+      } else {
+        // (the loads of the buffer the skipped window would have stored are
+        // settled on this path too; see settle)
+#pragma unroll
+        for (int k = 0; k < Gm::PRE; ++k)
+          for (int c = 0; c < 3; ++c) settle(pre[0][k][c]);
+      }
     }
   } else {
     for (int64_t w = w_begin; w < w_end; ++w) window(w, std::integral_constant<int, 0>{});

@@ -17,6 +17,9 @@ constexpr int kMaxI = 8;           // largest kernel size built into the library
 constexpr int kTileF32 = 12;       // FP32, BF16, FP16 storage
 constexpr int kTileF64 = 12;       // FP64 storage
 constexpr int kWindow = 5;
+// windows per x3 segment of a column (one workgroup): the kernel keeps the
+// segment's bin offsets in LDS
+constexpr int kMaxWps = 224;
 constexpr double kL = 6.283185307179586;  // fl64(2*pi)
 // learned correction form: features per particle, their row pitch, parameters
 constexpr int kLearnedNFeat = 195;
