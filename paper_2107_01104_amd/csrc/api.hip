@@ -798,7 +798,7 @@ int ptk_locate(ptk_ctx* c, const double* X, int64_t Np, int32_t* cell, double* t
   DeviceGuard g(c->device);
   if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
   hipStream_t s = S(stream);
-  PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
+  PTK_HIP(c, launch_fill_i32((int*)c->flag.ptr, 1, 0, s), "flag clear");
   PTK_HIP(c, launch_locate(X, 3 * Np, (int)c->geom.N, invd_of(c->geom.N), cell, t, (int*)c->flag.ptr, s),
           "locate");
   return check_flag(c, s);
@@ -909,7 +909,7 @@ int adv_load(ptk_ctx* c, const double* X, int64_t Np, const void* rhs_hist, int 
   c->bin_valid = false;  // the sort below reuses the interpolate calls' sort buffers
   uint32_t* keys = (uint32_t*)c->keys_a.ptr;
   int* flag = (int*)c->flag.ptr;
-  PTK_HIP(c, hipMemsetAsync(flag, 0, sizeof(int), s), "flag clear");
+  PTK_HIP(c, launch_fill_i32(flag, 1, 0, s), "flag clear");
   if (Np > 0) {
     {
       Timed t(c, s, PTK_T_KEYS);
@@ -1078,7 +1078,7 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
     std::swap(c->aoff, c->offsets2);
   };
 
-  PTK_HIP(c, hipMemsetAsync(flag, 0, sizeof(int), s), "flag clear");
+  PTK_HIP(c, launch_fill_i32(flag, 1, 0, s), "flag clear");
   for (int step = 0; step < nsteps; ++step) {
     const bool last = step == nsteps - 1;
     void* k1 = st.k1;
@@ -1579,7 +1579,7 @@ int ptk_learned_make_pairs(ptk_ctx* c, const double* X, int64_t Np, uint16_t* fe
     PTK_TRY(need(c, c->lwide, (size_t)Np * 12, "wide-kernel values"));
     PTK_TRY(interp_common(c, X, Np, c->lwide.ptr, nullptr, PTK_F32, stream));
   }
-  PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
+  PTK_HIP(c, launch_fill_i32((int*)c->flag.ptr, 1, 0, s), "flag clear");
   PTK_HIP(c,
           launch_learned_pairs(lf, X, Np, (const float*)c->lwide.ptr, feat, target, (int*)c->flag.ptr, s),
           "training pairs");
@@ -1738,7 +1738,7 @@ int ptk_interpolate_learned(ptk_ctx* c, const double* X, int64_t Np, float* out,
   const int64_t n_bins = n_bins_of(bg);
   c->bin_valid = false;
   PTK_TRY(ensure_binning(c, Np, n_bins));
-  PTK_HIP(c, hipMemsetAsync(c->flag.ptr, 0, sizeof(int), s), "flag clear");
+  PTK_HIP(c, launch_fill_i32((int*)c->flag.ptr, 1, 0, s), "flag clear");
   {
     Timed t(c, s, PTK_T_KEYS);
     PTK_HIP(c, launch_keys(X, Np, (int)N, invd_of(N), bg, (uint32_t*)c->keys_a.ptr, (int*)c->flag.ptr, s),

@@ -529,7 +529,7 @@ hipError_t rebin_incremental(const uint32_t* okeys, const uint32_t* ooff, const 
   const int64_t n_tiles = (n + kTile - 1) / kTile;
   hipError_t e;
   // movers per tile, exclusive scan: the last entry becomes the mover count m
-  if ((e = hipMemsetAsync(w.blockoff + n_tiles, 0, 4, s)) != hipSuccess) return e;
+  if ((e = launch_fill_i32((int*)(w.blockoff + n_tiles), 1, 0, s)) != hipSuccess) return e;
   k_rebin_count<<<(unsigned)n_tiles, 256, 0, s>>>(okeys, nkeys, n, w.blockoff);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = exclusive_scan_u32(w.blockoff, n_tiles + 1, w.scan_tmp, s)) != hipSuccess) return e;

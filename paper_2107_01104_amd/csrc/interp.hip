@@ -13,14 +13,16 @@
 // and 16-bit nodes the ring leaves room for two 512-thread workgroups per CU
 // (16 waves); FP64 nodes fill the LDS with one.
 //
-// Per particle: a group of 16 lanes (32 for the FP32/16-bit value kernels with
-// I = 4 or 8).  Lane j = lane & 7 owns the x1 node offset j; the half-rows
-// (and rows) split the particle's I planes between them.  Each lane contracts
-// x2 for each of its planes and x3 over them, scales by its x1 weight, and the
-// group sums over its lanes with DPP: the paper's split of the triple sum into
-// partial sums finished along the remaining direction (Sec. 3.3), inside one
-// wavefront.  Plane pitches are 128 mod 256 bytes and the lanes of a
-// half-wave read planes whose offsets make the 16-byte reads conflict-free.
+// Per particle: a group of 16 lanes (a DPP row).  Lane j = lane & 7 owns the
+// x1 node offset j; the two half-rows split the particle's I planes between
+// them.  Each lane contracts x2 for each of its planes and x3 over them,
+// scales by its x1 weight, and the group sums over its lanes with DPP: the
+// paper's split of the triple sum into partial sums finished along the
+// remaining direction (Sec. 3.3), inside one wavefront.  Plane pitches are
+// 128 mod 256 bytes, so a particle's 16 lanes read 256 consecutive bytes
+// modulo 256; the two particles of a half-wave are paired so that they read
+// at the same offsets (see the kappa pairing in the kernel), which the LDS
+// serves at its full 16-byte rate.
 //
 // Weights: every lane evaluates its own node of beta (and beta') by Horner from
 // its row of the coefficient table, in powers of t - 1/2 (the centred form
@@ -103,14 +105,6 @@ template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
   return __builtin_bit_cast(double, dpp64<CTRL>(__builtin_bit_cast(long, v)));
 }
-// a pair of FP32 values moved by one 64-bit DPP move
-__device__ __forceinline__ long pack2(float lo, float hi) {
-  return (long)(((unsigned long)__float_as_uint(hi) << 32) | __float_as_uint(lo));
-}
-__device__ __forceinline__ void unpack2(long p, float& lo, float& hi) {
-  lo = __uint_as_float((uint32_t)(unsigned long)p);
-  hi = __uint_as_float((uint32_t)((unsigned long)p >> 32));
-}
 // value of lane L of this row
 template <int L, typename V>
 __device__ __forceinline__ V bcast(V v) {
@@ -163,12 +157,6 @@ __device__ __forceinline__ V rowsum_scatter3(const V* e, int j, int h) {
   g += dpp<0xB1>(g);  // quad_perm [1,0,3,2]
   g += dpp<0x4E>(g);  // quad_perm [2,3,0,1]
   return g;
-}
-
-// The value of lane l ^ 16 within each 32-lane group (ds_swizzle, bit mode:
-// and-mask 0x1F, xor-mask 0x10): the other row of a 32-lane particle group.
-__device__ __forceinline__ float swap_rows(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
 }
 
 // ---- node access
@@ -318,7 +306,7 @@ __device__ __forceinline__ void store_unit(unsigned char* smem, int64_t zp, int 
   const int r = u / Gm::RG;
   const uint32_t w[12] = {c[0].x, c[0].y, c[0].z, c[0].w, c[1].x, c[1].y,
                           c[1].z, c[1].w, c[2].x, c[2].y, c[2].z, c[2].w};
-  const int slot = (int)(zp % Gm::R);
+  const int slot = (int)((uint32_t)zp % (uint32_t)Gm::R);  // plane indices are below 2^31
 #pragma unroll
   for (int q = 0; q < Gm::G; ++q) {
     const int x = g * Gm::G + q;
@@ -374,21 +362,7 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const f
   if (j >= I) w1 = (V)0;
   V w2[I], w3[HALF];
   V d1 = (V)0, dw2[I], dw3[HALF];
-  if constexpr (GRAD && sizeof(V) == 4) {
-    // FP32 gradients: each lane's (beta, beta') pair travels in one 64-bit move
-    V cd[I];
-    coef_row<I>(ctab, I * I + jj * I, cd);
-    const V dsel = horner<I - 1>(cd, tsel);
-    d1 = horner<I - 1>(cd, t1);
-    if (j >= I) d1 = (V)0;
-    const long pr = pack2(wsel, dsel);
-#define PTK_P2(k) if constexpr ((k) < I) unpack2(dpp64<0x150 + (k)>(pr), w2[k], dw2[k]);
-    PTK_P2(0) PTK_P2(1) PTK_P2(2) PTK_P2(3) PTK_P2(4) PTK_P2(5) PTK_P2(6) PTK_P2(7)
-#undef PTK_P2
-#define PTK_P3(m) if constexpr ((m) < HALF) unpack2(bcast2_64<8 + 2 * (m), 9 + 2 * (m)>(pr), w3[m], dw3[m]);
-    PTK_P3(0) PTK_P3(1) PTK_P3(2) PTK_P3(3)
-#undef PTK_P3
-  } else {
+  {
 #define PTK_B2(k) if constexpr ((k) < I) w2[k] = bcast<k>(wsel);
     PTK_B2(0) PTK_B2(1) PTK_B2(2) PTK_B2(3) PTK_B2(4) PTK_B2(5) PTK_B2(6) PTK_B2(7)
 #undef PTK_B2
@@ -517,76 +491,6 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const f
   }
 }
 
-// Value only, FP32/BF16/FP16 storage, I = 4 or 8: one particle per 32 lanes
-// (two rows of 16).  Row q (q = 0, 1) of the pair and half h of the row take
-// the planes k = 4m + 2q + h; the two rows of a half-wave then read planes
-// two ring slots apart (2 plane pitches = 0 mod 256 bytes), i.e. the same
-// banks at the same offsets, which the LDS serves at its full 16-byte rate.
-// Each row evaluates its own x2/x3 weights; the rows' partial sums meet with
-// a row broadcast.  Leaves the 3 totals in r on the odd rows.
-template <int ST, int I, typename V>
-__device__ __forceinline__ void particle_sums32(const unsigned char* smem, const V* cvrow, int j, int jj, int h,
-                                                V t1, V t2, V t3, int l1, int l2, int z3, V* r) {
-  using Gm = Geom<ST, I>;
-  constexpr int NB = Gm::NB, RP = Gm::RP, PL = Gm::PL, R = Gm::R;
-  constexpr int NM = I / 4;  // planes per lane
-  static_assert(I % 4 == 0, "32-lane groups need I divisible by 4");
-  const int q = (threadIdx.x >> 4) & 1;
-  const V tsel = h ? t3 : t2;
-  const V* cv = cvrow;
-  const V wsel = horner<I>(cv, tsel);
-  V w1 = horner<I>(cv, t1);
-  if (j >= I) w1 = (V)0;
-  V w2[I], w3[NM];
-#define PTK_B2(k) if constexpr ((k) < I) w2[k] = bcast<k>(wsel);
-  PTK_B2(0) PTK_B2(1) PTK_B2(2) PTK_B2(3) PTK_B2(4) PTK_B2(5) PTK_B2(6) PTK_B2(7)
-#undef PTK_B2
-  // w3[m] = beta_{4m + 2q + h}(t3), held by lane 8 + 4m + 2q + h of the row:
-  // row_mask 0x5 / 0xA picks the even / odd rows, bank_mask 0x3 / 0xC the halves
-#define PTK_B3(m)                                                                                        \
-  if constexpr ((m) < NM) {                                                                              \
-    const int src = __builtin_bit_cast(int, wsel);                                                       \
-    int x = __builtin_amdgcn_update_dpp(0, src, 0x150 + 8 + 4 * (m), 0x5, 0x3, false);                   \
-    x = __builtin_amdgcn_update_dpp(x, src, 0x150 + 9 + 4 * (m), 0x5, 0xC, false);                       \
-    x = __builtin_amdgcn_update_dpp(x, src, 0x150 + 10 + 4 * (m), 0xA, 0x3, false);                      \
-    x = __builtin_amdgcn_update_dpp(x, src, 0x150 + 11 + 4 * (m), 0xA, 0xC, false);                      \
-    w3[m] = __builtin_bit_cast(V, x);                                                                    \
-  }
-  PTK_B3(0) PTK_B3(1)
-#undef PTK_B3
-  const int noff = l2 * RP + (l1 + jj) * NB;
-  const int s0 = (z3 + 2 * q + h) % R;
-  V acc[3] = {0, 0, 0};
-  uint32_t sink = 0;  // as in particle_sums: the reads stay 16 bytes wide, unwaited
-#pragma unroll
-  for (int m = 0; m < NM; ++m) {
-    const int slot = s0 + 4 * m < R ? s0 + 4 * m : s0 + 4 * m - R;
-    const int base = slot * PL + noff;
-    V sum[3] = {0, 0, 0};
-    // the plane's I rows are read before any is used: I reads in flight
-    V v[I][3];
-    uint32_t keep[I];
-#pragma unroll
-    for (int i2 = 0; i2 < I; ++i2) lds_get<ST>(smem, base + i2 * RP, v[i2], keep[i2]);
-#pragma unroll
-    for (int i2 = 0; i2 < I; ++i2) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) sum[c] = fma(w2[i2], v[i2][c], sum[c]);
-      asm("" : "+v"(sink) : "v"(keep[i2]));
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] = fma(w3[m], sum[c], acc[c]);
-  }
-  asm volatile("" ::"v"(sink));
-  // each row reduce-scatters its three partials (lane (h, j) of the row: value
-  // 2h + (j >> 2)), then the two rows of the group add their totals
-  V e[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) e[c] = w1 * acc[c];
-  const V g = rowsum_scatter3(e, j, h);
-  r[0] = g + swap_rows(g);
-}
-
 // SPARSE: for launches with few particles per window -- visit only the
 // non-empty windows of each segment and fill the ring afresh for each,
 // instead of sweeping every plane.  Two workgroups per CU for FP32 and 16-bit
@@ -600,8 +504,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   constexpr int T = Gm::T;
   constexpr int W = kWindow;
   constexpr int NT = Gm::THREADS;
-  // lanes per particle: 32 for the FP32/16-bit value kernels with I = 4 or 8
-  constexpr int GL = (!GRAD && ST != ST_F64 && I % 4 == 0) ? 32 : 16;
+  constexpr int GL = 16;                 // lanes per particle
   constexpr int GROUPS = NT / GL;        // particles per round
   constexpr int NV = GRAD ? 12 : 3;
   constexpr int CH = NT / 3 / GROUPS * GROUPS;  // particles located per chunk: one thread per coordinate
@@ -610,6 +513,19 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   constexpr int RECB = 48;
   __shared__ __attribute__((aligned(16))) unsigned char smem[Gm::LDS];
   __shared__ __attribute__((aligned(16))) unsigned char recs[CH * RECB];
+  // Particle pairing (16-lane layouts with 16-byte nodes): a half-wave holds
+  // two particles, and a 16-byte read runs at full rate only when both
+  // quarter-waves read at the same offset modulo 256 bytes.  A particle's
+  // reads sit at offsets (up to a constant common to all lanes)
+  // 16 * kappa mod 256, kappa = 8 (c3 mod 2) + TX l2 + l1 mod 16 (plane
+  // pitch = 128 mod 256, row pitch = 16 TX, node = 16 bytes), so the rounds
+  // take the window's particles in an order that puts equal kappa side by
+  // side: rord[] lists record indices, pairs of each kappa first, then the
+  // unpaired ones.  Each particle's arithmetic is unchanged.
+  constexpr bool PAIR = GL == 16 && Gm::NB == 16;
+  __shared__ uint8_t rord[PAIR ? CH : 1];
+  __shared__ __attribute__((aligned(16))) int kcnt[16];
+  static_assert(CH <= 255, "record indices fit a byte");
   // FP32 gradient kernels hold the ring's planes relative to a reference
   // value per plane: U(z) of the plane in ring slot s (see particle_sums)
   constexpr bool PSHIFT = GRAD && ST == ST_F32;
@@ -651,6 +567,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   {
     const int64_t bin0 = tile * a.nw + w_begin;
     for (int e = threadIdx.x; e <= (int)(w_end - w_begin); e += Gm::THREADS) woff[e] = a.offsets[bin0 + e];
+    if (threadIdx.x < 16) kcnt[threadIdx.x] = 0;
   }
   const int tx = (int)(tile % a.ntx), ty = (int)(tile / a.ntx);
   const int64_t x0 = (int64_t)tx * T, y0 = (int64_t)ty * T;
@@ -730,11 +647,20 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   // the end of window w+3's range, read a window before it is needed
   uint32_t end3 = 0u;
 
+  // (the unit index of a thread is recomputed per window from a laundered
+  // thread index: hoisted out of the sweep, these per-thread addresses would
+  // hold registers through the particle rounds)
+  auto utid = [&]() {
+    int t = tid;
+    asm volatile("" : "+v"(t));
+    return t;
+  };
   auto issue_planes = [&](int64_t wn, uint4 (&pre)[Gm::PRE][3], bool (&ok)[Gm::PRE]) {
     const int64_t zn = W * wn + I - 1;  // planes window wn adds: [zn, zn + W)
+    const int t0 = utid();
 #pragma unroll
     for (int k = 0; k < Gm::PRE; ++k) {
-      const int uraw = tid + k * NT;
+      const int uraw = t0 + k * NT;
       const int u = min(uraw, W * Gm::UNITS_PER_PLANE - 1);
       const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
       ok[k] = load_unit<ST, I>(a, x0, y0, zn + pl, uu, pre[k]) && uraw < W * Gm::UNITS_PER_PLANE && wn < w_end;
@@ -754,9 +680,10 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   }
   auto post_refs = [&](const uint4 (&pre)[Gm::PRE][3], const bool (&ok)[Gm::PRE]) {
     if constexpr (PSHIFT) {
+      const int t0 = utid();
 #pragma unroll
       for (int k = 0; k < Gm::PRE; ++k) {
-        const int u = tid + k * NT;
+        const int u = t0 + k * NT;
         if (ok[k] && u % Gm::UNITS_PER_PLANE == ref_unit) {
           // node ref_q of the chunk, picked by selects (a run-time index into
           // the registers would move them to scratch memory)
@@ -779,16 +706,17 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
 #pragma unroll
     for (int k = 0; k < Gm::PRE; ++k)
       for (int c = 0; c < 3; ++c) settle(pre[k][c]);
+    const int t0 = utid();
 #pragma unroll
     for (int k = 0; k < Gm::PRE; ++k) {
-      const int u = tid + k * NT;
+      const int u = t0 + k * NT;
       if (ok[k]) {
         const int pl = u / Gm::UNITS_PER_PLANE, uu = u % Gm::UNITS_PER_PLANE;
         if constexpr (PSHIFT) {
           const float4 U4 = unext[pl];
           const float3 U = make_float3(U4.x, U4.y, U4.z);
           store_unit_shifted<ST, I>(smem, zn + pl, uu, pre[k], U);
-          if (uu == 0) uref[(zn + pl) % Gm::R] = U4;
+          if (uu == 0) uref[(uint32_t)(zn + pl) % (uint32_t)Gm::R] = U4;
         } else {
           store_unit<ST, I>(smem, zn + pl, uu, pre[k]);
         }
@@ -805,6 +733,7 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
     const uint32_t* src = (tid % 3 == 1 && a.grad_orig) ? a.grad_orig : a.orig;
     qv = src ? src[p] : (uint32_t)p;
   };
+  // steps 1-3 of Sec. 2.2 once per coordinate: one thread per (particle, axis)
   // steps 1-3 of Sec. 2.2 once per coordinate: one thread per (particle, axis)
   auto write_rec = [&](int64_t wr, int n, double xv, uint32_t qv) {
     settle(xv);
@@ -845,13 +774,59 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
       if (ax == 1) *(uint32_t*)(rp + 44) = qv;
     }
   };
+  // The round order of a chunk whose records are complete (after a barrier):
+  // rank_kappa ranks each particle within its kappa bucket (thread = particle,
+  // one LDS atomic); after a second barrier, place puts the pairs of every
+  // bucket first, bucket by bucket, then one left-over particle of each bucket
+  // with an odd count.  Returns / takes kappa + 16 * rank.
+  auto rank_kappa = [&](int n) -> int {
+    int kr = 0;
+    if constexpr (PAIR) {
+      if (tid < n) {
+        const uint2 lc = *(const uint2*)(recs + tid * RECB + 32);
+        const int l1 = (int)(lc.x & 0xFFFFu), l2 = (int)(lc.x >> 16), c3 = (int)(lc.y & 0xFFFFu);
+        const int kap = (8 * (c3 & 1) + Gm::TX * l2 + l1) & 15;
+        kr = kap + 16 * atomicAdd(&kcnt[kap], 1);
+      }
+    }
+    return kr;
+  };
+  auto place = [&](int n, int kr) {
+    if constexpr (PAIR) {
+      if ((tid & ~63) < n) {  // waves holding a particle of the chunk
+        // per 16-lane row: bucket l16's (pairs, odd) packed in one word, and
+        // its exclusive prefix over the buckets (DPP scan within the row)
+        const int cnt = kcnt[l16];
+        const int v = (cnt >> 1) | ((cnt & 1) << 16);
+        int inc = v;
+        inc += __builtin_amdgcn_mov_dpp(inc, 0x111, 0xF, 0xF, true);  // row_shr:1
+        inc += __builtin_amdgcn_mov_dpp(inc, 0x112, 0xF, 0xF, true);  // row_shr:2
+        inc += __builtin_amdgcn_mov_dpp(inc, 0x114, 0xF, 0xF, true);  // row_shr:4
+        inc += __builtin_amdgcn_mov_dpp(inc, 0x118, 0xF, 0xF, true);  // row_shr:8
+        const int total = __builtin_amdgcn_readlane(inc, 15);
+        const int kap = kr & 15, rank = kr >> 4;
+        const int row0 = (tid & 63) & ~15;
+        const int before = __shfl(inc - v, row0 + kap);
+        const int own = __shfl(v, row0 + kap);
+        if (tid < n) {
+          const int pos = rank < 2 * (own & 0xFFFF) ? 2 * (before & 0xFFFF) + rank
+                                                     : 2 * (total & 0xFFFF) + (before >> 16);
+          rord[pos] = (uint8_t)tid;
+        }
+      }
+    }
+  };
   auto compute_chunk = [&](int n) __attribute__((always_inline)) {
     const int wave_grp0 = __builtin_amdgcn_readfirstlane(grp & ~(64 / GL - 1));  // first group of this wave
+    // the pairing's counters are free again (every placement read them before
+    // the barrier that started this chunk; the next count follows a barrier)
+    if (PAIR && tid < 16) kcnt[tid] = 0;
     for (int r0 = 0; r0 < n; r0 += GROUPS) {
       if (r0 + wave_grp0 >= n) break;  // nothing left for this wave: its SIMD serves other waves
       const int pi = r0 + grp;
       const bool active = pi < n;
-      const unsigned char* rp = recs + (active ? pi : n - 1) * RECB;
+      const int ri = PAIR ? (int)rord[active ? pi : n - 1] : (active ? pi : n - 1);
+      const unsigned char* rp = recs + ri * RECB;
       V t1, t2, t3;
       if constexpr (sizeof(V) == 8) {
         const double2 ta = *(const double2*)rp;
@@ -871,17 +846,13 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
       const uint4 lc = *(const uint4*)(rp + 32);
       const int l1 = (int)(lc.x & 0xFFFFu), l2 = (int)(lc.x >> 16), z3 = (int)(lc.y & 0xFFFFu);
       V r[3];
-      if constexpr (GL == 32)
-        particle_sums32<ST, I>(smem, cvr, j, jj, h, t1, t2, t3, l1, l2, z3, r);
-      else
-        particle_sums<ST, I, GRAD>(smem, uref, ctab, cvr, j, jj, h, t1, t2, t3, l1, l2, z3, r);
+      particle_sums<ST, I, GRAD>(smem, uref, ctab, cvr, j, jj, h, t1, t2, t3, l1, l2, z3, r);
       // which of its totals this lane writes, and which value that is: the
       // gradient kernels hold three (value 6h + 3((j >> 2) & 1) + k in r[k],
       // lane j & 3 writes k = j & 3); the value kernels one (value 2h +
-      // (j >> 2) in r[0], written by lane j & 3 = 0, on the first row of a
-      // 32-lane group)
+      // (j >> 2) in r[0], written by lane j & 3 = 0)
       const int sub = GRAD ? (l16 & 3)
-                           : ((j & 3) == 0 && 2 * h + (j >> 2) < 3 && (GL == 16 || ((tid >> 4) & 1) == 0)) ? 0 : 3;
+                           : ((j & 3) == 0 && 2 * h + (j >> 2) < 3) ? 0 : 3;
       const int ev = GRAD ? 6 * (l16 >> 3) + 3 * ((l16 >> 2) & 1) + (l16 & 3) : 2 * h + (j >> 2);
       V val = r[0];
       val = sub == 1 ? r[1] : val;
@@ -959,6 +930,12 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
       __syncthreads();
       write_rec(w, m, xm, qm);
       __syncthreads();
+      if constexpr (PAIR) {
+        const int kr = rank_kappa(m);
+        __syncthreads();
+        place(m, kr);
+        __syncthreads();
+      }
       compute_chunk(m);
     }
     post_refs(pre[B1], pok[B1]);
@@ -966,7 +943,15 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
     // the ring holds at least the planes one window touches: w+1's new planes
     // replace planes no later window reads; then w+1's records
     store_planes(w + 1, pre[B1], pok[B1]);
-    if (w + 1 < w_end) write_rec(w + 1, pos_n, pos_x, pos_q);
+    if (w + 1 < w_end) {
+      write_rec(w + 1, pos_n, pos_x, pos_q);
+      if constexpr (PAIR) {
+        __syncthreads();  // w+1's records are complete
+        const int kr = rank_kappa(pos_n);
+        __syncthreads();  // every count is in
+        place(pos_n, kr);
+      }
+    }
   };
 
   {
@@ -983,6 +968,12 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
           issue_pos(c0, m, xm, qm);
           write_rec(w, m, xm, qm);
           __syncthreads();  // ring and records complete
+          if constexpr (PAIR) {
+            const int kr = rank_kappa(m);
+            __syncthreads();
+            place(m, kr);
+            __syncthreads();
+          }
           compute_chunk(m);
           __syncthreads();  // every read done before the next fill
         }
@@ -1002,6 +993,12 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
     issue_window_idx(woff[0], woff[1], iv, qv, nv, pos_s, pos_e);
     issue_window_x(iv, xv);
     write_rec(w_begin, nv, xv, qv);
+    if constexpr (PAIR) {
+      __syncthreads();
+      const int kr = rank_kappa(nv);
+      __syncthreads();
+      place(nv, kr);
+    }
     issue_window_idx(pos_e, w_begin + 1 < w_end ? woff[2] : pos_e, idx_i, idx_q, idx_n, idx_s, idx_e);
     if (w_begin + 2 < w_end) end3 = woff[3];
   }
