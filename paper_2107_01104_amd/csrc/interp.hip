@@ -74,7 +74,13 @@ struct Geom {
   static constexpr int TX = T + I - 1;                   // halo tile edge in nodes
   static constexpr int NB = StoreT<ST>::NB;
   static constexpr int RP = TX * NB;                      // row pitch
-  static constexpr int PL = TX * RP + ((128 - (TX * RP) % 256) + 256) % 256;  // plane pitch, = 128 mod 256
+  // plane pitch: the two half-rows of a particle read planes one ring slot
+  // apart, so this offset sets their banks.  16-byte nodes: = 128 mod 256,
+  // the halves cover the two 128-byte halves of the banks.  32-byte (FP64)
+  // nodes, read 16 bytes at a time at a 32-byte stride: = 144 mod 256 (an odd
+  // multiple of 16 bytes), the halves read the even and the odd 16-byte slots.
+  static constexpr int PLM = NB == 32 ? 144 : 128;
+  static constexpr int PL = TX * RP + ((PLM - (TX * RP) % 256) + 256) % 256;
   static constexpr int R = (kWindow + I - 1 + 1) / 2 * 2;  // ring slots (even): the planes one window touches
   static constexpr int LDS = R * PL;
   static constexpr int G = 48 / StoreT<ST>::GB;           // nodes per 48-byte chunk
