@@ -74,13 +74,12 @@ struct Geom {
   static constexpr int TX = T + I - 1;                   // halo tile edge in nodes
   static constexpr int NB = StoreT<ST>::NB;
   static constexpr int RP = TX * NB;                      // row pitch
-  // plane pitch: the two half-rows of a particle read planes one ring slot
-  // apart, so this offset sets their banks.  16-byte nodes: = 128 mod 256,
-  // the halves cover the two 128-byte halves of the banks.  32-byte (FP64)
-  // nodes, read 16 bytes at a time at a 32-byte stride: = 144 mod 256 (an odd
-  // multiple of 16 bytes), the halves read the even and the odd 16-byte slots.
-  static constexpr int PLM = NB == 32 ? 144 : 128;
-  static constexpr int PL = TX * RP + ((PLM - (TX * RP) % 256) + 256) % 256;
+  // plane pitch, = 128 mod 256: the two half-rows of a particle read planes
+  // one ring slot apart.  16-byte nodes: the half-rows cover the two 128-byte
+  // halves of the banks.  32-byte (FP64) nodes, read 16 bytes at a time at a
+  // 32-byte stride: the halves of a node are swapped in odd slots (lds_put),
+  // so the half-rows read the even and the odd 16-byte slots.
+  static constexpr int PL = TX * RP + ((128 - (TX * RP) % 256) + 256) % 256;
   static constexpr int R = (kWindow + I - 1 + 1) / 2 * 2;  // ring slots (even): the planes one window touches
   static constexpr int LDS = R * PL;
   static constexpr int G = 48 / StoreT<ST>::GB;           // nodes per 48-byte chunk
@@ -166,14 +165,19 @@ __device__ __forceinline__ V rowsum_scatter3(const V* e, int j, int h) {
 }
 
 // ---- node access
-// copy node q of a 48-byte chunk (12 words) into LDS at byte offset `off`
+// copy node q of a 48-byte chunk (12 words) into LDS at byte offset `off`.
+// FP64 nodes (32 bytes) in odd ring slots are stored with their halves
+// swapped, (z, pad) then (x, y): the two half-rows of a particle read planes
+// of opposite slot parity, so reading (x, y) first puts them on opposite
+// 16-byte slots of the banks.
 template <int ST>
-__device__ __forceinline__ void lds_put(unsigned char* smem, int off, const uint32_t* w, int q) {
+__device__ __forceinline__ void lds_put(unsigned char* smem, int off, const uint32_t* w, int q, bool odd_slot) {
   if constexpr (ST == ST_F32) {
     *(uint4*)(smem + off) = make_uint4(w[3 * q], w[3 * q + 1], w[3 * q + 2], 0u);
   } else if constexpr (ST == ST_F64) {
-    *(uint4*)(smem + off) = make_uint4(w[6 * q], w[6 * q + 1], w[6 * q + 2], w[6 * q + 3]);
-    *(uint4*)(smem + off + 16) = make_uint4(w[6 * q + 4], w[6 * q + 5], 0u, 0u);
+    const int sxy = odd_slot ? 16 : 0;
+    *(uint4*)(smem + off + sxy) = make_uint4(w[6 * q], w[6 * q + 1], w[6 * q + 2], w[6 * q + 3]);
+    *(uint4*)(smem + off + 16 - sxy) = make_uint4(w[6 * q + 4], w[6 * q + 5], 0u, 0u);
   } else {
     const int k = 3 * q;
     const uint32_t h0 = (w[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
@@ -195,9 +199,10 @@ __device__ __forceinline__ void lds_put(unsigned char* smem, int off, const uint
 
 // read a node; the caller consumes the unused fourth word (`keep`) in an empty
 // asm statement so the compiler issues one full 16-byte read (ds_read_b128)
-// instead of a slower b96
+// instead of a slower b96.  sxy: byte offset of an FP64 node's (x, y) half
+// (16 in odd ring slots, see lds_put).
 template <int ST, typename V>
-__device__ __forceinline__ void lds_get(const unsigned char* smem, int off, V* v, uint32_t& keep) {
+__device__ __forceinline__ void lds_get(const unsigned char* smem, int off, V* v, uint32_t& keep, int sxy) {
   if constexpr (ST == ST_F32) {
     const float4 f = *(const float4*)(smem + off);
     v[0] = f.x;
@@ -205,8 +210,8 @@ __device__ __forceinline__ void lds_get(const unsigned char* smem, int off, V* v
     v[2] = f.z;
     keep = __float_as_uint(f.w);
   } else if constexpr (ST == ST_F64) {
-    const double2 a = *(const double2*)(smem + off);
-    const double2 b = *(const double2*)(smem + off + 16);
+    const double2 a = *(const double2*)(smem + off + sxy);
+    const double2 b = *(const double2*)(smem + off + 16 - sxy);
     v[0] = a.x;
     v[1] = a.y;
     v[2] = b.x;
@@ -316,7 +321,7 @@ __device__ __forceinline__ void store_unit(unsigned char* smem, int64_t zp, int 
 #pragma unroll
   for (int q = 0; q < Gm::G; ++q) {
     const int x = g * Gm::G + q;
-    if (x < Gm::TX) lds_put<ST>(smem, slot * Gm::PL + r * Gm::RP + x * Gm::NB, w, q);
+    if (x < Gm::TX) lds_put<ST>(smem, slot * Gm::PL + r * Gm::RP + x * Gm::NB, w, q, (slot & 1) != 0);
   }
 }
 
@@ -392,6 +397,8 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const f
   // contraction: x2 over all rows per plane, x3 over this lane's planes
   const int noff = l2 * RP + (l1 + jj) * NB;
   const int s0 = (z3 + h) % R;
+  // every plane of this lane has the slot parity of s0 (R is even)
+  const int sxy = (s0 & 1) * 16;
   V acc[3] = {0, 0, 0}, ad2[3] = {0, 0, 0}, ad3[3] = {0, 0, 0};
   // the unused fourth word of every 16-byte node read is folded into `sink`
   // by an empty (schedulable) asm, so the reads stay 16 bytes wide without a
@@ -428,7 +435,7 @@ __device__ __forceinline__ void particle_sums(const unsigned char* smem, const f
       V v[G][3];
       uint32_t keep[G];
 #pragma unroll
-      for (int k = 0; k < G; ++k) lds_get<ST>(smem, base + (g + k) * RP, v[k], keep[k]);
+      for (int k = 0; k < G; ++k) lds_get<ST>(smem, base + (g + k) * RP, v[k], keep[k], sxy);
 #pragma unroll
       for (int k = 0; k < G; ++k) {
 #pragma unroll
@@ -519,16 +526,17 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
   constexpr int RECB = 48;
   __shared__ __attribute__((aligned(16))) unsigned char smem[Gm::LDS];
   __shared__ __attribute__((aligned(16))) unsigned char recs[CH * RECB];
-  // Particle pairing (16-lane layouts with 16-byte nodes): a half-wave holds
-  // two particles, and a 16-byte read runs at full rate only when both
-  // quarter-waves read at the same offset modulo 256 bytes.  A particle's
-  // reads sit at offsets (up to a constant common to all lanes)
-  // 16 * kappa mod 256, kappa = 8 (c3 mod 2) + TX l2 + l1 mod 16 (plane
-  // pitch = 128 mod 256, row pitch = 16 TX, node = 16 bytes), so the rounds
+  // Particle pairing: a half-wave holds two particles, and a 16-byte read
+  // runs at full rate only when both quarter-waves read at the same offset
+  // modulo 256 bytes.  A particle's reads sit at offsets (up to a constant
+  // common to all lanes) 16 * kappa mod 256: kappa = 8 (c3 mod 2) + TX l2 + l1
+  // mod 16 for 16-byte nodes (plane pitch = 128 mod 256, row pitch = 16 TX),
+  // 9 (c3 mod 2) + 2 TX l2 + 2 l1 for 32-byte FP64 nodes (row pitch 32 TX;
+  // the (x, y) half of a node in an odd slot sits 16 bytes in).  The rounds
   // take the window's particles in an order that puts equal kappa side by
   // side: rord[] lists record indices, pairs of each kappa first, then the
   // unpaired ones.  Each particle's arithmetic is unchanged.
-  constexpr bool PAIR = GL == 16 && Gm::NB == 16;
+  constexpr bool PAIR = GL == 16 && (Gm::NB == 16 || Gm::NB == 32);
   __shared__ uint8_t rord[PAIR ? CH : 1];
   __shared__ __attribute__((aligned(16))) int kcnt[16];
   static_assert(CH <= 255, "record indices fit a byte");
@@ -791,7 +799,11 @@ __global__ __launch_bounds__(StoreT<ST>::THREADS, ST == ST_F64 ? 2 : 4) void k_i
       if (tid < n) {
         const uint2 lc = *(const uint2*)(recs + tid * RECB + 32);
         const int l1 = (int)(lc.x & 0xFFFFu), l2 = (int)(lc.x >> 16), c3 = (int)(lc.y & 0xFFFFu);
-        const int kap = (8 * (c3 & 1) + Gm::TX * l2 + l1) & 15;
+        // 16-byte nodes: offsets 16 (8 p + TX l2 + l1); 32-byte nodes, whose
+        // (x, y) half sits 16 bytes in where the slot parity p is odd:
+        // 16 (9 p + 2 TX l2 + 2 l1), modulo 256 (p = c3 mod 2)
+        const int kap = Gm::NB == 16 ? (8 * (c3 & 1) + Gm::TX * l2 + l1) & 15
+                                     : (9 * (c3 & 1) + 2 * Gm::TX * l2 + 2 * l1) & 15;
         kr = kap + 16 * atomicAdd(&kcnt[kap], 1);
       }
     }
