@@ -475,8 +475,18 @@ __global__ __launch_bounds__(NT) void k_update(float* params, float* m, float* v
   if (e >= kLearnedNParams) return;
   float p = params[e];
   if (u.mode != 2) {
+    // the partials in their fixed order, loaded 16 at a time so that the
+    // loads are in flight together (the additions stay in order)
     float g = 0.f;
-    for (int w = 0; w < u.nparts; ++w) g += gpart[(int64_t)w * kLearnedNParams + e];
+    int w = 0;
+    for (; w + 16 <= u.nparts; w += 16) {
+      float part[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) part[k] = gpart[(int64_t)(w + k) * kLearnedNParams + e];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) g += part[k];
+    }
+    for (; w < u.nparts; ++w) g += gpart[(int64_t)w * kLearnedNParams + e];
     if (u.mode == 0) {
       u.grad_out[e] = g;
       return;
