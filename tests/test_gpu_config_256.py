@@ -4,7 +4,8 @@ with dt = 2e-3 and re-binning every step.
 
 The oracle computes a seeded sample of particles one by one: values and
 gradients, and the first two steps (Euler start-up, then AB2) of the sample's
-trajectories on the same stored FP32 values.  The 100-step run is checked by
+trajectories on the same stored FP32 values, and their first ten steps.  The
+100-step run is checked by
 properties that hold at any size: the history depth is 2, 100 steps equal
 40 + 60 steps resumed from the returned state bit for bit, and every particle
 moved by at most 100 dt max|u| (positions are not wrapped).  Bars as in
@@ -100,6 +101,34 @@ def test_ab2_first_steps_sampled(ptk, setup):
     # the returned history is u at the sample's previous positions, in caller order
     hv = hist[:, idx_d].cpu().numpy().astype(np.float64)
     check_f32(hv, ho, what="returned history")
+
+
+def test_ab2_ten_steps_sampled(ptk, setup):
+    """Ten AB2 steps (Euler start-up, then AB2) on all 1e7 particles; the
+    sample's trajectories against the oracle's.  Each step's velocity is
+    within the value bar E = 1e-5 rms(u), so a step adds at most
+    dt (1.5 + 0.5) E to a position difference, and a difference e grows by at
+    most (1 + dt (1.5 + 0.5) G) e per step (Gronwall), G twice the largest
+    Frobenius norm of the oracle's gradient over the sample."""
+    ctx, uh, X, idx = setup
+    say("[256^3] 10 AB2 steps")
+    idx_d = torch.from_numpy(idx).to(DEV)
+    Xs = X[idx_d].cpu().numpy()
+    Xa = X.clone()
+    hist = torch.zeros((2, NP, 3), dtype=torch.float32, device=DEV)
+    ctx.advance(Xa, stepping.AB2, DT, 10, hist=hist, hist_len=0)
+    X10 = Xa[idx_d].cpu().numpy()
+    del Xa, hist
+    vel = lambda Y: interp.interp_vec(uh, Y, FAM, I, M)
+    Xo, ho, _, _ = stepping.advance(Xs, vel, stepping.AB2, DT, 10)
+    _, rg = interp.interp_vec(uh, Xs, FAM, I, M, gradient=True)
+    urms = float(np.sqrt(np.mean(ho ** 2)))
+    G = 2.0 * float(np.sqrt((rg ** 2).sum(axis=(1, 2))).max())
+    growth = (1.0 + DT * 2.0 * G) ** 10
+    tol = 10 * DT * 2.0 * 1e-5 * urms * growth + 16 * np.spacing(L)
+    d = np.abs(X10 - Xo).max(axis=1)
+    say(f"  max position difference {d.max():.3e} (tolerance {tol:.3e}, growth {growth:.2f})")
+    assert np.all(d <= tol)
 
 
 def test_ab2_100_steps_resume_and_domain(ptk, setup):

@@ -2,8 +2,9 @@
 
 Workload: the 1024^3 FP32 spectral field (k <= 340, seed 2), 10^8 uniform
 particles (seed 12) and the C2 spline with I = 8 -- the launches the benchmark
-times (value + gradient kernel, value kernel, one Heun step with gradient, the
-re-binning) on the whole set.  The oracle cannot evaluate 10^8 particles, so it
+times (value + gradient kernel, value kernel, Heun steps with gradient, the
+re-binning) on the whole set; the sample's trajectories are compared with the
+oracle's after one step and after ten (the benchmark's count).  The oracle cannot evaluate 10^8 particles, so it
 computes a seeded sample of them one by one (plus the first and the last
 particle), and properties that hold at any size are checked on every particle:
 the bin permutation is a permutation, offsets are monotone and end at N_p,
@@ -130,4 +131,22 @@ def test_full_size_bench_configuration(ptk):
     d = np.abs(X1 - Xo).max(axis=1)
     say(f"  max position difference {d.max():.3e} (tolerance {tol:.3e})")
     assert np.all(d <= tol)
+
+    # nine more steps (the benchmark's ten): every step adds at most the bound
+    # above, and a position difference e grows by at most
+    # (1 + dt |grad u|) e per step (Gronwall), with |grad u| bounded by twice
+    # the largest Frobenius norm of the oracle's gradient over the sample
+    say("  nine more Heun steps on all 1e8 (ten in all)")
+    Xa10 = X.clone()
+    ctx.advance(Xa10, ptk.HEUN, DT, 10)
+    X10 = Xa10[idx_d].cpu().numpy()
+    del Xa10
+    torch.cuda.empty_cache()
+    Xo10, _, _, _ = stepping.advance(Xo, vel, stepping.HEUN, DT, 9)
+    gmax = 2.0 * float(np.sqrt((rg ** 2).sum(axis=(1, 2))).max())
+    growth = (1.0 + DT * gmax) ** 10
+    tol10 = 10 * tol * growth
+    d10 = np.abs(X10 - Xo10).max(axis=1)
+    say(f"  after 10 steps: max position difference {d10.max():.3e} (tolerance {tol10:.3e}, growth {growth:.2f})")
+    assert np.all(d10 <= tol10)
     ctx.close()
