@@ -239,6 +239,42 @@ def test_interp_reduced_storage_tight(ptk, storage, fam, I, m):
     ctx.close()
 
 
+@pytest.mark.parametrize("fam,I,m", [(K.LAGRANGE, 4, 0), (K.SPLINE, 8, 2)])
+def test_bf16_extreme_fields(ptk, fam, I, m):
+    """BF16 storage of fields far from the smooth test fields.  Component 0:
+    one large spike on a small background (its code about 180 in units of the
+    component's rms); component 1: magnitudes spread over ten decades (codes
+    from about 30 down to 1e-10); component 2: a smooth field.  Same bars as
+    every FP32 sum, against the oracle on the stored codes."""
+    say(f"[interp bf16 extreme fields] I={I}")
+    N = 32
+    rng = np.random.default_rng(77)
+    u = np.empty((N, N, N, 3), dtype=np.float32)
+    u[..., 0] = 1e-3 * rng.standard_normal((N, N, N))
+    u[5, 17, 30, 0] = 40.0
+    u[..., 1] = rng.standard_normal((N, N, N)) * 10.0 ** rng.uniform(-10.0, 0.0, (N, N, N))
+    u[..., 2] = fields.spectral_field(N, kc=6.0, seed=4, dtype=torch.float32).numpy()[..., 2]
+    ctx = ptk.Context(0)
+    ctx.set_field(torch.from_numpy(u).to(DEV), fam, I, m, storage=ptk.BF16)
+    vals, s = precision.store(u, ptk.BF16)
+    assert np.abs(vals[..., 0]).max() > 80.0  # the spike, in units of the component's rms
+    # points around the spike and uniform ones
+    X = np.concatenate([np.array([30.0, 17.0, 5.0]) * (L / N) + rng.uniform(-0.3, 0.3, (4000, 3)),
+                        rng.uniform(0.0, L, (4000, 3))])
+    uv, g = ctx.interpolate_gradient(torch.from_numpy(X).to(DEV), out_dtype=torch.float32)
+    ru, rg = interp.interp_vec(vals, X, fam, I, m, gradient=True)
+    ru, rg = ru * s, rg * s[None, :, None]
+    uv, g = uv.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+    for a in range(3):
+        ev = check_f32(uv[:, a], ru[:, a], f"bf16 value {a}")
+        eg = check_f32(g[:, a], rg[:, a], f"bf16 gradient {a}")
+        say(f"  component {a}: rel rms / max value {ev[0]:.2e} / {ev[1]:.2e}, gradient {eg[0]:.2e} / {eg[1]:.2e}")
+    val = ctx.interpolate(torch.from_numpy(X).to(DEV)).cpu().numpy().astype(np.float64)
+    for a in range(3):
+        check_f32(val[:, a], ru[:, a], f"bf16 value kernel {a}")
+    ctx.close()
+
+
 def test_heun_step_f64(ptk, f0):
     """One Heun step with dt = 1e-3 on the 32^3 Fourier-mode field, Lagrange I = 4."""
     say("[heun f64]")
