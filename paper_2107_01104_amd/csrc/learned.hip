@@ -95,11 +95,27 @@ __device__ __forceinline__ bool locate_quad(const double* Xp, int k3, int N, dou
   return locate_quad_x(Xp[k3 < 3 ? k3 : 2], k3, N, invd, c, td);
 }
 
-// One quarter of a particle's 4 x 4 x 4 stencil (the x3 plane k3): its 48
-// BF16 features, packed in pairs into fe[24] in feature order, and its part
-// of the Lagrange I = 4 sum.
-__device__ __forceinline__ void stencil_plane(const LearnedField& f, const int* c, const double* td, int k3,
-                                              uint32_t* fe, float* u) {
+// One quarter of a particle's 4 x 4 x 4 stencil (the x3 plane k3): the loads
+// of its 4 rows (4 nodes each: 12 consecutive floats, 4-byte aligned), ...
+__device__ __forceinline__ void stencil_issue(const LearnedField& f, const int* c, int k3, float4 (&q)[4][3]) {
+  const int64_t z = c[2] - 1 + k3 + f.halo_lo;
+  const unsigned char* plane = (const unsigned char*)f.field + z * f.plane_pitch;
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    const int64_t y = c[1] - 1 + k2 + f.halo_lo;
+    const f32x4a* row = (const f32x4a*)((const float*)(plane + y * f.row_pitch) + 3 * (c[0] - 1 + f.halo_lo));
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const f32x4a r = row[e];
+      q[k2][e] = make_float4(r.x, r.y, r.z, r.w);
+    }
+  }
+}
+
+// ... and from them its 48 BF16 features, packed in pairs into fe[24] in
+// feature order, and its part of the Lagrange I = 4 sum
+__device__ __forceinline__ void stencil_sums(const LearnedField& f, const double* td, int k3, const float4 (&q)[4][3],
+                                             uint32_t* fe, float* u) {
   float w[3][4];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -113,14 +129,9 @@ __device__ __forceinline__ void stencil_plane(const LearnedField& f, const int* 
     }
   }
   u[0] = u[1] = u[2] = 0.f;
-  const int64_t z = c[2] - 1 + k3 + f.halo_lo;
-  const unsigned char* plane = (const unsigned char*)f.field + z * f.plane_pitch;
 #pragma unroll
   for (int k2 = 0; k2 < 4; ++k2) {
-    const int64_t y = c[1] - 1 + k2 + f.halo_lo;
-    // the 4 nodes of the row: 12 consecutive floats, 4-byte aligned
-    const f32x4a* row = (const f32x4a*)((const float*)(plane + y * f.row_pitch) + 3 * (c[0] - 1 + f.halo_lo));
-    const f32x4a q0 = row[0], q1 = row[1], q2 = row[2];
+    const float4 q0 = q[k2][0], q1 = q[k2][1], q2 = q[k2][2];
     const float v[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
     const float w23 = w[2][k3] * w[1][k2];
 #pragma unroll
@@ -130,8 +141,15 @@ __device__ __forceinline__ void stencil_plane(const LearnedField& f, const int* 
       for (int a = 0; a < 3; ++a) u[a] = fmaf(ww, v[3 * k1 + a], u[a]);
     }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) fe[6 * k2 + q] = pack_bf16(v[2 * q], v[2 * q + 1]);
+    for (int qq = 0; qq < 6; ++qq) fe[6 * k2 + qq] = pack_bf16(v[2 * qq], v[2 * qq + 1]);
   }
+}
+
+__device__ __forceinline__ void stencil_plane(const LearnedField& f, const int* c, const double* td, int k3,
+                                              uint32_t* fe, float* u) {
+  float4 q[4][3];
+  stencil_issue(f, c, k3, q);
+  stencil_sums(f, td, k3, q, fe, u);
 }
 
 // ---------------------------------------------------------------- pairs
@@ -187,10 +205,24 @@ __device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[rt][v] = 0.f;
+  // the A fragments of step s + 1 are read while step s's products run; in
+  // inference an empty asm with a memory clobber ends every step, so the
+  // compiler reads no further ahead (holding all 26 fragments would take 104
+  // registers that inference spends on the next chunk's stencil loads)
+  bf16x8 an[2];
 #pragma unroll
-  for (int s = 0; s < 13; ++s)
+  for (int rt = 0; rt < 2; ++rt) an[rt] = frag(sX, PX, 32 * rt + r32, 8 * hi);
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) acc[rt] = mfma(frag(sX, PX, 32 * rt + r32, 16 * s + 8 * hi), bw1[s], acc[rt]);
+  for (int s = 0; s < 13; ++s) {
+    const bf16x8 a0 = an[0], a1 = an[1];
+    if (s + 1 < 13) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) an[rt] = frag(sX, PX, 32 * rt + r32, 16 * (s + 1) + 8 * hi);
+    }
+    acc[0] = mfma(a0, bw1[s], acc[0]);
+    acc[1] = mfma(a1, bw1[s], acc[1]);
+    if constexpr (!TRAIN) asm volatile("" ::: "memory");
+  }
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -216,9 +248,18 @@ __device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[rt][v] = 0.f;
 #pragma unroll
-  for (int s = 0; s < 8; ++s)
+  for (int rt = 0; rt < 2; ++rt) an[rt] = frag(sH1, PH, 32 * rt + r32, 8 * hi);
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) acc[rt] = mfma(frag(sH1, PH, 32 * rt + r32, 16 * s + 8 * hi), bw2[s], acc[rt]);
+  for (int s = 0; s < 8; ++s) {
+    const bf16x8 a0 = an[0], a1 = an[1];
+    if (s + 1 < 8) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) an[rt] = frag(sH1, PH, 32 * rt + r32, 16 * (s + 1) + 8 * hi);
+    }
+    acc[0] = mfma(a0, bw2[s], acc[0]);
+    acc[1] = mfma(a1, bw2[s], acc[1]);
+    if constexpr (!TRAIN) asm volatile("" ::: "memory");
+  }
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -230,7 +271,10 @@ __device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1
   __syncthreads();  // h2 complete
 }
 
-// y[r][a] = b3[a] + sum_c h2[r][c] W3[a][c] for thread t < 192 (r = t/3, a = t%3)
+// y[r][a] = b3[a] + sum_c h2[r][c] W3[a][c] for thread t < 192 (r = t/3, a = t%3).
+// LEAN: an empty asm with a memory clobber ends every unrolled step, so the
+// reads are not hoisted ahead into registers the caller holds otherwise.
+template <bool LEAN>
 __device__ __forceinline__ float output_layer(const float* sH2, const float* sW3, const float* b3, int t) {
   const int r = t / 3, a = t - 3 * (t / 3);
   const float4* h = (const float4*)(sH2 + r * PH2);
@@ -247,6 +291,7 @@ __device__ __forceinline__ float output_layer(const float* sH2, const float* sW3
     y1 = fmaf(h1.y, w1.y, y1);
     y1 = fmaf(h1.z, w1.z, y1);
     y1 = fmaf(h1.w, w1.w, y1);
+    if constexpr (LEAN) asm volatile("" ::: "memory");
   }
   return b3[a] + (y0 + y1);
 }
@@ -331,7 +376,7 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
   // output layer, loss and dy = 2 (y - target) / (3 batch)
   float se = 0.f;
   if (t < ROWS * NO) {
-    const float y = output_layer(sH2, sW3, params + oB3, t);
+    const float y = output_layer<false>(sH2, sW3, params + oB3, t);
     const float d = y - target[(row0 + t / 3) * NO + t % 3];
     se = d * d;
     sdy[t] = 2.0f * d / (float)(NO * batch);
@@ -509,11 +554,13 @@ __global__ __launch_bounds__(NT) void k_update(float* params, float* m, float* v
 }
 
 // ---------------------------------------------------------------- inference
-// Particles in bin order (the k-th is the caller's orig[k]), 64 per chunk;
+// Particles in bin order (the k-th is the caller's orig[k]; orig is required),
+// 64 per chunk;
 // every workgroup keeps its layer weights in registers and walks a range of
-// chunks.  The row index and coordinate of the next chunk's particles are
-// loaded while the current chunk runs, so a chunk waits for its stencil
-// loads only, not for the index -> position -> stencil chain.
+// chunks.  The loads run a chunk ahead of their use along the chain row
+// index -> coordinate -> stencil: while chunk ch's two layers run, chunk
+// ch + 1's stencil rows, chunk ch + 2's coordinates and chunk ch + 3's row
+// indices are in flight.
 __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X, int64_t n, const uint32_t* orig,
                                                  const float* params, const uint16_t* w1b, const uint16_t* w2b,
                                                  float* out, int* flag) {
@@ -523,7 +570,6 @@ __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X
   __shared__ __attribute__((aligned(16))) float sW3[NO * NH];
   __shared__ float sU[ROWS * NO];
   __shared__ float sB3[NO];
-  __shared__ uint32_t sOrig[ROWS];  // the chunk's rows of X (caller indices)
   uint16_t* sX = (uint16_t*)lds;
   float* sH2 = (float*)lds;
   uint16_t* sH1 = (uint16_t*)(lds + RX);
@@ -546,59 +592,74 @@ __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X
   const int64_t ch_end = min(nchunks, (bid + 1) * per_block);
   const int64_t ch0 = bid * per_block;
   const int kx = (t & 3) < 3 ? (t & 3) : 2;  // the coordinate this thread loads
-  // row of X of this thread's particle in chunk ch (clamped to the last particle)
-  auto xrow = [&](int64_t ch) -> uint32_t {
-    const int64_t p = min(ch * ROWS + (t >> 2), n - 1);
-    return orig ? orig[p] : (uint32_t)p;
-  };
-  uint32_t oi_c = 0, oi_n = 0;
-  double x_c = 0.0;
+  // row of X of this thread's particle in chunk ch
+  // caller row of bin-ordered particle p (clamped to the last particle;
+  // unconditional, so no branch merge waits for the load)
+  auto xrow_of = [&](int64_t p) -> uint32_t { return orig[min(p, n - 1)]; };
+  auto xrow = [&](int64_t ch) -> uint32_t { return xrow_of(ch * ROWS + (t >> 2)); };
+  // At the top of chunk ch: its stencil rows q (with their offsets td and
+  // domain check ok), loaded during chunk ch - 1, and chunk ch + 1's
+  // coordinate x_n.  Each load's result is consumed before the register is
+  // loaded again, and every wait finds the loads it needs issued before the
+  // ones still in flight (the counter retires loads in order).
+  const int pi = t >> 2, k3 = t & 3;
+  float4 q[4][3];
+  double td[3];
+  bool ok = true;
+  double x_n = 0.0;
   if (ch0 < ch_end) {
-    oi_c = xrow(ch0);
-    x_c = X[3 * (int64_t)oi_c + kx];
-    oi_n = xrow(min(ch0 + 1, ch_end - 1));
-  }
-  for (int64_t ch = ch0; ch < ch_end; ++ch) {
-    const int pi = t >> 2, k3 = t & 3;
-    const bool active = ch * ROWS + pi < n;
-    // the next chunk's coordinate and the row index of the one after it
-    const double x_n = X[3 * (int64_t)oi_n + kx];
-    const uint32_t oi_nn = xrow(min(ch + 2, ch_end - 1));
+    const double x_c = X[3 * (int64_t)xrow(ch0) + kx];
+    const uint32_t oi = xrow(min(ch0 + 1, ch_end - 1));
     int c[3];
-    double td[3];
-    const bool ok = locate_quad_x(x_c, k3, f.N, f.invd, c, td);
+    ok = locate_quad_x(x_c, k3, f.N, f.invd, c, td);
+    stencil_issue(f, c, k3, q);
+    x_n = X[3 * (int64_t)oi + kx];
+  }
+  // output thread t < 192 writes component t % 3 of the chunk's particle t / 3
+  const int orow = min(t / 3, ROWS - 1), oa = t % 3;
+  for (int64_t ch = ch0; ch < ch_end; ++ch) {
+    // the caller's row of this thread's output, and chunk ch + 2's rows of X
+    const uint32_t o_dst = xrow_of(ch * ROWS + orow);
+    const uint32_t oi_nn = xrow(min(ch + 2, ch_end - 1));
+    const bool active = ch * ROWS + pi < n;
     if (active && !ok) atomicOr(flag, kFlagDomain);
     uint32_t fe[24];
     float u[3];
-    stencil_plane(f, c, td, k3, fe, u);
+    stencil_sums(f, td, k3, q, fe, u);
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = quad_sum(u[a]);
     uint16_t* row = sX + pi * PX;
 #pragma unroll
-    for (int q = 0; q < 12; ++q) *(uint2*)(row + 48 * k3 + 4 * q) = make_uint2(fe[2 * q], fe[2 * q + 1]);
+    for (int e = 0; e < 12; ++e) *(uint2*)(row + 48 * k3 + 4 * e) = make_uint2(fe[2 * e], fe[2 * e + 1]);
     if (k3 == 0) {
       *(uint32_t*)(row + 192) = pack_bf16((float)td[0], (float)td[1]);
       row[194] = to_bf16((float)td[2]);
       sU[pi * NO] = u[0];
       sU[pi * NO + 1] = u[1];
       sU[pi * NO + 2] = u[2];
-      sOrig[pi] = oi_c;
     } else if (k3 == 1) {
 #pragma unroll
       for (int k = NF; k < PX; ++k) row[k] = 0;
     }
+    // the next chunk: locate its particles and put its stencil loads in
+    // flight (clamped to the last chunk: the loads are unconditional, so no
+    // path waits for them early); then the coordinates of the chunk after it.
+    // The empty asm keeps these loads below the use of this chunk's rows, so
+    // the two sets of rows are never held at once.
+    asm volatile("" ::: "memory");
+    {
+      int c[3];
+      ok = locate_quad_x(x_n, k3, f.N, f.invd, c, td);
+      stencil_issue(f, c, k3, q);
+      x_n = X[3 * (int64_t)oi_nn + kx];
+    }
     __syncthreads();
     forward_hidden<false>(sX, sH1, nullptr, sH2, bw1, bw2, bias1, bias2, unused1, unused2);
     if (t < ROWS * NO) {
-      const int r = t / 3, a = t % 3;
-      const int64_t q = ch * ROWS + r;
-      const float y = output_layer(sH2, sW3, sB3, t);
-      if (q < n) out[3 * (int64_t)sOrig[r] + a] = sU[r * NO + a] + y;
+      const float y = output_layer<true>(sH2, sW3, sB3, t);
+      if (ch * ROWS + orow < n) out[3 * (int64_t)o_dst + oa] = sU[orow * NO + oa] + y;
     }
-    __syncthreads();  // h2, sU and sOrig are read before the next chunk overwrites them
-    oi_c = oi_n;
-    x_c = x_n;
-    oi_n = oi_nn;
+    __syncthreads();  // h2 and sU are read before the next chunk overwrites them
   }
 }
 
@@ -672,6 +733,7 @@ hipError_t launch_learned_infer(const LearnedField& f, const double* X, int64_t 
                                 const float* params, const uint16_t* w1b, const uint16_t* w2b, float* out,
                                 int* flag, hipStream_t s) {
   if (n <= 0) return hipSuccess;
+  if (!orig) return hipErrorInvalidValue;  // the kernel reads every particle's row through it
   const int64_t nchunks = (n + ROWS - 1) / ROWS;
   const int64_t grid = min((nchunks + 7) / 8 * 8, (int64_t)256 * 2 * 4);  // a multiple of the 8 XCDs
   k_infer<<<(unsigned)grid, NT, 0, s>>>(f, X, n, orig, params, w1b, w2b, out, flag);
