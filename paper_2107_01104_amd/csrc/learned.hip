@@ -189,14 +189,13 @@ __global__ __launch_bounds__(NT) void k_pairs(LearnedField f, const double* X, i
 }
 
 // ---------------------------------------------------------------- forward
-// Both hidden layers for the 64 rows whose features are in sX.  Leaves the
-// pre-activations' derivatives (training) in ds1/ds2, h1 in sH1 (and its
-// transpose in sH1t if given), h2 (FP32) in sH2.  sX and sH2 may alias: sX is
-// dead once layer 1 is done (a barrier separates them).
+// Hidden layer 1 for the 64 rows whose features are in sX: h1 (BF16) in sH1
+// (and its transpose in sH1t if given), the pre-activations' derivatives
+// (training) in ds1.  Ends with the barrier after which h1 is complete and sX
+// is dead.
 template <bool TRAIN>
-__device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1, uint16_t* sH1t, float* sH2,
-                                               const bf16x8 (&bw1)[13], const bf16x8 (&bw2)[8], float bias1,
-                                               float bias2, f32x16 (&ds1)[2], f32x16 (&ds2)[2]) {
+__device__ __forceinline__ void hidden_layer1(const uint16_t* sX, uint16_t* sH1, uint16_t* sH1t,
+                                              const bf16x8 (&bw1)[13], float bias1, f32x16 (&ds1)[2]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r32 = lane & 31, hi = lane >> 5;
   const int J = 32 * wave + r32;
@@ -243,10 +242,24 @@ __device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1
       if (sH1t) *(uint2*)(sH1t + J * PT + r0) = make_uint2(p01, p23);
     }
   __syncthreads();  // h1 complete; sX is dead from here on
+}
+
+// Both hidden layers: layer 1 as above, then h2 (FP32) in sH2 and its
+// pre-activations' derivatives (training) in ds2.  sX and sH2 may alias.
+template <bool TRAIN>
+__device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1, uint16_t* sH1t, float* sH2,
+                                               const bf16x8 (&bw1)[13], const bf16x8 (&bw2)[8], float bias1,
+                                               float bias2, f32x16 (&ds1)[2], f32x16 (&ds2)[2]) {
+  hidden_layer1<TRAIN>(sX, sH1, sH1t, bw1, bias1, ds1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r32 = lane & 31, hi = lane >> 5;
+  const int J = 32 * wave + r32;
+  f32x16 acc[2];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[rt][v] = 0.f;
+  bf16x8 an[2];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt) an[rt] = frag(sH1, PH, 32 * rt + r32, 8 * hi);
 #pragma unroll
@@ -271,10 +284,75 @@ __device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1
   __syncthreads();  // h2 complete
 }
 
-// y[r][a] = b3[a] + sum_c h2[r][c] W3[a][c] for thread t < 192 (r = t/3, a = t%3).
-// LEAN: an empty asm with a memory clobber ends every unrolled step, so the
-// reads are not hoisted ahead into registers the caller holds otherwise.
-template <bool LEAN>
+// Inference: hidden layer 2 with the operands swapped (W2 rows as the A tile,
+// h1 rows as the B tile), so that lane l holds particle 32 rt + l % 32 and,
+// in register v, the wave's hidden unit 32 wave + acc_row(v, l / 32); then
+// the output layer straight from those registers.  Each lane adds its 16
+// units' h2 W3 products, the wave's two lane halves add theirs (lane l ^ 32
+// holds the other 16 units of the same particles), and lanes l < 32 leave the
+// wave's sums in sY[wave][row][a].  Ends with the barrier after which sY is
+// complete.  Training keeps the FP32 h2 tile (forward_hidden): its backward
+// pass reads h2 by rows.
+__device__ __forceinline__ void infer_layer2_out(const uint16_t* sH1, const bf16x8 (&bw2)[8], const float* sB2,
+                                                 const float* sW3, float* sY) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r32 = lane & 31, hi = lane >> 5;
+  f32x16 acc[2];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[rt][v] = 0.f;
+  bf16x8 bn[2];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) bn[rt] = frag(sH1, PH, 32 * rt + r32, 8 * hi);
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const bf16x8 b0 = bn[0], b1 = bn[1];
+    if (s + 1 < 8) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) bn[rt] = frag(sH1, PH, 32 * rt + r32, 16 * (s + 1) + 8 * hi);
+    }
+    acc[0] = mfma(bw2[s], b0, acc[0]);
+    acc[1] = mfma(bw2[s], b1, acc[1]);
+    asm volatile("" ::: "memory");
+  }
+  float y[2][NO];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int a = 0; a < NO; ++a) y[rt][a] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    // registers 4k .. 4k+3 hold units u0 .. u0+3
+    const int u0 = 32 * wave + 8 * k + 4 * hi;
+    const float4 b = *(const float4*)(sB2 + u0);
+    const float4 w0 = *(const float4*)(sW3 + u0), w1 = *(const float4*)(sW3 + NH + u0),
+                 w2 = *(const float4*)(sW3 + 2 * NH + u0);
+    const float bb[4] = {b.x, b.y, b.z, b.w};
+    const float ww[NO][4] = {{w0.x, w0.y, w0.z, w0.w}, {w1.x, w1.y, w1.z, w1.w}, {w2.x, w2.y, w2.z, w2.w}};
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float h = silu(acc[rt][4 * k + q] + bb[q]);
+#pragma unroll
+        for (int a = 0; a < NO; ++a) y[rt][a] = fmaf(h, ww[a][q], y[rt][a]);
+      }
+  }
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int a = 0; a < NO; ++a) y[rt][a] += __shfl_xor(y[rt][a], 32);
+  if (hi == 0) {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int a = 0; a < NO; ++a) sY[(wave * ROWS + 32 * rt + r32) * NO + a] = y[rt][a];
+  }
+  __syncthreads();  // every wave's sums are in sY
+}
+
+// y[r][a] = b3[a] + sum_c h2[r][c] W3[a][c] for thread t < 192 (r = t/3, a = t%3)
 __device__ __forceinline__ float output_layer(const float* sH2, const float* sW3, const float* b3, int t) {
   const int r = t / 3, a = t - 3 * (t / 3);
   const float4* h = (const float4*)(sH2 + r * PH2);
@@ -291,7 +369,6 @@ __device__ __forceinline__ float output_layer(const float* sH2, const float* sW3
     y1 = fmaf(h1.y, w1.y, y1);
     y1 = fmaf(h1.z, w1.z, y1);
     y1 = fmaf(h1.w, w1.w, y1);
-    if constexpr (LEAN) asm volatile("" ::: "memory");
   }
   return b3[a] + (y0 + y1);
 }
@@ -376,7 +453,7 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
   // output layer, loss and dy = 2 (y - target) / (3 batch)
   float se = 0.f;
   if (t < ROWS * NO) {
-    const float y = output_layer<false>(sH2, sW3, params + oB3, t);
+    const float y = output_layer(sH2, sW3, params + oB3, t);
     const float d = y - target[(row0 + t / 3) * NO + t % 3];
     se = d * d;
     sdy[t] = 2.0f * d / (float)(NO * batch);
@@ -564,24 +641,25 @@ __global__ __launch_bounds__(NT) void k_update(float* params, float* m, float* v
 __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X, int64_t n, const uint32_t* orig,
                                                  const float* params, const uint16_t* w1b, const uint16_t* w2b,
                                                  float* out, int* flag) {
-  constexpr int RX = ROWS * PH2 * 4;  // features, then h2
-  static_assert(RX >= ROWS * PX * 2, "feature tile");
+  constexpr int RX = ROWS * PX * 2;  // features
   __shared__ __attribute__((aligned(16))) unsigned char lds[RX + ROWS * PH * 2];
   __shared__ __attribute__((aligned(16))) float sW3[NO * NH];
+  __shared__ __attribute__((aligned(16))) float sB2[NH];
+  __shared__ float sY[4 * ROWS * NO];  // the 4 waves' output-layer sums
   __shared__ float sU[ROWS * NO];
   __shared__ float sB3[NO];
   uint16_t* sX = (uint16_t*)lds;
-  float* sH2 = (float*)lds;
   uint16_t* sH1 = (uint16_t*)(lds + RX);
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int J = 32 * wave + (lane & 31);
   for (int e = t; e < NO * NH; e += NT) sW3[e] = params[oW3 + e];
+  if (t < NH) sB2[t] = params[oB2 + t];
   if (t < NO) sB3[t] = params[oB3 + t];
   bf16x8 bw1[13], bw2[8];
   load_weight_frags(w1b, w2b, bw1, bw2);
-  const float bias1 = params[oB1 + J], bias2 = params[oB2 + J];
-  f32x16 unused1[2], unused2[2];
+  const float bias1 = params[oB1 + J];
+  f32x16 unused1[2];
   // each block walks a contiguous range of chunks (neighbouring bins, so its
   // stencil reads stay in L2 and in the translation caches); consecutive
   // blocks go round-robin to the 8 XCDs, so XCD x is given a contiguous range
@@ -654,12 +732,14 @@ __global__ __launch_bounds__(NT, 2) void k_infer(LearnedField f, const double* X
       x_n = X[3 * (int64_t)oi_nn + kx];
     }
     __syncthreads();
-    forward_hidden<false>(sX, sH1, nullptr, sH2, bw1, bw2, bias1, bias2, unused1, unused2);
+    hidden_layer1<false>(sX, sH1, nullptr, bw1, bias1, unused1);
+    infer_layer2_out(sH1, bw2, sB2, sW3, sY);
     if (t < ROWS * NO) {
-      const float y = output_layer<true>(sH2, sW3, sB3, t);
+      const float* yw = sY + orow * NO + oa;
+      const float y = sB3[oa] + ((yw[0] + yw[ROWS * NO]) + (yw[2 * ROWS * NO] + yw[3 * ROWS * NO]));
       if (ch * ROWS + orow < n) out[3 * (int64_t)o_dst + oa] = sU[orow * NO + oa] + y;
     }
-    __syncthreads();  // h2 and sU are read before the next chunk overwrites them
+    __syncthreads();  // sY and sU are read before the next chunk overwrites them
   }
 }
 
