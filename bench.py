@@ -50,6 +50,12 @@ TARGET_RMS = 1e-4  # the stated error target of the reduced-precision and learne
 # value + gradient 4080 FMA (x3 stage, x2 stage, x1 stage, Horner weights)
 FLOP_VALUE_I8 = 2 * 1920
 FLOP_GRAD_I8 = 2 * 4080
+# learned form, matrix-core products per training pair (195-128-128 hidden
+# layers): forward 2 (195*128 + 128*128), backward dh1 2*128*128, dW2
+# 2*128*128, dW1 2*195*128 (the 3-wide output layer runs in FP32 VALU)
+TRAIN_MFMA_FLOP_PER_PAIR = 2 * (195 * 128 + 128 * 128) + 2 * 128 * 128 + 2 * 128 * 128 + 2 * 195 * 128
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+TRAIN_BATCH = 4096  # the learned form's training batch (16384 trains 2.6x faster, to a worse model)
 COPY_BYTES = 1 << 30  # the calibration copy: 1 GiB read and 1 GiB written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "interp_grad_f32_i8_1024_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2107_01104_amd", "csrc", "interp.hip")
@@ -764,13 +770,30 @@ def run_learned(ctx, ptk, u_dev, X0, Np, refs, rms_ref, out):
     ctx.learned_set_params(p0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    curve = ctx.learned_train(feat, tg, epochs=8, batch=4096, lr=1e-3)
+    curve = ctx.learned_train(feat, tg, epochs=8, batch=TRAIN_BATCH, lr=1e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     n_pairs = feat.shape[0]
     curve = curve.cpu().numpy()
-    del feat, tg
     params = ctx.learned_get_params()
+    # throughput by batch (one epoch each from the same start; at 16384, the
+    # largest the trainer takes, a step spans every CU)
+    sweep = []
+    for bsz in (4096, 16384):
+        ctx.learned_set_params(p0)
+        ctx.learned_train(feat[: 64 * bsz], tg[: 64 * bsz], epochs=1, batch=bsz, lr=1e-3)  # warm-up
+        ctx.learned_set_params(p0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c1 = ctx.learned_train(feat, tg, epochs=1, batch=bsz, lr=1e-3)
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t1
+        rate = len(c1) * bsz / dt1
+        sweep.append({"batch": bsz, "steps": int(len(c1)), "pairs_per_s": rate,
+                      "mfma_tflops": round(rate * TRAIN_MFMA_FLOP_PER_PAIR / 1e12, 2),
+                      "mfma_frac": round(rate * TRAIN_MFMA_FLOP_PER_PAIR / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4),
+                      "loss_last": float(c1[-1].item())})
+    del feat, tg
     ctx.set_field(u_dev, ptk.SPLINE, 8, 2, storage=ptk.F32)
     ctx.learned_set_params(params)
     stream = torch.cuda.current_stream(dev)
@@ -797,7 +820,12 @@ def run_learned(ctx, ptk, u_dev, X0, Np, refs, rms_ref, out):
                                         tol_rel_rms=float("inf"))
     err = got.cpu().numpy().astype(np.float64) - ref
     res = {"train_pairs": int(n_pairs), "pairs_per_s": n_pairs / t_pairs, "train_s": round(t_train, 3),
-           "train_pairs_per_s": len(curve) * 4096 / t_train, "steps": int(len(curve)),
+           "train_batch": TRAIN_BATCH,
+           "train_pairs_per_s": len(curve) * TRAIN_BATCH / t_train, "steps": int(len(curve)),
+           "train_mfma_flop_per_pair": TRAIN_MFMA_FLOP_PER_PAIR,
+           "train_mfma_frac": round(len(curve) * TRAIN_BATCH / t_train * TRAIN_MFMA_FLOP_PER_PAIR / 1e12
+                                    / BF16_MFMA_PEAK_TFLOPS, 4),
+           "train_throughput_by_batch": sweep,
            "loss_first": float(curve[0]), "loss_last": float(curve[-1]),
            "tol_rel_rms": TARGET_RMS, "audit_rms": audit, "fell_back": bool(fell),
            "end_to_end_ms": round(ms, 3), "interp_per_s_end_to_end": Np / (ms * 1e-3),
