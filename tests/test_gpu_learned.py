@@ -188,6 +188,29 @@ def test_inference_and_audit(ptk, setup):
     assert audit == pytest.approx(ref_audit, rel=1e-3)
 
 
+def test_inference_many_chunks_per_workgroup(ptk, setup):
+    """300 001 particles: 4 688 chunks of 64 on the launch's 2 048
+    workgroups, so each workgroup runs up to three chunks with the next
+    chunk's loads in flight, and the last chunk is ragged."""
+    ctx, u = setup
+    say("[learned infer] N=32, 300001 particles")
+    p = params_init(9, scale=0.3)
+    ctx.learned_set_params(p)
+    X = particles.uniform_particles(300_001, seed=26).numpy()
+    out, _, fell = ctx.interpolate_learned(torch.from_numpy(X).to(DEV), audit_frac=1e-3,
+                                           tol_rel_rms=float("inf"))
+    out = out.cpu().numpy().astype(np.float64)
+    assert not fell
+    narrow = interp.interp_vec(u, X, K.LAGRANGE, 4, 0)
+    a_n = interp.interp_vec(u, X, K.LAGRANGE, 4, 0, absolute=True)
+    y, _ = LN.forward(p.astype(np.float64), bf16_bits_to_f64(LN.features(u, X)), emulate_bf16=True)
+    d = out - (narrow + y)
+    ry = float(np.sqrt(np.mean(y * y)))
+    say(f"  rms(y) {ry:.3e}  rms diff {np.sqrt(np.mean(d * d)):.3e}  max diff {np.max(np.abs(d)):.3e}")
+    assert np.sqrt(np.mean(d * d)) <= 2e-4 * ry
+    assert np.all(np.abs(d) <= 1e-2 * ry + F32_BOUND * a_n)
+
+
 def test_fallback(ptk, setup):
     ctx, u = setup
     say("[learned fallback] tol 0")
