@@ -402,6 +402,7 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
   __shared__ __attribute__((aligned(16))) unsigned char lds[R0 + R1 + R2 + R3];
   __shared__ float sW3[NO * NH];
   __shared__ float sdy[ROWS * NO];
+  __shared__ float sdw3[2 * NO * NH];  // dW3 sums of the two halves of the rows
   __shared__ float sred[NT / 64];
   uint16_t* sXt = (uint16_t*)lds;
   uint16_t* sH1t = (uint16_t*)(lds + R0);
@@ -419,26 +420,35 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   float* gp = gpart + (int64_t)blockIdx.x * kLearnedNParams;
 
-  // features -> sX (row-major) and sXt (transposed); entries 195.. are zero
-  for (int e = t; e < ROWS * (K1 / 8); e += NT) {
+  // features -> sX (row-major) and sXt (transposed); entries 195.. are zero.
+  // This thread's 16-byte pieces are loaded together (unconditionally, from
+  // a clamped address), then stored.
+  constexpr int FE = ROWS * (K1 / 8), FI = (FE + NT - 1) / NT;
+  uint4 fq[FI];
+#pragma unroll
+  for (int i = 0; i < FI; ++i) {
+    const int e = min(t + i * NT, FE - 1);
+    const int r = e / (K1 / 8), k0 = (e % (K1 / 8)) * 8;
+    fq[i] = *(const uint4*)(feat + (row0 + r) * FP + (k0 < FP ? k0 : 0));
+  }
+#pragma unroll
+  for (int i = 0; i < FI; ++i) {
+    const int e = t + i * NT;
+    if (e >= FE) break;
     const int r = e / (K1 / 8), k0 = (e % (K1 / 8)) * 8;
     uint16_t v[8];
-    if (k0 < FP) {
-      const uint4 q = *(const uint4*)(feat + (row0 + r) * FP + k0);
-      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+    {
+      const uint32_t w[4] = {fq[i].x, fq[i].y, fq[i].z, fq[i].w};
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = 0;
+      for (int j = 0; j < 8; ++j) v[j] = k0 < FP ? (uint16_t)(w[j >> 1] >> (16 * (j & 1))) : (uint16_t)0;
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (k0 + i >= NF) v[i] = 0;
+    for (int j = 0; j < 8; ++j)
+      if (k0 + j >= NF) v[j] = 0;
     *(uint4*)(sX + r * PX + k0) = make_uint4((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
                                              (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16));
 #pragma unroll
-    for (int i = 0; i < 8; ++i) sXt[(k0 + i) * PT + r] = v[i];
+    for (int j = 0; j < 8; ++j) sXt[(k0 + j) * PT + r] = v[j];
   }
   for (int e = t; e < (224 - K1) * ROWS; e += NT) sXt[(K1 + e / ROWS) * PT + e % ROWS] = 0;
   for (int e = t; e < NO * NH; e += NT) sW3[e] = params[oW3 + e];
@@ -463,12 +473,21 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
   if (lane == 0) sred[wave] = se;
   __syncthreads();
   if (t == 0) lpart[blockIdx.x] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
-  // dW3[a][c] = sum_r dy[r][a] h2[r][c]; db3[a] = sum_r dy[r][a]
-  for (int o = t; o < NO * NH; o += NT) {
-    const int a = o / NH, c = o % NH;
-    float g = 0.f;
-    for (int r = 0; r < ROWS; ++r) g = fmaf(sdy[r * NO + a], sH2[r * PH2 + c], g);
-    gp[oW3 + o] = g;
+  // dW3[a][c] = sum_r dy[r][a] h2[r][c]: thread (c, half) sums its half of
+  // the rows for the three a (the halves are added after the barrier);
+  // db3[a] = sum_r dy[r][a]
+  static_assert(NT == 2 * NH, "dW3 split");
+  {
+    const int c = t & (NH - 1), r0 = (t / NH) * (ROWS / 2);
+    float g[NO] = {0.f, 0.f, 0.f};
+#pragma unroll 8
+    for (int r = r0; r < r0 + ROWS / 2; ++r) {
+      const float h = sH2[r * PH2 + c];
+#pragma unroll
+      for (int a = 0; a < NO; ++a) g[a] = fmaf(sdy[r * NO + a], h, g[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < NO; ++a) sdw3[(t / NH) * NO * NH + a * NH + c] = g[a];
   }
   if (t < NO) {
     float g = 0.f;
@@ -476,6 +495,7 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
     gp[oB3 + t] = g;
   }
   __syncthreads();  // every read of h2 is done: R2 now takes dz2
+  for (int o = t; o < NO * NH; o += NT) gp[oW3 + o] = sdw3[o] + sdw3[NO * NH + o];
 
   // dz2 = (dy W3) * silu'(z2), stored as BF16 row-major and transposed
   {
