@@ -604,31 +604,44 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
 
 // Sum of the workgroups' gradients, then (mode 1) one Adam step with BF16
 // copies of W1, W2 (and W2 transposed), (mode 0) the gradient and loss only,
-// (mode 2) the BF16 copies only.
+// (mode 2) the BF16 copies only.  A workgroup takes 64 parameters: wave q
+// sums the q-th quarter of the partials (consecutive, in order, their loads
+// in flight together), and wave 0 adds the four sums in order, so the order
+// of every addition is fixed.
+constexpr int UPD_E = 64;  // parameters per workgroup of k_update
 __global__ __launch_bounds__(NT) void k_update(float* params, float* m, float* v, const float* gpart,
                                                const float* lpart, LearnedUpdate u, uint16_t* w1b, uint16_t* w2b,
                                                uint16_t* w2bt) {
-  const int e = blockIdx.x * NT + threadIdx.x;
+  __shared__ float sq[4][UPD_E];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = blockIdx.x * UPD_E + lane;
   if (blockIdx.x == 0 && threadIdx.x == 0 && u.loss_out && u.mode != 2) {
     float l = 0.f;
     for (int w = 0; w < u.nparts; ++w) l += lpart[w];
     u.loss_out[0] = l * u.loss_scale;
   }
-  if (e >= kLearnedNParams) return;
+  float g = 0.f;
+  if (u.mode != 2) {
+    const int per = (u.nparts + 3) / 4;
+    const int w0 = wave * per, w1 = min(u.nparts, w0 + per);
+    if (e < kLearnedNParams) {
+      int w = w0;
+      for (; w + 16 <= w1; w += 16) {
+        float part[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) part[k] = gpart[(int64_t)(w + k) * kLearnedNParams + e];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) g += part[k];
+      }
+      for (; w < w1; ++w) g += gpart[(int64_t)w * kLearnedNParams + e];
+    }
+    sq[wave][lane] = g;
+    __syncthreads();
+    g = ((sq[0][lane] + sq[1][lane]) + sq[2][lane]) + sq[3][lane];
+  }
+  if (wave != 0 || e >= kLearnedNParams) return;
   float p = params[e];
   if (u.mode != 2) {
-    // the partials in their fixed order, loaded 16 at a time so that the
-    // loads are in flight together (the additions stay in order)
-    float g = 0.f;
-    int w = 0;
-    for (; w + 16 <= u.nparts; w += 16) {
-      float part[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) part[k] = gpart[(int64_t)(w + k) * kLearnedNParams + e];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) g += part[k];
-    }
-    for (; w < u.nparts; ++w) g += gpart[(int64_t)w * kLearnedNParams + e];
     if (u.mode == 0) {
       u.grad_out[e] = g;
       return;
@@ -824,7 +837,7 @@ hipError_t launch_learned_forward_backward(const uint16_t* feat, const float* ta
 hipError_t launch_learned_update(float* params, float* m, float* v, const float* gpart, const float* lpart,
                                  const LearnedUpdate& u, uint16_t* w1b, uint16_t* w2b, uint16_t* w2bt,
                                  hipStream_t s) {
-  const int blocks = (kLearnedNParams + NT - 1) / NT;
+  const int blocks = (kLearnedNParams + UPD_E - 1) / UPD_E;
   k_update<<<blocks, NT, 0, s>>>(params, m, v, gpart, lpart, u, w1b, w2b, w2bt);
   return hipGetLastError();
 }
