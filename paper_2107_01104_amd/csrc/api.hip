@@ -1686,11 +1686,13 @@ int ptk_learned_train(ptk_ctx* c, const uint16_t* feat, const float* target, int
   for (int64_t st = 0; st < total; ++st) {
     const int64_t b = st % nb;
     const int64_t r0 = b * cfg->batch;
+    const int64_t r1 = ((st + 1) % nb) * cfg->batch;  // the next step's rows
     PTK_HIP(c,
             launch_learned_forward_backward(feat + r0 * kLearnedPitch, target + r0 * 3, cfg->batch,
                                             (const float*)c->lparams.ptr, (const uint16_t*)c->lw1b.ptr,
                                             (const uint16_t*)c->lw2b.ptr, (const uint16_t*)c->lw2bt.ptr,
-                                            (float*)c->lgpart.ptr, (float*)c->llpart.ptr, s),
+                                            (float*)c->lgpart.ptr, (float*)c->llpart.ptr, s,
+                                            st + 1 < total ? feat + r1 * kLearnedPitch : nullptr),
             "forward and backward");
     const int64_t gs = c->learned_step + 1;
     LearnedUpdate u;

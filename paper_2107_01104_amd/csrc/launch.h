@@ -148,9 +148,11 @@ struct LearnedUpdate {
 };
 hipError_t launch_learned_pairs(const LearnedField& f, const double* X, int64_t n, const float* uwide,
                                 uint16_t* feat, float* target, int* flag, hipStream_t s);
+// feat_next: the next step's batch rows (read ahead into L2), or NULL
 hipError_t launch_learned_forward_backward(const uint16_t* feat, const float* target, int64_t batch,
                                            const float* params, const uint16_t* w1b, const uint16_t* w2b,
-                                           const uint16_t* w2bt, float* gpart, float* lpart, hipStream_t s);
+                                           const uint16_t* w2bt, float* gpart, float* lpart, hipStream_t s,
+                                           const uint16_t* feat_next = nullptr);
 hipError_t launch_learned_update(float* params, float* m, float* v, const float* gpart, const float* lpart,
                                  const LearnedUpdate& u, uint16_t* w1b, uint16_t* w2b, uint16_t* w2bt,
                                  hipStream_t s);

@@ -390,7 +390,7 @@ __device__ __forceinline__ void load_weight_frags(const uint16_t* w1b, const uin
 __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat, const float* target, int64_t batch,
                                                             const float* params, const uint16_t* w1b,
                                                             const uint16_t* w2b, const uint16_t* w2bt, float* gpart,
-                                                            float* lpart) {
+                                                            float* lpart, const uint16_t* feat_next) {
   // LDS regions (bytes): R0 transposed features [224][PT]; R1 transposed h1
   // [128][PT]; R2 features [64][PX] -> h2 FP32 [64][PH2] -> dz2 [64][PH] +
   // transposed dz2 [128][PT]; R3 h1 [64][PH] -> transposed dz1 [128][PT]
@@ -431,6 +431,18 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
     const int r = e / (K1 / 8), k0 = (e % (K1 / 8)) * 8;
     fq[i] = *(const uint4*)(feat + (row0 + r) * FP + (k0 < FP ? k0 : 0));
   }
+  // the same rows of the next step's batch, read now so that they are in
+  // this XCD's L2 when that step's workgroup (same block index, same XCD)
+  // starts; their registers are consumed only at the end of the kernel
+  uint4 fnext[FI];
+  if (feat_next) {
+#pragma unroll
+    for (int i = 0; i < FI; ++i) {
+      const int e = min(t + i * NT, FE - 1);
+      const int r = e / (K1 / 8), k0 = (e % (K1 / 8)) * 8;
+      fnext[i] = *(const uint4*)(feat_next + (row0 + r) * FP + (k0 < FP ? k0 : 0));
+    }
+  }
 #pragma unroll
   for (int i = 0; i < FI; ++i) {
     const int e = t + i * NT;
@@ -447,10 +459,20 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
       if (k0 + j >= NF) v[j] = 0;
     *(uint4*)(sX + r * PX + k0) = make_uint4((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
                                              (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16));
-#pragma unroll
-    for (int j = 0; j < 8; ++j) sXt[(k0 + j) * PT + r] = v[j];
   }
-  for (int e = t; e < (224 - K1) * ROWS; e += NT) sXt[(K1 + e / ROWS) * PT + e % ROWS] = 0;
+  __syncthreads();  // sX complete
+  // sXt from sX: item (k, 8 rows from r0) per thread, consecutive threads on
+  // consecutive k, so the 2-byte reads of a row are contiguous and the
+  // 16-byte writes (row pitch 144 bytes) fall on distinct banks within each
+  // quarter-wave; rows k >= K1 are zero
+  for (int i = t; i < 224 * (ROWS / 8); i += NT) {
+    const int k = i % 224, r0 = (i / 224) * 8;
+    uint16_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = k < K1 ? sX[(r0 + j) * PX + k] : (uint16_t)0;
+    *(uint4*)(sXt + k * PT + r0) = make_uint4((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+                                              (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16));
+  }
   for (int e = t; e < NO * NH; e += NT) sW3[e] = params[oW3 + e];
   bf16x8 bw1[13], bw2[8];
   load_weight_frags(w1b, w2b, bw1, bw2);
@@ -599,6 +621,10 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
 #pragma unroll
         for (int v = 0; v < 16; ++v) gp[oW1 + (32 * wave + acc_row(v, hi)) * NF + fcol] = acc[q][v];
     }
+  }
+  if (feat_next) {
+#pragma unroll
+    for (int i = 0; i < FI; ++i) asm volatile("" ::"v"(fnext[i].x));
   }
 }
 
@@ -827,10 +853,11 @@ hipError_t launch_learned_pairs(const LearnedField& f, const double* X, int64_t 
 
 hipError_t launch_learned_forward_backward(const uint16_t* feat, const float* target, int64_t batch,
                                            const float* params, const uint16_t* w1b, const uint16_t* w2b,
-                                           const uint16_t* w2bt, float* gpart, float* lpart, hipStream_t s) {
+                                           const uint16_t* w2bt, float* gpart, float* lpart, hipStream_t s,
+                                           const uint16_t* feat_next) {
   if (batch <= 0 || batch % ROWS) return hipErrorInvalidValue;
   k_forward_backward<<<(unsigned)(batch / ROWS), NT, 0, s>>>(feat, target, batch, params, w1b, w2b, w2bt, gpart,
-                                                             lpart);
+                                                             lpart, feat_next);
   return hipGetLastError();
 }
 
