@@ -1,4 +1,6 @@
-"""Tracer time stepping for dX/dt = u(X) (oracle; test infrastructure only).
+"""Tracer time stepping for dX/dt = u(X) (oracle; test infrastructure only),
+and the other particle types built on it (ellipsoid axes, inertial
+particles).
 
 Follows Sec. 2.2, Eq. "tracers" (tracer ODE with X(x,0) = x) and the
 multi-step Adams-Bashforth integration with an rhs history kept per particle
@@ -176,6 +178,62 @@ def advance(X, velocity, scheme: int, dt: float, nsteps: int, hist=None, hist_le
     if P is not None:
         return X, hist, hist_len, grad_last, P, ph
     return X, hist, hist_len, grad_last
+
+
+def drag_rhs(u, V, tau: float):
+    """Rate of change of an inertial particle's velocity V in the fluid
+    velocity u at its position, (u - V)/tau: a small heavy particle under
+    linear (Stokes) drag with response time tau.  Reading: the paper names
+    inertial particles among TurTLE's particle types (Sec. 2.2) without their
+    equation; this is the heavy-particle limit with drag only (no gravity,
+    added mass or history force)."""
+    return np.divide(np.subtract(u, V), tau)
+
+
+def advance_inertial(X, V, velocity, tau: float, scheme: int, dt: float, nsteps: int, vhist=None, rhist=None,
+                     hist_len: int = 0):
+    """Advance inertial particles, dX/dt = V and dV/dt = drag_rhs(u(X), V, tau),
+    by nsteps with the tracer schemes applied to the pair (X, V) (reading, as
+    for the ellipsoid axes: every stage evaluates u at its own position):
+
+    * Euler:  r = drag(u(X), V); X <- X + dt*V; V <- V + dt*r.
+    * Heun:   r1 = drag(u(X), V); Xs = X + dt*V; Vs = V + dt*r1;
+              r2 = drag(u(Xs), Vs); X <- X + (dt/2)*(V + Vs);
+              V <- V + (dt/2)*(r1 + r2).
+    * AB2..AB4: X <- X + dt*sum_j b_j*V_{n-j}, V <- V + dt*sum_j b_j*r_{n-j}
+      with the weights, start-up and history rules of ``advance``: vhist holds
+      the earlier particle velocities and rhist the earlier drag terms, most
+      recent first, with one shared length.
+
+    ``velocity(X) -> u[Np][3]``.  Returns (X, V, vhist, rhist, hist_len)."""
+    X = np.array(X, dtype=np.float64)
+    V = np.array(V, dtype=np.float64)
+    K = AB_ORDER.get(scheme, 2)
+    vh = np.zeros((K,) + X.shape) if vhist is None else np.array(vhist, dtype=np.float64)
+    rh = np.zeros((K,) + X.shape) if rhist is None else np.array(rhist, dtype=np.float64)
+    for _ in range(nsteps):
+        r1 = drag_rhs(velocity(X), V, tau)
+        if scheme == EULER:
+            X, V = euler_update(X, dt, V), euler_update(V, dt, r1)
+        elif scheme == HEUN:
+            Xs = heun_predict(X, dt, V)
+            Vs = heun_predict(V, dt, r1)
+            r2 = drag_rhs(velocity(Xs), Vs, tau)
+            X, V = heun_correct(X, dt, V, Vs), heun_correct(V, dt, r1, r2)
+        elif scheme in (AB2, AB3, AB4):
+            q = min(K, hist_len + 1)
+            Xn = ab_update(X, dt, [V] + [vh[j] for j in range(q - 1)], q)
+            Vn = ab_update(V, dt, [r1] + [rh[j] for j in range(q - 1)], q)
+            for j in range(K - 1, 0, -1):
+                vh[j] = vh[j - 1]
+                rh[j] = rh[j - 1]
+            vh[0] = V
+            rh[0] = r1
+            hist_len = min(hist_len + 1, K)
+            X, V = Xn, Vn
+        else:
+            raise ValueError("unknown scheme")
+    return X, V, vh, rh, hist_len
 
 
 def heun_two_fields(X, vel_now, vel_next, dt: float, gradient_now=None):

@@ -261,3 +261,101 @@ def test_jeffery_rhs_special_cases():
         assert np.max(np.abs(np.sum(r * p, axis=1))) < 1e-14
     strain = jeffery_rhs(A, p, 1.0) - jeffery_rhs(A, p, 0.0)
     assert np.allclose(jeffery_rhs(A, p, -1.0), jeffery_rhs(A, p, 0.0) - strain, atol=1e-15)
+
+
+# ---- inertial particles: dX/dt = V, dV/dt = (u(X) - V)/tau
+
+def _const_field(U0):
+    return lambda Y: np.broadcast_to(U0, np.shape(Y)).copy()
+
+
+@pytest.mark.parametrize("scheme", [EULER, HEUN])
+def test_inertial_constant_field_closed_forms(scheme):
+    """In a uniform field U0 the schemes' recurrences close: V_n - U0 =
+    (V_0 - U0) g^n with g = 1 - h (Euler) or 1 - h + h^2/2 (Heun), h = dt/tau,
+    and X_n = X_0 + n dt U0 + c (V_0 - U0) (1 - g^n)/(1 - g) with c = dt
+    (Euler) or dt (1 - h/2) (Heun)."""
+    rng = np.random.default_rng(40)
+    X0, V0 = rng.uniform(-3, 3, (50, 3)), rng.standard_normal((50, 3))
+    U0 = np.array([0.7, -1.3, 0.2])
+    tau, dt, n = 0.37, 0.05, 23
+    h = dt / tau
+    X, V, _, _, _ = stepping.advance_inertial(X0, V0, _const_field(U0), tau, scheme, dt, n)
+    g = 1 - h if scheme == EULER else 1 - h + h * h / 2
+    c = dt if scheme == EULER else dt * (1 - h / 2)
+    assert np.allclose(V, U0 + (V0 - U0) * g ** n, rtol=0, atol=1e-13)
+    assert np.allclose(X, X0 + n * dt * U0 + c * (V0 - U0) * (1 - g ** n) / (1 - g), rtol=0, atol=1e-12)
+
+
+def _shear_u(Y):
+    Y = np.asarray(Y)
+    return np.stack([np.sin(Y[..., 1]), 0.5 * np.cos(Y[..., 2]), 0.3 * np.sin(Y[..., 0] + Y[..., 1])], axis=-1)
+
+
+def _exact_inertial(X0, V0, tau, T):
+    """The continuous solution by scipy's adaptive Runge-Kutta (tight tolerances)."""
+    from scipy.integrate import solve_ivp
+
+    def f(t, y):
+        Y = y.reshape(-1, 6)
+        Xp, Vp = Y[:, :3], Y[:, 3:]
+        return np.concatenate([Vp, (_shear_u(Xp) - Vp) / tau], axis=1).ravel()
+    y0 = np.concatenate([X0, V0], axis=1).ravel()
+    sol = solve_ivp(f, (0.0, T), y0, method="DOP853", rtol=1e-12, atol=1e-13)
+    Y = sol.y[:, -1].reshape(-1, 6)
+    return Y[:, :3], Y[:, 3:]
+
+
+@pytest.mark.parametrize("scheme,order", [(EULER, 1), (HEUN, 2), (AB2, 2)])
+def test_inertial_convergence_order(scheme, order):
+    """Against the continuous solution in a smooth steady field, halving dt
+    divides the error at a fixed time by about 2^order."""
+    rng = np.random.default_rng(41)
+    X0, V0 = rng.uniform(0, 6, (8, 3)), 0.5 * rng.standard_normal((8, 3))
+    tau, T = 0.4, 0.8
+    Xe, Ve = _exact_inertial(X0, V0, tau, T)
+    errs = []
+    for n in (40, 80):
+        X, V, _, _, _ = stepping.advance_inertial(X0, V0, _shear_u, tau, scheme, T / n, n)
+        errs.append(max(np.abs(X - Xe).max(), np.abs(V - Ve).max()))
+    ratio = errs[0] / errs[1]
+    assert 2 ** order * 0.8 < ratio < 2 ** order * 1.25, (errs, ratio)
+
+
+@pytest.mark.parametrize("scheme,order", [(stepping.AB3, 3), (stepping.AB4, 4)])
+def test_inertial_ab_high_order_with_exact_history(scheme, order):
+    """AB3/AB4 started from the exact particle velocities and drag terms at
+    the previous times (no lower-order start-up) converge at their order."""
+    rng = np.random.default_rng(42)
+    X0, V0 = rng.uniform(0, 6, (6, 3)), 0.5 * rng.standard_normal((6, 3))
+    tau, T = 0.5, 0.6
+    K = order
+    errs = []
+    for n in (30, 60):
+        dt = T / n
+        # exact states at times 0, dt, ..., (K-1) dt; start at (K-1) dt
+        states = [(X0, V0)] + [_exact_inertial(X0, V0, tau, j * dt) for j in range(1, K)]
+        Xs, Vs = states[-1]
+        vh = np.stack([states[K - 2 - j][1] for j in range(K - 1)] + [np.zeros_like(V0)])
+        rh = np.stack([stepping.drag_rhs(_shear_u(states[K - 2 - j][0]), states[K - 2 - j][1], tau)
+                       for j in range(K - 1)] + [np.zeros_like(V0)])
+        steps = n - (K - 1)
+        X, V, _, _, _ = stepping.advance_inertial(Xs, Vs, _shear_u, tau, scheme, dt, steps, vhist=vh, rhist=rh,
+                                                  hist_len=K - 1)
+        Xe, Ve = _exact_inertial(X0, V0, tau, T)
+        errs.append(max(np.abs(X - Xe).max(), np.abs(V - Ve).max()))
+    ratio = errs[0] / errs[1]
+    assert 2 ** order * 0.75 < ratio < 2 ** order * 1.3, (errs, ratio)
+
+
+@pytest.mark.parametrize("scheme", [AB2, stepping.AB4])
+def test_inertial_resume_bitwise(scheme):
+    rng = np.random.default_rng(43)
+    X0, V0 = rng.uniform(0, 6, (10, 3)), rng.standard_normal((10, 3))
+    a = stepping.advance_inertial(X0, V0, _shear_u, 0.3, scheme, 0.02, 7)
+    b = stepping.advance_inertial(X0, V0, _shear_u, 0.3, scheme, 0.02, 3)
+    b = stepping.advance_inertial(b[0], b[1], _shear_u, 0.3, scheme, 0.02, 4, vhist=b[2], rhist=b[3],
+                                  hist_len=b[4])
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
+    assert a[4] == b[4]
