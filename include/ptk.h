@@ -322,21 +322,47 @@ int ptk_particles_set_orientation(ptk_ctx *ctx, const double *p, const double *p
                                   void *stream);
 int ptk_particles_get_orientation(ptk_ctx *ctx, double *p, double *p_hist, void *stream);
 
+/* Inertial particles (NEXT-4; Sec. 2.2 names them among the particle types
+ * without their equation): small heavy particles under linear (Stokes) drag,
+ * dX/dt = V, dV/dt = (u(X) - V)/tau with response time tau.  Once set,
+ * ptk_particles_advance and ptk_particles_step_next_field move the loaded
+ * particles with their own velocities V instead of u, and V with the drag:
+ * the pair (X, V) takes the scheme of the call (Euler; Heun with the
+ * predictor X + dt V, V + dt r1 and the drag r2 at the predicted position and
+ * velocity; AB2-AB4 with two histories of the position history's length,
+ * the earlier velocities and the earlier drag terms, [k][Np][3] FP64 each).
+ * Every stage interpolates u at its own position; V and the drag are FP64.
+ * A particle set carries either axes or inertia: setting one drops the other.
+ * ptk_particles_set_inertia: V device [Np][3] FP64 in the caller's order;
+ *    v_hist and r_hist device [k][Np][3] FP64 with the first hist_len entries
+ *    valid, where hist_len must equal the loaded position history's length
+ *    (0 without one); tau > 0.  Needs loaded particles; a new load drops the
+ *    inertia.
+ * ptk_particles_get_inertia: V and its two histories in the caller's order.
+ * Errors: PTK_EINVAL (nothing loaded, no inertia set, tau not positive and
+ *    finite, NULL pointers, history length). */
+int ptk_particles_set_inertia(ptk_ctx *ctx, const double *V, const double *v_hist, const double *r_hist,
+                              int hist_len, double tau, void *stream);
+int ptk_particles_get_inertia(ptk_ctx *ctx, double *V, double *v_hist, double *r_hist, void *stream);
+
 /* In-order particle state files: checkpoint / restart and output for
  * post-processing (Sec. 3.4: the particles are written in the original order
  * given as input, so that outputs are consistent from one to the next whatever
  * order the library keeps them in).
  * ptk_particles_save writes the loaded state to `path` (host file, replaced):
  * a 64-byte header -- "PTKSTATE", uint32 version 1, uint32 flags (bit 0: axes
- * follow), int64 Np, int32 history depth k, int32 valid history entries h,
- * int32 bytes per history component (8 or 4), int32 grid N, float64 axis
- * shape, 16 reserved bytes, little-endian -- then, in the caller's order,
- * positions [Np][3] float64, the history [h][Np][3], and with axes the axes
- * [Np][3] float64 and their history [h][Np][3] float64.  Waits for the
+ * follow, bit 1: inertia follows), int64 Np, int32 history depth k, int32
+ * valid history entries h, int32 bytes per history component (8 or 4), int32
+ * grid N, float64 axis shape, float64 response time tau (inertia; else 0), 8
+ * reserved bytes, little-endian -- then, in the caller's order, positions
+ * [Np][3] float64, the history [h][Np][3], and with axes the axes [Np][3]
+ * float64 and their history [h][Np][3] float64, or with inertia the
+ * velocities [Np][3] float64, their history and the drag history
+ * ([h][Np][3] float64 each).  Waits for the
  * stream; goes through the device (a staging copy of the state) and one
  * 32 MiB pinned host buffer.
  * ptk_particles_restore makes a file's state the loaded state, as
- * ptk_particles_load (and ptk_particles_set_orientation) would from those
+ * ptk_particles_load (and ptk_particles_set_orientation or _set_inertia) would from those
  * arrays; needs a field with the file's N (and, with a history, a storage
  * type of its velocity precision).  A run restored from a file continues bit
  * for bit as the run that saved it.

@@ -934,6 +934,7 @@ int adv_load(ptk_ctx* c, const double* X, int64_t Np, const void* rhs_hist, int 
     }
   }
   st.ori = false;
+  st.inert = false;
   st.Np = Np;
   st.N = N;
   st.vb = vb;
@@ -976,16 +977,17 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
     st.k1 = c->k1.ptr;
   }
   if (scheme == PTK_HEUN) PTK_TRY(ensure(c, c->k2, v3));
-  const bool ori = st.ori;
+  const bool ori = st.ori, inert = st.inert;
+  const bool pst = ori || inert;  // a per-particle 3-vector state beside X (axes or velocities)
   const size_t g9 = (size_t)Np * 9 * vb, p3 = (size_t)Np * 24;
   if (grad_out || ori) PTK_TRY(ensure(c, c->gint, g9));
-  if (ori) {
-    // the stage rhs and the predictor's axes and gradient (the axes and their
-    // history were allocated when the orientation was set)
+  if (pst) {
+    // the stage rhs and the predictor's axes (velocities) and gradient (the
+    // state and its history were allocated when it was set)
     PTK_TRY(ensure(c, c->ori_r1, p3));
     PTK_TRY(ensure(c, c->ori_r2, p3));
     PTK_TRY(ensure(c, c->ori_ps, p3));
-    if (scheme == PTK_HEUN) PTK_TRY(ensure(c, c->gint2, g9));
+    if (scheme == PTK_HEUN && ori) PTK_TRY(ensure(c, c->gint2, g9));
     if (st.K == 0) st.r1 = (double*)c->ori_r1.ptr;
     st.r2 = (double*)c->ori_r2.ptr;
     st.ps = (double*)c->ori_ps.ptr;
@@ -1006,14 +1008,18 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
     }
     if (scheme == PTK_HEUN) PTK_TRY(need(c, c->k2, v3, "predictor velocities"));
     if (grad_out || ori) PTK_TRY(need(c, c->gint, g9, "gradients"));
-    if (ori) {
+    if (pst) {
       const DevBuf* o3[] = {&c->ori_p, &c->ori_pn, &c->ori_r1, &c->ori_r2, &c->ori_ps};
-      for (const DevBuf* b : o3) PTK_TRY(need(c, *b, p3, "orientations"));
+      for (const DevBuf* b : o3) PTK_TRY(need(c, *b, p3, "per-particle state"));
       for (int j = 0; j < st.K; ++j) {
-        PTK_TRY(need(c, c->ori_h[j], p3, "orientation history"));
-        PTK_TRY(need(c, c->ori_hb[j], p3, "orientation history"));
+        PTK_TRY(need(c, c->ori_h[j], p3, "per-particle state history"));
+        PTK_TRY(need(c, c->ori_hb[j], p3, "per-particle state history"));
+        if (inert) {
+          PTK_TRY(need(c, c->in_vh[j], p3, "velocity history"));
+          PTK_TRY(need(c, c->in_vhb[j], p3, "velocity history"));
+        }
       }
-      if (scheme == PTK_HEUN) PTK_TRY(need(c, c->gint2, g9, "predictor gradients"));
+      if (scheme == PTK_HEUN && ori) PTK_TRY(need(c, c->gint2, g9, "predictor gradients"));
     }
   }
 
@@ -1034,9 +1040,12 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
   // bin order to xnext.  After a re-binning the next step reads xnext through
   // the new permutation instead of gathering it: the permutation of one time
   // step is close to the identity, so those reads stay nearly unit-stride.
+  // (inertial particles move with their own FP64 velocities)
   auto update = [&](int kind, const UpdateVel& v) -> int {
     Timed t(c, s, PTK_T_UPDATE);
-    PTK_HIP(c, launch_update(kind, vf64, st.xcur, st.xrow, v, dt, Np, st.xnext, keys, (int)N, invd, bg, flag, s),
+    PTK_HIP(c,
+            launch_update(kind, inert ? 1 : vf64, st.xcur, st.xrow, v, dt, Np, st.xnext, keys, (int)N, invd, bg, flag,
+                          s),
             "position update");
     return PTK_OK;
   };
@@ -1104,6 +1113,9 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
         Timed t(c, s, PTK_T_UPDATE);
         if (grad_out && last) PTK_HIP(c, scatter_v(c->gint.ptr, st.orig, 9, grad_out), "scatter gradient");
         PTK_HIP(c, launch_jeffery_rhs(vf64, c->gint.ptr, st.p, st.shape, Np, st.r1, s), "axis rhs");
+      } else if (inert) {
+        Timed t(c, s, PTK_T_UPDATE);
+        PTK_HIP(c, launch_drag_rhs(vf64, k1, st.p, st.tau, Np, st.r1, s), "drag");
       }
     }
     // the axes' update with the stage rhs in v (unit length at the step's end)
@@ -1112,14 +1124,16 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
       PTK_HIP(c, launch_orient_update(kind, st.p, v, dt, Np, unit, out, s), "axis update");
       return PTK_OK;
     };
+    // axes are normalized at the end of each step, velocities not
+    const int unit = ori ? 1 : 0;
     if (scheme == PTK_EULER) {
-      PTK_TRY(update(kEulerOrPredict, vel(k1, nullptr)));
-      if (ori) PTK_TRY(orient(kEulerOrPredict, vel(st.r1, nullptr), st.pn, 1));
+      PTK_TRY(update(kEulerOrPredict, inert ? vel(st.p, nullptr) : vel(k1, nullptr)));
+      if (pst) PTK_TRY(orient(kEulerOrPredict, vel(st.r1, nullptr), st.pn, unit));
     } else if (scheme == PTK_HEUN) {
       // predictor (into xnext), re-binned; u at the predictor is written
       // back in the step's bin order
-      PTK_TRY(update(kEulerOrPredict, vel(k1, nullptr)));
-      if (ori) PTK_TRY(orient(kEulerOrPredict, vel(st.r1, nullptr), st.ps, 0));
+      PTK_TRY(update(kEulerOrPredict, inert ? vel(st.p, nullptr) : vel(k1, nullptr)));
+      if (pst) PTK_TRY(orient(kEulerOrPredict, vel(st.r1, nullptr), st.ps, 0));
       uint32_t* pp = (uint32_t*)c->aperm_p.ptr;
       PTK_TRY(rebin(pp));
       {
@@ -1138,13 +1152,16 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
         Timed t(c, s, ori ? PTK_T_INTERP_GRAD : PTK_T_INTERP);
         PTK_HIP(c, launch_interp(c->storage, c->I, b, s), "interpolate predictor");
       }
-      PTK_TRY(update(kHeunCorrect, vel(k1, k2)));
-      if (ori) {
+      PTK_TRY(update(kHeunCorrect, inert ? vel(st.p, st.ps) : vel(k1, k2)));
+      if (pst) {
         {
           Timed t(c, s, PTK_T_UPDATE);
-          PTK_HIP(c, launch_jeffery_rhs(vf64, c->gint2.ptr, st.ps, st.shape, Np, st.r2, s), "axis rhs");
+          if (ori)
+            PTK_HIP(c, launch_jeffery_rhs(vf64, c->gint2.ptr, st.ps, st.shape, Np, st.r2, s), "axis rhs");
+          else
+            PTK_HIP(c, launch_drag_rhs(vf64, k2, st.ps, st.tau, Np, st.r2, s), "drag");
         }
-        PTK_TRY(orient(kHeunCorrect, vel(st.r1, st.r2), st.pn, 1));
+        PTK_TRY(orient(kHeunCorrect, vel(st.r1, st.r2), st.pn, unit));
       }
     } else {
       // order min(K, hl + 1): u_n = k1 and the hl stored velocities
@@ -1155,16 +1172,32 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
       for (int j = 1; j < q; ++j) v.k[j] = st.h[j - 1];
       for (int j = 0; j < q; ++j) v.b[j] = kABW[q][j];
       v.nk = q;
-      PTK_TRY(update(q == 1 ? kEulerOrPredict : kAB, v));
-      if (ori) {
+      if (inert) {
+        // the positions' history is the earlier particle velocities
+        UpdateVel vx = v;
+        vx.k[0] = st.p;
+        for (int j = 1; j < q; ++j) vx.k[j] = st.vh[j - 1];
+        PTK_TRY(update(q == 1 ? kEulerOrPredict : kAB, vx));
+      } else {
+        PTK_TRY(update(q == 1 ? kEulerOrPredict : kAB, v));
+      }
+      if (pst) {
         UpdateVel vp = v;
         vp.k[0] = st.r1;
         for (int j = 1; j < q; ++j) vp.k[j] = st.ph[j - 1];
-        PTK_TRY(orient(q == 1 ? kEulerOrPredict : kAB, vp, st.pn, 1));
+        PTK_TRY(orient(q == 1 ? kEulerOrPredict : kAB, vp, st.pn, unit));
         double* tp = st.ph[K - 1];
         for (int j = K - 1; j > 0; --j) st.ph[j] = st.ph[j - 1];
         st.ph[0] = st.r1;
         st.r1 = tp;
+      }
+      if (inert) {
+        // V_n joins the velocity history; the dropped buffer takes the next
+        // step's velocities (gathered into it below)
+        double* tv = st.vh[K - 1];
+        for (int j = K - 1; j > 0; --j) st.vh[j] = st.vh[j - 1];
+        st.vh[0] = st.p;
+        st.p = tv;
       }
       // history rotation: u_{n-j-1} <- u_{n-j}, u_n <- k1; the dropped buffer
       // takes the next step's velocity
@@ -1190,11 +1223,17 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
       Timed t(c, s, PTK_T_PERMUTE);
       PTK_HIP(c, gather_u32(st.orig, perm, Np, st.orig_b, s), "gather order");
       for (int j = 0; j < hl; ++j) PTK_HIP(c, gather_v(st.h[j], perm, st.hb[j]), "gather history");
-      if (ori) {
-        // the new axes into the new bin order (the old axes' buffer takes them)
+      if (pst) {
+        // the new axes (velocities) into the new bin order (the old ones'
+        // buffer takes them)
         PTK_HIP(c, gather3_f64(st.pn, perm, Np, st.p, s), "gather axes");
         for (int j = 0; j < hl; ++j) PTK_HIP(c, gather3_f64(st.ph[j], perm, Np, st.phb[j], s), "gather axis history");
         for (int j = 0; j < hl; ++j) std::swap(st.ph[j], st.phb[j]);
+      }
+      if (inert) {
+        for (int j = 0; j < hl; ++j)
+          PTK_HIP(c, gather3_f64(st.vh[j], perm, Np, st.vhb[j], s), "gather velocity history");
+        for (int j = 0; j < hl; ++j) std::swap(st.vh[j], st.vhb[j]);
       }
     }
     st.xrow = perm;
@@ -1318,6 +1357,7 @@ int ptk_particles_set_orientation(ptk_ctx* c, const double* p, const double* p_h
   const int64_t Np = st.Np;
   const size_t p3 = (size_t)Np * 24;
   st.ori = false;
+  st.inert = false;  // axes replace inertia (they share the state slots)
   PTK_TRY(ensure(c, c->ori_p, p3));
   PTK_TRY(ensure(c, c->ori_pn, p3));
   PTK_TRY(ensure(c, c->ori_r1, p3));
@@ -1363,20 +1403,91 @@ int ptk_particles_get_orientation(ptk_ctx* c, double* p, double* p_hist, void* s
   return PTK_OK;
 }
 
+int ptk_particles_set_inertia(ptk_ctx* c, const double* V, const double* v_hist, const double* r_hist, int hist_len,
+                              double tau, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  auto& st = c->adv;
+  if (!st.valid) return fail(c, PTK_EINVAL, "no particles loaded");
+  if (!(tau > 0.0) || !std::isfinite(tau)) return fail(c, PTK_EINVAL, "tau must be positive and finite");
+  if (st.Np > 0 && !V) return fail(c, PTK_EINVAL, "NULL velocities");
+  if (hist_len != (st.K ? st.hl : 0))
+    return fail(c, PTK_EINVAL, "hist_len must equal the loaded position history's length");
+  if (hist_len > 0 && st.Np > 0 && (!v_hist || !r_hist)) return fail(c, PTK_EINVAL, "NULL history");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  const int64_t Np = st.Np;
+  const size_t p3 = (size_t)Np * 24;
+  st.ori = false;  // inertia replaces axes (they share the state slots)
+  st.inert = false;
+  PTK_TRY(ensure(c, c->ori_p, p3));
+  PTK_TRY(ensure(c, c->ori_pn, p3));
+  PTK_TRY(ensure(c, c->ori_r1, p3));
+  for (int j = 0; j < st.K; ++j) {
+    PTK_TRY(ensure(c, c->ori_h[j], p3));
+    PTK_TRY(ensure(c, c->ori_hb[j], p3));
+    PTK_TRY(ensure(c, c->in_vh[j], p3));
+    PTK_TRY(ensure(c, c->in_vhb[j], p3));
+  }
+  PTK_TRY(need(c, c->ori_p, p3, "velocities"));
+  st.p = (double*)c->ori_p.ptr;
+  st.pn = (double*)c->ori_pn.ptr;
+  st.r1 = (double*)c->ori_r1.ptr;
+  for (int j = 0; j < 4; ++j) {
+    st.ph[j] = j < st.K ? (double*)c->ori_h[j].ptr : nullptr;
+    st.phb[j] = j < st.K ? (double*)c->ori_hb[j].ptr : nullptr;
+    st.vh[j] = j < st.K ? (double*)c->in_vh[j].ptr : nullptr;
+    st.vhb[j] = j < st.K ? (double*)c->in_vhb[j].ptr : nullptr;
+  }
+  if (Np > 0) {
+    // into the current bin order: particle i is the caller's orig[i]
+    PTK_HIP(c, gather3_f64(V, st.orig, Np, st.p, s), "gather velocities");
+    for (int j = 0; j < hist_len; ++j) {
+      PTK_HIP(c, gather3_f64(v_hist + (size_t)j * Np * 3, st.orig, Np, st.vh[j], s), "gather velocity history");
+      PTK_HIP(c, gather3_f64(r_hist + (size_t)j * Np * 3, st.orig, Np, st.ph[j], s), "gather drag history");
+    }
+  }
+  st.tau = tau;
+  st.inert = true;
+  return PTK_OK;
+}
+
+int ptk_particles_get_inertia(ptk_ctx* c, double* V, double* v_hist, double* r_hist, void* stream) {
+  if (!c) return PTK_EINVAL;
+  c->err.clear();
+  auto& st = c->adv;
+  if (!st.valid) return fail(c, PTK_EINVAL, "no particles loaded");
+  if (!st.inert) return fail(c, PTK_EINVAL, "the loaded particles carry no inertia");
+  const int hl = st.K ? st.hl : 0;
+  if (st.Np > 0 && (!V || (hl > 0 && (!v_hist || !r_hist)))) return fail(c, PTK_EINVAL, "NULL pointer");
+  DeviceGuard g(c->device);
+  if (g.err != hipSuccess) return hip_fail(c, g.err, "hipSetDevice");
+  hipStream_t s = S(stream);
+  const int64_t Np = st.Np;
+  if (Np == 0) return PTK_OK;
+  PTK_HIP(c, scatter_f64(st.p, st.orig, Np, 3, V, s), "scatter velocities");
+  for (int j = 0; j < hl; ++j) {
+    PTK_HIP(c, scatter_f64(st.vh[j], st.orig, Np, 3, v_hist + (size_t)j * Np * 3, s), "scatter velocity history");
+    PTK_HIP(c, scatter_f64(st.ph[j], st.orig, Np, 3, r_hist + (size_t)j * Np * 3, s), "scatter drag history");
+  }
+  return PTK_OK;
+}
+
 namespace {
 
 // ---- particle state files (in the caller's order, Sec. 3.4)
 struct StateHeader {
   char magic[8];       // "PTKSTATE"
   uint32_t version;    // 1
-  uint32_t flags;      // bit 0: axes (and their history) follow
+  uint32_t flags;      // bit 0: axes (and their history) follow; bit 1: inertia (V and its histories)
   int64_t np;
   int32_t depth;       // Adams-Bashforth history depth k (0 without history)
   int32_t hist_len;    // valid history entries
   int32_t vel_bytes;   // 8 (FP64 storage) or 4
   int32_t grid;        // N of the field the state was saved with
   double shape;        // axes' shape factor
-  uint64_t reserved[2];
+  uint64_t reserved[2];  // [0]: inertial particles' response time tau (float64 bits)
 };
 static_assert(sizeof(StateHeader) == 64, "state header is 64 bytes");
 constexpr size_t kIoChunk = (size_t)32 << 20;
@@ -1431,8 +1542,10 @@ int ptk_particles_save(ptk_ctx* c, const char* path, void* stream) {
   const int hl = st.K ? st.hl : 0;
   const size_t x3 = (size_t)Np * 24, v3 = (size_t)Np * 3 * st.vb;
   // the state in the caller's order, staged on the device (positions, then
-  // each history entry, then the axes and theirs)
-  const size_t total = x3 + (size_t)hl * v3 + (st.ori ? x3 + (size_t)hl * x3 : 0);
+  // each history entry, then the axes and theirs, or the velocities and
+  // their two histories)
+  const size_t total = x3 + (size_t)hl * v3 + (st.ori ? x3 + (size_t)hl * x3 : 0) +
+                       (st.inert ? x3 + (size_t)2 * hl * x3 : 0);
   PTK_TRY(ensure(c, c->io, total > 0 ? total : 256));
   PTK_TRY(need(c, c->io, total, "state staging"));
   char* dst = (char*)c->io.ptr;
@@ -1441,18 +1554,23 @@ int ptk_particles_save(ptk_ctx* c, const char* path, void* stream) {
     if (st.ori)
       PTK_TRY(ptk_particles_get_orientation(c, (double*)(dst + x3 + (size_t)hl * v3),
                                             (double*)(dst + x3 + (size_t)hl * v3 + x3), stream));
+    if (st.inert) {
+      char* b = dst + x3 + (size_t)hl * v3;
+      PTK_TRY(ptk_particles_get_inertia(c, (double*)b, (double*)(b + x3), (double*)(b + x3 + (size_t)hl * x3), stream));
+    }
   }
   StateHeader hd;
   std::memset(&hd, 0, sizeof(hd));
   std::memcpy(hd.magic, "PTKSTATE", 8);
   hd.version = 1;
-  hd.flags = st.ori ? 1u : 0u;
+  hd.flags = (st.ori ? 1u : 0u) | (st.inert ? 2u : 0u);
   hd.np = Np;
   hd.depth = st.K;
   hd.hist_len = hl;
   hd.vel_bytes = st.vb;
   hd.grid = (int32_t)st.N;
   hd.shape = st.ori ? st.shape : 0.0;
+  if (st.inert) std::memcpy(&hd.reserved[0], &st.tau, sizeof(double));
   FileCloser fc{fopen(path, "wb")};
   if (!fc.f) return fail(c, PTK_EIO, std::string("cannot open ") + path + " for writing");
   if (fwrite(&hd, sizeof(hd), 1, fc.f) != 1) return fail(c, PTK_EIO, "short write of the state header");
@@ -1475,8 +1593,11 @@ int ptk_particles_restore(ptk_ctx* c, const char* path, void* stream) {
     return fail(c, PTK_EIO, "not a particle state file of this version");
   if (hd.np < 0 || hd.np > (int64_t)0xFFFFFFFF || !(hd.depth == 0 || (hd.depth >= 2 && hd.depth <= 4)) ||
       hd.hist_len < 0 || hd.hist_len > hd.depth || (hd.vel_bytes != 4 && hd.vel_bytes != 8) ||
-      (hd.flags & ~1u) != 0 || !(hd.shape >= -1.0 && hd.shape <= 1.0))
+      (hd.flags & ~3u) != 0 || hd.flags == 3u || !(hd.shape >= -1.0 && hd.shape <= 1.0))
     return fail(c, PTK_EIO, "corrupt particle state header");
+  double tau = 0.0;
+  std::memcpy(&tau, &hd.reserved[0], sizeof(double));
+  if ((hd.flags & 2u) && !(tau > 0.0 && std::isfinite(tau))) return fail(c, PTK_EIO, "corrupt particle state header");
   if (hd.grid != (int32_t)c->geom.N) return fail(c, PTK_EINVAL, "the state was saved on a grid of another N");
   if (hd.depth > 0 && hd.vel_bytes != vel_bytes(c))
     return fail(c, PTK_EINVAL, "the state's history has another velocity precision than the field's storage");
@@ -1485,9 +1606,10 @@ int ptk_particles_restore(ptk_ctx* c, const char* path, void* stream) {
   hipStream_t s = S(stream);
   const int64_t Np = hd.np;
   const int hl = hd.hist_len;
-  const bool axes = hd.flags & 1u;
+  const bool axes = hd.flags & 1u, inertia = hd.flags & 2u;
   const size_t x3 = (size_t)Np * 24, v3 = (size_t)Np * 3 * hd.vel_bytes;
-  const size_t total = x3 + (size_t)hl * v3 + (axes ? x3 + (size_t)hl * x3 : 0);
+  const size_t total = x3 + (size_t)hl * v3 + (axes ? x3 + (size_t)hl * x3 : 0) +
+                       (inertia ? x3 + (size_t)2 * hl * x3 : 0);
   PTK_TRY(ensure(c, c->io, total > 0 ? total : 256));
   PTK_TRY(need(c, c->io, total, "state staging"));
   char* src = (char*)c->io.ptr;
@@ -1500,6 +1622,11 @@ int ptk_particles_restore(ptk_ctx* c, const char* path, void* stream) {
   if (axes)
     PTK_TRY(ptk_particles_set_orientation(c, (const double*)(src + x3 + (size_t)hl * v3),
                                           (const double*)(src + x3 + (size_t)hl * v3 + x3), hl, hd.shape, stream));
+  if (inertia) {
+    const char* b = src + x3 + (size_t)hl * v3;
+    PTK_TRY(ptk_particles_set_inertia(c, (const double*)b, (const double*)(b + x3),
+                                      (const double*)(b + x3 + (size_t)hl * x3), hl, tau, stream));
+  }
   return PTK_OK;
 }
 

@@ -127,6 +127,9 @@ hipError_t launch_jeffery_rhs(int grad_f64, const void* G, const double* p, doub
                               hipStream_t s);
 hipError_t launch_orient_update(int kind, const double* p, const UpdateVel& v, double dt, int64_t n, int unit,
                                 double* out, hipStream_t s);
+// inertial particles: r = (u - V) / tau (u FP64 or FP32 [n][3], V and r FP64)
+hipError_t launch_drag_rhs(int vel_f64, const void* u, const double* V, double tau, int64_t n, double* r,
+                           hipStream_t s);
 
 // learned.hip
 struct LearnedField {

@@ -138,8 +138,18 @@ struct ptk_ctx {
     double* ps = nullptr;
     double* ph[4] = {nullptr, nullptr, nullptr, nullptr};
     double* phb[4] = {nullptr, nullptr, nullptr, nullptr};
+    // inertial particles (dX/dt = V, dV/dt = (u - V)/tau) use the same slots
+    // for V: p the velocities, pn the next step's, r1 and r2 the drag terms of
+    // the stages, ps the predictor's velocities, ph the drag history; vh holds
+    // the earlier velocities (the positions' Adams-Bashforth history).  A
+    // particle set has axes or inertia, not both.
+    bool inert = false;
+    double tau = 0.0;
+    double* vh[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* vhb[4] = {nullptr, nullptr, nullptr, nullptr};
   } adv;
   ptk::DevBuf ori_p, ori_pn, ori_r1, ori_r2, ori_ps, ori_h[4], ori_hb[4], gint2;
+  ptk::DevBuf in_vh[4], in_vhb[4];  // inertial particles' velocity history and its permuted copy
   ptk::DevBuf io;  // the particle state in the caller's order, for state files
   // learned form: FP32 master parameters, Adam moments, BF16 layer copies,
   // per-workgroup gradient and loss partials, audit scratch

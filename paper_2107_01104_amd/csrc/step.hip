@@ -204,6 +204,28 @@ hipError_t launch_jeffery_rhs(int grad_f64, const void* G, const double* p, doub
   return hipGetLastError();
 }
 
+// Drag on inertial particles: r = (u - V) / tau per component, FP64 (u in
+// the interpolation's precision, converted exactly).
+template <typename U>
+__global__ __launch_bounds__(256) void k_drag_rhs(const U* __restrict__ u, const double* __restrict__ V, double tau,
+                                                  int64_t n3, double* __restrict__ r) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n3) return;
+  r[e] = ((double)u[e] - V[e]) / tau;
+}
+
+hipError_t launch_drag_rhs(int vel_f64, const void* u, const double* V, double tau, int64_t n, double* r,
+                           hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t n3 = 3 * n;
+  const unsigned blocks = (unsigned)((n3 + 255) / 256);
+  if (vel_f64)
+    k_drag_rhs<double><<<blocks, 256, 0, s>>>((const double*)u, V, tau, n3, r);
+  else
+    k_drag_rhs<float><<<blocks, 256, 0, s>>>((const float*)u, V, tau, n3, r);
+  return hipGetLastError();
+}
+
 hipError_t launch_orient_update(int kind, const double* p, const UpdateVel& v, double dt, int64_t n, int unit,
                                 double* out, hipStream_t s) {
   if (n == 0) return hipSuccess;

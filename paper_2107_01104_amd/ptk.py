@@ -30,7 +30,8 @@ LEARNED_NFEAT, LEARNED_FEAT_PITCH, LEARNED_NPARAMS = 195, 200, 41987
 EXPORTS = ["ptk_kernel_table", "ptk_kernel_table_centred", "ptk_create", "ptk_destroy", "ptk_last_error", "ptk_set_field", "ptk_get_field_scale",
            "ptk_set_field_spectral", "ptk_set_field_next", "ptk_get_field", "ptk_particles_load",
            "ptk_particles_advance", "ptk_particles_store", "ptk_particles_step_next_field",
-           "ptk_particles_set_orientation", "ptk_particles_get_orientation", "ptk_particles_save",
+           "ptk_particles_set_orientation", "ptk_particles_get_orientation", "ptk_particles_set_inertia",
+           "ptk_particles_get_inertia", "ptk_particles_save",
            "ptk_particles_restore",
            "ptk_locate", "ptk_interpolate", "ptk_interpolate_gradient", "ptk_advance_particles",
            "ptk_binning_info", "ptk_get_binning", "ptk_timing_enable", "ptk_timing_read",
@@ -69,6 +70,8 @@ lib.ptk_set_field_next.argtypes = [_vp, _vp, _i64, _int, _int, _vp]
 lib.ptk_particles_step_next_field.argtypes = [_vp, _dbl, _vp, _vp]
 lib.ptk_particles_set_orientation.argtypes = [_vp, _vp, _vp, _int, _dbl, _vp]
 lib.ptk_particles_get_orientation.argtypes = [_vp, _vp, _vp, _vp]
+lib.ptk_particles_set_inertia.argtypes = [_vp, _vp, _vp, _vp, _int, _dbl, _vp]
+lib.ptk_particles_get_inertia.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.ptk_particles_save.argtypes = [_vp, ctypes.c_char_p, _vp]
 lib.ptk_particles_restore.argtypes = [_vp, ctypes.c_char_p, _vp]
 lib.ptk_locate.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
@@ -391,6 +394,27 @@ class Context:
         if hist is not None:
             _dev_tensor(hist, torch.float64, (3,), "p_hist")
         self._check(lib.ptk_particles_get_orientation(self._h, _ptr(p), _ptr(hist), _stream(self.device)))
+
+    def particles_set_inertia(self, V: torch.Tensor, tau: float, v_hist=None, r_hist=None, hist_len: int = 0):
+        """Velocities V ([Np][3] float64, caller order) of the loaded particles,
+        which from then on move with V under linear drag, dV/dt = (u - V)/tau;
+        with an Adams-Bashforth history, the earlier velocities and drag terms
+        ([k][Np][3] float64 each) with as many valid entries as the position
+        history.  Replaces axes set before."""
+        _dev_tensor(V, torch.float64, (3,), "V")
+        for name, h in (("v_hist", v_hist), ("r_hist", r_hist)):
+            if h is not None:
+                _dev_tensor(h, torch.float64, (3,), name)
+        self._check(lib.ptk_particles_set_inertia(self._h, _ptr(V), _ptr(v_hist), _ptr(r_hist), int(hist_len),
+                                                  float(tau), _stream(self.device)))
+
+    def particles_get_inertia(self, V: torch.Tensor, v_hist=None, r_hist=None):
+        _dev_tensor(V, torch.float64, (3,), "V")
+        for name, h in (("v_hist", v_hist), ("r_hist", r_hist)):
+            if h is not None:
+                _dev_tensor(h, torch.float64, (3,), name)
+        self._check(lib.ptk_particles_get_inertia(self._h, _ptr(V), _ptr(v_hist), _ptr(r_hist),
+                                                  _stream(self.device)))
 
     def particles_save(self, path: str):
         """Write the loaded state to a file in the caller's order."""

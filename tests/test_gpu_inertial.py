@@ -1,0 +1,216 @@
+"""Inertial particles under linear drag (marked gpu): dX/dt = V,
+dV/dt = (u(X) - V)/tau.
+
+Against the oracle's steps (``stepping.advance_inertial``) on the same stored
+field: FP64 storage, positions within 1e-12 * 2 pi and velocities within
+1e-12 * rms(u) (the stepping parity bar), for Euler, Heun and
+Adams-Bashforth 2-4; FP32 storage within the FP32 value bar carried through
+the steps (each stage's u within 1e-5 rms(u), entering V through h = dt/tau
+and X through dt, with a factor 8 for the Adams-Bashforth weights); a resumed
+run (velocities and both histories taken out and put back) and a run
+restored from a state file equal to an uninterrupted one bit for bit;
+argument errors, and axes and inertia replacing each other.
+"""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import geometry, interp, stepping
+from oracle import kernels as K
+from synthetic import particles
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+L = geometry.L
+SCHEMES = {"euler": 1, "heun": 2, "ab2": 3, "ab3": 4, "ab4": 5}
+AB_DEPTH = {"euler": 0, "heun": 0, "ab2": 2, "ab3": 3, "ab4": 4}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ptk():
+    from paper_2107_01104_amd import ptk as mod
+    return mod
+
+
+@pytest.mark.parametrize("scheme", ["euler", "heun", "ab2", "ab3", "ab4"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_inertial_match_oracle(ptk, scheme, storage):
+    say(f"[inertial] {scheme} {storage}")
+    N, NP, dt, steps, tau = 16, 4000, 0.01, 6, 0.05
+    rng = np.random.default_rng(95)
+    u = rng.standard_normal((N, N, N, 3)) * 0.5
+    code = ptk.F64 if storage == "f64" else ptk.F32
+    vdt = torch.float64 if storage == "f64" else torch.float32
+    if storage == "f32":
+        u = u.astype(np.float32)
+    X0 = particles.uniform_particles(NP, seed=96, device="cpu").numpy()
+    V0 = 0.5 * rng.standard_normal((NP, 3))
+    k = AB_DEPTH[scheme]
+    ctx = ptk.Context(0)
+    ctx.set_field(torch.from_numpy(u).to(DEV), K.SPLINE, 8, 2, storage=code)
+    ctx.particles_load(torch.from_numpy(X0).to(DEV),
+                       hist=torch.zeros((k, NP, 3), dtype=vdt, device=DEV) if k else None, hist_len=0, hist_depth=k)
+    ctx.particles_set_inertia(torch.from_numpy(V0).to(DEV), tau)
+    ctx.particles_advance(SCHEMES[scheme], dt, steps)
+    X = torch.empty((NP, 3), dtype=torch.float64, device=DEV)
+    V = torch.empty((NP, 3), dtype=torch.float64, device=DEV)
+    ctx.particles_store(X, hist=torch.zeros((k, NP, 3), dtype=vdt, device=DEV) if k else None)
+    vh = torch.zeros((k, NP, 3), dtype=torch.float64, device=DEV) if k else None
+    rh = torch.zeros((k, NP, 3), dtype=torch.float64, device=DEV) if k else None
+    ctx.particles_get_inertia(V, v_hist=vh, r_hist=rh)
+    u64 = u.astype(np.float64)
+    vel = lambda Y: interp.interp_vec(u64, Y, K.SPLINE, 8, 2)
+    Xo, Vo, vho, rho, hlo = stepping.advance_inertial(X0, V0, vel, tau, SCHEMES[scheme], dt, steps)
+    dx = np.max(np.abs(X.cpu().numpy() - Xo))
+    dv = np.max(np.abs(V.cpu().numpy() - Vo))
+    urms = float(np.sqrt(np.mean(vel(X0) ** 2)))
+    say(f"  max position difference {dx:.2e}, max velocity difference {dv:.2e} (rms u {urms:.2f})")
+    if storage == "f64":
+        assert dx <= 1e-12 * L and dv <= 1e-12 * urms
+        if k:
+            assert np.max(np.abs(vh.cpu().numpy()[:hlo] - vho[:hlo])) <= 1e-12 * urms
+            assert np.max(np.abs(rh.cpu().numpy()[:hlo] - rho[:hlo])) <= 1e-12 * urms / tau
+    else:
+        h = dt / tau
+        vbar = steps * h * 1e-5 * urms * 8
+        assert dv <= vbar
+        assert dx <= dt * steps * vbar + 8 * np.spacing(L)
+    ctx.close()
+
+
+def _zeros(k, NP, dtype=torch.float64):
+    return torch.zeros((k, NP, 3), dtype=dtype, device=DEV) if k else None
+
+
+@pytest.mark.parametrize("scheme", ["heun", "ab3"])
+def test_inertial_resume_equals_one_run(ptk, scheme):
+    say(f"[inertial resume] {scheme}")
+    N, NP, dt, tau = 16, 3000, 0.02, 0.1
+    rng = np.random.default_rng(97)
+    u = torch.from_numpy(rng.standard_normal((N, N, N, 3)) * 0.5).to(DEV)
+    X0 = particles.uniform_particles(NP, seed=98, device=DEV)
+    V0 = torch.from_numpy(0.3 * rng.standard_normal((NP, 3))).to(DEV)
+    k = AB_DEPTH[scheme]
+    sc = SCHEMES[scheme]
+    ctx = ptk.Context(0)
+    ctx.set_field(u, K.LAGRANGE, 6, 0, storage=ptk.F64)
+    # one run of 7 steps
+    ctx.particles_load(X0, hist=_zeros(k, NP), hist_len=0, hist_depth=k)
+    ctx.particles_set_inertia(V0, tau)
+    ctx.particles_advance(sc, dt, 7)
+    Xa, Va = torch.empty_like(X0), torch.empty_like(V0)
+    ha, vha, rha = _zeros(k, NP), _zeros(k, NP), _zeros(k, NP)
+    ctx.particles_store(Xa, hist=ha)
+    ctx.particles_get_inertia(Va, v_hist=vha, r_hist=rha)
+    # 3 steps, everything taken out, put back, 4 more
+    ctx.particles_load(X0, hist=_zeros(k, NP), hist_len=0, hist_depth=k)
+    ctx.particles_set_inertia(V0, tau)
+    ctx.particles_advance(sc, dt, 3)
+    Xb, Vb = torch.empty_like(X0), torch.empty_like(V0)
+    hb, vhb, rhb = _zeros(k, NP), _zeros(k, NP), _zeros(k, NP)
+    hl = ctx.particles_store(Xb, hist=hb)
+    ctx.particles_get_inertia(Vb, v_hist=vhb, r_hist=rhb)
+    ctx.particles_load(Xb, hist=hb, hist_len=hl, hist_depth=k)
+    ctx.particles_set_inertia(Vb, tau, v_hist=vhb, r_hist=rhb, hist_len=hl)
+    ctx.particles_advance(sc, dt, 4)
+    Xc, Vc = torch.empty_like(X0), torch.empty_like(V0)
+    hc, vhc, rhc = _zeros(k, NP), _zeros(k, NP), _zeros(k, NP)
+    ctx.particles_store(Xc, hist=hc)
+    ctx.particles_get_inertia(Vc, v_hist=vhc, r_hist=rhc)
+    assert torch.equal(Xa, Xc) and torch.equal(Va, Vc)
+    if k:
+        assert torch.equal(vha, vhc) and torch.equal(rha, rhc)
+    ctx.close()
+
+
+def test_inertial_state_file_continues_bit_for_bit(ptk):
+    say("[inertial state file] ab2")
+    N, NP, dt, tau, k = 16, 2000, 0.02, 0.08, 2
+    rng = np.random.default_rng(99)
+    u = torch.from_numpy((rng.standard_normal((N, N, N, 3)) * 0.5).astype(np.float32)).to(DEV)
+    X0 = particles.uniform_particles(NP, seed=100, device=DEV)
+    V0 = torch.from_numpy(0.3 * rng.standard_normal((NP, 3))).to(DEV)
+    ctx = ptk.Context(0)
+    ctx.set_field(u, K.SPLINE, 6, 1, storage=ptk.F32)
+    ctx.particles_load(X0, hist=_zeros(k, NP, torch.float32), hist_len=0, hist_depth=k)
+    ctx.particles_set_inertia(V0, tau)
+    ctx.particles_advance(SCHEMES["ab2"], dt, 6)
+    Xa, Va = torch.empty_like(X0), torch.empty_like(V0)
+    ctx.particles_store(Xa, hist=_zeros(k, NP, torch.float32))
+    ctx.particles_get_inertia(Va, v_hist=_zeros(k, NP), r_hist=_zeros(k, NP))
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "inertial.bin")
+        ctx.particles_load(X0, hist=_zeros(k, NP, torch.float32), hist_len=0, hist_depth=k)
+        ctx.particles_set_inertia(V0, tau)
+        ctx.particles_advance(SCHEMES["ab2"], dt, 2)
+        ctx.particles_save(path)
+        c2 = ptk.Context(0)
+        c2.set_field(u, K.SPLINE, 6, 1, storage=ptk.F32)
+        c2.particles_restore(path)
+        c2.particles_advance(SCHEMES["ab2"], dt, 4)
+        Xb, Vb = torch.empty_like(X0), torch.empty_like(V0)
+        c2.particles_store(Xb, hist=_zeros(k, NP, torch.float32))
+        c2.particles_get_inertia(Vb, v_hist=_zeros(k, NP), r_hist=_zeros(k, NP))
+        with pytest.raises(ptk.PtkError) as e:
+            c2.particles_get_orientation(torch.empty_like(V0), hist=_zeros(k, NP))  # inertia, not axes
+        assert e.value.code == ptk.EINVAL
+        c2.close()
+    assert torch.equal(Xa, Xb) and torch.equal(Va, Vb)
+    ctx.close()
+
+
+def test_inertial_errors_and_replacement(ptk):
+    say("[inertial] errors")
+    N = 16
+    u = torch.zeros((N, N, N, 3), dtype=torch.float64, device=DEV)
+    ctx = ptk.Context(0)
+    ctx.set_field(u, K.LAGRANGE, 4, 0, storage=ptk.F64)
+    V = torch.zeros((10, 3), dtype=torch.float64, device=DEV)
+    with pytest.raises(ptk.PtkError) as e:
+        ctx.particles_set_inertia(V, 0.1)                # nothing loaded
+    assert e.value.code == ptk.EINVAL
+    ctx.particles_load(particles.uniform_particles(10, seed=1, device=DEV))
+    with pytest.raises(ptk.PtkError) as e:
+        ctx.particles_get_inertia(V)                     # no inertia set
+    assert e.value.code == ptk.EINVAL
+    for tau in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(ptk.PtkError) as e:
+            ctx.particles_set_inertia(V, tau)
+        assert e.value.code == ptk.EINVAL
+    with pytest.raises(ptk.PtkError) as e:
+        ctx.particles_set_inertia(V, 0.1, hist_len=1)    # no position history loaded
+    assert e.value.code == ptk.EINVAL
+    # axes and inertia replace each other
+    ctx.particles_set_inertia(V, 0.1)
+    p = torch.zeros((10, 3), dtype=torch.float64, device=DEV)
+    p[:, 0] = 1.0
+    ctx.particles_set_orientation(p, 0.5)
+    with pytest.raises(ptk.PtkError) as e:
+        ctx.particles_get_inertia(V)
+    assert e.value.code == ptk.EINVAL
+    ctx.particles_set_inertia(V, 0.1)
+    with pytest.raises(ptk.PtkError) as e:
+        ctx.particles_get_orientation(p)
+    assert e.value.code == ptk.EINVAL
+    # a zero field: V decays as (1 - dt/tau)^n under Euler, X moves with it
+    ctx.particles_load(torch.zeros((10, 3), dtype=torch.float64, device=DEV) + 1.0)
+    V0 = torch.ones((10, 3), dtype=torch.float64, device=DEV)
+    ctx.particles_set_inertia(V0, 0.5)
+    ctx.particles_advance(SCHEMES["euler"], 0.1, 3)
+    Vn = torch.empty_like(V0)
+    Xn = torch.empty_like(V0)
+    ctx.particles_get_inertia(Vn)
+    ctx.particles_store(Xn)
+    assert torch.allclose(Vn, torch.full_like(Vn, 0.8 ** 3), rtol=0, atol=1e-15)
+    assert torch.allclose(Xn, torch.full_like(Xn, 1.0 + 0.1 * (1 + 0.8 + 0.64)), rtol=0, atol=1e-15)
+    ctx.close()
