@@ -221,6 +221,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip the 32^3 and 256^3 workloads")
     ap.add_argument("--no-f64-step", action="store_true", help="skip the FP64-storage Heun step")
     ap.add_argument("--no-medians", action="store_true", help="skip the per-step medians")
+    ap.add_argument("--no-particle-types", action="store_true",
+                    help="skip the resident Heun steps of tracers, ellipsoids and inertial particles")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic record from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
@@ -307,6 +309,7 @@ def main():
     # (cpu_baseline) and the reference values the forms' errors are stated
     # against (cpu_references); nothing on the GPU path calls it
     modes = None if args.no_modes else run_modes(ctx, ptk, X0, Np, timers, K, total_ms)
+    ptypes = None if args.no_particle_types else run_particle_types(ctx, ptk, X0, Np)
     cpu = None if args.no_cpu_baseline else cpu_baseline(u_host, X0)
     forms = None
     if not args.no_forms:
@@ -333,6 +336,7 @@ def main():
         "ms_per_step_breakdown": breakdown,
         "step_medians": medians,
         "modes": modes,
+        "particle_types": ptypes,
         "forms": forms,
         "ift": ift,
         "paper_precision_f64_step": f64_step,
@@ -394,6 +398,35 @@ def run_step_medians(ctx, ptk, X0, Np, grad, runs=10, warmup=3):
         out[f"{k}_ms_median"] = round(statistics.median(v), 3)
     log(f"step medians: {out}")
     return out
+
+
+def run_particle_types(ctx, ptk, X0, Np, steps=3):
+    """One resident Heun step on the headline field (median of `steps` after a
+    warm-up step) for each particle type: tracers (velocity only), ellipsoid
+    axes (Jeffery's equation; the gradient at both stages) and inertial
+    particles (linear drag, tau = 0.05, the particles' own velocities)."""
+    import torch
+    dev = X0.device
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    res = {}
+    for kind in ("tracers", "ellipsoids", "inertial"):
+        ctx.particles_load(X0)
+        if kind == "ellipsoids":
+            p = torch.randn((Np, 3), dtype=torch.float64, device=dev, generator=g)
+            p /= p.norm(dim=1, keepdim=True)
+            ctx.particles_set_orientation(p, 0.8)
+            del p
+        elif kind == "inertial":
+            V = 0.5 * torch.randn((Np, 3), dtype=torch.float64, device=dev, generator=g)
+            ctx.particles_set_inertia(V, 0.05)
+            del V
+        ctx.particles_advance(ptk.HEUN, DT, 1)
+        ms, lo, hi = median_runs(lambda: ctx.particles_advance(ptk.HEUN, DT, 1), runs=steps, warmup=0)
+        res[kind] = {"heun_step_ms_median": round(ms, 3), "min": round(lo, 3), "max": round(hi, 3)}
+    torch.cuda.empty_cache()
+    log(f"particle types: {res}")
+    return res
 
 
 def run_f64_step(ptk, N, kc, X0, Np, steps=3):
