@@ -236,6 +236,25 @@ def advance_inertial(X, V, velocity, tau: float, scheme: int, dt: float, nsteps:
     return X, V, vh, rh, hist_len
 
 
+def heun_inertial_two_fields(X, V, vel_now, vel_next, tau: float, dt: float):
+    """One Heun step of inertial particles (``advance_inertial``) in a field
+    that changes during the step, the stages taking the fields of their own
+    times as in ``heun_two_fields``:
+
+        r1 = drag(u(X, t_n), V);  Xs = X + dt*V;  Vs = V + dt*r1;
+        r2 = drag(u(Xs, t_n + dt), Vs);
+        X <- X + (dt/2)*(V + Vs);  V <- V + (dt/2)*(r1 + r2).
+
+    Returns (X, V)."""
+    X = np.array(X, dtype=np.float64)
+    V = np.array(V, dtype=np.float64)
+    r1 = drag_rhs(vel_now(X), V, tau)
+    Xs = heun_predict(X, dt, V)
+    Vs = heun_predict(V, dt, r1)
+    r2 = drag_rhs(vel_next(Xs), Vs, tau)
+    return heun_correct(X, dt, V, Vs), heun_correct(V, dt, r1, r2)
+
+
 def heun_two_fields(X, vel_now, vel_next, dt: float, gradient_now=None):
     """One Heun step in a field that changes during the step (Eq. "tracers"
     with u = u(x, t)): the first stage takes the velocity of the field at the

@@ -359,3 +359,37 @@ def test_inertial_resume_bitwise(scheme):
     for x, y in zip(a[:4], b[:4]):
         assert np.array_equal(x, y)
     assert a[4] == b[4]
+
+
+def test_inertial_two_fields_equal_fields_is_one_heun_step():
+    rng = np.random.default_rng(44)
+    X0, V0 = rng.uniform(0, 6, (10, 3)), rng.standard_normal((10, 3))
+    a = stepping.heun_inertial_two_fields(X0, V0, _shear_u, _shear_u, 0.3, 0.02)
+    b = stepping.advance_inertial(X0, V0, _shear_u, 0.3, HEUN, 0.02, 1)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_inertial_two_fields_second_order_in_a_field_linear_in_time():
+    """A uniform field u(t) = A + B t: dV/dt = (A + B t - V)/tau has the
+    closed form V(t) = A + B (t - tau) + (V0 - A + B tau) e^(-t/tau), and
+    X(t) = X0 + (A - B tau) t + B t^2/2 + tau (V0 - A + B tau)(1 - e^(-t/tau)).
+    Steps that take each stage's field at its own time converge to it at
+    second order."""
+    A, B = np.array([0.4, -0.2, 0.9]), np.array([1.5, 0.7, -2.0])
+    tau, T = 0.3, 0.6
+    X0, V0 = np.array([[1.0, 2.0, 3.0]]), np.array([[-0.5, 0.25, 0.1]])
+    e = np.exp(-T / tau)
+    Ve = A + B * (T - tau) + (V0 - A + B * tau) * e
+    Xe = X0 + (A - B * tau) * T + B * T * T / 2 + tau * (V0 - A + B * tau) * (1 - e)
+    errs = []
+    for n in (30, 60):
+        dt = T / n
+        X, V = X0, V0
+        for k in range(n):
+            t0, t1 = k * dt, (k + 1) * dt
+            X, V = stepping.heun_inertial_two_fields(X, V, lambda Y, t=t0: np.broadcast_to(A + B * t, np.shape(Y)),
+                                                     lambda Y, t=t1: np.broadcast_to(A + B * t, np.shape(Y)),
+                                                     tau, dt)
+        errs.append(max(np.abs(X - Xe).max(), np.abs(V - Ve).max()))
+    ratio = errs[0] / errs[1]
+    assert 3.4 < ratio < 4.6, (errs, ratio)
