@@ -214,3 +214,36 @@ def test_inertial_errors_and_replacement(ptk):
     assert torch.allclose(Vn, torch.full_like(Vn, 0.8 ** 3), rtol=0, atol=1e-15)
     assert torch.allclose(Xn, torch.full_like(Xn, 1.0 + 0.1 * (1 + 0.8 + 0.64)), rtol=0, atol=1e-15)
     ctx.close()
+
+
+def test_inertial_two_field_heun_matches_oracle(ptk):
+    """ptk_particles_step_next_field with inertial particles: each Heun stage
+    interpolates the field of its own time (stepping.heun_inertial_two_fields),
+    three steps through a sequence of FP64 fields."""
+    say("[inertial two fields] f64")
+    N, NP, dt, tau = 24, 4000, 0.02, 0.1
+    rng = np.random.default_rng(101)
+    us = [rng.standard_normal((N, N, N, 3)) * 0.3 for _ in range(4)]
+    X0 = particles.uniform_particles(NP, seed=102, device="cpu").numpy()
+    V0 = 0.3 * rng.standard_normal((NP, 3))
+    ctx = ptk.Context(0)
+    ctx.set_field(torch.from_numpy(us[0]).to(DEV), K.SPLINE, 8, 2, storage=ptk.F64)
+    ctx.particles_load(torch.from_numpy(X0).to(DEV))
+    ctx.particles_set_inertia(torch.from_numpy(V0).to(DEV), tau)
+    X, V = X0.copy(), V0.copy()
+    urms = float(np.sqrt(np.mean(us[0] ** 2)))
+    for k in range(3):
+        ctx.set_field_next(torch.from_numpy(us[k + 1]).to(DEV))
+        ctx.particles_step_next_field(dt)
+        now, nxt = us[k], us[k + 1]
+        X, V = stepping.heun_inertial_two_fields(X, V, lambda Y: interp.interp_vec(now, Y, K.SPLINE, 8, 2),
+                                                 lambda Y: interp.interp_vec(nxt, Y, K.SPLINE, 8, 2), tau, dt)
+        Xg = torch.empty((NP, 3), dtype=torch.float64, device=DEV)
+        Vg = torch.empty((NP, 3), dtype=torch.float64, device=DEV)
+        ctx.particles_store(Xg)
+        ctx.particles_get_inertia(Vg)
+        dx = np.max(np.abs(Xg.cpu().numpy() - X))
+        dv = np.max(np.abs(Vg.cpu().numpy() - V))
+        say(f"  step {k}: max position difference {dx:.2e}, max velocity difference {dv:.2e}")
+        assert dx <= 1e-12 * L * (k + 1) and dv <= 1e-12 * urms * (k + 1)
+    ctx.close()
