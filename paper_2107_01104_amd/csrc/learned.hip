@@ -244,13 +244,13 @@ __device__ __forceinline__ void hidden_layer1(const uint16_t* sX, uint16_t* sH1,
   __syncthreads();  // h1 complete; sX is dead from here on
 }
 
-// Both hidden layers: layer 1 as above, then h2 (FP32) in sH2 and its
-// pre-activations' derivatives (training) in ds2.  sX and sH2 may alias.
-template <bool TRAIN>
+// Training's forward pass: layer 1 as above, then h2 (FP32) in sH2 and its
+// pre-activations' derivatives in ds2 (the backward pass reads h2 by rows).
+// sX and sH2 may alias.
 __device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1, uint16_t* sH1t, float* sH2,
                                                const bf16x8 (&bw1)[13], const bf16x8 (&bw2)[8], float bias1,
                                                float bias2, f32x16 (&ds1)[2], f32x16 (&ds2)[2]) {
-  hidden_layer1<TRAIN>(sX, sH1, sH1t, bw1, bias1, ds1);
+  hidden_layer1<true>(sX, sH1, sH1t, bw1, bias1, ds1);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r32 = lane & 31, hi = lane >> 5;
   const int J = 32 * wave + r32;
@@ -271,7 +271,6 @@ __device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1
     }
     acc[0] = mfma(a0, bw2[s], acc[0]);
     acc[1] = mfma(a1, bw2[s], acc[1]);
-    if constexpr (!TRAIN) asm volatile("" ::: "memory");
   }
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
@@ -279,7 +278,7 @@ __device__ __forceinline__ void forward_hidden(const uint16_t* sX, uint16_t* sH1
     for (int v = 0; v < 16; ++v) {
       const float z = acc[rt][v] + bias2;
       sH2[(32 * rt + acc_row(v, hi)) * PH2 + J] = silu(z);
-      if constexpr (TRAIN) ds2[rt][v] = dsilu(z);
+      ds2[rt][v] = dsilu(z);
     }
   __syncthreads();  // h2 complete
 }
@@ -480,7 +479,7 @@ __global__ __launch_bounds__(NT, 1) void k_forward_backward(const uint16_t* feat
   __syncthreads();
 
   f32x16 ds1[2], ds2[2];
-  forward_hidden<true>(sX, sH1, sH1t, sH2, bw1, bw2, bias1, bias2, ds1, ds2);
+  forward_hidden(sX, sH1, sH1t, sH2, bw1, bw2, bias1, bias2, ds1, ds2);
 
   // output layer, loss and dy = 2 (y - target) / (3 batch)
   float se = 0.f;
