@@ -1118,7 +1118,8 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
         PTK_HIP(c, launch_drag_rhs(vf64, k1, st.p, st.tau, Np, st.r1, s), "drag");
       }
     }
-    // the axes' update with the stage rhs in v (unit length at the step's end)
+    // the axes' (inertial particles' velocities') update with the stage rhs
+    // in v; axes are brought to unit length at the step's end
     auto orient = [&](int kind, const UpdateVel& v, double* out, int unit) -> int {
       Timed t(c, s, PTK_T_UPDATE);
       PTK_HIP(c, launch_orient_update(kind, st.p, v, dt, Np, unit, out, s), "axis update");
