@@ -51,6 +51,9 @@ int main() {
             PTK_EINVAL,
         "advance NULL");
   check(ptk_particles_advance(nullptr, PTK_HEUN, 1e-3, 1, nullptr, nullptr) == PTK_EINVAL, "particles NULL");
+  check(ptk_particles_set_inertia(nullptr, nullptr, nullptr, nullptr, 0, 0.1, nullptr) == PTK_EINVAL,
+        "set_inertia NULL");
+  check(ptk_particles_get_inertia(nullptr, nullptr, nullptr, nullptr, nullptr) == PTK_EINVAL, "get_inertia NULL");
   ptk_destroy(nullptr);
   if (failures) return 1;
   std::printf("host driver: all checks passed\n");

@@ -76,6 +76,10 @@ def test_null_and_bad_arguments_without_device(ptk):
     assert ptk.lib.ptk_particles_load(None, None, 0, None, 0, 0, None) == ptk.EINVAL
     assert ptk.lib.ptk_particles_advance(None, 2, 1e-3, 1, None, None) == ptk.EINVAL
     assert ptk.lib.ptk_particles_store(None, None, None, None, None) == ptk.EINVAL
+    assert ptk.lib.ptk_particles_set_orientation(None, None, None, 0, 0.5, None) == ptk.EINVAL
+    assert ptk.lib.ptk_particles_get_orientation(None, None, None, None) == ptk.EINVAL
+    assert ptk.lib.ptk_particles_set_inertia(None, None, None, None, 0, 0.1, None) == ptk.EINVAL
+    assert ptk.lib.ptk_particles_get_inertia(None, None, None, None, None) == ptk.EINVAL
     ptk.lib.ptk_destroy(None)
 
 
