@@ -266,7 +266,19 @@ def main():
     torch.cuda.synchronize()
     del a, b
 
-    ctx.advance(X, ptk.HEUN, DT, args.warmup, grad_out=grad)
+    # the workload is the velocity and its gradient at every step: one
+    # single-step call per step returns that step's gradient in the caller's
+    # order (a multi-step call evaluates the gradient on its last step only).
+    # The particles stay in the library between the calls: one sort and
+    # gather before the steps, one scatter back after them, as in a one-shot
+    # multi-step call.
+    def heun_steps(k):
+        ctx.particles_load(X)
+        for _ in range(k):
+            ctx.particles_advance(ptk.HEUN, DT, 1, grad_out=grad)
+        ctx.particles_store(X)
+
+    heun_steps(args.warmup)
     torch.cuda.synchronize()
     log("warmup done")
     ctx.timing(True)
@@ -274,7 +286,7 @@ def main():
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    ctx.advance(X, ptk.HEUN, DT, args.steps, grad_out=grad)
+    heun_steps(args.steps)
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
@@ -432,9 +444,10 @@ def run_particle_types(ctx, ptk, X0, Np, steps=3):
 def run_f64_step(ptk, N, kc, X0, Np, steps=3):
     """The paper's precision (all FP64, Sec. 4.1-4.2): the same workload with the
     field stored in FP64 and FP64 sums, velocities and gradients -- Heun steps
-    with gradient, timed like the headline (one advance call of `steps` steps
-    after a warm-up step), with the value + gradient kernel against the FP64
-    vector peak and against HBM."""
+    with gradient, timed like the headline (after a warm-up step: the load,
+    `steps` single-step calls that each return their step's gradient, and
+    the store), with the value + gradient kernel against the FP64 vector peak
+    and against HBM."""
     import torch
     from synthetic import fields
     dev = torch.device("cuda", 0)
@@ -445,13 +458,17 @@ def run_f64_step(ptk, N, kc, X0, Np, steps=3):
     torch.cuda.empty_cache()
     X = X0.clone()
     grad = torch.empty((Np, 3, 3), dtype=torch.float64, device=dev)
-    ctx.advance(X, ptk.HEUN, DT, 1, grad_out=grad)
+    ctx.particles_load(X)
+    ctx.particles_advance(ptk.HEUN, DT, 1, grad_out=grad)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
     ctx.timing(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    ctx.advance(X, ptk.HEUN, DT, steps, grad_out=grad)
+    ctx.particles_load(X)
+    for _ in range(steps):
+        ctx.particles_advance(ptk.HEUN, DT, 1, grad_out=grad)
+    ctx.particles_store(X)
     e1.record(stream)
     torch.cuda.synchronize()
     total = e0.elapsed_time(e1)
@@ -573,7 +590,7 @@ def run_modes(ctx, ptk, X0, Np, timers, K, total_ms, calls=3):
     identity), E = whole ptk_interpolate / ptk_interpolate_gradient calls on
     the caller-ordered X0 (keys, sort, kernel reading positions through the
     permutation, caller-order writes; HIP events on the stream), S = inside
-    ptk_advance_particles (Heun with gradient: per step one velocity+gradient
+    the headline's Heun steps (per step one velocity+gradient
     evaluation at X_n and one velocity evaluation at the re-binned predictor;
     kernel times per step, and the whole step with re-binning and updates
     amortised over its two evaluations)."""

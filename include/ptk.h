@@ -252,8 +252,11 @@ int ptk_interpolate_noalloc(ptk_ctx *ctx, const double *X, int64_t Np, void *out
  *    rhs_hist/hist_len may be NULL for Euler and Heun.
  * Every update is separately rounded binary64.
  * grad_out: device [Np][3][3] (binary64 for F64 storage, else FP32) or NULL;
- *    if given, every step also evaluates the gradient at its start position,
- *    and on return grad_out holds the one of the last step.
+ *    if given, the last step also evaluates the gradient at its start
+ *    position, and on return grad_out holds it (the steps before it evaluate
+ *    the velocity only; a caller that samples the gradient along the
+ *    trajectory at every step advances one step per call, e.g. through
+ *    ptk_particles_advance).
  * Particles are re-binned after every position update to the stable order of
  * their new bins (only the particles whose bin changed are sorted, then merged
  * with the others) and kept in bin order internally; results are returned in

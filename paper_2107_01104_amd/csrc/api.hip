@@ -980,7 +980,7 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
   const bool ori = st.ori, inert = st.inert;
   const bool pst = ori || inert;  // a per-particle 3-vector state beside X (axes or velocities)
   const size_t g9 = (size_t)Np * 9 * vb, p3 = (size_t)Np * 24;
-  if (grad_out || ori) PTK_TRY(ensure(c, c->gint, g9));
+  if (ori) PTK_TRY(ensure(c, c->gint, g9));
   if (pst) {
     // the stage rhs and the predictor's axes (velocities) and gradient (the
     // state and its history were allocated when it was set)
@@ -1007,7 +1007,7 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
       PTK_TRY(need(c, c->abh_b[j], v3, "history"));
     }
     if (scheme == PTK_HEUN) PTK_TRY(need(c, c->k2, v3, "predictor velocities"));
-    if (grad_out || ori) PTK_TRY(need(c, c->gint, g9, "gradients"));
+    if (ori) PTK_TRY(need(c, c->gint, g9, "gradients"));
     if (pst) {
       const DevBuf* o3[] = {&c->ori_p, &c->ori_pn, &c->ori_r1, &c->ori_r2, &c->ori_ps};
       for (const DevBuf* b : o3) PTK_TRY(need(c, *b, p3, "per-particle state"));
@@ -1100,9 +1100,9 @@ int adv_steps(ptk_ctx* c, int scheme, double dt, int nsteps, void* grad_out, hip
       a.xrow = st.xrow;
       a.np = Np;
       a.out = k1;
-      // the axes' rhs needs the gradient in bin order; without axes the last
-      // step writes it straight to the caller's order
-      a.grad = ori ? c->gint.ptr : grad_out ? (last ? grad_out : c->gint.ptr) : nullptr;
+      // the axes' rhs needs the gradient in bin order at every step; without
+      // axes only the last step evaluates it, straight into the caller's order
+      a.grad = ori ? c->gint.ptr : grad_out && last ? grad_out : nullptr;
       a.grad_orig = !ori && grad_out && last ? st.orig : nullptr;
       a.out_f64 = vf64;
       {

@@ -65,11 +65,11 @@ def test_resident_equals_one_shot(ptk, scheme, storage):
     # resident: 2 + 3 steps
     ctx.particles_load(X0, hist=torch.zeros((k, NP, 3), dtype=vdt, device=DEV) if k else None,
                        hist_len=0, hist_depth=k)
-    # with a gradient in every step, as the one-shot run (its velocity then
-    # comes from the value + gradient kernel, whose summation order differs
-    # from the value kernel's)
+    # the gradient requested at the same step as in the one-shot run (its
+    # last): at that step the velocity comes from the value + gradient kernel,
+    # whose summation order differs from the value kernel's
     gb = torch.zeros((NP, 3, 3), dtype=vdt, device=DEV)
-    ctx.particles_advance(sc, 3e-3, 2, grad_out=gb)
+    ctx.particles_advance(sc, 3e-3, 2)
     ctx.particles_advance(sc, 3e-3, 3, grad_out=gb)
     Xb = torch.empty_like(X0)
     hb = torch.zeros((k, NP, 3), dtype=vdt, device=DEV) if k else None
