@@ -39,8 +39,7 @@ EXPORTS = ["ptk_kernel_table", "ptk_kernel_table_centred", "ptk_create", "ptk_de
            "ptk_learned_train", "ptk_interpolate_learned", "ptk_selftest", "ptk_interpolate_noalloc"]
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run paper_2107_01104_amd/build.py (or "
-                      "__graft_entry__.build()) first")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2107_01104_amd/build.py` first")
 
 lib = ctypes.CDLL(LIB_PATH)
 
