@@ -64,7 +64,7 @@ def build_host_sanitized(driver: str, out_dir: str) -> str:
     """Build of the library's sources with AddressSanitizer and
     UndefinedBehaviorSanitizer on the host code only (the device code is built
     as usual, without them), linked with the C++ `driver` into an executable;
-    returns its path.  The driver is meant to run without a GPU."""
+    returns its path.  The test program is meant to run without a GPU."""
     os.makedirs(out_dir, exist_ok=True)
     san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
