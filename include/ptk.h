@@ -257,9 +257,10 @@ int ptk_interpolate_noalloc(ptk_ctx *ctx, const double *X, int64_t Np, void *out
  *    the velocity only; a caller that samples the gradient along the
  *    trajectory at every step advances one step per call, e.g. through
  *    ptk_particles_advance).  At a step that evaluates the gradient the
- *    velocity comes from the value + gradient kernel, whose reduced-precision
- *    sums are ordered differently from the value kernel's: runs agree bit for
- *    bit when they request the gradient at the same steps.
+ *    velocity comes from the value + gradient kernel, whose sums are ordered
+ *    differently from the value kernel's (the results can differ in the last
+ *    bits): runs agree bit for bit when they request the gradient at the same
+ *    steps.
  * Particles are re-binned after every position update to the stable order of
  * their new bins (only the particles whose bin changed are sorted, then merged
  * with the others) and kept in bin order internally; results are returned in
