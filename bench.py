@@ -55,7 +55,12 @@ FLOP_GRAD_I8 = 2 * 4080
 # 2*128*128, dW1 2*195*128 (the 3-wide output layer runs in FP32 VALU)
 TRAIN_MFMA_FLOP_PER_PAIR = 2 * (195 * 128 + 128 * 128) + 2 * 128 * 128 + 2 * 128 * 128 + 2 * 195 * 128
 BF16_MFMA_PEAK_TFLOPS = 2500.0
-TRAIN_BATCH = 4096  # the learned form's training batch (16384 trains 2.6x faster, to a worse model)
+# the learned form's training: batch 16384 (the largest the trainer takes:
+# each step's 256 workgroups span every CU), 24 epochs, peak lr 2e-3 (cosine
+# decay).  Against batch 4096 with 8 epochs at lr 1e-3 it trains in about the
+# same time to a lower error (audited 2.8e-3 against 2.9e-3 of the I = 8 rms),
+# at 2.8 times the pairs per second.
+TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR = 16384, 24, 2e-3
 COPY_BYTES = 1 << 30  # the calibration copy: 1 GiB read and 1 GiB written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "interp_grad_f32_i8_1024_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2107_01104_amd", "csrc", "interp.hip")
@@ -783,8 +788,8 @@ def run_forms(ctx, ptk, u_host, X0, N, Np, refs):
 
 def run_learned(ctx, ptk, u_dev, X0, Np, refs, rms_ref, out):
     """Learned correction form: pairs on two 256^3 fields (k <= 80, seeds 100 and
-    101, 5e6 uniform positions each), 8 epochs of Adam (batch 4096, lr 1e-3,
-    output layer starting at zero), then inference on the benchmark field with
+    101, 5e6 uniform positions each), 24 epochs of Adam (batch 16384, peak lr
+    2e-3, output layer starting at zero), then inference on the benchmark field with
     a 1e-3 audit; errors against the FP64 oracle on the same 20000-particle
     sample as the storage forms."""
     import numpy as np
@@ -817,10 +822,14 @@ def run_learned(ctx, ptk, u_dev, X0, Np, refs, rms_ref, out):
         del Xt
     feat, tg = torch.cat(feats), torch.cat(tgts)
     del feats, tgts
+    # an untimed warm-up (the trainer's buffers for this batch), then the run
+    # from the initial parameters
+    ctx.learned_set_params(p0)
+    ctx.learned_train(feat[: 4 * TRAIN_BATCH], tg[: 4 * TRAIN_BATCH], epochs=1, batch=TRAIN_BATCH, lr=TRAIN_LR)
     ctx.learned_set_params(p0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    curve = ctx.learned_train(feat, tg, epochs=8, batch=TRAIN_BATCH, lr=1e-3)
+    curve = ctx.learned_train(feat, tg, epochs=TRAIN_EPOCHS, batch=TRAIN_BATCH, lr=TRAIN_LR)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     n_pairs = feat.shape[0]
@@ -870,7 +879,7 @@ def run_learned(ctx, ptk, u_dev, X0, Np, refs, rms_ref, out):
                                         tol_rel_rms=float("inf"))
     err = got.cpu().numpy().astype(np.float64) - ref
     res = {"train_pairs": int(n_pairs), "pairs_per_s": n_pairs / t_pairs, "train_s": round(t_train, 3),
-           "train_batch": TRAIN_BATCH,
+           "train_batch": TRAIN_BATCH, "train_epochs": TRAIN_EPOCHS, "train_lr": TRAIN_LR,
            "train_pairs_per_s": len(curve) * TRAIN_BATCH / t_train, "steps": int(len(curve)),
            "train_mfma_flop_per_pair": TRAIN_MFMA_FLOP_PER_PAIR,
            "train_mfma_frac": round(len(curve) * TRAIN_BATCH / t_train * TRAIN_MFMA_FLOP_PER_PAIR / 1e12
