@@ -82,7 +82,10 @@ struct Geom {
   static constexpr int PL = TX * RP + ((128 - (TX * RP) % 256) + 256) % 256;
   static constexpr int R = (kWindow + I - 1 + 1) / 2 * 2;  // ring slots (even): the planes one window touches
   static constexpr int LDS = R * PL;
-  static constexpr int G = 48 / StoreT<ST>::GB;           // nodes per 48-byte chunk
+  // nodes per staged chunk: 48 bytes of FP64 and FP32 nodes, 24 of 16-bit
+  // ones (four nodes, as FP32: every thread stages about as many nodes)
+  static constexpr int CB = StoreT<ST>::GB == 6 ? 24 : 48;
+  static constexpr int G = CB / StoreT<ST>::GB;
   static constexpr int RG = (TX + G - 1) / G;             // chunks per halo row
   static constexpr int UNITS_PER_PLANE = TX * RG;
   static constexpr int THREADS = StoreT<ST>::THREADS;
@@ -290,7 +293,7 @@ __device__ __forceinline__ V horner(const V* c, V t) {
   return acc;
 }
 
-// load unit u (one 48-byte chunk of a halo row of plane zp) from HBM.  The
+// load unit u (one chunk of G nodes of a halo row of plane zp) from HBM.  The
 // load is unconditional (a chunk outside the padded field reads the field's
 // first chunk instead and is reported invalid), so the compiler keeps it in
 // flight rather than waiting for it at a branch merge.
@@ -305,8 +308,14 @@ __device__ __forceinline__ bool load_unit(const InterpArgs& a, int64_t x0, int64
   const int64_t off = ok ? zp * a.plane_pitch + Y * a.row_pitch + X * StoreT<ST>::GB : 0;
   const uint4* src = (const uint4*)((const unsigned char*)a.field + off);
   c[0] = src[0];
-  c[1] = src[1];
-  c[2] = src[2];
+  if constexpr (Gm::CB == 24) {
+    const uint2 t = *(const uint2*)(src + 1);
+    c[1] = make_uint4(t.x, t.y, 0u, 0u);
+    c[2] = make_uint4(0u, 0u, 0u, 0u);
+  } else {
+    c[1] = src[1];
+    c[2] = src[2];
+  }
   return ok;
 }
 
